@@ -1,0 +1,248 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU parity tests and
+the benchmark: meshes, velocity-grid specifications and initial distributions.
+
+This module holds none of the method's arithmetic (no moments, no equilibrium
+solve, no FR operator).  It builds the *inputs* the method is applied to:
+
+* hexahedral meshes in the layout of the C ABI (nodes, x-fastest element
+  node lists, face neighbours / orientation codes / boundary tags);
+* velocity-grid specifications ``{"n": (n,n,n), "umin": ..., "umax": ...}``;
+* initial distributions f0 = Maxwellian sampled at every velocity node for a
+  seeded macroscopic field (the paper initialises f as the equilibrium of a
+  macroscopic state), evaluated with torch on the requested device.
+
+The workloads stand in for the paper's capsule cases (whose mesh and data are
+not available): periodic boxes at the paper's orders and velocity
+resolutions, and an O-grid around a cylinder at Mach 8.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SQRT_2_OVER_PI = math.sqrt(2.0 / math.pi)
+
+# Face numbering: face = 2*d + side, side 0 at xi_d = -1, side 1 at xi_d = +1.
+FACE_OPPOSITE = [1, 0, 3, 2, 5, 4]
+
+
+def mu_ref_from_knudsen(kn: float) -> float:
+    """Reference viscosity from a Knudsen number with unit length, density and
+    temperature, through the mean free path lambda = (mu/rho) sqrt(pi/(2 theta))."""
+    return kn * SQRT_2_OVER_PI
+
+
+def box_mesh(N, length=1.0, periodic=True) -> dict:
+    """Axis-aligned box [0,L]^3 of N[0] x N[1] x N[2] straight 8-node hexes.
+
+    Element (ix,iy,iz) has id ix + N0 (iy + N1 iz).  With ``periodic`` every
+    face has a neighbour (wrapping around), orientation code 0."""
+    if np.isscalar(N):
+        N = (int(N),) * 3
+    N = tuple(int(v) for v in N)
+    L = (length,) * 3 if np.isscalar(length) else tuple(length)
+    nx, ny, nz = N
+    gx = [np.linspace(0.0, L[d], N[d] + 1) for d in range(3)]
+    nodes = np.stack(np.meshgrid(gx[0], gx[1], gx[2], indexing="ij"), axis=-1)
+    nodes = nodes.transpose(2, 1, 0, 3).reshape(-1, 3)  # node id = i + (nx+1)(j + (ny+1) k)
+
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    ne = nx * ny * nz
+    en = np.zeros((ne, 8), np.int32)
+    nbr = np.full((ne, 6), -1, np.int32)
+    nbf = np.zeros((ne, 6), np.int8)
+    bc = np.zeros((ne, 6), np.int8)
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(nx):
+                e = ix + nx * (iy + ny * iz)
+                en[e] = [nid(ix + a, iy + b, iz + c) for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+                idx = [ix, iy, iz]
+                for d in range(3):
+                    for side in (0, 1):
+                        f = 2 * d + side
+                        j = list(idx)
+                        j[d] += 1 if side else -1
+                        if 0 <= j[d] < N[d] or periodic:
+                            j[d] %= N[d]
+                            nbr[e, f] = j[0] + nx * (j[1] + ny * j[2])
+                            nbf[e, f] = FACE_OPPOSITE[f]
+                        else:
+                            bc[e, f] = 1
+    return {"n_elem": ne, "n_nodes": nodes.shape[0], "geom_order": 1,
+            "nodes": np.ascontiguousarray(nodes), "elem_nodes": en, "nbr_elem": nbr,
+            "nbr_face": nbf, "nbr_orient": np.zeros((ne, 6), np.int8), "bc": bc,
+            "N": N, "length": L}
+
+
+def gauss_points(p: int) -> np.ndarray:
+    return np.polynomial.legendre.leggauss(p + 1)[0]
+
+
+def box_solution_points(mesh: dict, p: int) -> np.ndarray:
+    """Physical coordinates [ne][ns][3] of the Gauss solution points of an
+    axis-aligned box mesh (solution index i + n (j + n l), x fastest)."""
+    xi = gauss_points(p)
+    n = p + 1
+    nodes, en = mesh["nodes"], mesh["elem_nodes"]
+    lo = nodes[en[:, 0]]
+    hi = nodes[en[:, 7]]
+    r = (xi + 1.0) / 2.0
+    rx, ry, rz = np.meshgrid(r, r, r, indexing="ij")
+    ref = np.stack([rx, ry, rz], -1).transpose(2, 1, 0, 3).reshape(n ** 3, 3)
+    return lo[:, None, :] + ref[None, :, :] * (hi - lo)[:, None, :]
+
+
+def velocity_axes(grid: dict):
+    out = []
+    for d in range(3):
+        n = int(grid["n"][d])
+        if n == 1:
+            out.append(np.array([float(grid["umin"][d])]))
+        else:
+            out.append(np.linspace(float(grid["umin"][d]), float(grid["umax"][d]), n))
+    return out
+
+
+def grid_spec(n, umax, umin=None) -> dict:
+    n = (int(n),) * 3 if np.isscalar(n) else tuple(int(v) for v in n)
+    umax = (float(umax),) * 3 if np.isscalar(umax) else tuple(float(v) for v in umax)
+    umin = tuple(-v for v in umax) if umin is None else (
+        (float(umin),) * 3 if np.isscalar(umin) else tuple(float(v) for v in umin))
+    return {"n": n, "umin": umin, "umax": umax}
+
+
+# --------------------------------------------------------------------------
+# Macroscopic initial fields
+# --------------------------------------------------------------------------
+
+def _wavevectors(kmin=1.0, kmax=2.0):
+    ks = []
+    for a in range(-2, 3):
+        for b in range(-2, 3):
+            for c in range(-2, 3):
+                k = np.array([a, b, c], float)
+                nk = np.linalg.norm(k)
+                if nk < kmin - 1e-12 or nk > kmax + 1e-12:
+                    continue
+                nz = k[np.nonzero(k)[0][0]]
+                if nz > 0:  # half-space representative
+                    ks.append(k)
+    return np.array(ks)
+
+
+def divergence_free_field(xs: np.ndarray, seed: int, amp: float) -> np.ndarray:
+    """Sum of Fourier modes with 1 <= |k| <= 2 whose amplitudes are projected
+    perpendicular to k (divergence free), scaled to max |U| = amp."""
+    rng = np.random.default_rng(seed)
+    ks = _wavevectors()
+    U = np.zeros(xs.shape)
+    for k in ks:
+        a, b = rng.standard_normal(3), rng.standard_normal(3)
+        kh = k / np.linalg.norm(k)
+        a -= kh * (a @ kh)
+        b -= kh * (b @ kh)
+        ph = 2 * np.pi * (xs @ k)
+        U += np.cos(ph)[..., None] * a + np.sin(ph)[..., None] * b
+    m = np.linalg.norm(U, axis=-1).max()
+    return U * (amp / m)
+
+
+def prim_random_modes(xs: np.ndarray, seed: int = 1, U_amp: float = 0.2) -> np.ndarray:
+    """Config-1 field: rho = 1 + 0.1 sin sin sin, U = random divergence-free
+    modes (|k| in [1,2]) with max |U| = U_amp, theta = 1 + 0.05 cos(2 pi k*.x + phi)."""
+    rng = np.random.default_rng(seed + 1000)
+    x, y, z = xs[..., 0], xs[..., 1], xs[..., 2]
+    rho = 1.0 + 0.1 * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) * np.sin(2 * np.pi * z)
+    U = divergence_free_field(xs, seed, U_amp)
+    ks = _wavevectors()
+    kst = ks[rng.integers(len(ks))]
+    phi = rng.uniform(0, 2 * np.pi)
+    theta = 1.0 + 0.05 * np.cos(2 * np.pi * (xs @ kst) + phi)
+    return np.concatenate([rho[..., None], U, theta[..., None]], -1)
+
+
+def prim_taylor_green(xs: np.ndarray, U0: float, pert: float = 0.0, seed: int = 5) -> np.ndarray:
+    """Taylor-Green vortex on the unit box, rho = theta = 1, plus an optional
+    seeded divergence-free perturbation of amplitude pert * U0."""
+    x, y, z = xs[..., 0], xs[..., 1], xs[..., 2]
+    s2 = 2 * np.pi
+    U = np.stack([U0 * np.sin(s2 * x) * np.cos(s2 * y) * np.cos(s2 * z),
+                  -U0 * np.cos(s2 * x) * np.sin(s2 * y) * np.cos(s2 * z),
+                  np.zeros_like(x)], -1)
+    if pert > 0:
+        U = U + divergence_free_field(xs, seed, pert * U0)
+    one = np.ones(x.shape + (1,))
+    return np.concatenate([one, U, one], -1)
+
+
+def maxwellian(prim, grid: dict, dtype=None, device="cpu", chunk_pts: int = 1 << 14):
+    """f[..., k] = rho (2 pi theta)^(-3/2) exp(-|u_k - U|^2 / (2 theta)) at every
+    node k = i + n0 (j + n1 l) of the velocity grid, computed in FP64 with torch
+    and cast to ``dtype``.  prim[..., 5] = (rho, Ux, Uy, Uz, theta)."""
+    import torch
+    dtype = dtype or torch.float64
+    prim = torch.as_tensor(np.asarray(prim), dtype=torch.float64)
+    lead = prim.shape[:-1]
+    pr = prim.reshape(-1, 5)
+    ax = [torch.as_tensor(a, dtype=torch.float64, device=device) for a in velocity_axes(grid)]
+    n0, n1, n2 = (len(a) for a in ax)
+    out = torch.empty((pr.shape[0], n0 * n1 * n2), dtype=dtype, device=device)
+    for s in range(0, pr.shape[0], chunk_pts):
+        p = pr[s:s + chunk_pts].to(device)
+        rho, U, th = p[:, 0:1], p[:, 1:4], p[:, 4:5]
+        ex = torch.exp(-(ax[0][None, :] - U[:, 0:1]) ** 2 / (2 * th))
+        ey = torch.exp(-(ax[1][None, :] - U[:, 1:2]) ** 2 / (2 * th))
+        ez = torch.exp(-(ax[2][None, :] - U[:, 2:3]) ** 2 / (2 * th))
+        c = rho * (2 * math.pi * th) ** -1.5
+        f = (c[:, :, None, None] * ez[:, :, None, None] * ey[:, None, :, None]
+             * ex[:, None, None, :])
+        out[s:s + chunk_pts] = f.reshape(p.shape[0], -1).to(dtype)
+    return out.reshape(tuple(lead) + (n0 * n1 * n2,))
+
+
+# --------------------------------------------------------------------------
+# Named workloads (the shapes of the paper's runs, scaled to one GPU)
+# --------------------------------------------------------------------------
+
+OMEGA_POWER_LAW = 0.81
+
+
+def workload(name: str) -> dict:
+    """Definition of a named workload: mesh builder args, order, grid, physics."""
+    W = {
+        # 4^3 periodic box, p=1, 8^3 grid on [-6,6]^3, BGK, Kn=0.05, 10 SSP-RK3 steps
+        "box4_p1_v8": dict(N=4, p=1, grid=grid_spec(8, 6.0), model=0, prandtl=1.0,
+                           kn=0.05, ic="modes", seed=1, steps=10, rk=0, precision=0),
+        # 16^3 periodic box, p=3, 16^3 grid on [-6,6]^3, BGK, Kn=1e-3, Taylor-Green U0=0.3
+        "box16_p3_v16": dict(N=16, p=3, grid=grid_spec(16, 6.0), model=0, prandtl=1.0,
+                             kn=1e-3, ic="tgv", U0=0.3, pert=0.0, seed=2, steps=100, rk=0,
+                             precision=0),
+        # 24^3 periodic box, p=3, 20^3 grid on [-8,8]^3, ES-BGK Pr=0.71, Kn=2e-4,
+        # Taylor-Green U0=0.5 with a 1% seeded perturbation
+        "box24_p3_v20_es": dict(N=24, p=3, grid=grid_spec(20, 8.0), model=1, prandtl=0.71,
+                                kn=2e-4, ic="tgv", U0=0.5, pert=0.01, seed=5, steps=200,
+                                rk=1, precision=1),
+    }
+    w = dict(W[name])
+    w["name"] = name
+    w["mu_ref"] = mu_ref_from_knudsen(w["kn"])
+    return w
+
+
+def initial_prim(mesh: dict, p: int, w: dict) -> np.ndarray:
+    xs = box_solution_points(mesh, p)
+    if w["ic"] == "modes":
+        return prim_random_modes(xs, seed=w["seed"])
+    if w["ic"] == "tgv":
+        return prim_taylor_green(xs, w["U0"], w.get("pert", 0.0), w.get("seed", 5))
+    raise ValueError(w["ic"])
+
+
+def physics_params(w: dict) -> dict:
+    return {"model": w["model"], "prandtl": w["prandtl"], "mu_ref": w["mu_ref"],
+            "theta_ref": 1.0, "omega": OMEGA_POWER_LAW, "visc_law": 0, "theta_s": 0.0,
+            "newton_tol": 1e-13, "newton_max_iter": 50}
