@@ -1,0 +1,193 @@
+/*
+ * fr_dvm.h -- C ABI of libfrdvm, the MI355X (gfx950) implementation of the
+ * explicit residual-and-update step of a flux-reconstruction (FR)
+ * discretisation of the Boltzmann-BGK / ES-BGK equation on hexahedra, applied
+ * to every node of a conservative discrete velocity model.
+ *
+ * Paper: T. Dzanic & L. Martinelli, "Direct molecular gas dynamics
+ * simulations of re-entry vehicles via the Boltzmann equation",
+ * arXiv 2312.06567.  Section "Governing equations" defines the moments
+ * (eq. moments), the BGK / ES-BGK operator and tau; Section "Numerical
+ * method" defines the FR scheme (solution/flux nodes, corrected flux,
+ * upwind common flux, eq. transport) and the conservative discrete velocity
+ * model (eq. discrete_compatibility).
+ *
+ * Conventions
+ *  - Layout of a distribution f: f[e][s][k], row-major, velocity index k
+ *    fastest.  s = i + n (j + n l) over the (p+1)^3 Gauss-Legendre solution
+ *    points of element e (x fastest), k = i + n0 (j + n1 l) over the velocity
+ *    grid (x fastest).
+ *  - Element types: hexahedra with 8 (trilinear) or 27 (triquadratic) nodes
+ *    listed x-fastest.  Faces: face = 2 d + side, side 0 at xi_d = -1, side 1
+ *    at xi_d = +1.
+ *  - All f / R / S buffers are caller-owned DEVICE pointers of the handle's
+ *    precision (double for FR_DVM_FP64, float for FR_DVM_FP32).  Q / Qp /
+ *    totals are caller-owned DEVICE double buffers unless said otherwise.
+ *    The library never frees or reallocates caller memory.
+ *  - Every call is asynchronous on the handle's stream (default: the null
+ *    stream) unless documented as synchronising.  Calls on one handle are not
+ *    thread safe.
+ *  - Return value: FR_DVM_OK (0) or a negative FR_DVM_E* code; the message is
+ *    kept in fr_dvm_last_error(h).  A kernel fault surfaces at the next
+ *    synchronising call.  Per-point Newton failure is not an error (see
+ *    fr_dvm_newton_stats).
+ */
+#ifndef FR_DVM_H
+#define FR_DVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FR_DVM_OK 0
+#define FR_DVM_EINVAL (-1)      /* invalid argument or inconsistent mesh */
+#define FR_DVM_ENOMEM (-2)      /* device allocation failed */
+#define FR_DVM_EHIP (-3)        /* HIP runtime error */
+#define FR_DVM_EUNSUPPORTED (-4) /* valid input this build does not handle */
+
+/* collision models (Section "Governing equations") */
+#define FR_DVM_BGK 0
+#define FR_DVM_ESBGK 1
+#define FR_DVM_FREE 2 /* collisionless transport (S = 0), for verification */
+
+/* storage / arithmetic precision of f and of the FR operators */
+#define FR_DVM_FP64 0
+#define FR_DVM_FP32 1
+
+/* Newton initial guess for the conservative equilibrium */
+#define FR_DVM_GUESS_COLD 0 /* continuous equilibrium of the moments of f */
+#define FR_DVM_GUESS_WARM 1 /* previous solution at the same point */
+#define FR_DVM_GUESS_MLP 2  /* learned guess (fr_dvm_mlp_set_weights) */
+
+/* explicit time integration (the paper names no scheme) */
+#define FR_DVM_SSPRK3 0   /* three-stage SSP-RK, Shu-Osher form */
+#define FR_DVM_LSRK3_2N 1 /* Williamson's three-stage low-storage scheme */
+
+/* per-point Newton status */
+#define FR_DVM_NEWTON_OK 0
+#define FR_DVM_NEWTON_FALLBACK 1 /* no convergence: continuous g(Q) used */
+#define FR_DVM_NEWTON_NONREAL 2  /* rho <= 0 or theta <= 0: no relaxation */
+#define FR_DVM_NEWTON_ESGUARD 3  /* ES tensor near-singular: BGK used there */
+
+typedef struct fr_dvm *fr_dvm_t; /* opaque, library-owned */
+
+/* Mesh, caller-owned HOST arrays, copied at create. */
+typedef struct {
+    int32_t n_elem, n_nodes, geom_order; /* geom_order 1 (8-node) or 2 (27-node) */
+    const double *nodes;                 /* [n_nodes][3] */
+    const int32_t *elem_nodes;           /* [n_elem][8 | 27], x-fastest tensor order */
+    const int32_t *nbr_elem;             /* [n_elem][6], -1 on a boundary face */
+    const int8_t *nbr_face;              /* [n_elem][6] neighbour's face number */
+    const int8_t *nbr_orient;            /* [n_elem][6] face-point map: bit0 swaps the two
+                                            face indices (a,b), bit1 reverses the first,
+                                            bit2 the second; (a,b) run along the two other
+                                            reference axes in increasing order */
+    const int8_t *bc;                    /* [n_elem][6] 0 interior/periodic, 1 farfield,
+                                            2 diffuse isothermal wall */
+} fr_dvm_mesh;
+
+/* Uniform Cartesian velocity grid, closed (end points are nodes), trapezoid
+ * weights (Section "Numerical method": Cartesian velocity nodes, strictly
+ * positive integration operator M).  An axis with n = 1 has one node at umin
+ * with weight 1. */
+typedef struct {
+    int32_t n[3];
+    double umin[3], umax[3];
+} fr_dvm_vgrid;
+
+typedef struct {
+    int32_t model;        /* FR_DVM_BGK | FR_DVM_ESBGK | FR_DVM_FREE */
+    double prandtl;       /* ES-BGK Prandtl number (ignored for BGK) */
+    double mu_ref, theta_ref, omega; /* power law mu = mu_ref (theta/theta_ref)^omega */
+    int32_t visc_law;     /* 0 power law, 1 Sutherland with theta_s */
+    double theta_s;
+    int32_t precision;    /* FR_DVM_FP64 | FR_DVM_FP32 */
+    double newton_tol;    /* max-norm of the scaled compatibility residual */
+    int32_t newton_max_iter;
+    int32_t guess;        /* FR_DVM_GUESS_* */
+    int32_t rk;           /* FR_DVM_SSPRK3 | FR_DVM_LSRK3_2N */
+    double farfield[5];   /* rho, Ux, Uy, Uz, theta of the farfield Maxwellian (bc 1) */
+    double theta_wall;    /* diffuse wall temperature (bc 2), wall at rest */
+} fr_dvm_params;
+
+/* Fill p with defaults: BGK, Pr 1, mu_ref 1e-3, theta_ref 1, omega 0.81,
+ * FP64, tol 1e-13, 50 iterations, cold guess, SSP-RK3. */
+void fr_dvm_default_params(fr_dvm_params *p);
+
+/* Create a handle for a mesh, FR order p (solution points (p+1)^3 per
+ * element) and velocity grid.  Builds the FR operators, metrics,
+ * connectivity and velocity tables on the device of the current HIP device.
+ * Returns FR_DVM_EINVAL for an inconsistent mesh (non-positive Jacobian,
+ * unmatched neighbours), FR_DVM_EUNSUPPORTED for p outside 1..3. */
+int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out);
+
+/* Set physics / precision / solver parameters; allocates the work buffers
+ * of the chosen precision.  Must be called before any compute call. */
+int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p);
+
+/* Run subsequent calls on this hipStream_t (passed as void*). */
+int fr_dvm_set_stream(fr_dvm_t h, void *stream);
+
+/* Sizes and the bytes of device memory the handle owns. */
+int fr_dvm_sizes(fr_dvm_t h, int64_t *n_elem, int32_t *ns, int32_t *nf, int32_t *nu,
+                 size_t *workspace_bytes);
+
+/* Host copies of the velocity nodes [nu][3] and weights [nu] (either may be NULL). */
+int fr_dvm_velocity_nodes(fr_dvm_t h, double *u, double *w);
+
+/* Explicit time step dt = cfl h_min / ((2p+1) max_k sum_d |u_k,d|), h = 2|J|/|a^d|. */
+int fr_dvm_dt(fr_dvm_t h, double cfl, double *dt);
+
+/* Advective FR residual R = -div(u f) at every solution point and velocity
+ * node (eq. transport with the corrected flux and the upwind interface
+ * flux; boundary exteriors from bc tags).  f, R: device [e][s][k]. */
+int fr_dvm_residual(fr_dvm_t h, const void *f, void *R);
+
+/* Collision source S = (g(Q') - f)/tau, where g(Q') is the conservative
+ * equilibrium with the same discrete moments as f (eq.
+ * discrete_compatibility), solved per point by FP64 Newton.  If accumulate,
+ * S += source.  Qp (nullable, device double [e][s][5]) receives the
+ * primitive state (rho', U', theta') of g(Q').  f, S: device [e][s][k]. */
+int fr_dvm_collide(fr_dvm_t h, const void *f, void *S, double *Qp, int accumulate);
+
+/* Discrete moments Q = M.(f psi), psi = (1, u, |u|^2/2) (eq. moments) into
+ * device Q[e][s][5]; totals (nullable, HOST double[5]) receives the domain
+ * integrals (Gauss weights x |J|).  Synchronises when totals != NULL. */
+int fr_dvm_moments(fr_dvm_t h, const void *f, double *Q, double *totals);
+
+/* Advance f (device, in place) by one / nsteps explicit steps of size dt of
+ * df/dt = R(f) + S(f) with the scheme chosen in the parameters. */
+int fr_dvm_rk_step(fr_dvm_t h, void *f, double dt);
+int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps);
+
+/* Newton statistics accumulated since the last reset (synchronising):
+ * iters_hist[64] histogram of iterations per point solve, number of fallback
+ * and ES-guard points, and the largest final scaled residual.  Any pointer
+ * may be NULL.  reset != 0 clears the counters afterwards. */
+int fr_dvm_newton_stats(fr_dvm_t h, int64_t *iters_hist, int64_t *n_fallback,
+                        int64_t *n_guard, double *max_resid, int reset);
+
+/* Weights of the learned Newton initial guess: an MLP 7 -> H -> H -> H -> 5
+ * with SiLU activations (FP32, layout documented in fr_dvm_mlp.h).  n is the
+ * number of floats; the guess mode FR_DVM_GUESS_MLP uses them. */
+int fr_dvm_mlp_set_weights(fr_dvm_t h, const float *w, size_t n);
+
+/* Kernel timing with HIP events recorded on the handle's stream around each
+ * launch.  fr_dvm_profile(h, 1) starts recording (0 stops);
+ * fr_dvm_profile_read (synchronising) returns, per kernel kind, the summed
+ * milliseconds and launch counts: [0] fused FR stage, [1] Newton, [2] prime
+ * (traces/moments of the incoming f), [3] other.  reset != 0 clears them. */
+#define FR_DVM_PROF_KINDS 4
+int fr_dvm_profile(fr_dvm_t h, int enable);
+int fr_dvm_profile_read(fr_dvm_t h, double *ms, int64_t *launches, int reset);
+
+const char *fr_dvm_last_error(fr_dvm_t h);
+void fr_dvm_destroy(fr_dvm_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FR_DVM_H */

@@ -1,0 +1,67 @@
+/*
+ * fr_dvm_mlp.h -- C ABI of the learned initial guess for the conservative-
+ * equilibrium Newton solve of libfrdvm (see fr_dvm.h).
+ *
+ * The paper finds the modified equilibrium of eq. (discrete_compatibility)
+ * per solution point by Newton's method (Section "Numerical method").  This
+ * part of the library trains, on the GPU, a small network that predicts the
+ * starting point of that Newton solve; Newton stays the judge of the
+ * residual and falls back to the cold start when the prediction fails.
+ *
+ * Network: 7 -> H -> H -> H -> 5, SiLU on the hidden layers, FP32.
+ *   inputs  x = [ln rho, U/u_max (3), ln theta, u_max/10, n_v/32]
+ *   outputs y (normalised); prediction dz = y * scale + offset is added to
+ *   the cold Newton unknowns z_cold = (-3/2 ln 2 pi, 0, 0, 0, 1) (BGK frame
+ *   c = (u-U)/sqrt(theta)).
+ * Flat parameter layout (floats): for each of the 4 layers W (out x in, row
+ * major) then b (out); then scale[5], offset[5].
+ *
+ * All arrays are caller-owned DEVICE float arrays unless stated; every call
+ * is asynchronous on `stream` (a hipStream_t passed as void*, may be NULL).
+ * Return: 0 or a negative FR_DVM_E* code (fr_dvm.h).  Batches are row
+ * major: X[B][7], T[B][5].  GEMMs run on MFMA (v_mfma_f32_16x16x4_f32).
+ */
+#ifndef FR_DVM_MLP_H
+#define FR_DVM_MLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fr_dvm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Number of floats of the flat parameter vector for hidden width H. */
+size_t fr_mlp_param_count(int H);
+
+/* Floats of scratch memory the forward / gradient calls need for a batch. */
+size_t fr_mlp_workspace_floats(int H, int64_t B);
+
+/* Prediction dz[B][5] (denormalised) for features X[B][7]. */
+int fr_mlp_forward(int H, const float *w, const float *X, int64_t B, float *dz, float *work, void *stream);
+
+/* Mean-squared-error loss L = 1/(2B) sum |y - T|^2 on normalised targets T,
+ * its gradient grad[param_count] (zero on the output affine) and L itself
+ * (device float[1]). */
+int fr_mlp_grad(int H, const float *w, const float *X, const float *T, int64_t B, float *grad, float *loss,
+                float *work, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at iteration `step` (1-based)
+ * on the network weights; the output affine (last 10 floats) is not updated. */
+int fr_mlp_adam(int H, float *w, const float *grad, float *m, float *v, int step, float lr, void *stream);
+
+/* Conservative equilibria for n given moment vectors Q[n][5] (rho, rho U, E)
+ * on the handle's velocity grid (BGK form): FP64 Newton from the cold start
+ * (guess = FR_DVM_GUESS_COLD) or from the handle's MLP (FR_DVM_GUESS_MLP).
+ * Outputs (device, nullable): z[n][5] Newton unknowns in the frame
+ * c = (u-U)/sqrt(theta), iters[n], status[n] (FR_DVM_NEWTON_*), resid[n]
+ * final scaled residual.  Uses the handle's tolerance and iteration cap. */
+int fr_dvm_equilibrium(fr_dvm_t h, const double *Q, int64_t n, int guess, double *z, int32_t *iters,
+                       int32_t *status, double *resid);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FR_DVM_MLP_H */

@@ -672,7 +672,7 @@ static int point_equilibrium(const orc_problem *P, const double *f, double *g, d
                 for (int j = 0; j < 3; ++j) A[i][j] = theta * Ti[i][j];
         }
     }
-    /* scaled velocity nodes and weights: c = (u-U)/sqrt(theta), wt = w theta^-3/2 / rho */
+    /* scaled velocity nodes and weights: c = (u-U)/sqrt(theta), wt = w theta^-3/2; g = rho wt exp(...) */
     ld st = sqrtl(theta);
     ld *c = (ld *)malloc(sizeof(ld) * 3 * nu);
     ld *wt = (ld *)malloc(sizeof(ld) * nu);

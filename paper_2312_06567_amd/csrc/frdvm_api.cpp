@@ -1,0 +1,204 @@
+// Compute entry points of the C ABI (include/fr_dvm.h): orchestration of the
+// moment, Newton, FR-stage and collision kernels on the handle's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "frdvm_common.h"
+
+using namespace frdvm;
+
+namespace {
+
+int ready(fr_dvm *h) {
+    if (!h) return FR_DVM_EINVAL;
+    if (!h->have_params) return h->fail(FR_DVM_EINVAL, "fr_dvm_set_params has not been called");
+    return FR_DVM_OK;
+}
+
+StageArgs blank() {
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.beta = 1.0;
+    return a;
+}
+
+// Moments (and, if traces, the outflow traces) of f into h->d_Q / h->d_tr[cur].
+int prime(fr_dvm *h, const void *f, int traces, int moments) {
+    StageArgs a = blank();
+    a.f = f;
+    a.tr_out = h->d_tr[h->cur_tr];
+    a.Q = h->d_Q;
+    ProfScope ps(h, 2);
+    return launch_fr_axis(h, 0, a, traces, moments);
+}
+
+int guess_mode(fr_dvm *h) {
+    if (h->prm.guess == FR_DVM_GUESS_MLP && !h->d_mlp) return FR_DVM_GUESS_COLD;
+    return h->prm.guess;
+}
+
+}  // namespace
+
+extern "C" int fr_dvm_moments(fr_dvm_t h, const void *f, double *Q, double *totals) {
+    int rc = ready(h);
+    if (rc) return rc;
+    if (!f) return h->fail(FR_DVM_EINVAL, "null f");
+    if ((rc = prime(h, f, 0, 1))) return rc;
+    if (Q && (rc = launch_moments_out(h, Q))) return rc;
+    if (totals && (rc = launch_totals(h, totals))) return rc;
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_residual(fr_dvm_t h, const void *f, void *R) {
+    int rc = ready(h);
+    if (rc) return rc;
+    if (!f || !R) return h->fail(FR_DVM_EINVAL, "null f or R");
+    if (f == R) return h->fail(FR_DVM_EINVAL, "R must not alias f");
+    if ((rc = prime(h, f, 1, 0))) return rc;
+    StageArgs a = blank();
+    a.f = f;
+    a.fout = R;
+    a.tr_in = h->d_tr[h->cur_tr];
+    return launch_fr_axis(h, 2, a, 0, 0);
+}
+
+extern "C" int fr_dvm_collide(fr_dvm_t h, const void *f, void *S, double *Qp, int accumulate) {
+    int rc = ready(h);
+    if (rc) return rc;
+    if (!f || !S) return h->fail(FR_DVM_EINVAL, "null f or S");
+    if (h->prm.model == FR_DVM_FREE) {
+        if (!accumulate) {
+            size_t es = h->prm.precision == FR_DVM_FP64 ? sizeof(double) : sizeof(float);
+            if (hipMemsetAsync(S, 0, es * h->ne * h->ns * h->vg.nu, h->stream) != hipSuccess)
+                return h->fail(FR_DVM_EHIP, "memset");
+        }
+        if (Qp && hipMemsetAsync(Qp, 0, sizeof(double) * 5 * h->ne * h->ns, h->stream) != hipSuccess)
+            return h->fail(FR_DVM_EHIP, "memset");
+        return FR_DVM_OK;
+    }
+    if ((rc = prime(h, f, 0, 1))) return rc;
+    if ((rc = launch_newton(h, guess_mode(h)))) return rc;
+    if ((rc = launch_collide(h, f, S, accumulate))) return rc;
+    if (Qp && (rc = launch_prim_out(h, Qp))) return rc;
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
+    int rc = ready(h);
+    if (rc) return rc;
+    if (!f) return h->fail(FR_DVM_EINVAL, "null f");
+    if (nsteps < 0) return h->fail(FR_DVM_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return FR_DVM_OK;
+    const int collide = h->prm.model != FR_DVM_FREE;
+    // traces and moments of the incoming f (afterwards each stage leaves those
+    // of its result for the next stage)
+    if ((rc = prime(h, f, 1, collide))) return rc;
+    const int guess = guess_mode(h);
+    for (int step = 0; step < nsteps; ++step) {
+        for (int st = 0; st < 3; ++st) {
+            if (collide) {
+                ProfScope ps(h, 1);
+                if ((rc = launch_newton(h, guess))) return rc;
+            }
+            StageArgs a = blank();
+            a.dt = dt;
+            a.collide = collide;
+            a.eq = h->d_eq;
+            a.tr_in = h->d_tr[h->cur_tr];
+            a.tr_out = h->d_tr[h->cur_tr ^ 1];
+            a.Q = h->d_Q;
+            if (h->prm.rk == FR_DVM_SSPRK3) {
+                static const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
+                a.scheme = 0;
+                a.alpha = al[st];
+                a.beta = be[st];
+                a.f = st == 0 ? f : h->d_reg;
+                a.fn = f;
+                a.fout = st == 2 ? f : h->d_reg;
+            } else {
+                static const double lA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0}, lB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+                a.scheme = 1;
+                a.lsA = lA[st];
+                a.lsB = lB[st];
+                a.f = f;
+                a.fout = f;
+                a.dF = h->d_reg;
+            }
+            const int last = (step == nsteps - 1) && (st == 2);
+            {
+                ProfScope ps(h, 0);
+                if ((rc = launch_fr_axis(h, 1, a, last ? 0 : 1, (last || !collide) ? 0 : 1))) return rc;
+            }
+            h->cur_tr ^= 1;
+        }
+    }
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_rk_step(fr_dvm_t h, void *f, double dt) { return fr_dvm_rk_steps(h, f, dt, 1); }
+
+extern "C" int fr_dvm_newton_stats(fr_dvm_t h, int64_t *iters_hist, int64_t *n_fallback, int64_t *n_guard,
+                                   double *max_resid, int reset) {
+    if (!h) return FR_DVM_EINVAL;
+    int64_t buf[kHist + 2];
+    double mr;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(FR_DVM_EHIP, "stream synchronise");
+    if (hipMemcpy(buf, h->d_stats, sizeof(buf), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(&mr, h->d_maxres, sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return h->fail(FR_DVM_EHIP, "stats copy");
+    if (iters_hist) std::memcpy(iters_hist, buf, kHist * sizeof(int64_t));
+    if (n_fallback) *n_fallback = buf[kHist];
+    if (n_guard) *n_guard = buf[kHist + 1];
+    if (max_resid) *max_resid = mr;
+    if (reset) {
+        hipMemset(h->d_stats, 0, sizeof(buf));
+        hipMemset(h->d_maxres, 0, sizeof(double));
+    }
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_mlp_set_weights(fr_dvm_t h, const float *w, size_t n) {
+    if (!h || !w) return FR_DVM_EINVAL;
+    // 7 -> H -> H -> H -> 5 plus 10 output affine floats: solve for H
+    int H = 0;
+    for (int c = 1; c <= 64; ++c) {
+        size_t need = (size_t)c * 7 + c + 2 * ((size_t)c * c + c) + (size_t)5 * c + 5 + 10;
+        if (need == n) { H = c; break; }
+    }
+    if (!H) return h->fail(FR_DVM_EINVAL, "weight count does not match a 7-H-H-H-5 network with H <= 64");
+    if (h->d_mlp) { hipFree(h->d_mlp); h->d_mlp = nullptr; h->owned_bytes -= h->mlp_n * sizeof(float); }
+    if (hipMalloc(&h->d_mlp, n * sizeof(float)) != hipSuccess) { h->d_mlp = nullptr; return h->fail(FR_DVM_ENOMEM, "mlp"); }
+    h->owned_bytes += n * sizeof(float);
+    if (hipMemcpy(h->d_mlp, w, n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return h->fail(FR_DVM_EHIP, "mlp upload");
+    h->mlp_n = n;
+    h->mlp_hidden = H;
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_profile(fr_dvm_t h, int enable) {
+    if (!h) return FR_DVM_EINVAL;
+    h->prof = enable != 0;
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_profile_read(fr_dvm_t h, double *ms, int64_t *launches, int reset) {
+    if (!h) return FR_DVM_EINVAL;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(FR_DVM_EHIP, "stream synchronise");
+    for (auto &r : h->prof_recs) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+            h->prof_ms[r.kind] += t;
+            h->prof_n[r.kind] += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    h->prof_recs.clear();
+    for (int k = 0; k < FR_DVM_PROF_KINDS; ++k) {
+        if (ms) ms[k] = h->prof_ms[k];
+        if (launches) launches[k] = h->prof_n[k];
+        if (reset) { h->prof_ms[k] = 0; h->prof_n[k] = 0; }
+    }
+    return FR_DVM_OK;
+}

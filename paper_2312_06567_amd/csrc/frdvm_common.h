@@ -1,0 +1,163 @@
+// Internal declarations of libfrdvm: the handle, kernel argument blocks and
+// the launchers implemented in the .hip translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fr_dvm.h"
+
+namespace frdvm {
+
+constexpr int kMaxP = 3;
+constexpr int kMaxN = kMaxP + 1;
+constexpr int kEqW = 12;   // per-point equilibrium record (see EqRec below)
+constexpr int kHist = 64;  // Newton iteration histogram bins
+constexpr int kBlock = 256;
+
+// Per-point equilibrium record written by the Newton kernels and read by the
+// collision (fused or stand-alone):
+//   g(u) = exp(c0 - 1/2 (u-V)^T B (u-V)),  S = (g - f) * inv_tau
+enum EqRec { EQ_C0 = 0, EQ_V = 1, EQ_B = 4 /* xx yy zz xy xz yz */, EQ_INVTAU = 10, EQ_RES = 11 };
+
+// One-dimensional FR operators on Gauss-Legendre points (n = p+1 <= 4).
+struct Ops1D {
+    double D[kMaxN * kMaxN];  // D[i*n+m] = l_m'(xi_i)
+    double lam[2][kMaxN];     // lam[side][m] = l_m(-1 | +1)
+    double corr[2][kMaxN];    // corr[side][i]: correction derivative at xi_i for a unit jump on face side
+    double wq[kMaxN];         // Gauss weights
+    double xi[kMaxN];
+};
+
+// Velocity grid on the device side: per-axis uniform nodes.
+struct VGrid {
+    int nv[3];
+    int nu;
+    double umin[3], du[3];
+    int neg_end[3];    // nodes with u_d < 0 are idx < neg_end
+    int pos_start[3];  // nodes with u_d > 0 are idx >= pos_start
+};
+
+// Compact "outflow half" trace layout for axis-aligned box meshes.  For face
+// (d, side) only velocities leaving the element through it are stored:
+// side 1: idx_d >= pos_start_d, side 0: idx_d < neg_end_d.
+struct TraceLayout {
+    int64_t cnt[6];       // velocity entries per face point
+    int64_t face_off[6];  // offset of the face block inside the element block
+    int64_t elem;         // element block size
+};
+
+struct Handle;
+
+}  // namespace frdvm
+
+struct fr_dvm {
+    std::string err;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // discretisation
+    int p = 0, n = 0, ns = 0, nfp = 0;
+    int64_t ne = 0;
+    frdvm::VGrid vg{};
+    std::vector<double> wax[3];  // 1-D trapezoid weights per axis
+    frdvm::Ops1D ops{};
+    bool axis_mode = false;
+    frdvm::TraceLayout tl{};
+    double hmin = 0;
+
+    // host geometry (for totals / dt)
+    std::vector<double> h_gfac;  // [ne][3]  2/h_d for axis boxes
+    std::vector<double> h_detJ;  // [ne][ns]
+
+    // device: geometry and tables
+    double *d_gfac = nullptr;    // [ne][3]
+    int32_t *d_nbr = nullptr;    // [ne][6]
+    double *d_wq3J = nullptr;    // [ne*ns] Gauss weight x |J| per solution point
+    double *d_wpsi = nullptr;    // [nu_pad][nmom] velocity weight x collision invariant
+    double *d_wax = nullptr;     // [3][64] 1-D weights
+    int nu_pad = 0;
+
+    // parameters
+    fr_dvm_params prm{};
+    bool have_params = false;
+    int nmom = 5;                // 5 (BGK) or 10 (ES: rho, rho U, raw second moments)
+
+    // work buffers
+    void *d_reg = nullptr;       // second RK register [ne*ns*nu]
+    void *d_tr[2] = {nullptr, nullptr};
+    int cur_tr = 0;
+    double *d_Q = nullptr;       // [ne*ns][nmom]
+    double *d_eq = nullptr;      // [ne*ns][kEqW]
+    double *d_z = nullptr;       // [ne*ns][5] Newton solution (warm start)
+    double *d_prim = nullptr;    // [ne*ns][5] primitive state of g(Q')
+    int zvalid = 0;
+    int64_t *d_stats = nullptr;  // [kHist + 2]
+    double *d_maxres = nullptr;  // [1] (as ordered bits)
+    double *d_tot = nullptr;     // [5]
+    float *d_mlp = nullptr;
+    size_t mlp_n = 0;
+    int mlp_hidden = 0;
+    size_t owned_bytes = 0;
+
+    // HIP-event kernel timing (fr_dvm_profile)
+    bool prof = false;
+    struct ProfRec { int kind; hipEvent_t a, b; };
+    std::vector<ProfRec> prof_recs;
+    double prof_ms[FR_DVM_PROF_KINDS] = {0, 0, 0, 0};
+    int64_t prof_n[FR_DVM_PROF_KINDS] = {0, 0, 0, 0};
+
+    int fail(int code, const std::string &m) { err = m; return code; }
+};
+
+namespace frdvm {
+// Brackets a launch with events when profiling is on.
+struct ProfScope {
+    fr_dvm *h;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(fr_dvm *h_, int k) : h(h_), kind(k) {
+        if (h->prof && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, h->stream);
+    }
+    ~ProfScope() {
+        if (a && b) {
+            (void)hipEventRecord(b, h->stream);
+            h->prof_recs.push_back({kind, a, b});
+        }
+    }
+};
+}  // namespace frdvm
+
+namespace frdvm {
+
+// ---- launchers (frdvm_fr.hip) ----
+// mode: 0 = prime (traces + moments of f), 1 = stage (RK update of f into
+// fout, traces + moments of the result), 2 = residual only (R into fout).
+struct StageArgs {
+    const void *f;      // current stage value
+    const void *fn;     // f^n (SSP) or dF (LSRK), may be null at stage 1
+    void *fout;         // output register
+    void *dF;           // LSRK dF register (in/out)
+    const void *tr_in;  // neighbour traces of f
+    void *tr_out;       // own outflow traces of the result
+    double *Q;          // moments of the result [ne*ns][nmom]
+    const double *eq;   // equilibrium records [ne*ns][kEqW]
+    double dt, alpha, beta;  // SSP: fout = alpha fn + beta (f + dt L)
+    double lsA, lsB;         // LSRK: dF = lsA dF + dt L; fout = f + lsB dF
+    int scheme;              // 0 SSP, 1 LSRK
+    int collide;             // include the collision source
+};
+int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);
+
+// ---- launchers (frdvm_newton.hip) ----
+int launch_newton(fr_dvm *h, int guess);
+int launch_collide(fr_dvm *h, const void *f, void *S, int accumulate);
+int launch_prim_out(fr_dvm *h, double *Qp);
+int launch_moments_out(fr_dvm *h, double *Q);
+int launch_totals(fr_dvm *h, double *host_tot);
+
+}  // namespace frdvm

@@ -1,0 +1,378 @@
+// Host-side set-up of libfrdvm: FR operators, mesh checks, element metrics,
+// velocity tables and device allocations.
+//
+// Section "Numerical method" of the paper: nodal degree-p polynomial per
+// element on N_s solution nodes, flux nodes on the faces, correction
+// functions that recover nodal DG, Cartesian velocity grid with a strictly
+// positive trapezoid integration operator.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "frdvm_common.h"
+
+using namespace frdvm;
+
+namespace {
+
+// Legendre P_n and its derivative at x (recurrence on n).
+void legendre_eval(int n, double x, double &P, double &dP) {
+    double pm = 1.0, pc = x;
+    if (n == 0) { P = 1.0; dP = 0.0; return; }
+    for (int k = 2; k <= n; ++k) {
+        double pn = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
+        pm = pc;
+        pc = pn;
+    }
+    P = pc;
+    dP = n * (x * pc - pm) / (x * x - 1.0);  // valid inside (-1,1)
+}
+
+// Gauss-Legendre rule and the FR operators in barycentric form.
+// D: l_m'(xi_i) from barycentric weights; traces l_m(+-1); the correction
+// derivative at xi_i for a unit jump on a face is the DG lifting l_i(face)/w_i
+// (Huynh's g_DG correction reproduces nodal DG exactly).
+void build_ops(int p, Ops1D &o) {
+    int n = p + 1;
+    std::memset(&o, 0, sizeof(o));
+    for (int i = 0; i < n; ++i) {
+        double x = std::cos(M_PI * (4.0 * (n - i) - 1.0) / (4.0 * n + 2.0));
+        if (n == 1) x = 0.0;
+        for (int it = 0; it < 60 && n > 1; ++it) {
+            double P, dP;
+            legendre_eval(n, x, P, dP);
+            double dx = P / dP;
+            x -= dx;
+            if (std::fabs(dx) < 1e-17) break;
+        }
+        double P, dP;
+        if (n > 1) {
+            legendre_eval(n, x, P, dP);
+        } else {
+            dP = 1.0;
+        }
+        o.xi[i] = x;
+        o.wq[i] = 2.0 / ((1.0 - x * x) * dP * dP);
+    }
+    double lamb[kMaxN];
+    for (int j = 0; j < n; ++j) {
+        double pr = 1.0;
+        for (int m = 0; m < n; ++m)
+            if (m != j) pr *= (o.xi[j] - o.xi[m]);
+        lamb[j] = 1.0 / pr;
+    }
+    for (int i = 0; i < n; ++i) {
+        double diag = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double v = (lamb[j] / lamb[i]) / (o.xi[i] - o.xi[j]);
+            o.D[i * n + j] = v;
+            diag -= v;
+        }
+        o.D[i * n + i] = diag;
+    }
+    for (int side = 0; side < 2; ++side) {
+        double x = side ? 1.0 : -1.0, den = 0.0;
+        for (int m = 0; m < n; ++m) den += lamb[m] / (x - o.xi[m]);
+        for (int m = 0; m < n; ++m) o.lam[side][m] = (lamb[m] / (x - o.xi[m])) / den;
+        for (int i = 0; i < n; ++i) o.corr[side][i] = o.lam[side][i] / o.wq[i];
+    }
+}
+
+template <typename T>
+int dev_alloc(fr_dvm *h, T **p, size_t count) {
+    if (*p) { hipFree(*p); *p = nullptr; }
+    if (count == 0) return FR_DVM_OK;
+    if (hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        return h->fail(FR_DVM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    h->owned_bytes += count * sizeof(T);
+    return FR_DVM_OK;
+}
+
+int upload(fr_dvm *h, void *dst, const void *src, size_t bytes) {
+    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return h->fail(FR_DVM_EHIP, "hipMemcpy upload failed");
+    return FR_DVM_OK;
+}
+
+// Axis-aligned box check: the 8 corner nodes of element e span a box
+// lo + (a0 hx, a1 hy, a2 hz).  Returns false otherwise.
+bool element_box(const fr_dvm_mesh *m, int e, double lo[3], double hh[3]) {
+    const int32_t *en = m->elem_nodes + (int64_t)e * 8;
+    const double *x0 = m->nodes + 3 * (int64_t)en[0];
+    const double *x7 = m->nodes + 3 * (int64_t)en[7];
+    for (int d = 0; d < 3; ++d) { lo[d] = x0[d]; hh[d] = x7[d] - x0[d]; }
+    double scale = std::max(std::fabs(hh[0]), std::max(std::fabs(hh[1]), std::fabs(hh[2])));
+    for (int a = 0; a < 8; ++a) {
+        const double *x = m->nodes + 3 * (int64_t)en[a];
+        for (int d = 0; d < 3; ++d) {
+            double want = lo[d] + ((a >> d) & 1) * hh[d];
+            if (std::fabs(x[d] - want) > 1e-12 * (scale + std::fabs(lo[d]))) return false;
+        }
+    }
+    return hh[0] > 0 && hh[1] > 0 && hh[2] > 0;
+}
+
+}  // namespace
+
+extern "C" void fr_dvm_default_params(fr_dvm_params *p) {
+    std::memset(p, 0, sizeof(*p));
+    p->model = FR_DVM_BGK;
+    p->prandtl = 1.0;
+    p->mu_ref = 1e-3;
+    p->theta_ref = 1.0;
+    p->omega = 0.81;
+    p->visc_law = 0;
+    p->precision = FR_DVM_FP64;
+    p->newton_tol = 1e-13;
+    p->newton_max_iter = 50;
+    p->guess = FR_DVM_GUESS_COLD;
+    p->rk = FR_DVM_SSPRK3;
+    p->farfield[0] = 1.0;
+    p->farfield[4] = 1.0;
+    p->theta_wall = 1.0;
+}
+
+extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out) {
+    if (!out) return FR_DVM_EINVAL;
+    *out = nullptr;
+    if (!mesh || !grid || !mesh->nodes || !mesh->elem_nodes || !mesh->nbr_elem || !mesh->nbr_face ||
+        !mesh->nbr_orient || !mesh->bc)
+        return FR_DVM_EINVAL;
+    fr_dvm *h = new fr_dvm();
+    auto bail = [&](int rc) { *out = h; return rc; };  // keep the handle so the error is readable
+    if (order < 1 || order > kMaxP) return bail(h->fail(FR_DVM_EUNSUPPORTED, "order must be 1..3"));
+    if (mesh->n_elem <= 0 || mesh->n_nodes <= 0) return bail(h->fail(FR_DVM_EINVAL, "empty mesh"));
+    hipGetDevice(&h->device);
+    h->p = order;
+    h->n = order + 1;
+    h->ns = h->n * h->n * h->n;
+    h->nfp = h->n * h->n;
+    h->ne = mesh->n_elem;
+    build_ops(order, h->ops);
+
+    // velocity grid
+    VGrid &vg = h->vg;
+    int64_t nu = 1;
+    for (int d = 0; d < 3; ++d) {
+        int nd = grid->n[d];
+        if (nd < 1 || nd > 64) return bail(h->fail(FR_DVM_EINVAL, "velocity nodes per axis must be 1..64"));
+        if (nd > 1 && !(grid->umax[d] > grid->umin[d])) return bail(h->fail(FR_DVM_EINVAL, "umax <= umin"));
+        vg.nv[d] = nd;
+        vg.umin[d] = grid->umin[d];
+        vg.du[d] = nd > 1 ? (grid->umax[d] - grid->umin[d]) / (nd - 1) : 0.0;
+        h->wax[d].assign(nd, 1.0);
+        for (int i = 0; i < nd && nd > 1; ++i) h->wax[d][i] = (i == 0 || i == nd - 1) ? 0.5 * vg.du[d] : vg.du[d];
+        int ne_ = 0, ps = nd;
+        for (int i = 0; i < nd; ++i) {
+            double u = vg.umin[d] + i * vg.du[d];
+            if (u < 0) ne_ = i + 1;
+            if (u > 0 && ps == nd) ps = i;
+        }
+        vg.neg_end[d] = ne_;
+        vg.pos_start[d] = ps;
+        nu *= nd;
+    }
+    vg.nu = (int)nu;
+
+    // mesh: this build handles straight axis-aligned boxes with interior /
+    // periodic faces (matching opposite faces, orientation 0)
+    if (mesh->geom_order != 1) return bail(h->fail(FR_DVM_EUNSUPPORTED, "curved (27-node) elements are not handled by this build"));
+    h->axis_mode = true;
+    h->h_gfac.resize(3 * h->ne);
+    h->h_detJ.resize(h->ne * h->ns);
+    std::vector<double> wq3J(h->ne * h->ns);
+    std::vector<double> hsz(3 * h->ne);
+    double hmin = 1e300;
+    for (int64_t e = 0; e < h->ne; ++e) {
+        double lo[3], hh[3];
+        for (int a = 0; a < 8; ++a) {
+            int32_t id = mesh->elem_nodes[e * 8 + a];
+            if (id < 0 || id >= mesh->n_nodes) return bail(h->fail(FR_DVM_EINVAL, "element node id out of range"));
+        }
+        if (!element_box(mesh, (int)e, lo, hh))
+            return bail(h->fail(FR_DVM_EUNSUPPORTED, "element " + std::to_string(e) + " is not an axis-aligned box"));
+        double detJ = hh[0] * hh[1] * hh[2] / 8.0;
+        for (int d = 0; d < 3; ++d) {
+            h->h_gfac[3 * e + d] = 2.0 / hh[d];
+            hsz[3 * e + d] = hh[d];
+            hmin = std::min(hmin, hh[d]);
+        }
+        int s = 0;
+        for (int l = 0; l < h->n; ++l)
+            for (int j = 0; j < h->n; ++j)
+                for (int i = 0; i < h->n; ++i, ++s) {
+                    h->h_detJ[e * h->ns + s] = detJ;
+                    wq3J[e * h->ns + s] = h->ops.wq[i] * h->ops.wq[j] * h->ops.wq[l] * detJ;
+                }
+    }
+    h->hmin = hmin;
+    for (int64_t e = 0; e < h->ne; ++e)
+        for (int f = 0; f < 6; ++f) {
+            int32_t nb = mesh->nbr_elem[e * 6 + f];
+            int d = f / 2;
+            if (nb < 0) {
+                if (mesh->bc[e * 6 + f] != 0)
+                    return bail(h->fail(FR_DVM_EUNSUPPORTED, "boundary conditions need the curved-mesh path"));
+                return bail(h->fail(FR_DVM_EINVAL, "face without neighbour and without a boundary tag"));
+            }
+            if (nb >= h->ne) return bail(h->fail(FR_DVM_EINVAL, "neighbour id out of range"));
+            if (mesh->nbr_face[e * 6 + f] != (f ^ 1) || mesh->nbr_orient[e * 6 + f] != 0)
+                return bail(h->fail(FR_DVM_EUNSUPPORTED, "axis-aligned path needs opposite-face neighbours with orientation 0"));
+            if (mesh->nbr_elem[(int64_t)nb * 6 + (f ^ 1)] != e)
+                return bail(h->fail(FR_DVM_EINVAL, "neighbour relation is not symmetric"));
+            for (int t = 0; t < 3; ++t)
+                if (t != d && std::fabs(hsz[3 * e + t] - hsz[3 * (int64_t)nb + t]) > 1e-12 * hsz[3 * e + t])
+                    return bail(h->fail(FR_DVM_EINVAL, "non-conforming face"));
+        }
+
+    // trace layout
+    TraceLayout &tl = h->tl;
+    int64_t off = 0;
+    for (int f = 0; f < 6; ++f) {
+        int d = f / 2;
+        int64_t per = nu / vg.nv[d];
+        tl.cnt[f] = (f & 1) ? (int64_t)(vg.nv[d] - vg.pos_start[d]) * per : (int64_t)vg.neg_end[d] * per;
+        tl.face_off[f] = off;
+        off += tl.cnt[f] * h->nfp;
+    }
+    tl.elem = off;
+
+    // device tables
+    int rc;
+    if ((rc = dev_alloc(h, &h->d_gfac, 3 * h->ne))) return bail(rc);
+    if ((rc = upload(h, h->d_gfac, h->h_gfac.data(), 3 * h->ne * sizeof(double)))) return bail(rc);
+    if ((rc = dev_alloc(h, &h->d_nbr, 6 * h->ne))) return bail(rc);
+    if ((rc = upload(h, h->d_nbr, mesh->nbr_elem, 6 * h->ne * sizeof(int32_t)))) return bail(rc);
+    if ((rc = dev_alloc(h, &h->d_wq3J, h->ne * h->ns))) return bail(rc);
+    if ((rc = upload(h, h->d_wq3J, wq3J.data(), wq3J.size() * sizeof(double)))) return bail(rc);
+    std::vector<double> wax(3 * 64, 0.0);
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < vg.nv[d]; ++i) wax[64 * d + i] = h->wax[d][i];
+    if ((rc = dev_alloc(h, &h->d_wax, 3 * 64))) return bail(rc);
+    if ((rc = upload(h, h->d_wax, wax.data(), wax.size() * sizeof(double)))) return bail(rc);
+    if ((rc = dev_alloc(h, &h->d_stats, kHist + 2))) return bail(rc);
+    if ((rc = dev_alloc(h, &h->d_maxres, 1))) return bail(rc);
+    if ((rc = dev_alloc(h, &h->d_tot, 8))) return bail(rc);
+    hipMemset(h->d_stats, 0, (kHist + 2) * sizeof(int64_t));
+    hipMemset(h->d_maxres, 0, sizeof(double));
+    *out = h;
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
+    if (!h || !p) return FR_DVM_EINVAL;
+    if (p->model < 0 || p->model > 2) return h->fail(FR_DVM_EINVAL, "unknown model");
+    if (p->precision != FR_DVM_FP64 && p->precision != FR_DVM_FP32) return h->fail(FR_DVM_EINVAL, "unknown precision");
+    if (p->model == FR_DVM_ESBGK && !(p->prandtl > 0)) return h->fail(FR_DVM_EINVAL, "Prandtl number must be positive");
+    if (!(p->mu_ref > 0) && p->model != FR_DVM_FREE) return h->fail(FR_DVM_EINVAL, "mu_ref must be positive");
+    if (p->newton_max_iter < 1 || p->newton_max_iter > 200) return h->fail(FR_DVM_EINVAL, "newton_max_iter out of range");
+    if (p->rk != FR_DVM_SSPRK3 && p->rk != FR_DVM_LSRK3_2N) return h->fail(FR_DVM_EINVAL, "unknown RK scheme");
+    if (p->guess < 0 || p->guess > 2) return h->fail(FR_DVM_EINVAL, "unknown guess mode");
+    bool realloc_all = !h->have_params || p->precision != h->prm.precision;
+    int nmom = (p->model == FR_DVM_ESBGK) ? 10 : 5;
+    bool realloc_mom = !h->have_params || nmom != h->nmom;
+    h->prm = *p;
+    h->nmom = nmom;
+    size_t es = p->precision == FR_DVM_FP64 ? sizeof(double) : sizeof(float);
+    int64_t npts = h->ne * h->ns;
+    int64_t nu = h->vg.nu;
+    int rc;
+    if (realloc_all) {
+        if (h->d_reg) { hipFree(h->d_reg); h->owned_bytes -= npts * nu * es; h->d_reg = nullptr; }
+        for (int b = 0; b < 2; ++b)
+            if (h->d_tr[b]) { hipFree(h->d_tr[b]); h->d_tr[b] = nullptr; h->owned_bytes -= h->ne * h->tl.elem * es; }
+        if (hipMalloc(&h->d_reg, npts * nu * es) != hipSuccess) { h->d_reg = nullptr; return h->fail(FR_DVM_ENOMEM, "register allocation failed"); }
+        h->owned_bytes += npts * nu * es;
+        for (int b = 0; b < 2; ++b) {
+            if (hipMalloc(&h->d_tr[b], h->ne * h->tl.elem * es) != hipSuccess) { h->d_tr[b] = nullptr; return h->fail(FR_DVM_ENOMEM, "trace allocation failed"); }
+            h->owned_bytes += h->ne * h->tl.elem * es;
+        }
+        if ((rc = dev_alloc(h, &h->d_eq, npts * kEqW))) return rc;
+        if ((rc = dev_alloc(h, &h->d_z, npts * 5))) return rc;
+        if ((rc = dev_alloc(h, &h->d_prim, npts * 5))) return rc;
+        h->zvalid = 0;
+    }
+    if (realloc_mom) {
+        if ((rc = dev_alloc(h, &h->d_Q, npts * nmom))) return rc;
+        h->nu_pad = (int)((nu + kBlock - 1) / kBlock * kBlock);
+        std::vector<double> wpsi((size_t)h->nu_pad * nmom, 0.0);
+        const VGrid &vg = h->vg;
+        for (int64_t k = 0; k < nu; ++k) {
+            int i = (int)(k % vg.nv[0]), j = (int)((k / vg.nv[0]) % vg.nv[1]), l = (int)(k / ((int64_t)vg.nv[0] * vg.nv[1]));
+            double ux = vg.umin[0] + i * vg.du[0], uy = vg.umin[1] + j * vg.du[1], uz = vg.umin[2] + l * vg.du[2];
+            double w = h->wax[0][i] * h->wax[1][j] * h->wax[2][l];
+            double *o = &wpsi[(size_t)k * nmom];
+            o[0] = w; o[1] = w * ux; o[2] = w * uy; o[3] = w * uz;
+            if (nmom == 5) {
+                o[4] = 0.5 * w * (ux * ux + uy * uy + uz * uz);
+            } else {
+                o[4] = w * ux * ux; o[5] = w * uy * uy; o[6] = w * uz * uz;
+                o[7] = w * ux * uy; o[8] = w * ux * uz; o[9] = w * uy * uz;
+            }
+        }
+        if ((rc = dev_alloc(h, &h->d_wpsi, wpsi.size()))) return rc;
+        if ((rc = upload(h, h->d_wpsi, wpsi.data(), wpsi.size() * sizeof(double)))) return rc;
+    }
+    h->have_params = true;
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_set_stream(fr_dvm_t h, void *stream) {
+    if (!h) return FR_DVM_EINVAL;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_sizes(fr_dvm_t h, int64_t *n_elem, int32_t *ns, int32_t *nf, int32_t *nu, size_t *ws) {
+    if (!h) return FR_DVM_EINVAL;
+    if (n_elem) *n_elem = h->ne;
+    if (ns) *ns = h->ns;
+    if (nf) *nf = 6 * h->nfp;
+    if (nu) *nu = h->vg.nu;
+    if (ws) *ws = h->owned_bytes;
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_velocity_nodes(fr_dvm_t h, double *u, double *w) {
+    if (!h) return FR_DVM_EINVAL;
+    const VGrid &vg = h->vg;
+    for (int64_t k = 0; k < vg.nu; ++k) {
+        int i = (int)(k % vg.nv[0]), j = (int)((k / vg.nv[0]) % vg.nv[1]), l = (int)(k / ((int64_t)vg.nv[0] * vg.nv[1]));
+        if (u) {
+            u[3 * k] = vg.umin[0] + i * vg.du[0];
+            u[3 * k + 1] = vg.umin[1] + j * vg.du[1];
+            u[3 * k + 2] = vg.umin[2] + l * vg.du[2];
+        }
+        if (w) w[k] = h->wax[0][i] * h->wax[1][j] * h->wax[2][l];
+    }
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_dt(fr_dvm_t h, double cfl, double *dt) {
+    if (!h || !dt || !(cfl > 0)) return FR_DVM_EINVAL;
+    double um = 0;
+    for (int d = 0; d < 3; ++d) {
+        double a = std::fabs(h->vg.umin[d]), b = std::fabs(h->vg.umin[d] + (h->vg.nv[d] - 1) * h->vg.du[d]);
+        um += std::max(a, b);
+    }
+    *dt = cfl * h->hmin / ((2 * h->p + 1) * um);
+    return FR_DVM_OK;
+}
+
+extern "C" const char *fr_dvm_last_error(fr_dvm_t h) { return h ? h->err.c_str() : "null handle"; }
+
+extern "C" void fr_dvm_destroy(fr_dvm_t h) {
+    if (!h) return;
+    if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
+    void *ptrs[] = {h->d_gfac, h->d_nbr, h->d_wq3J, h->d_wpsi, h->d_wax, h->d_reg, h->d_tr[0], h->d_tr[1],
+                    h->d_Q, h->d_eq, h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    delete h;
+}

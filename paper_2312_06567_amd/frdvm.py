@@ -1,0 +1,273 @@
+"""Python binding of libfrdvm (include/fr_dvm.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libfrdvm.so``; torch tensors
+are used only as device memory (their ``data_ptr``) and streams.  There is
+no CPU fallback: if the library is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfrdvm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "fr_dvm.h")
+
+BGK, ESBGK, FREE = 0, 1, 2
+FP64, FP32 = 0, 1
+GUESS_COLD, GUESS_WARM, GUESS_MLP = 0, 1, 2
+SSPRK3, LSRK3_2N = 0, 1
+NEWTON_OK, NEWTON_FALLBACK, NEWTON_NONREAL, NEWTON_ESGUARD = 0, 1, 2, 3
+
+
+class FrDvmError(RuntimeError):
+    pass
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("n_elem", C.c_int32), ("n_nodes", C.c_int32), ("geom_order", C.c_int32),
+                ("nodes", C.POINTER(C.c_double)), ("elem_nodes", C.POINTER(C.c_int32)),
+                ("nbr_elem", C.POINTER(C.c_int32)), ("nbr_face", C.POINTER(C.c_int8)),
+                ("nbr_orient", C.POINTER(C.c_int8)), ("bc", C.POINTER(C.c_int8))]
+
+
+class _VGrid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("umin", C.c_double * 3), ("umax", C.c_double * 3)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("model", C.c_int32), ("prandtl", C.c_double), ("mu_ref", C.c_double),
+                ("theta_ref", C.c_double), ("omega", C.c_double), ("visc_law", C.c_int32),
+                ("theta_s", C.c_double), ("precision", C.c_int32), ("newton_tol", C.c_double),
+                ("newton_max_iter", C.c_int32), ("guess", C.c_int32), ("rk", C.c_int32),
+                ("farfield", C.c_double * 5), ("theta_wall", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree libfrdvm.so (built by ``paper_2312_06567_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2312_06567_amd.build` "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+        L.fr_dvm_default_params.argtypes = [C.POINTER(_Params)]
+        L.fr_dvm_create.argtypes = [C.POINTER(_Mesh), C.c_int, C.POINTER(_VGrid), C.POINTER(vp)]
+        L.fr_dvm_set_params.argtypes = [vp, C.POINTER(_Params)]
+        L.fr_dvm_set_stream.argtypes = [vp, vp]
+        L.fr_dvm_sizes.argtypes = [vp, i64p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]
+        L.fr_dvm_velocity_nodes.argtypes = [vp, dp, dp]
+        L.fr_dvm_dt.argtypes = [vp, C.c_double, dp]
+        L.fr_dvm_residual.argtypes = [vp, vp, vp]
+        L.fr_dvm_collide.argtypes = [vp, vp, vp, vp, C.c_int]
+        L.fr_dvm_moments.argtypes = [vp, vp, vp, dp]
+        L.fr_dvm_rk_step.argtypes = [vp, vp, C.c_double]
+        L.fr_dvm_rk_steps.argtypes = [vp, vp, C.c_double, C.c_int]
+        L.fr_dvm_newton_stats.argtypes = [vp, i64p, i64p, i64p, dp, C.c_int]
+        L.fr_dvm_mlp_set_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
+        L.fr_dvm_profile.argtypes = [vp, C.c_int]
+        L.fr_dvm_profile_read.argtypes = [vp, dp, i64p, C.c_int]
+        L.fr_dvm_last_error.argtypes = [vp]
+        L.fr_dvm_last_error.restype = C.c_char_p
+        L.fr_dvm_destroy.argtypes = [vp]
+        L.fr_dvm_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/fr_dvm.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(fr_dvm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class FrDvm:
+    """One handle of the library: a mesh, an FR order and a velocity grid."""
+
+    def __init__(self, mesh: dict, order: int, grid: dict, params: dict | None = None):
+        L = lib()
+        self._keep = {
+            "nodes": np.ascontiguousarray(mesh["nodes"], np.float64),
+            "elem_nodes": np.ascontiguousarray(mesh["elem_nodes"], np.int32),
+            "nbr_elem": np.ascontiguousarray(mesh["nbr_elem"], np.int32),
+            "nbr_face": np.ascontiguousarray(mesh["nbr_face"], np.int8),
+            "nbr_orient": np.ascontiguousarray(mesh["nbr_orient"], np.int8),
+            "bc": np.ascontiguousarray(mesh["bc"], np.int8),
+        }
+        k = self._keep
+        m = _Mesh(int(mesh["n_elem"]), int(k["nodes"].shape[0]), int(mesh["geom_order"]),
+                  k["nodes"].ctypes.data_as(C.POINTER(C.c_double)),
+                  k["elem_nodes"].ctypes.data_as(C.POINTER(C.c_int32)),
+                  k["nbr_elem"].ctypes.data_as(C.POINTER(C.c_int32)),
+                  k["nbr_face"].ctypes.data_as(C.POINTER(C.c_int8)),
+                  k["nbr_orient"].ctypes.data_as(C.POINTER(C.c_int8)),
+                  k["bc"].ctypes.data_as(C.POINTER(C.c_int8)))
+        g = _VGrid()
+        for d in range(3):
+            g.n[d] = int(grid["n"][d])
+            g.umin[d] = float(grid["umin"][d])
+            g.umax[d] = float(grid["umax"][d])
+        h = C.c_void_p()
+        rc = L.fr_dvm_create(C.byref(m), int(order), C.byref(g), C.byref(h))
+        self._h = h
+        if rc != 0:
+            msg = self.last_error() if h.value else "invalid argument"
+            self.destroy()
+            raise FrDvmError(f"fr_dvm_create failed ({rc}): {msg}")
+        ne, ns, nf, nu = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+        L.fr_dvm_sizes(h, C.byref(ne), C.byref(ns), C.byref(nf), C.byref(nu), None)
+        self.ne, self.ns, self.nf, self.nu = ne.value, ns.value, nf.value, nu.value
+        self.order = int(order)
+        self.precision = FP64
+        if params is not None:
+            self.set_params(**params)
+
+    # -- plumbing --------------------------------------------------------
+    def _check(self, rc, what):
+        if rc != 0:
+            raise FrDvmError(f"{what} failed ({rc}): {self.last_error()}")
+
+    def last_error(self) -> str:
+        if not self._h or not self._h.value:
+            return ""
+        return lib().fr_dvm_last_error(self._h).decode()
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fr_dvm_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.ne, self.ns, self.nu)
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.precision == FP64 else torch.float32
+
+    def _check_f(self, t, name):
+        import torch
+        if t is None:
+            raise FrDvmError(f"{name} is None")
+        if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous() or t.numel() != self.ne * self.ns * self.nu:
+            raise FrDvmError(f"{name} must be a contiguous {self.dtype} CUDA tensor with {self.shape} elements")
+
+    def _check_d(self, t, n, name):
+        import torch
+        if t is not None and (not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n):
+            raise FrDvmError(f"{name} must be a contiguous float64 CUDA tensor of {n} elements")
+
+    # -- ABI -------------------------------------------------------------
+    def set_params(self, **kw):
+        p = _Params()
+        lib().fr_dvm_default_params(C.byref(p))
+        alias = {"prandtl": "prandtl", "Pr": "prandtl"}
+        for key, val in kw.items():
+            key = alias.get(key, key)
+            if key == "farfield":
+                for i, v in enumerate(val):
+                    p.farfield[i] = float(v)
+            elif key in dict(_Params._fields_):
+                setattr(p, key, type(getattr(p, key))(val))
+            else:
+                raise FrDvmError(f"unknown parameter {key}")
+        self._check(lib().fr_dvm_set_params(self._h, C.byref(p)), "fr_dvm_set_params")
+        self.precision = int(p.precision)
+        self.params = {f: (list(getattr(p, f)) if f == "farfield" else getattr(p, f)) for f, _ in _Params._fields_}
+        return self
+
+    def set_stream(self, stream):
+        s = getattr(stream, "cuda_stream", stream)
+        self._check(lib().fr_dvm_set_stream(self._h, C.c_void_p(int(s) if s else 0)), "fr_dvm_set_stream")
+
+    def sizes(self):
+        ne, ns, nf, nu, ws = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_size_t()
+        self._check(lib().fr_dvm_sizes(self._h, C.byref(ne), C.byref(ns), C.byref(nf), C.byref(nu),
+                                       C.byref(ws)), "fr_dvm_sizes")
+        return {"n_elem": ne.value, "ns": ns.value, "nf": nf.value, "nu": nu.value, "workspace_bytes": ws.value}
+
+    def velocity_nodes(self):
+        u, w = np.zeros((self.nu, 3)), np.zeros(self.nu)
+        self._check(lib().fr_dvm_velocity_nodes(self._h, u.ctypes.data_as(C.POINTER(C.c_double)),
+                                                w.ctypes.data_as(C.POINTER(C.c_double))), "velocity_nodes")
+        return u, w
+
+    def dt(self, cfl: float) -> float:
+        out = C.c_double()
+        self._check(lib().fr_dvm_dt(self._h, float(cfl), C.byref(out)), "fr_dvm_dt")
+        return out.value
+
+    def residual(self, f, R):
+        self._check_f(f, "f")
+        self._check_f(R, "R")
+        self._check(lib().fr_dvm_residual(self._h, _ptr(f), _ptr(R)), "fr_dvm_residual")
+        return R
+
+    def collide(self, f, S, Qp=None, accumulate=False):
+        self._check_f(f, "f")
+        self._check_f(S, "S")
+        self._check_d(Qp, self.ne * self.ns * 5, "Qp")
+        self._check(lib().fr_dvm_collide(self._h, _ptr(f), _ptr(S), _ptr(Qp), int(bool(accumulate))),
+                    "fr_dvm_collide")
+        return S
+
+    def moments(self, f, Q=None, totals=False):
+        self._check_f(f, "f")
+        self._check_d(Q, self.ne * self.ns * 5, "Q")
+        tot = np.zeros(5) if totals else None
+        tp = tot.ctypes.data_as(C.POINTER(C.c_double)) if totals else None
+        self._check(lib().fr_dvm_moments(self._h, _ptr(f), _ptr(Q), tp), "fr_dvm_moments")
+        return tot
+
+    def rk_step(self, f, dt):
+        self._check_f(f, "f")
+        self._check(lib().fr_dvm_rk_step(self._h, _ptr(f), float(dt)), "fr_dvm_rk_step")
+        return f
+
+    def rk_steps(self, f, dt, nsteps):
+        self._check_f(f, "f")
+        self._check(lib().fr_dvm_rk_steps(self._h, _ptr(f), float(dt), int(nsteps)), "fr_dvm_rk_steps")
+        return f
+
+    def newton_stats(self, reset=False):
+        hist = np.zeros(64, np.int64)
+        nf, ng, mr = C.c_int64(), C.c_int64(), C.c_double()
+        self._check(lib().fr_dvm_newton_stats(self._h, hist.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(nf),
+                                              C.byref(ng), C.byref(mr), int(bool(reset))), "fr_dvm_newton_stats")
+        return {"hist": hist, "n_fallback": nf.value, "n_guard": ng.value, "max_resid": mr.value}
+
+    def profile(self, enable=True):
+        self._check(lib().fr_dvm_profile(self._h, int(bool(enable))), "fr_dvm_profile")
+
+    def profile_read(self, reset=False):
+        """Summed HIP-event milliseconds and launch counts per kernel kind:
+        stage (fused FR stage), newton, prime, other."""
+        ms, n = np.zeros(4), np.zeros(4, np.int64)
+        self._check(lib().fr_dvm_profile_read(self._h, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                              n.ctypes.data_as(C.POINTER(C.c_int64)), int(bool(reset))),
+                    "fr_dvm_profile_read")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(("stage", "newton", "prime", "other"))}
+
+    def mlp_set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        self._check(lib().fr_dvm_mlp_set_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size),
+                    "fr_dvm_mlp_set_weights")

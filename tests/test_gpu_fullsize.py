@@ -1,0 +1,101 @@
+"""GPU parity at the full size of the 16^3-element, p = 3, 16^3-velocity
+periodic box (1.07e9 DOFs per register), in the launch configuration the
+benchmark times.  The oracle cannot run the whole box, so:
+
+* the residual of sampled elements is checked against the oracle run on a
+  7-element patch (the element and its six face neighbours), which is all
+  the residual of that element depends on;
+* the collision at sampled solution points is checked point by point;
+* one full step conserves the global totals to 1e-12 relative (FP64).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def big():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_06567_amd.frdvm import FrDvm
+    w = W.workload("box16_p3_v16")
+    mesh = W.box_mesh(w["N"])
+    par = W.physics_params(w)
+    s = FrDvm(mesh, w["p"], w["grid"], par)
+    prim = W.initial_prim(mesh, w["p"], w)
+    f = W.maxwellian(prim, w["grid"], device="cuda").reshape(s.shape)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12)
+    f *= 1.0 + 0.1 * (2 * torch.rand(f.shape, generator=g, device="cuda", dtype=torch.float64) - 1)
+    torch.cuda.synchronize()
+    return w, mesh, par, s, f
+
+
+def _patch(mesh, e):
+    """Mesh of element e and its six face neighbours (patch-local ids 0..6)."""
+    nb = mesh["nbr_elem"][e]
+    ids = [e] + [int(x) for x in nb]
+    en = mesh["elem_nodes"][ids]
+    uniq, inv = np.unique(en.reshape(-1), return_inverse=True)
+    nodes = mesh["nodes"][uniq]
+    pe = np.zeros((7, 6), np.int32)
+    pf = np.zeros((7, 6), np.int8)
+    for f in range(6):
+        pe[0, f] = 1 + f
+        pf[0, f] = f ^ 1
+    for j in range(1, 7):
+        f_back = (j - 1) ^ 1  # face of neighbour j that touches e
+        for f in range(6):
+            pe[j, f] = 0 if f == f_back else j
+            pf[j, f] = f ^ 1
+    return {"n_elem": 7, "n_nodes": len(uniq), "geom_order": 1, "nodes": nodes,
+            "elem_nodes": inv.reshape(7, 8).astype(np.int32), "nbr_elem": pe, "nbr_face": pf,
+            "nbr_orient": np.zeros((7, 6), np.int8), "bc": np.zeros((7, 6), np.int8)}, ids
+
+
+def test_fullsize_residual_sampled_elements(big, orc):
+    w, mesh, par, s, f = big
+    R = torch.empty_like(f)
+    s.residual(f, R)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for e in [0, s.ne - 1, *rng.integers(0, s.ne, 2)]:
+        pm, ids = _patch(mesh, int(e))
+        fp = f[ids].cpu().numpy()
+        Rr = orc.Problem(pm, w["p"], w["grid"], dict(par, model=2)).residual(fp)[0]
+        assert rel(R[int(e)].cpu().numpy(), Rr) < 1e-12, e
+
+
+def test_fullsize_collide_sampled_points(big, orc):
+    w, mesh, par, s, f = big
+    S = torch.empty_like(f)
+    Qp = torch.empty(s.ne * s.ns * 5, dtype=torch.float64, device="cuda")
+    s.collide(f, S, Qp)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    pts = rng.integers(0, s.ne * s.ns, 24)
+    fpts = f.reshape(-1, s.nu)[pts].cpu().numpy()
+    Sr, prim, *_ = orc.Problem.points_only(w["grid"], par).collide(fpts)
+    Sg = S.reshape(-1, s.nu)[pts].cpu().numpy()
+    scale = np.abs(fpts).max() * par["mu_ref"] ** -1
+    assert np.abs(Sg - Sr).max() < 1e-12 * scale
+    assert rel(Qp.reshape(-1, 5)[pts].cpu().numpy(), prim) < 1e-12
+    assert s.newton_stats(reset=True)["n_fallback"] == 0
+
+
+def test_fullsize_step_conserves(big):
+    w, mesh, par, s, f = big
+    t0 = s.moments(f, totals=True)
+    s.rk_step(f, s.dt(0.2))
+    t1 = s.moments(f, totals=True)
+    scale = np.abs(t0).max()
+    assert np.abs(t1 - t0).max() < 1e-12 * scale
+    assert torch.isfinite(f).all().item()
