@@ -61,6 +61,7 @@ extern "C" {
 #define FR_DVM_GUESS_COLD 0 /* continuous equilibrium of the moments of f */
 #define FR_DVM_GUESS_WARM 1 /* previous solution at the same point */
 #define FR_DVM_GUESS_MLP 2  /* learned guess (fr_dvm_mlp_set_weights) */
+#define FR_DVM_GUESS_MLP_WARM 3 /* learned guess where no previous solution exists, warm afterwards */
 
 /* explicit time integration (the paper names no scheme) */
 #define FR_DVM_SSPRK3 0   /* three-stage SSP-RK, Shu-Osher form */
@@ -164,11 +165,12 @@ int fr_dvm_rk_step(fr_dvm_t h, void *f, double dt);
 int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps);
 
 /* Newton statistics accumulated since the last reset (synchronising):
- * iters_hist[64] histogram of iterations per point solve, number of fallback
- * and ES-guard points, and the largest final scaled residual.  Any pointer
- * may be NULL.  reset != 0 clears the counters afterwards. */
+ * iters_hist[64] histogram of iterations (linear solves) per point solve,
+ * number of fallback and ES-guard points, total residual evaluations (passes
+ * over the velocity grid), and the largest final scaled residual.  Any
+ * pointer may be NULL.  reset != 0 clears the counters afterwards. */
 int fr_dvm_newton_stats(fr_dvm_t h, int64_t *iters_hist, int64_t *n_fallback,
-                        int64_t *n_guard, double *max_resid, int reset);
+                        int64_t *n_guard, int64_t *n_evals, double *max_resid, int reset);
 
 /* Weights of the learned Newton initial guess: an MLP 7 -> H -> H -> H -> 5
  * with SiLU activations (FP32, layout documented in fr_dvm_mlp.h).  n is the
@@ -183,6 +185,13 @@ int fr_dvm_mlp_set_weights(fr_dvm_t h, const float *w, size_t n);
 #define FR_DVM_PROF_KINDS 4
 int fr_dvm_profile(fr_dvm_t h, int enable);
 int fr_dvm_profile_read(fr_dvm_t h, double *ms, int64_t *launches, int reset);
+
+/* HBM bandwidth probe (no handle): plain copy of nbytes from src to dst,
+ * both device pointers, 16-byte loads and stores, on stream (hipStream_t as
+ * void*, may be NULL).  nbytes must be a multiple of 16 and the ranges must
+ * not overlap.  Used to calibrate hardware byte counters against a kernel
+ * of known traffic. */
+int fr_dvm_hbm_copy(void *dst, const void *src, size_t nbytes, void *stream);
 
 const char *fr_dvm_last_error(fr_dvm_t h);
 void fr_dvm_destroy(fr_dvm_t h);

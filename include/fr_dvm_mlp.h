@@ -54,12 +54,15 @@ int fr_mlp_adam(int H, float *w, const float *grad, float *m, float *v, int step
 
 /* Conservative equilibria for n given moment vectors Q[n][5] (rho, rho U, E)
  * on the handle's velocity grid (BGK form): FP64 Newton from the cold start
- * (guess = FR_DVM_GUESS_COLD) or from the handle's MLP (FR_DVM_GUESS_MLP).
+ * (guess = FR_DVM_GUESS_COLD) or from the better (smaller residual) of the
+ * cold start and the handle's MLP prediction (FR_DVM_GUESS_MLP).
  * Outputs (device, nullable): z[n][5] Newton unknowns in the frame
- * c = (u-U)/sqrt(theta), iters[n], status[n] (FR_DVM_NEWTON_*), resid[n]
- * final scaled residual.  Uses the handle's tolerance and iteration cap. */
+ * c = (u-U)/sqrt(theta), iters[n] linear solves, evals[n] residual/Jacobian
+ * evaluations (sum passes over the grid), status[n] (FR_DVM_NEWTON_*),
+ * resid[n] final scaled residual.  Uses the handle's tolerance and
+ * iteration cap.  Synchronises the handle's stream. */
 int fr_dvm_equilibrium(fr_dvm_t h, const double *Q, int64_t n, int guess, double *z, int32_t *iters,
-                       int32_t *status, double *resid);
+                       int32_t *evals, int32_t *status, double *resid);
 
 #ifdef __cplusplus
 }

@@ -4,6 +4,7 @@
 
 #include <cstring>
 
+#include "../../include/fr_dvm_mlp.h"
 #include "frdvm_common.h"
 
 using namespace frdvm;
@@ -97,10 +98,7 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
     const int guess = guess_mode(h);
     for (int step = 0; step < nsteps; ++step) {
         for (int st = 0; st < 3; ++st) {
-            if (collide) {
-                ProfScope ps(h, 1);
-                if ((rc = launch_newton(h, guess))) return rc;
-            }
+            if (collide && (rc = launch_newton(h, guess))) return rc;
             StageArgs a = blank();
             a.dt = dt;
             a.collide = collide;
@@ -139,9 +137,9 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
 extern "C" int fr_dvm_rk_step(fr_dvm_t h, void *f, double dt) { return fr_dvm_rk_steps(h, f, dt, 1); }
 
 extern "C" int fr_dvm_newton_stats(fr_dvm_t h, int64_t *iters_hist, int64_t *n_fallback, int64_t *n_guard,
-                                   double *max_resid, int reset) {
+                                   int64_t *n_evals, double *max_resid, int reset) {
     if (!h) return FR_DVM_EINVAL;
-    int64_t buf[kHist + 2];
+    int64_t buf[kHist + 4];
     double mr;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return h->fail(FR_DVM_EHIP, "stream synchronise");
     if (hipMemcpy(buf, h->d_stats, sizeof(buf), hipMemcpyDeviceToHost) != hipSuccess ||
@@ -150,6 +148,7 @@ extern "C" int fr_dvm_newton_stats(fr_dvm_t h, int64_t *iters_hist, int64_t *n_f
     if (iters_hist) std::memcpy(iters_hist, buf, kHist * sizeof(int64_t));
     if (n_fallback) *n_fallback = buf[kHist];
     if (n_guard) *n_guard = buf[kHist + 1];
+    if (n_evals) *n_evals = buf[kHist + 2];
     if (max_resid) *max_resid = mr;
     if (reset) {
         hipMemset(h->d_stats, 0, sizeof(buf));
@@ -201,4 +200,13 @@ extern "C" int fr_dvm_profile_read(fr_dvm_t h, double *ms, int64_t *launches, in
         if (reset) { h->prof_ms[k] = 0; h->prof_n[k] = 0; }
     }
     return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_equilibrium(fr_dvm_t h, const double *Q, int64_t n, int guess, double *z, int32_t *iters,
+                                  int32_t *evals, int32_t *status, double *resid) {
+    int rc = ready(h);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && !Q)) return h->fail(FR_DVM_EINVAL, "bad moment array");
+    if (guess != FR_DVM_GUESS_COLD && guess != FR_DVM_GUESS_MLP) return h->fail(FR_DVM_EINVAL, "guess must be cold or MLP");
+    return launch_newton_points(h, Q, n, guess, z, iters, evals, status, resid);
 }

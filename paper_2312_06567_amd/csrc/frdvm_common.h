@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/fr_dvm.h"
+#include "../../include/fr_dvm_mlp.h"
 
 namespace frdvm {
 
@@ -85,6 +86,7 @@ struct fr_dvm {
     fr_dvm_params prm{};
     bool have_params = false;
     int nmom = 5;                // 5 (BGK) or 10 (ES: rho, rho U, raw second moments)
+    bool es_direct = false;      // ES Newton: force the direct per-node sums (env FRDVM_ES_DIRECT=1)
 
     // work buffers
     void *d_reg = nullptr;       // second RK register [ne*ns*nu]
@@ -95,12 +97,20 @@ struct fr_dvm {
     double *d_z = nullptr;       // [ne*ns][5] Newton solution (warm start)
     double *d_prim = nullptr;    // [ne*ns][5] primitive state of g(Q')
     int zvalid = 0;
-    int64_t *d_stats = nullptr;  // [kHist + 2]
+    int32_t *d_pt_iters = nullptr;   // [ne*ns] per-point Newton outcome of the last solve
+    int32_t *d_pt_evals = nullptr;
+    int32_t *d_pt_status = nullptr;
+    double *d_pt_resid = nullptr;
+    int64_t *d_stats = nullptr;  // [kHist + 4]: histogram, fallback, ES guard, evaluations
     double *d_maxres = nullptr;  // [1] (as ordered bits)
     double *d_tot = nullptr;     // [5]
-    float *d_mlp = nullptr;
+    float *d_mlp = nullptr;      // learned-guess network weights
     size_t mlp_n = 0;
     int mlp_hidden = 0;
+    float *d_mlp_x = nullptr;    // feature batch
+    float *d_mlp_work = nullptr; // forward workspace
+    float *d_mlp_dz = nullptr;   // [npts][5] predicted Newton corrections
+    size_t mlp_x_n = 0, mlp_work_n = 0, dz_n = 0;
     size_t owned_bytes = 0;
 
     // HIP-event kernel timing (fr_dvm_profile)
@@ -155,6 +165,8 @@ int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int d
 
 // ---- launchers (frdvm_newton.hip) ----
 int launch_newton(fr_dvm *h, int guess);
+int launch_newton_points(fr_dvm *h, const double *Q, int64_t n, int guess, double *z, int32_t *iters, int32_t *evals,
+                         int32_t *status, double *resid);
 int launch_collide(fr_dvm *h, const void *f, void *S, int accumulate);
 int launch_prim_out(fr_dvm *h, double *Qp);
 int launch_moments_out(fr_dvm *h, double *Q);

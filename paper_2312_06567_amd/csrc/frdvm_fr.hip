@@ -9,24 +9,22 @@
 // function.  The collision source (g(Q') - f)/tau follows Section
 // "Governing equations"; Q' comes from the Newton kernels.
 //
-// Work decomposition: one workgroup (4 wave64) per element; each lane owns
-// one velocity node and holds the element's (p+1)^3 solution values in
-// registers.  On a tensor-product Gauss element every operator factorises
-// along lines, so the divergence is 3 (p+1)^4 FMAs and each face trace or
-// correction touches only the line through its flux node: the kernel is HBM
-// bound and uses plain VALU FMAs (no MFMA: the sum-factorised contraction has
-// K = p+1 <= 4).
+// Work decomposition: one workgroup (4 wave64) per element.  A lane owns one
+// velocity node and one z-layer of the element's N^3 Gauss points (N = p+1):
+// N lanes share a velocity, a wave covers 64/N velocities.  On a
+// tensor-product Gauss element every operator factorises along lines, so the
+// x and y derivatives, traces and corrections are local to the lane's layer;
+// z lines are gathered from a per-wave LDS tile that holds the wave's
+// N^3 x (64/N) block of f.  The same tile, refilled with the stage result,
+// serves the z traces of the result and the moment reduction (lane = solution
+// point, FP64 accumulation with wave-uniform scalar weights, fixed order:
+// bitwise reproducible).  Everything is VALU FMA: the factorised contractions
+// have K = p+1 <= 4 and the kernel is HBM bound.
 //
 // Traces: each element stores, for the velocities leaving it through a face,
 // its trace on that face ("outflow half", compact layout) into the trace
 // buffer of the next stage; the downwind neighbour reads exactly those
 // entries as its exterior state.  Two trace buffers alternate between stages.
-//
-// Moments of the produced stage value are reduced inside the kernel: each
-// wave transposes its 64-velocity x NS-point tile through LDS so that a lane
-// owns one solution point, and accumulates sum_k w_k psi_k f_k in FP64 with
-// wave-uniform (scalar) weights.  The sum order is fixed: results are
-// bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
 #include "frdvm_common.h"
@@ -62,10 +60,13 @@ __device__ __forceinline__ int compact_index(const VGrid &vg, int d, int side, c
     return idx[0] + ext[0] * (idx[1] + ext[1] * idx[2]);
 }
 
-template <int N>
-__device__ __forceinline__ constexpr int line_pt(int d, int fp, int m) {
-    // solution index of the m-th point along axis d through face point fp = a + N b
-    return d == 0 ? m + N * fp : (d == 1 ? (fp % N) + N * (m + N * (fp / N)) : fp + N * N * m);
+// The LDS tile region of a wave is private to that wave, and one wave's LDS
+// operations complete in issue order, so exchanging data through it only
+// needs the compiler kept from moving LDS accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename Real>
@@ -89,22 +90,26 @@ __device__ __forceinline__ float eval_g<float>(const double *eq, const double u[
 }
 
 template <typename Real, int P, int NMOM, int MODE>
-__global__ __launch_bounds__(kBlock) void k_fr_axis(const FrArgs A) {
-    constexpr int N = P + 1, NS = N * N * N, NFP = N * N;
-    constexpr int TILE_LD = 33;  // padded row of the transpose tile
-    // LDS: equilibrium records, then a union of the transpose tiles and the
-    // cross-wave reduction buffer
+__global__ __launch_bounds__(kBlock) void k_fr_layer(const FrArgs A) {
+    constexpr int N = P + 1, NS = N * N * N, NL = N * N;
+    constexpr int VPW = 64 / N;       // velocities per wave
+    constexpr int VPB = 4 * VPW;      // velocities per workgroup and chunk
+    constexpr int TLD = VPW + 1;      // padded tile row
     __shared__ double s_eq[(MODE == MODE_STAGE) ? NS * kEqW : 1];
-    constexpr size_t TILE_BYTES = sizeof(Real) * 4 * NS * TILE_LD;
+    constexpr size_t TILE_BYTES = sizeof(Real) * 4 * NS * TLD;
     constexpr size_t RED_BYTES = sizeof(double) * 4 * NS * NMOM;
     __shared__ __attribute__((aligned(16))) unsigned char s_raw[TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES];
-    Real(*tile)[NS][TILE_LD] = reinterpret_cast<Real(*)[NS][TILE_LD]>(s_raw);
+    Real(*tile)[NS][TLD] = reinterpret_cast<Real(*)[NS][TLD]>(s_raw);
     double(*red)[NS][NMOM] = reinterpret_cast<double(*)[NS][NMOM]>(s_raw);
 
     const int64_t e = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lay = lane / VPW;        // z-layer owned by this lane (N for an idle lane)
+    const int vl = lane - lay * VPW;   // velocity slot inside the wave
+    const bool lane_ok = lay < N;
+    const int l = lane_ok ? lay : 0;
     const VGrid &vg = A.vg;
     const int nu = A.nu;
     const int64_t ebase = e * (int64_t)NS * nu;
@@ -112,30 +117,55 @@ __global__ __launch_bounds__(kBlock) void k_fr_axis(const FrArgs A) {
     if (MODE == MODE_STAGE && A.sa.collide) {
         for (int i = tid; i < NS * kEqW; i += kBlock) s_eq[i] = A.sa.eq[e * NS * kEqW + i];
     }
-    __syncthreads();
 
-    const double gx = A.gfac[3 * e], gy = A.gfac[3 * e + 1], gz = A.gfac[3 * e + 2];
-    const double gf[3] = {gx, gy, gz};
+    // z-direction operator entries of this lane's layer
+    Real Dz[N], corrz[2];
+#pragma unroll
+    for (int m = 0; m < N; ++m) Dz[m] = (Real)A.ops.D[l * N + m];
+    corrz[0] = (Real)A.ops.corr[0][l];
+    corrz[1] = (Real)A.ops.corr[1][l];
+    const double gf[3] = {A.gfac[3 * e], A.gfac[3 * e + 1], A.gfac[3 * e + 2]};
 
     double acc[NMOM];
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) acc[a] = 0.0;
 
-    const Real *__restrict__ fin = reinterpret_cast<const Real *>(A.sa.f) + ebase;
-    const int nchunk = (nu + kBlock - 1) / kBlock;
+    const Real *__restrict__ fin = reinterpret_cast<const Real *>(A.sa.f) + ebase + (int64_t)l * NL * nu;
+    const Real *__restrict__ trin = reinterpret_cast<const Real *>(A.sa.tr_in);
+    Real *__restrict__ trout = reinterpret_cast<Real *>(A.sa.tr_out);
+    const int nchunk = (nu + VPB - 1) / VPB;
+    __syncthreads();
+
+    // stage value of the first chunk; later chunks are prefetched one ahead
+    Real fnx[NL];
+    {
+        const int k0 = wave * VPW + vl;
+        const bool a0 = lane_ok && k0 < nu;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) fnx[q] = a0 ? fin[(int64_t)q * nu + k0] : Real(0);
+    }
 
     for (int ch = 0; ch < nchunk; ++ch) {
-        const int k = ch * kBlock + tid;
-        const bool act = k < nu;
+        const int k = ch * VPB + wave * VPW + vl;
+        const bool act = lane_ok && k < nu;
         const int kk = act ? k : 0;
+        Real f[NL];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) f[q] = fnx[q];
+        {
+            const int k1 = k + VPB;
+            const bool a1 = lane_ok && k1 < nu;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) fnx[q] = a1 ? fin[(int64_t)q * nu + k1] : Real(0);
+        }
         int iv[3];
         iv[0] = kk % vg.nv[0];
         iv[1] = (kk / vg.nv[0]) % vg.nv[1];
         iv[2] = kk / (vg.nv[0] * vg.nv[1]);
-        // The sign of each velocity component is taken from the integer
-        // split of the grid computed on the host (not from the rounded
-        // value), so the compact trace slots of writer and reader always
-        // agree; a node classified as zero carries exactly zero flux.
+        // The sign of each velocity component is taken from the integer split
+        // of the grid computed on the host (not from the rounded value), so
+        // the compact trace slots of writer and reader always agree; a node
+        // classified as zero carries exactly zero flux.
         double u[3];
         int sgn[3];
 #pragma unroll
@@ -144,129 +174,170 @@ __global__ __launch_bounds__(kBlock) void k_fr_axis(const FrArgs A) {
             u[d] = sgn[d] == 0 ? 0.0 : __dadd_rn(vg.umin[d], __dmul_rn((double)iv[d], vg.du[d]));
         }
 
-        Real f[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) f[s] = act ? fin[(int64_t)s * nu + k] : Real(0);
-
         if (MODE != MODE_PRIME) {
-            Real r[NS];
+            // publish the stage value for the z-line gathers
+            wave_sync();
+            if (lane_ok) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) r[s] = Real(0);
-            // flux divergence: sum_d a_d D_d f along every line, a_d = (2/h_d) u_d
+                for (int q = 0; q < NL; ++q) tile[wave][l * NL + q][vl] = f[q];
+            }
+            wave_sync();
+            Real r[NL];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const Real ad = (Real)(gf[d] * u[d]);
+            for (int q = 0; q < NL; ++q) r[q] = Real(0);
+            const Real ax = (Real)(gf[0] * u[0]), ay = (Real)(gf[1] * u[1]), az = (Real)(gf[2] * u[2]);
+            // x and y derivatives inside the layer
 #pragma unroll
-                for (int fp = 0; fp < NFP; ++fp) {
+            for (int j = 0; j < N; ++j)
 #pragma unroll
-                    for (int i = 0; i < N; ++i) {
-                        Real t = Real(0);
+                for (int i = 0; i < N; ++i) {
+                    Real tx = Real(0), ty = Real(0);
 #pragma unroll
-                        for (int m = 0; m < N; ++m) t += (Real)A.ops.D[i * N + m] * f[line_pt<N>(d, fp, m)];
-                        r[line_pt<N>(d, fp, i)] += ad * t;
+                    for (int m = 0; m < N; ++m) {
+                        tx += (Real)A.ops.D[i * N + m] * f[m + N * j];
+                        ty += (Real)A.ops.D[j * N + m] * f[i + N * m];
                     }
+                    r[i + N * j] += ax * tx + ay * ty;
+                }
+            // z lines: derivative and the inflow correction of the z faces
+            const int zin = sgn[2] > 0 ? 0 : 1;
+            const bool zflow = act && sgn[2] != 0;
+            int64_t zbase = 0, zcnt = 0;
+            Real unz = Real(0);
+            if (zflow) {
+                const int nface = 4 + (zin ^ 1);
+                zcnt = A.tl.cnt[nface];
+                zbase = (int64_t)A.nbr[6 * e + 4 + zin] * A.tl.elem + A.tl.face_off[nface] + compact_index(vg, 2, zin ^ 1, iv);
+                unz = (Real)((zin ? 1.0 : -1.0) * gf[2] * u[2]);
+            }
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                Real g[N];
+#pragma unroll
+                for (int m = 0; m < N; ++m) g[m] = tile[wave][m * NL + q][vl];
+                Real t = Real(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) t += Dz[m] * g[m];
+                r[q] += az * t;
+                if (zflow) {
+                    Real fm = Real(0);
+#pragma unroll
+                    for (int m = 0; m < N; ++m) fm += (Real)A.ops.lam[zin][m] * g[m];
+                    const Real fp = trin[zbase + q * zcnt];
+                    r[q] += corrz[zin] * (unz * (fp - fm));
                 }
             }
-            // interface corrections on the inflow face of each axis: the
-            // common flux is the neighbour's value, jump = u_n (f+ - f-)
-            const Real *__restrict__ trin = reinterpret_cast<const Real *>(A.sa.tr_in);
+            // x faces: face points (j, l); y faces: face points (i, l)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
+            for (int d = 0; d < 2; ++d) {
                 if (act && sgn[d] != 0) {
-                    const int side_in = sgn[d] > 0 ? 0 : 1;
-                    const int nface = 2 * d + (side_in ^ 1);  // neighbour's outflow face
-                    const int64_t nb = A.nbr[6 * e + 2 * d + side_in];
+                    const int sin_ = sgn[d] > 0 ? 0 : 1;
+                    const int nface = 2 * d + (sin_ ^ 1);
                     const int64_t cnt = A.tl.cnt[nface];
-                    const int64_t base = nb * A.tl.elem + A.tl.face_off[nface] + compact_index(vg, d, side_in ^ 1, iv);
-                    const Real un = (Real)((side_in ? 1.0 : -1.0) * gf[d] * u[d]);
+                    const int64_t base = (int64_t)A.nbr[6 * e + 2 * d + sin_] * A.tl.elem + A.tl.face_off[nface] +
+                                         compact_index(vg, d, sin_ ^ 1, iv);
+                    const Real un = (Real)((sin_ ? 1.0 : -1.0) * gf[d] * u[d]);
 #pragma unroll
-                    for (int fp = 0; fp < NFP; ++fp) {
-                        const Real fplus = trin[base + fp * cnt];
-                        Real fminus = Real(0);
+                    for (int a = 0; a < N; ++a) {
+                        const Real fp = trin[base + (a + N * l) * cnt];
+                        Real fm = Real(0);
 #pragma unroll
-                        for (int m = 0; m < N; ++m) fminus += (Real)A.ops.lam[side_in][m] * f[line_pt<N>(d, fp, m)];
-                        const Real jmp = un * (fplus - fminus);
+                        for (int m = 0; m < N; ++m)
+                            fm += (Real)A.ops.lam[sin_][m] * (d == 0 ? f[m + N * a] : f[a + N * m]);
+                        const Real jmp = un * (fp - fm);
 #pragma unroll
-                        for (int m = 0; m < N; ++m) r[line_pt<N>(d, fp, m)] += (Real)A.ops.corr[side_in][m] * jmp;
+                        for (int m = 0; m < N; ++m)
+                            r[d == 0 ? m + N * a : a + N * m] += (Real)A.ops.corr[sin_][m] * jmp;
                     }
                 }
             }
+            Real *__restrict__ out = reinterpret_cast<Real *>(A.sa.fout) + ebase + (int64_t)l * NL * nu;
             if (MODE == MODE_RESID) {
-                Real *__restrict__ out = reinterpret_cast<Real *>(A.sa.fout) + ebase;
                 if (act) {
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) out[(int64_t)s * nu + k] = -r[s];
+                    for (int q = 0; q < NL; ++q) out[(int64_t)q * nu + k] = -r[q];
                 }
                 continue;
             }
             // collision source and the Runge-Kutta combination, point by point
-            Real *__restrict__ out = reinterpret_cast<Real *>(A.sa.fout) + ebase;
-            const Real *__restrict__ fnp = reinterpret_cast<const Real *>(A.sa.fn) + ebase;
-            Real *__restrict__ dF = reinterpret_cast<Real *>(A.sa.dF) + ebase;
+            const Real *__restrict__ fnp = reinterpret_cast<const Real *>(A.sa.fn) + ebase + (int64_t)l * NL * nu;
+            Real *__restrict__ dF = reinterpret_cast<Real *>(A.sa.dF) + ebase + (int64_t)l * NL * nu;
             const Real dt = (Real)A.sa.dt;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                Real L = -r[s];
+            for (int q = 0; q < NL; ++q) {
+                Real L = -r[q];
                 if (A.sa.collide) {
-                    const double *eq = &s_eq[s * kEqW];
-                    const Real g = eval_g<Real>(eq, u);
-                    L += (g - f[s]) * (Real)eq[EQ_INVTAU];
+                    const double *eq = &s_eq[(l * NL + q) * kEqW];
+                    const Real gq = eval_g<Real>(eq, u);
+                    L += (gq - f[q]) * (Real)eq[EQ_INVTAU];
                 }
                 Real fo;
                 if (A.sa.scheme == 0) {
-                    fo = (Real)A.sa.beta * (f[s] + dt * L);
-                    if (A.sa.alpha != 0.0 && act) fo += (Real)A.sa.alpha * fnp[(int64_t)s * nu + k];
+                    fo = (Real)A.sa.beta * (f[q] + dt * L);
+                    if (A.sa.alpha != 0.0 && act) fo += (Real)A.sa.alpha * fnp[(int64_t)q * nu + k];
                 } else {
                     Real dd = dt * L;
-                    if (A.sa.lsA != 0.0 && act) dd += (Real)A.sa.lsA * dF[(int64_t)s * nu + k];
-                    if (act) dF[(int64_t)s * nu + k] = dd;
-                    fo = f[s] + (Real)A.sa.lsB * dd;
+                    if (A.sa.lsA != 0.0 && act) dd += (Real)A.sa.lsA * dF[(int64_t)q * nu + k];
+                    if (act) dF[(int64_t)q * nu + k] = dd;
+                    fo = f[q] + (Real)A.sa.lsB * dd;
                 }
-                f[s] = act ? fo : Real(0);
-                if (act) out[(int64_t)s * nu + k] = fo;
+                f[q] = act ? fo : Real(0);
+                if (act) out[(int64_t)q * nu + k] = fo;
             }
         }
 
-        // outflow traces of the produced value (the next stage's exterior states)
+        // outflow traces of the produced value on the x and y faces
         if (A.do_traces && act) {
-            Real *__restrict__ trout = reinterpret_cast<Real *>(A.sa.tr_out);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
+            for (int d = 0; d < 2; ++d) {
                 if (sgn[d] != 0) {
                     const int side = sgn[d] > 0 ? 1 : 0;
                     const int face = 2 * d + side;
                     const int64_t cnt = A.tl.cnt[face];
                     const int64_t base = e * A.tl.elem + A.tl.face_off[face] + compact_index(vg, d, side, iv);
 #pragma unroll
-                    for (int fp = 0; fp < NFP; ++fp) {
+                    for (int a = 0; a < N; ++a) {
                         Real t = Real(0);
 #pragma unroll
-                        for (int m = 0; m < N; ++m) t += (Real)A.ops.lam[side][m] * f[line_pt<N>(d, fp, m)];
-                        trout[base + fp * cnt] = t;
+                        for (int m = 0; m < N; ++m)
+                            t += (Real)A.ops.lam[side][m] * (d == 0 ? f[m + N * a] : f[a + N * m]);
+                        trout[base + (a + N * l) * cnt] = t;
                     }
                 }
             }
         }
 
-        // moments: transpose each wave's tile through LDS, lane = solution point
-        if (A.do_moments) {
+        // tile of the produced value: z traces and the moment reduction
+        if (A.do_moments || A.do_traces) {
+            wave_sync();
+            if (lane_ok) {
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                __syncthreads();
-                if ((lane >> 5) == half) {
+                for (int q = 0; q < NL; ++q) tile[wave][l * NL + q][vl] = f[q];
+            }
+            wave_sync();
+            if (A.do_traces && act && sgn[2] != 0) {
+                // this lane writes the z-face points (i, j = l)
+                const int side = sgn[2] > 0 ? 1 : 0;
+                const int face = 4 + side;
+                const int64_t cnt = A.tl.cnt[face];
+                const int64_t base = e * A.tl.elem + A.tl.face_off[face] + compact_index(vg, 2, side, iv);
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) tile[wave][s][lane & 31] = act ? f[s] : Real(0);
+                for (int i = 0; i < N; ++i) {
+                    const int q = i + N * l;
+                    Real t = Real(0);
+#pragma unroll
+                    for (int m = 0; m < N; ++m) t += (Real)A.ops.lam[side][m] * tile[wave][m * NL + q][vl];
+                    trout[base + q * cnt] = t;
                 }
-                __syncthreads();
-                if (lane < NS) {
-                    const int kb = ch * kBlock + wave * 64 + half * 32;
-                    const double *__restrict__ wp = A.wpsi + (int64_t)kb * NMOM;
+            }
+            if (A.do_moments && lane < NS) {
+                const int kb = ch * VPB + wave * VPW;
+                const double *__restrict__ wp = A.wpsi + (int64_t)kb * NMOM;
 #pragma unroll 4
-                    for (int j = 0; j < 32; ++j) {
-                        const double v = (double)tile[wave][lane][j];
+                for (int j = 0; j < VPW; ++j) {
+                    const double v = (double)tile[wave][lane][j];
 #pragma unroll
-                        for (int a = 0; a < NMOM; ++a) acc[a] += wp[j * NMOM + a] * v;
-                    }
+                    for (int a = 0; a < NMOM; ++a) acc[a] += wp[j * NMOM + a] * v;
                 }
             }
         }
@@ -290,11 +361,11 @@ template <typename Real, int P, int NMOM>
 int launch_p(fr_dvm *h, int mode, const FrArgs &A) {
     dim3 grid((unsigned)h->ne), block(kBlock);
     if (mode == MODE_PRIME)
-        hipLaunchKernelGGL((k_fr_axis<Real, P, NMOM, MODE_PRIME>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_fr_layer<Real, P, NMOM, MODE_PRIME>), grid, block, 0, h->stream, A);
     else if (mode == MODE_STAGE)
-        hipLaunchKernelGGL((k_fr_axis<Real, P, NMOM, MODE_STAGE>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_fr_layer<Real, P, NMOM, MODE_STAGE>), grid, block, 0, h->stream, A);
     else
-        hipLaunchKernelGGL((k_fr_axis<Real, P, NMOM, MODE_RESID>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_fr_layer<Real, P, NMOM, MODE_RESID>), grid, block, 0, h->stream, A);
     hipError_t st = hipGetLastError();
     if (st != hipSuccess) return h->fail(FR_DVM_EHIP, std::string("FR kernel launch: ") + hipGetErrorString(st));
     return FR_DVM_OK;
@@ -308,6 +379,12 @@ int launch_np(fr_dvm *h, int mode, const FrArgs &A) {
         case 3: return launch_p<Real, 3, NMOM>(h, mode, A);
     }
     return h->fail(FR_DVM_EUNSUPPORTED, "order");
+}
+
+// Streaming copy with 16-byte accesses, grid-stride.
+__global__ __launch_bounds__(256) void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 }  // namespace
@@ -332,3 +409,16 @@ int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int 
 }
 
 }  // namespace frdvm
+
+extern "C" int fr_dvm_hbm_copy(void *dst, const void *src, size_t nbytes, void *stream) {
+    if (!dst || !src || nbytes % 16 != 0) return FR_DVM_EINVAL;
+    const char *d = static_cast<const char *>(dst), *s = static_cast<const char *>(src);
+    if (d < s + nbytes && s < d + nbytes) return FR_DVM_EINVAL;
+    int64_t n = (int64_t)(nbytes / 16);
+    if (n == 0) return FR_DVM_OK;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    hipLaunchKernelGGL(frdvm::k_copy16, dim3((unsigned)blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                       static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), n);
+    return hipGetLastError() == hipSuccess ? FR_DVM_OK : FR_DVM_EHIP;
+}

@@ -10,18 +10,24 @@
 // T = theta/Pr I + (1 - 1/Pr) Pi/rho.
 //
 // Formulation (the same reading as the CPU oracle): in the frame
-// c = (u - U)/sqrt(theta) with weights w theta^-3/2 the five equations
+// c = (u - U)/sqrt(theta) with weights wt = w theta^-3/2 the five equations
 // are sum_k wt_k (1, c_k, |c_k|^2/2) exp(z0 + z.c_k - z4 q(c_k)/2) =
-// (1, 0, 0, 0, 3/2), q = |c|^2 (BGK) or c^T A c with A = theta T^-1 (ES-BGK).
+// (1, 0, 0, 0, 3/2), q = |c|^2 (BGK) or c^T A c with A = theta T^-1 (ES-BGK),
+// and g' = rho wt exp(...).
 //
 // BGK kernel: one thread per point.  On a tensor velocity grid the BGK
 // exponential factorises per axis, so each Newton iteration costs 3 n_v
 // exponentials and 1-D power sums instead of n_v^3 terms.
 // ES kernel: one wave64 per point, lanes over velocity nodes, butterfly
-// reduction of the 17 sums (lane-symmetric: every lane gets the same bits).
+// reduction of the 18 sums (lane-symmetric: every lane gets the same bits).
+// Starting points: cold (continuous equilibrium of the moments), warm (the
+// previous solution at the point) or learned (cold + a correction predicted
+// by the MLP kernels; the start with the smaller residual is kept, so the
+// learned start never costs more than one extra evaluation).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
 #include "frdvm_common.h"
 
@@ -40,14 +46,17 @@ struct NewtonArgs {
     double *prim;        // [npts][5]
     unsigned long long *stats;  // [kHist] histogram, [kHist] fallback, [kHist+1] ES guard
     unsigned long long *maxres;
-    int model;
+    int32_t *pt_iters;   // optional per-point outputs
+    int32_t *pt_evals;
+    int32_t *pt_status;
+    double *pt_resid;
     double Pr, mu_ref, theta_ref, omega, theta_s;
     int visc_law;
     double tol;
     int max_iter;
     int guess;
-    const float *mlp;
-    int mlp_hidden;
+    const float *dz_guess;  // [npts][5] learned correction (guess == MLP)
+    int use_fact;           // ES: factorised sums with per-wave LDS tables
 };
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
@@ -64,8 +73,9 @@ __device__ double viscosity(const NewtonArgs &A, double th) {
     return A.mu_ref * pow(th / A.theta_ref, A.omega);
 }
 
-// Gaussian elimination with partial pivoting on a 5x5 system (copies J).
-__device__ bool solve5(const double J[5][5], const double b[5], double x[5]) {
+// Gaussian elimination with partial pivoting on a 5x5 system.  Every loop is
+// unrolled so the row exchange is a set of selects on registers.
+__device__ __forceinline__ bool solve5(const double J[5][5], const double b[5], double x[5]) {
     double M[5][6];
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
@@ -73,24 +83,29 @@ __device__ bool solve5(const double J[5][5], const double b[5], double x[5]) {
         for (int j = 0; j < 5; ++j) M[i][j] = J[i][j];
         M[i][5] = b[i];
     }
+    bool ok = true;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        int piv = c;
         double best = fabs(M[c][c]);
+        int piv = c;
 #pragma unroll
         for (int r = c + 1; r < 5; ++r)
             if (fabs(M[r][c]) > best) { best = fabs(M[r][c]); piv = r; }
-        if (!(best > 0.0)) return false;
-#pragma unroll
-        for (int r = c; r < 5; ++r) {
-            if (r == piv && piv != c) {
-#pragma unroll
-                for (int j = 0; j < 6; ++j) { double t = M[c][j]; M[c][j] = M[r][j]; M[r][j] = t; }
-            }
-        }
+        ok = ok && (best > 0.0);
 #pragma unroll
         for (int r = c + 1; r < 5; ++r) {
-            double fct = M[r][c] / M[c][c];
+            const bool sw = (r == piv);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                double a = M[c][j], bb = M[r][j];
+                M[c][j] = sw ? bb : a;
+                M[r][j] = sw ? a : bb;
+            }
+        }
+        const double inv = 1.0 / M[c][c];
+#pragma unroll
+        for (int r = c + 1; r < 5; ++r) {
+            const double fct = M[r][c] * inv;
 #pragma unroll
             for (int j = c; j < 6; ++j) M[r][j] -= fct * M[c][j];
         }
@@ -102,58 +117,53 @@ __device__ bool solve5(const double J[5][5], const double b[5], double x[5]) {
         for (int j = i + 1; j < 5; ++j) s -= M[i][j] * x[j];
         x[i] = s / M[i][i];
     }
-    return true;
+    return ok;
 }
 
-__device__ double norm2_5(const double r[5]) {
+__device__ __forceinline__ double norm2_5(const double r[5]) {
     return sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + r[3] * r[3] + r[4] * r[4]);
 }
-__device__ double normi_5(const double r[5]) {
+__device__ __forceinline__ double normi_5(const double r[5]) {
     double m = 0;
 #pragma unroll
     for (int a = 0; a < 5; ++a) m = fmax(m, fabs(r[a]));
     return m;
 }
 
-// Assemble residual and Jacobian from the raw sums
+// Raw sums over the velocity grid:
 //   S0 = sum wt e, Sc_i = sum wt c_i e, Scc (xx yy zz xy xz yz), Sq = sum wt q e,
 //   Scq_i = sum wt c_i q e, Sc2c_i = sum wt |c|^2 c_i e, Sc2q = sum wt |c|^2 q e.
-// Rows psi = (1, c, |c|^2/2), columns d/dz = (1, c, -q/2).
 struct Sums {
     double S0, Sc[3], Scc[6], Sq, Scq[3], Sc2c[3], Sc2q;
 };
 
-__device__ void assemble(const Sums &s, double r[5], double J[5][5]) {
-    const int ij[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    double c2 = s.Scc[0] + s.Scc[1] + s.Scc[2];
+// Residual and Jacobian; rows psi = (1, c, |c|^2/2), columns d/dz = (1, c, -q/2).
+__device__ __forceinline__ void assemble(const Sums &s, double r[5], double J[5][5]) {
+    const double c2 = s.Scc[0] + s.Scc[1] + s.Scc[2];
     r[0] = s.S0 - 1.0;
     r[1] = s.Sc[0];
     r[2] = s.Sc[1];
     r[3] = s.Sc[2];
     r[4] = 0.5 * c2 - 1.5;
-    J[0][0] = s.S0;
-    for (int j = 0; j < 3; ++j) J[0][1 + j] = s.Sc[j];
-    J[0][4] = -0.5 * s.Sq;
-    for (int i = 0; i < 3; ++i) {
-        J[1 + i][0] = s.Sc[i];
-        for (int j = 0; j < 3; ++j) J[1 + i][1 + j] = s.Scc[ij[i][j]];
-        J[1 + i][4] = -0.5 * s.Scq[i];
-    }
-    J[4][0] = 0.5 * c2;
-    for (int j = 0; j < 3; ++j) J[4][1 + j] = 0.5 * s.Sc2c[j];
+    J[0][0] = s.S0; J[0][1] = s.Sc[0]; J[0][2] = s.Sc[1]; J[0][3] = s.Sc[2]; J[0][4] = -0.5 * s.Sq;
+    J[1][0] = s.Sc[0]; J[1][1] = s.Scc[0]; J[1][2] = s.Scc[3]; J[1][3] = s.Scc[4]; J[1][4] = -0.5 * s.Scq[0];
+    J[2][0] = s.Sc[1]; J[2][1] = s.Scc[3]; J[2][2] = s.Scc[1]; J[2][3] = s.Scc[5]; J[2][4] = -0.5 * s.Scq[1];
+    J[3][0] = s.Sc[2]; J[3][1] = s.Scc[4]; J[3][2] = s.Scc[5]; J[3][3] = s.Scc[2]; J[3][4] = -0.5 * s.Scq[2];
+    J[4][0] = 0.5 * c2; J[4][1] = 0.5 * s.Sc2c[0]; J[4][2] = 0.5 * s.Sc2c[1]; J[4][3] = 0.5 * s.Sc2c[2];
     J[4][4] = -0.25 * s.Sc2q;
 }
 
 // BGK sums by axis factorisation: e = exp(z0) prod_d exp(z_d c_d - z4 c_d^2 / 2).
-__device__ void sums_bgk(const NewtonArgs &A, const double U[3], double st, const double z[5], Sums &s) {
+__device__ void sums_bgk(const NewtonArgs &A, const double U[3], double ist, const double z[5], Sums &s) {
     double m[3][5];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
         const int nv = A.vg.nv[d];
+        const double zd = z[1 + d], hz = 0.5 * z[4];
         for (int i = 0; i < nv; ++i) {
-            double c = (gridu(A.vg, d, i) - U[d]) / st;
-            double w = A.wax[64 * d + i] / st;
-            double ev = w * exp(z[1 + d] * c - 0.5 * z[4] * c * c);
+            const double c = (gridu(A.vg, d, i) - U[d]) * ist;
+            const double ev = A.wax[64 * d + i] * ist * exp(c * (zd - hz * c));
             double t = ev;
             a0 += t; t *= c;
             a1 += t; t *= c;
@@ -163,53 +173,62 @@ __device__ void sums_bgk(const NewtonArgs &A, const double U[3], double st, cons
         }
         m[d][0] = a0; m[d][1] = a1; m[d][2] = a2; m[d][3] = a3; m[d][4] = a4;
     }
-    double K = exp(z[0]) * m[0][0] * m[1][0] * m[2][0];
+    const double K = exp(z[0]) * m[0][0] * m[1][0] * m[2][0];
     double Pn[3][5];
-    for (int d = 0; d < 3; ++d)
-        for (int a = 0; a < 5; ++a) Pn[d][a] = m[d][a] / m[d][0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double inv = 1.0 / m[d][0];
+#pragma unroll
+        for (int a = 0; a < 5; ++a) Pn[d][a] = m[d][a] * inv;
+    }
     s.S0 = K;
+#pragma unroll
     for (int i = 0; i < 3; ++i) s.Sc[i] = K * Pn[i][1];
     s.Scc[0] = K * Pn[0][2]; s.Scc[1] = K * Pn[1][2]; s.Scc[2] = K * Pn[2][2];
     s.Scc[3] = K * Pn[0][1] * Pn[1][1];
     s.Scc[4] = K * Pn[0][1] * Pn[2][1];
     s.Scc[5] = K * Pn[1][1] * Pn[2][1];
     s.Sq = s.Scc[0] + s.Scc[1] + s.Scc[2];
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
         double t = 0;
+#pragma unroll
         for (int mm = 0; mm < 3; ++mm) t += (mm == i) ? Pn[i][3] : Pn[i][1] * Pn[mm][2];
         s.Scq[i] = K * t;
         s.Sc2c[i] = K * t;
     }
     double t4 = 0;
+#pragma unroll
     for (int a = 0; a < 3; ++a)
+#pragma unroll
         for (int b = 0; b < 3; ++b) t4 += (a == b) ? Pn[a][4] : Pn[a][2] * Pn[b][2];
     s.Sc2q = K * t4;
 }
 
-__device__ double wave_sum(double v) {
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
 // ES sums over all velocity nodes: lane-strided, butterfly reduced.
-__device__ void sums_es(const NewtonArgs &A, int lane, const double U[3], double st, double wscale,
+__device__ void sums_es(const NewtonArgs &A, int lane, const double U[3], double ist, double wscale,
                         const double Am[3][3], const double z[5], Sums &s) {
     double acc[18];
 #pragma unroll
     for (int a = 0; a < 18; ++a) acc[a] = 0.0;
     const VGrid &vg = A.vg;
     for (int k = lane; k < vg.nu; k += 64) {
-        int i = k % vg.nv[0], j = (k / vg.nv[0]) % vg.nv[1], l = k / (vg.nv[0] * vg.nv[1]);
-        double c0 = (gridu(vg, 0, i) - U[0]) / st;
-        double c1 = (gridu(vg, 1, j) - U[1]) / st;
-        double c2 = (gridu(vg, 2, l) - U[2]) / st;
-        double q = Am[0][0] * c0 * c0 + Am[1][1] * c1 * c1 + Am[2][2] * c2 * c2 +
-                   2.0 * (Am[0][1] * c0 * c1 + Am[0][2] * c0 * c2 + Am[1][2] * c1 * c2);
-        double w = A.wax[i] * A.wax[64 + j] * A.wax[128 + l] * wscale;
-        double ev = w * exp(z[0] + z[1] * c0 + z[2] * c1 + z[3] * c2 - 0.5 * z[4] * q);
-        double cc = c0 * c0 + c1 * c1 + c2 * c2;
-        double eq_ = ev * q, ec = ev * cc;
+        const int i = k % vg.nv[0], j = (k / vg.nv[0]) % vg.nv[1], l = k / (vg.nv[0] * vg.nv[1]);
+        const double c0 = (gridu(vg, 0, i) - U[0]) * ist;
+        const double c1 = (gridu(vg, 1, j) - U[1]) * ist;
+        const double c2 = (gridu(vg, 2, l) - U[2]) * ist;
+        const double q = Am[0][0] * c0 * c0 + Am[1][1] * c1 * c1 + Am[2][2] * c2 * c2 +
+                         2.0 * (Am[0][1] * c0 * c1 + Am[0][2] * c0 * c2 + Am[1][2] * c1 * c2);
+        const double w = A.wax[i] * A.wax[64 + j] * A.wax[128 + l] * wscale;
+        const double ev = w * exp(z[0] + z[1] * c0 + z[2] * c1 + z[3] * c2 - 0.5 * z[4] * q);
+        const double cc = c0 * c0 + c1 * c1 + c2 * c2;
+        const double eq_ = ev * q, ec = ev * cc;
         acc[0] += ev;
         acc[1] += ev * c0; acc[2] += ev * c1; acc[3] += ev * c2;
         acc[4] += ev * c0 * c0; acc[5] += ev * c1 * c1; acc[6] += ev * c2 * c2;
@@ -220,47 +239,205 @@ __device__ void sums_es(const NewtonArgs &A, int lane, const double U[3], double
         acc[17] += ec * q;
     }
     s.S0 = wave_sum(acc[0]);
+#pragma unroll
     for (int d = 0; d < 3; ++d) s.Sc[d] = wave_sum(acc[1 + d]);
+#pragma unroll
     for (int a = 0; a < 6; ++a) s.Scc[a] = wave_sum(acc[4 + a]);
     s.Sq = wave_sum(acc[10]);
+#pragma unroll
     for (int d = 0; d < 3; ++d) s.Scq[d] = wave_sum(acc[11 + d]);
+#pragma unroll
     for (int d = 0; d < 3; ++d) s.Sc2c[d] = wave_sum(acc[14 + d]);
     s.Sc2q = wave_sum(acc[17]);
 }
 
-// Closed-form eigenvalues of a symmetric 3x3 matrix; returns the smallest.
+// ---- factorised ES sums -------------------------------------------------
+// On a tensor grid the exponent z0 + z.c - z4 c^T A c / 2 splits into one-axis
+// terms and three two-axis cross terms, so e = X(i) Y(j) Z(l) P(i,j) Q(i,l)
+// R(j,l): 3n + 3n^2 exponentials per evaluation instead of n^3; the sums
+// follow from T_e(i,j) = sum_l Z c2^e Q R and the pair sums, reduced over the
+// wave.
+
+
+// Layout of one wave's table region (doubles); rows of the pair tables are
+// padded to an odd length to spread LDS banks.
+struct FactLayout {
+    int n0, n1, n2, ld1, ld2;  // ld1 = row length of P (over j), ld2 of Q and R (over l)
+    int c0, c1, c2, X, Y, Zc, P, Q, R, total;
+};
+
+__host__ __device__ inline FactLayout fact_layout(const VGrid &vg) {
+    FactLayout L;
+    L.n0 = vg.nv[0];
+    L.n1 = vg.nv[1];
+    L.n2 = vg.nv[2];
+    L.ld1 = L.n1 | 1;
+    L.ld2 = L.n2 | 1;
+    int o = 0;
+    L.c0 = o; o += L.n0;
+    L.c1 = o; o += L.n1;
+    L.c2 = o; o += L.n2;
+    L.X = o; o += L.n0;
+    L.Y = o; o += L.n1;
+    L.Zc = o; o += 5 * L.n2;
+    L.P = o; o += L.n0 * L.ld1;
+    L.Q = o; o += L.n0 * L.ld2;
+    L.R = o; o += L.n1 * L.ld2;
+    L.total = o;
+    return L;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Returns false (and leaves s untouched) when a factor exponent exceeds the
+// safe range; the caller then uses the direct sum.
+__device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const double U[3], double ist,
+                             const double Am[3][3], const double z[5], Sums &s) {
+    const VGrid &vg = A.vg;
+    const FactLayout L = fact_layout(vg);
+    const double hz = 0.5 * z[4];
+    double amax = -1e300;
+    lds_wave_sync();  // previous evaluation's readers are done with the tables
+    for (int t = lane; t < L.n0 + L.n1 + L.n2; t += 64) {
+        const int d = t < L.n0 ? 0 : (t < L.n0 + L.n1 ? 1 : 2);
+        const int i = t - (d == 0 ? 0 : (d == 1 ? L.n0 : L.n0 + L.n1));
+        const double c = (gridu(vg, d, i) - U[d]) * ist;
+        double arg = c * (z[1 + d] - hz * Am[d][d] * c);
+        if (d == 0) arg += z[0];
+        amax = fmax(amax, arg);
+        const double v = A.wax[64 * d + i] * ist * exp(arg);
+        if (d == 0) {
+            tb[L.c0 + i] = c;
+            tb[L.X + i] = v;
+        } else if (d == 1) {
+            tb[L.c1 + i] = c;
+            tb[L.Y + i] = v;
+        } else {
+            tb[L.c2 + i] = c;
+            double p = v;
+#pragma unroll
+            for (int e = 0; e < 5; ++e) { tb[L.Zc + 5 * i + e] = p; p *= c; }
+        }
+    }
+    lds_wave_sync();
+    const double k01 = -z[4] * Am[0][1], k02 = -z[4] * Am[0][2], k12 = -z[4] * Am[1][2];
+    const int nP = L.n0 * L.n1, nQ = L.n0 * L.n2, nR = L.n1 * L.n2;
+    for (int t = lane; t < nP + nQ + nR; t += 64) {
+        if (t < nP) {
+            const int i = t % L.n0, j = t / L.n0;
+            const double arg = k01 * tb[L.c0 + i] * tb[L.c1 + j];
+            amax = fmax(amax, arg);
+            tb[L.P + i * L.ld1 + j] = exp(arg);
+        } else if (t < nP + nQ) {
+            const int u = t - nP, i = u % L.n0, l = u / L.n0;
+            const double arg = k02 * tb[L.c0 + i] * tb[L.c2 + l];
+            amax = fmax(amax, arg);
+            tb[L.Q + i * L.ld2 + l] = exp(arg);
+        } else {
+            const int u = t - nP - nQ, j = u % L.n1, l = u / L.n1;
+            const double arg = k12 * tb[L.c1 + j] * tb[L.c2 + l];
+            amax = fmax(amax, arg);
+            tb[L.R + j * L.ld2 + l] = exp(arg);
+        }
+    }
+    lds_wave_sync();
+    if (wave_max(amax) > 600.0) return false;
+    // Per pair (i,j) the c2 dependence is carried by T_e = sum_l Z c2^e Q R;
+    // with q = qa + qb c2 + A22 c2^2 and |c|^2 = r2 + c2^2 (qa, qb, r2 from
+    // c0, c1) every one of the 18 sums is a short combination of T_0..T_4.
+    double acc[18];
+#pragma unroll
+    for (int a = 0; a < 18; ++a) acc[a] = 0.0;
+    const double a00 = Am[0][0], a11 = Am[1][1], a22 = Am[2][2];
+    const double t01 = 2.0 * Am[0][1], t02 = 2.0 * Am[0][2], t12 = 2.0 * Am[1][2];
+    for (int p = lane; p < nP; p += 64) {
+        const int i = p % L.n0, j = p / L.n0;
+        double T0 = 0, T1 = 0, T2 = 0, T3 = 0, T4 = 0;
+        const double *Qi = tb + L.Q + i * L.ld2;
+        const double *Rj = tb + L.R + j * L.ld2;
+        for (int l = 0; l < L.n2; ++l) {
+            const double qr = Qi[l] * Rj[l];
+            const double *zc = tb + L.Zc + 5 * l;
+            T0 += zc[0] * qr; T1 += zc[1] * qr; T2 += zc[2] * qr; T3 += zc[3] * qr; T4 += zc[4] * qr;
+        }
+        const double c0 = tb[L.c0 + i], c1 = tb[L.c1 + j];
+        const double b = tb[L.X + i] * tb[L.Y + j] * tb[L.P + i * L.ld1 + j];
+        const double qa = c0 * (a00 * c0 + t01 * c1) + a11 * c1 * c1, qb = t02 * c0 + t12 * c1;
+        const double r2 = c0 * c0 + c1 * c1;
+        const double q0 = qa * T0 + qb * T1 + a22 * T2;      // sum q
+        const double q1 = qa * T1 + qb * T2 + a22 * T3;      // sum c2 q
+        const double q2 = qa * T2 + qb * T3 + a22 * T4;      // sum c2^2 q
+        const double s2 = r2 * T0 + T2;                      // sum |c|^2
+        acc[0] += b * T0;
+        acc[1] += b * c0 * T0; acc[2] += b * c1 * T0; acc[3] += b * T1;
+        acc[4] += b * c0 * c0 * T0; acc[5] += b * c1 * c1 * T0; acc[6] += b * T2;
+        acc[7] += b * c0 * c1 * T0; acc[8] += b * c0 * T1; acc[9] += b * c1 * T1;
+        acc[10] += b * q0;
+        acc[11] += b * c0 * q0; acc[12] += b * c1 * q0; acc[13] += b * q1;
+        acc[14] += b * c0 * s2; acc[15] += b * c1 * s2; acc[16] += b * (r2 * T1 + T3);
+        acc[17] += b * (r2 * q0 + q2);
+    }
+    s.S0 = wave_sum(acc[0]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s.Sc[d] = wave_sum(acc[1 + d]);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) s.Scc[a] = wave_sum(acc[4 + a]);
+    s.Sq = wave_sum(acc[10]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s.Scq[d] = wave_sum(acc[11 + d]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s.Sc2c[d] = wave_sum(acc[14 + d]);
+    s.Sc2q = wave_sum(acc[17]);
+    return true;
+}
+
+// Smallest eigenvalue of a symmetric 3x3 matrix (closed form, trigonometric).
 __device__ double sym3_min_eig(const double T[3][3]) {
-    double p1 = T[0][1] * T[0][1] + T[0][2] * T[0][2] + T[1][2] * T[1][2];
-    double q = (T[0][0] + T[1][1] + T[2][2]) / 3.0;
+    const double p1 = T[0][1] * T[0][1] + T[0][2] * T[0][2] + T[1][2] * T[1][2];
+    const double q = (T[0][0] + T[1][1] + T[2][2]) / 3.0;
     if (p1 == 0.0) return fmin(T[0][0], fmin(T[1][1], T[2][2]));
-    double p2 = (T[0][0] - q) * (T[0][0] - q) + (T[1][1] - q) * (T[1][1] - q) + (T[2][2] - q) * (T[2][2] - q) + 2.0 * p1;
-    double p = sqrt(p2 / 6.0);
+    const double p2 = (T[0][0] - q) * (T[0][0] - q) + (T[1][1] - q) * (T[1][1] - q) +
+                      (T[2][2] - q) * (T[2][2] - q) + 2.0 * p1;
+    const double p = sqrt(p2 / 6.0);
     double B[3][3];
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) B[i][j] = (T[i][j] - (i == j ? q : 0.0)) / p;
-    double detB = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) - B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
-                  B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
-    double r = fmin(1.0, fmax(-1.0, 0.5 * detB));
-    double phi = acos(r) / 3.0;
+    const double detB = B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+                        B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                        B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0]);
+    const double r = fmin(1.0, fmax(-1.0, 0.5 * detB));
+    const double phi = acos(r) / 3.0;
     return q + 2.0 * p * cos(phi + kTwoPi / 3.0);
 }
 
-__device__ double det3(const double M[3][3]) {
+__device__ __forceinline__ double det3(const double M[3][3]) {
     return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
            M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
 }
 
-__device__ void inv3(const double M[3][3], double R[3][3]) {
-    double d = det3(M);
-    R[0][0] = (M[1][1] * M[2][2] - M[1][2] * M[2][1]) / d;
-    R[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) / d;
-    R[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) / d;
-    R[1][0] = (M[1][2] * M[2][0] - M[1][0] * M[2][2]) / d;
-    R[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) / d;
-    R[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / d;
-    R[2][0] = (M[1][0] * M[2][1] - M[1][1] * M[2][0]) / d;
-    R[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) / d;
-    R[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / d;
+__device__ __forceinline__ void inv3(const double M[3][3], double R[3][3]) {
+    const double d = 1.0 / det3(M);
+    R[0][0] = (M[1][1] * M[2][2] - M[1][2] * M[2][1]) * d;
+    R[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) * d;
+    R[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) * d;
+    R[1][0] = (M[1][2] * M[2][0] - M[1][0] * M[2][2]) * d;
+    R[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) * d;
+    R[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) * d;
+    R[2][0] = (M[1][0] * M[2][1] - M[1][1] * M[2][0]) * d;
+    R[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) * d;
+    R[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) * d;
 }
 
 // Equilibrium record and primitive output from the converged parameters.
@@ -269,22 +446,28 @@ __device__ void write_point(const NewtonArgs &A, int64_t pt, double rho, const d
     double Ai[3][3];
     inv3(Am, Ai);
     double m[3], mAm = 0;
+#pragma unroll
     for (int i = 0; i < 3; ++i) m[i] = (Ai[i][0] * z[1] + Ai[i][1] * z[2] + Ai[i][2] * z[3]) / z[4];
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) mAm += m[i] * Am[i][j] * m[j];
-    double st = sqrt(th);
+    const double st = sqrt(th);
     double *eq = A.eq + pt * kEqW;
     eq[EQ_C0] = log(rho) - 1.5 * log(th) + z[0] + 0.5 * z[4] * mAm;
+#pragma unroll
     for (int d = 0; d < 3; ++d) eq[EQ_V + d] = U[d] + st * m[d];
-    double sc = z[4] / th;
+    const double sc = z[4] / th;
     eq[EQ_B] = sc * Am[0][0]; eq[EQ_B + 1] = sc * Am[1][1]; eq[EQ_B + 2] = sc * Am[2][2];
     eq[EQ_B + 3] = sc * Am[0][1]; eq[EQ_B + 4] = sc * Am[0][2]; eq[EQ_B + 5] = sc * Am[1][2];
     eq[EQ_INVTAU] = inv_tau;
     eq[EQ_RES] = res;
     double *pp = A.prim + pt * 5;
     pp[0] = rho * exp(z[0] + 0.5 * z[4] * mAm) * pow(kTwoPi / z[4], 1.5) / sqrt(det3(Am));
+#pragma unroll
     for (int d = 0; d < 3; ++d) pp[1 + d] = eq[EQ_V + d];
     pp[4] = th / z[4];
+#pragma unroll
     for (int a = 0; a < 5; ++a) A.z[pt * 5 + a] = z[a];
 }
 
@@ -295,24 +478,104 @@ __device__ void write_nonreal(const NewtonArgs &A, int64_t pt) {
     for (int a = 0; a < 5; ++a) { A.prim[pt * 5 + a] = 0.0; A.z[pt * 5 + a] = 0.0; }
 }
 
-// Learned initial guess: MLP on (ln rho, U/u_max, ln theta, u_max/10, n_v/32) -> dz.
-__device__ bool mlp_guess(const NewtonArgs &A, double rho, const double U[3], double th, double z[5]);
+// Per-point outcome; the counters are aggregated afterwards by k_stats_reduce
+// (per-point atomics on a handful of counters would serialise the kernel).
+__device__ void record_stats(const NewtonArgs &A, int64_t pt, int iters, int evals, int status, double res) {
+    if (A.pt_iters) A.pt_iters[pt] = iters;
+    if (A.pt_evals) A.pt_evals[pt] = evals;
+    if (A.pt_status) A.pt_status[pt] = status;
+    if (A.pt_resid) A.pt_resid[pt] = res;
+}
 
-// Newton iteration shared by both kernels.  Sum evaluation is a functor.
+// Histogram of iterations, fallback / ES-guard counts, total evaluations and
+// the largest final residual, aggregated per workgroup in LDS and then added
+// to the handle's counters with one atomic per non-empty bin.
+__global__ __launch_bounds__(256) void k_stats_reduce(int64_t npts, const int32_t *__restrict__ iters,
+                                                      const int32_t *__restrict__ evals,
+                                                      const int32_t *__restrict__ status,
+                                                      const double *__restrict__ resid, unsigned long long *stats,
+                                                      unsigned long long *maxres) {
+    __shared__ unsigned int hist[kHist + 3];
+    __shared__ double rmax[256];
+    for (int i = threadIdx.x; i < kHist + 3; i += 256) hist[i] = 0u;
+    __syncthreads();
+    double m = 0.0;
+    for (int64_t pt = (int64_t)blockIdx.x * 256 + threadIdx.x; pt < npts; pt += (int64_t)gridDim.x * 256) {
+        const int it = iters[pt];
+        atomicAdd(&hist[it < kHist ? (it < 0 ? 0 : it) : kHist - 1], 1u);
+        if (status[pt] == FR_DVM_NEWTON_FALLBACK) atomicAdd(&hist[kHist], 1u);
+        if (status[pt] == FR_DVM_NEWTON_ESGUARD) atomicAdd(&hist[kHist + 1], 1u);
+        atomicAdd(&hist[kHist + 2], (unsigned int)evals[pt]);
+        const double r = resid[pt];
+        if (r >= 0.0 && isfinite(r)) m = fmax(m, r);
+    }
+    rmax[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + o]);
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < kHist + 3; i += 256)
+        if (hist[i]) atomicAdd(&stats[i], (unsigned long long)hist[i]);
+    if (threadIdx.x == 0 && rmax[0] > 0.0) atomicMax(maxres, (unsigned long long)__double_as_longlong(rmax[0]));
+}
+
+// Second starting point besides the cold one (warm or learned), if any.
+__device__ bool alt_start(const NewtonArgs &A, int64_t pt, const double zc[5], double z[5]) {
+    bool ok = false;
+    if (A.guess == FR_DVM_GUESS_WARM) {
+        ok = true;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) { z[a] = A.z[pt * 5 + a]; ok = ok && isfinite(z[a]); }
+    } else if (A.guess == FR_DVM_GUESS_MLP && A.dz_guess) {
+        ok = true;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) { z[a] = zc[a] + (double)A.dz_guess[pt * 5 + a]; ok = ok && isfinite(z[a]); }
+    }
+    return ok && z[4] > 0.0;
+}
+
+// Damped Newton from the better of the cold start and the alternative start.
+// Returns 1 on convergence; z, res, iterations (linear solves) and evals
+// (sum passes) are outputs.
 template <typename SumsFn>
-__device__ int newton_solve(const NewtonArgs &A, SumsFn sums, const double zc[5], double z[5], double &res,
-                            int &iters) {
+__device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const double zc[5], double z[5],
+                            double &res, int &iters, int &evals) {
+    // The state is kept as the 18 raw sums (the Jacobian is assembled from
+    // them right before each solve) to keep register pressure low.
     double r[5], J[5][5];
     Sums s;
+    // the alternative start is tried first; the cold start is evaluated too
+    // only when the alternative is not already close (scaled residual > 1e-2)
+    const bool have_alt = A.guess != FR_DVM_GUESS_COLD && alt_start(A, pt, zc, z);
+    if (!have_alt) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) z[a] = zc[a];
+    }
     sums(z, s);
     assemble(s, r, J);
+    evals = 1;
+    if (have_alt && !(norm2_5(r) <= 1e-2)) {
+        Sums sc;
+        double rc[5], Jc[5][5];
+        sums(zc, sc);
+        assemble(sc, rc, Jc);
+        ++evals;
+        if (!(norm2_5(r) <= norm2_5(rc))) {
+            s = sc;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) { z[a] = zc[a]; r[a] = rc[a]; }
+        }
+    }
     int conv = 0, it;
     for (it = 0; it < A.max_iter; ++it) {
-        double rn = norm2_5(r), ri = normi_5(r);
+        const double rn = norm2_5(r), ri = normi_5(r);
         double rhs[5] = {-r[0], -r[1], -r[2], -r[3], -r[4]}, dz[5];
-        bool ok = solve5(J, rhs, dz);
+        assemble(s, r, J);
+        const bool ok = solve5(J, rhs, dz);
         if (ok && ri <= A.tol) {
             // converged: one extra full step makes the result path independent
+#pragma unroll
             for (int a = 0; a < 5; ++a) z[a] += dz[a];
             res = ri;
             conv = 1;
@@ -320,14 +583,17 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, const double zc[5]
             break;
         }
         if (!ok) break;
-        double alpha = 1.0, zt[5], rt[5], Jt[5][5];
+        double alpha = 1.0, zt[5];
+        Sums st;
         bool acc = false;
         for (int hh = 0; hh < 40; ++hh) {
+#pragma unroll
             for (int a = 0; a < 5; ++a) zt[a] = z[a] + alpha * dz[a];
             if (zt[4] > 0.0) {
-                Sums st;
                 sums(zt, st);
-                assemble(st, rt, Jt);
+                ++evals;
+                const double c2 = st.Scc[0] + st.Scc[1] + st.Scc[2];
+                const double rt[5] = {st.S0 - 1.0, st.Sc[0], st.Sc[1], st.Sc[2], 0.5 * c2 - 1.5};
                 if (norm2_5(rt) < (1.0 - 1e-4 * alpha) * rn) { acc = true; break; }
             }
             alpha *= 0.5;
@@ -337,40 +603,19 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, const double zc[5]
             if (ri <= 100.0 * A.tol) { res = ri; conv = 1; ++it; }
             break;
         }
-        for (int a = 0; a < 5; ++a) {
-            z[a] = zt[a];
-            r[a] = rt[a];
-            for (int b = 0; b < 5; ++b) J[a][b] = Jt[a][b];
-        }
+        s = st;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) z[a] = zt[a];
+        r[0] = s.S0 - 1.0; r[1] = s.Sc[0]; r[2] = s.Sc[1]; r[3] = s.Sc[2];
+        r[4] = 0.5 * (s.Scc[0] + s.Scc[1] + s.Scc[2]) - 1.5;
     }
     iters = it;
     if (!conv) {
         res = normi_5(r);
+#pragma unroll
         for (int a = 0; a < 5; ++a) z[a] = zc[a];
     }
     return conv;
-}
-
-__device__ void record_stats(const NewtonArgs &A, int iters, int status, double res) {
-    atomicAdd(&A.stats[iters < kHist ? iters : kHist - 1], 1ull);
-    if (status == FR_DVM_NEWTON_FALLBACK) atomicAdd(&A.stats[kHist], 1ull);
-    if (status == FR_DVM_NEWTON_ESGUARD) atomicAdd(&A.stats[kHist + 1], 1ull);
-    if (res >= 0.0 && isfinite(res)) atomicMax(A.maxres, (unsigned long long)__double_as_longlong(res));
-}
-
-__device__ bool initial_guess(const NewtonArgs &A, int64_t pt, double rho, const double U[3], double th,
-                              const double zc[5], double z[5]) {
-    for (int a = 0; a < 5; ++a) z[a] = zc[a];
-    if (A.guess == FR_DVM_GUESS_WARM) {
-        double zw[5];
-        bool ok = true;
-        for (int a = 0; a < 5; ++a) { zw[a] = A.z[pt * 5 + a]; ok = ok && isfinite(zw[a]); }
-        if (ok && zw[4] > 0.0) for (int a = 0; a < 5; ++a) z[a] = zw[a];
-    } else if (A.guess == FR_DVM_GUESS_MLP && A.mlp) {
-        double zm[5];
-        if (mlp_guess(A, rho, U, th, zm)) for (int a = 0; a < 5; ++a) z[a] = zc[a] + zm[a];
-    }
-    return true;
 }
 
 __global__ __launch_bounds__(256) void k_newton_bgk(const NewtonArgs A) {
@@ -378,25 +623,26 @@ __global__ __launch_bounds__(256) void k_newton_bgk(const NewtonArgs A) {
     if (pt >= A.npts) return;
     const double *Q = A.Q + pt * A.nmom;
     const double rho = Q[0];
-    double U[3] = {Q[1] / rho, Q[2] / rho, Q[3] / rho};
-    const double th = (2.0 / 3.0) * (Q[4] / rho - 0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
+    const double irho = 1.0 / rho;
+    double U[3] = {Q[1] * irho, Q[2] * irho, Q[3] * irho};
+    const double E = A.nmom == 5 ? Q[4] : 0.5 * (Q[4] + Q[5] + Q[6]);
+    const double th = (2.0 / 3.0) * (E * irho - 0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
     if (!(rho > 0.0) || !(th > 0.0) || !isfinite(rho) || !isfinite(th)) {
         write_nonreal(A, pt);
-        record_stats(A, 0, FR_DVM_NEWTON_NONREAL, -1.0);
+        record_stats(A, pt, 0, 0, FR_DVM_NEWTON_NONREAL, -1.0);
         return;
     }
     const double inv_tau = rho * th / viscosity(A, th);
-    const double st = sqrt(th);
+    const double ist = 1.0 / sqrt(th);
     const double zc[5] = {-1.5 * log(kTwoPi), 0.0, 0.0, 0.0, 1.0};
     double z[5];
-    initial_guess(A, pt, rho, U, th, zc, z);
-    auto fn = [&](const double zz[5], Sums &s) { sums_bgk(A, U, st, zz, s); };
+    auto fn = [&](const double zz[5], Sums &s) { sums_bgk(A, U, ist, zz, s); };
     double res;
-    int iters;
-    int conv = newton_solve(A, fn, zc, z, res, iters);
+    int iters, evals;
+    const int conv = newton_solve(A, fn, pt, zc, z, res, iters, evals);
     const double Am[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     write_point(A, pt, rho, U, th, Am, z, inv_tau, res);
-    record_stats(A, iters, conv ? FR_DVM_NEWTON_OK : FR_DVM_NEWTON_FALLBACK, res);
+    record_stats(A, pt, iters, evals, conv ? FR_DVM_NEWTON_OK : FR_DVM_NEWTON_FALLBACK, res);
 }
 
 __global__ __launch_bounds__(256) void k_newton_es(const NewtonArgs A) {
@@ -405,83 +651,102 @@ __global__ __launch_bounds__(256) void k_newton_es(const NewtonArgs A) {
     if (pt >= A.npts) return;  // whole waves exit together
     const double *Q = A.Q + pt * A.nmom;
     const double rho = Q[0];
-    double U[3] = {Q[1] / rho, Q[2] / rho, Q[3] / rho};
+    const double irho = 1.0 / rho;
+    double U[3] = {Q[1] * irho, Q[2] * irho, Q[3] * irho};
     // raw second moments -> pressure tensor Pi = M2 - rho U U^T
-    double Pi[6] = {Q[4] - rho * U[0] * U[0], Q[5] - rho * U[1] * U[1], Q[6] - rho * U[2] * U[2],
-                    Q[7] - rho * U[0] * U[1], Q[8] - rho * U[0] * U[2], Q[9] - rho * U[1] * U[2]};
+    const double Pi[6] = {Q[4] - rho * U[0] * U[0], Q[5] - rho * U[1] * U[1], Q[6] - rho * U[2] * U[2],
+                          Q[7] - rho * U[0] * U[1], Q[8] - rho * U[0] * U[2], Q[9] - rho * U[1] * U[2]};
     const double th = (Pi[0] + Pi[1] + Pi[2]) / (3.0 * rho);
     if (!(rho > 0.0) || !(th > 0.0) || !isfinite(rho) || !isfinite(th)) {
         if (lane == 0) {
             write_nonreal(A, pt);
-            record_stats(A, 0, FR_DVM_NEWTON_NONREAL, -1.0);
+            record_stats(A, pt, 0, 0, FR_DVM_NEWTON_NONREAL, -1.0);
         }
         return;
     }
     const double Pr = A.Pr;
     const double inv_tau = Pr * rho * th / viscosity(A, th);
-    const double st = sqrt(th);
+    const double ist = 1.0 / sqrt(th);
     double Am[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     int status = FR_DVM_NEWTON_OK;
     {
-        double a1 = th / Pr, a2 = (1.0 - 1.0 / Pr) / rho;
-        double T[3][3] = {{a1 + a2 * Pi[0], a2 * Pi[3], a2 * Pi[4]},
-                          {a2 * Pi[3], a1 + a2 * Pi[1], a2 * Pi[5]},
-                          {a2 * Pi[4], a2 * Pi[5], a1 + a2 * Pi[2]}};
+        const double a1 = th / Pr, a2 = (1.0 - 1.0 / Pr) * irho;
+        const double T[3][3] = {{a1 + a2 * Pi[0], a2 * Pi[3], a2 * Pi[4]},
+                                {a2 * Pi[3], a1 + a2 * Pi[1], a2 * Pi[5]},
+                                {a2 * Pi[4], a2 * Pi[5], a1 + a2 * Pi[2]}};
         if (sym3_min_eig(T) <= 1e-8 * th) {
             status = FR_DVM_NEWTON_ESGUARD;
         } else {
             double Ti[3][3];
             inv3(T, Ti);
+#pragma unroll
             for (int i = 0; i < 3; ++i)
+#pragma unroll
                 for (int j = 0; j < 3; ++j) Am[i][j] = th * Ti[i][j];
         }
     }
     const double zc[5] = {-1.5 * log(kTwoPi) + 0.5 * log(det3(Am)), 0.0, 0.0, 0.0, 1.0};
     double z[5];
-    initial_guess(A, pt, rho, U, th, zc, z);
-    const double wscale = 1.0 / (th * st);
-    auto fn = [&](const double zz[5], Sums &s) { sums_es(A, lane, U, st, wscale, Am, zz, s); };
+    const double wscale = ist * ist * ist;
+    extern __shared__ double es_tables[];
+    double *tb = es_tables + (threadIdx.x >> 6) * (A.use_fact ? fact_layout(A.vg).total : 0);
+    auto fn = [&](const double zz[5], Sums &s) {
+        if (!(A.use_fact && sums_es_fact(A, lane, tb, U, ist, Am, zz, s))) sums_es(A, lane, U, ist, wscale, Am, zz, s);
+    };
     double res;
-    int iters;
-    int conv = newton_solve(A, fn, zc, z, res, iters);
+    int iters, evals;
+    const int conv = newton_solve(A, fn, pt, zc, z, res, iters, evals);
     if (lane == 0) {
         write_point(A, pt, rho, U, th, Am, z, inv_tau, res);
-        record_stats(A, iters, conv ? status : FR_DVM_NEWTON_FALLBACK, res);
+        record_stats(A, pt, iters, evals, conv ? status : FR_DVM_NEWTON_FALLBACK, res);
     }
 }
 
-// MLP: 7 -> H -> H -> H -> 5, SiLU, FP32 weights packed layer by layer as
-// [W (out x in, row major), b (out)], plus 5 output scales and 5 offsets.
-__device__ bool mlp_guess(const NewtonArgs &A, double rho, const double U[3], double th, double z[5]) {
-    const int H = A.mlp_hidden;
-    if (H <= 0 || H > 64) return false;
-    double umax = 0;
-    for (int d = 0; d < 3; ++d) umax = fmax(umax, fmax(fabs(A.vg.umin[d]), fabs(A.vg.umin[d] + (A.vg.nv[d] - 1) * A.vg.du[d])));
-    float x[64], y[64];
+// Size of the discrete-velocity error of the continuous equilibrium, which
+// scales the learned correction: trapezoid aliasing exp(-2 pi^2 theta/du^2)
+// plus truncation by the velocity box exp(-(u_max - |U_d|)^2 / (2 theta)).
+__device__ __forceinline__ double guess_envelope(const double U[3], double th, double umax, double du) {
+    double tr = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double g = fmax(umax - fabs(U[d]), 0.0);
+        tr = fmax(tr, exp(-g * g / (2.0 * th)));
+    }
+    const double s = exp(-0.5 * kTwoPi * kTwoPi * th / (du * du)) + tr;
+    return fmin(fmax(s, 1e-10), 1.0);  // below 1e-10 the correction is Newton round-off
+}
+
+__global__ void k_mlp_scale(int64_t n, const float *__restrict__ env, float *__restrict__ dz) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n * 5) dz[i] *= env[i / 5];
+}
+
+// Features of the learned guess from the moments: [ln rho, U/u_max, ln theta,
+// u_max/10, n_v/32] (FP32) and the correction envelope; non-realizable
+// points get zeros (Newton marks them).
+__global__ void k_mlp_features(int64_t npts, int nmom, const double *__restrict__ Q, double umax, double nv,
+                               double du, float *__restrict__ X, float *__restrict__ env) {
+    const int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pt >= npts) return;
+    const double *q = Q + pt * nmom;
+    const double rho = q[0];
+    const double U[3] = {q[1] / rho, q[2] / rho, q[3] / rho};
+    const double E = nmom == 5 ? q[4] : 0.5 * (q[4] + q[5] + q[6]);
+    const double th = (2.0 / 3.0) * (E / rho - 0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
+    float *x = X + pt * 7;
+    if (!(rho > 0.0) || !(th > 0.0)) {
+        for (int a = 0; a < 7; ++a) x[a] = 0.f;
+        env[pt] = 0.f;
+        return;
+    }
+    env[pt] = (float)guess_envelope(U, th, umax, du);
     x[0] = (float)log(rho);
-    for (int d = 0; d < 3; ++d) x[1 + d] = (float)(U[d] / umax);
+    x[1] = (float)(U[0] / umax);
+    x[2] = (float)(U[1] / umax);
+    x[3] = (float)(U[2] / umax);
     x[4] = (float)log(th);
     x[5] = (float)(umax / 10.0);
-    x[6] = (float)(A.vg.nv[0] / 32.0);
-    const float *w = A.mlp;
-    int nin = 7;
-    for (int layer = 0; layer < 4; ++layer) {
-        int nout = layer == 3 ? 5 : H;
-        const float *W = w, *b = w + nout * nin;
-        for (int o = 0; o < nout; ++o) {
-            float s = b[o];
-            for (int i = 0; i < nin; ++i) s += W[o * nin + i] * x[i];
-            y[o] = layer == 3 ? s : s / (1.0f + __expf(-s));
-        }
-        w = b + nout;
-        for (int o = 0; o < nout; ++o) x[o] = y[o];
-        nin = nout;
-    }
-    for (int a = 0; a < 5; ++a) {
-        z[a] = (double)(x[a] * w[a] + w[5 + a]);
-        if (!isfinite(z[a])) return false;
-    }
-    return true;
+    x[6] = (float)(nv / 32.0);
 }
 
 __global__ void k_collide(const VGrid vg, const double *__restrict__ eqs, const void *fv, void *Sv, int accumulate,
@@ -489,27 +754,29 @@ __global__ void k_collide(const VGrid vg, const double *__restrict__ eqs, const 
     const int64_t pt = blockIdx.x;
     const double *eqp = eqs + pt * kEqW;
     double eq[kEqW];
+#pragma unroll
     for (int a = 0; a < kEqW; ++a) eq[a] = eqp[a];
     for (int k = threadIdx.x; k < vg.nu; k += blockDim.x) {
-        int i = k % vg.nv[0], j = (k / vg.nv[0]) % vg.nv[1], l = k / (vg.nv[0] * vg.nv[1]);
-        double u[3] = {gridu(vg, 0, i), gridu(vg, 1, j), gridu(vg, 2, l)};
-        int64_t idx = pt * vg.nu + k;
+        const int i = k % vg.nv[0], j = (k / vg.nv[0]) % vg.nv[1], l = k / (vg.nv[0] * vg.nv[1]);
+        const double u[3] = {gridu(vg, 0, i), gridu(vg, 1, j), gridu(vg, 2, l)};
+        const int64_t idx = pt * vg.nu + k;
         if (fp64) {
-            double c0 = u[0] - eq[EQ_V], c1 = u[1] - eq[EQ_V + 1], c2 = u[2] - eq[EQ_V + 2];
-            double q = eq[EQ_B] * c0 * c0 + eq[EQ_B + 1] * c1 * c1 + eq[EQ_B + 2] * c2 * c2 +
-                       2.0 * (eq[EQ_B + 3] * c0 * c1 + eq[EQ_B + 4] * c0 * c2 + eq[EQ_B + 5] * c1 * c2);
-            double g = exp(eq[EQ_C0] - 0.5 * q);
-            double f = ((const double *)fv)[idx];
-            double S = (g - f) * eq[EQ_INVTAU];
+            const double c0 = u[0] - eq[EQ_V], c1 = u[1] - eq[EQ_V + 1], c2 = u[2] - eq[EQ_V + 2];
+            const double q = eq[EQ_B] * c0 * c0 + eq[EQ_B + 1] * c1 * c1 + eq[EQ_B + 2] * c2 * c2 +
+                             2.0 * (eq[EQ_B + 3] * c0 * c1 + eq[EQ_B + 4] * c0 * c2 + eq[EQ_B + 5] * c1 * c2);
+            const double g = exp(eq[EQ_C0] - 0.5 * q);
+            const double f = ((const double *)fv)[idx];
+            const double S = (g - f) * eq[EQ_INVTAU];
             double *So = (double *)Sv;
             So[idx] = accumulate ? So[idx] + S : S;
         } else {
-            float c0 = (float)(u[0] - eq[EQ_V]), c1 = (float)(u[1] - eq[EQ_V + 1]), c2 = (float)(u[2] - eq[EQ_V + 2]);
-            float q = (float)eq[EQ_B] * c0 * c0 + (float)eq[EQ_B + 1] * c1 * c1 + (float)eq[EQ_B + 2] * c2 * c2 +
-                      2.0f * ((float)eq[EQ_B + 3] * c0 * c1 + (float)eq[EQ_B + 4] * c0 * c2 + (float)eq[EQ_B + 5] * c1 * c2);
-            float g = __expf((float)eq[EQ_C0] - 0.5f * q);
-            float f = ((const float *)fv)[idx];
-            float S = (g - f) * (float)eq[EQ_INVTAU];
+            const float c0 = (float)(u[0] - eq[EQ_V]), c1 = (float)(u[1] - eq[EQ_V + 1]), c2 = (float)(u[2] - eq[EQ_V + 2]);
+            const float q = (float)eq[EQ_B] * c0 * c0 + (float)eq[EQ_B + 1] * c1 * c1 + (float)eq[EQ_B + 2] * c2 * c2 +
+                            2.0f * ((float)eq[EQ_B + 3] * c0 * c1 + (float)eq[EQ_B + 4] * c0 * c2 +
+                                    (float)eq[EQ_B + 5] * c1 * c2);
+            const float g = __expf((float)eq[EQ_C0] - 0.5f * q);
+            const float f = ((const float *)fv)[idx];
+            const float S = (g - f) * (float)eq[EQ_INVTAU];
             float *So = (float *)Sv;
             So[idx] = accumulate ? So[idx] + S : S;
         }
@@ -517,7 +784,7 @@ __global__ void k_collide(const VGrid vg, const double *__restrict__ eqs, const 
 }
 
 __global__ void k_moments_out(int64_t npts, int nmom, const double *__restrict__ Q, double *__restrict__ out) {
-    int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pt >= npts) return;
     const double *q = Q + pt * nmom;
     double *o = out + pt * 5;
@@ -532,14 +799,16 @@ __global__ __launch_bounds__(1024) void k_totals(int64_t npts, int nmom, const d
     double a[5] = {0, 0, 0, 0, 0};
     for (int64_t pt = threadIdx.x; pt < npts; pt += 1024) {
         const double *q = Q + pt * nmom;
-        double w = wJ[pt];
+        const double w = wJ[pt];
         a[0] += w * q[0]; a[1] += w * q[1]; a[2] += w * q[2]; a[3] += w * q[3];
         a[4] += w * (nmom == 5 ? q[4] : 0.5 * (q[4] + q[5] + q[6]));
     }
+#pragma unroll
     for (int c = 0; c < 5; ++c) red[c][threadIdx.x] = a[c];
     __syncthreads();
     for (int o = 512; o >= 1; o >>= 1) {
         if ((int)threadIdx.x < o)
+#pragma unroll
             for (int c = 0; c < 5; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + o];
         __syncthreads();
     }
@@ -552,10 +821,9 @@ int check(fr_dvm *h, const char *what) {
     return FR_DVM_OK;
 }
 
-}  // namespace
-
-int launch_newton(fr_dvm *h, int guess) {
+NewtonArgs newton_args(fr_dvm *h, int guess) {
     NewtonArgs A;
+    std::memset(&A, 0, sizeof(A));
     A.vg = h->vg;
     A.npts = h->ne * h->ns;
     A.nmom = h->nmom;
@@ -566,7 +834,6 @@ int launch_newton(fr_dvm *h, int guess) {
     A.prim = h->d_prim;
     A.stats = reinterpret_cast<unsigned long long *>(h->d_stats);
     A.maxres = reinterpret_cast<unsigned long long *>(h->d_maxres);
-    A.model = h->prm.model;
     A.Pr = h->prm.prandtl;
     A.mu_ref = h->prm.mu_ref;
     A.theta_ref = h->prm.theta_ref;
@@ -576,15 +843,132 @@ int launch_newton(fr_dvm *h, int guess) {
     A.tol = h->prm.newton_tol;
     A.max_iter = h->prm.newton_max_iter;
     A.guess = (guess == FR_DVM_GUESS_WARM && !h->zvalid) ? FR_DVM_GUESS_COLD : guess;
-    A.mlp = h->d_mlp;
-    A.mlp_hidden = h->mlp_hidden;
+    if (A.guess == FR_DVM_GUESS_MLP && !h->d_mlp) A.guess = FR_DVM_GUESS_COLD;
+    return A;
+}
+
+double grid_umax(const VGrid &vg) {
+    double m = 0;
+    for (int d = 0; d < 3; ++d)
+        m = std::fmax(m, std::fmax(std::fabs(vg.umin[d]), std::fabs(vg.umin[d] + (vg.nv[d] - 1) * vg.du[d])));
+    return m;
+}
+
+// Learned correction dz[n][5] (float) for moment vectors Q[n][nmom], batched
+// through the MLP forward kernels.
+int mlp_predict(fr_dvm *h, const double *Q, int64_t n, int nmom, float *dz) {
+    const int64_t batch = 65536;
+    const int64_t nb = n < batch ? n : batch;
+    const size_t need_x = (size_t)nb * 8, need_w = fr_mlp_workspace_floats(h->mlp_hidden, nb);
+    if (h->mlp_x_n < need_x || h->mlp_work_n < need_w) {
+        if (h->d_mlp_x) (void)hipFree(h->d_mlp_x);
+        if (h->d_mlp_work) (void)hipFree(h->d_mlp_work);
+        h->d_mlp_x = nullptr;
+        h->d_mlp_work = nullptr;
+        if (hipMalloc(&h->d_mlp_x, need_x * sizeof(float)) != hipSuccess ||
+            hipMalloc(&h->d_mlp_work, need_w * sizeof(float)) != hipSuccess)
+            return h->fail(FR_DVM_ENOMEM, "MLP workspace");
+        h->mlp_x_n = need_x;
+        h->mlp_work_n = need_w;
+    }
+    const double umax = grid_umax(h->vg);
+    const double du = std::fmax(h->vg.du[0], std::fmax(h->vg.du[1], h->vg.du[2]));
+    float *env = h->d_mlp_x + (size_t)nb * 7;
+    for (int64_t b0 = 0; b0 < n; b0 += batch) {
+        const int64_t m = (n - b0) < batch ? (n - b0) : batch;
+        hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, h->stream, m, nmom,
+                           Q + b0 * nmom, umax, (double)h->vg.nv[0], du, h->d_mlp_x, env);
+        int rc = fr_mlp_forward(h->mlp_hidden, h->d_mlp, h->d_mlp_x, m, dz + b0 * 5, h->d_mlp_work, h->stream);
+        if (rc) return h->fail(rc, "MLP forward");
+        hipLaunchKernelGGL(k_mlp_scale, dim3((unsigned)((m * 5 + 255) / 256)), dim3(256), 0, h->stream, m, env,
+                           dz + b0 * 5);
+    }
+    return check(h, "MLP features");
+}
+
+int ensure_dz(fr_dvm *h, int64_t n) {
+    if (h->dz_n >= (size_t)n) return FR_DVM_OK;
+    if (h->d_mlp_dz) (void)hipFree(h->d_mlp_dz);
+    h->d_mlp_dz = nullptr;
+    if (hipMalloc(&h->d_mlp_dz, sizeof(float) * 5 * n) != hipSuccess) return h->fail(FR_DVM_ENOMEM, "MLP output");
+    h->dz_n = n;
+    return FR_DVM_OK;
+}
+
+}  // namespace
+
+int launch_newton(fr_dvm *h, int guess) {
+    // learned start where no previous solution exists, warm start afterwards
+    if (guess == FR_DVM_GUESS_MLP_WARM) guess = h->zvalid ? FR_DVM_GUESS_WARM : FR_DVM_GUESS_MLP;
+    NewtonArgs A = newton_args(h, guess);
+    if (A.guess == FR_DVM_GUESS_MLP) {
+        ProfScope ps(h, 3);
+        int rc = ensure_dz(h, A.npts);
+        if (!rc) rc = mlp_predict(h, h->d_Q, A.npts, h->nmom, h->d_mlp_dz);
+        if (rc) return rc;
+        A.dz_guess = h->d_mlp_dz;
+    }
+    A.pt_iters = h->d_pt_iters;
+    A.pt_evals = h->d_pt_evals;
+    A.pt_status = h->d_pt_status;
+    A.pt_resid = h->d_pt_resid;
+    ProfScope ps(h, 1);
     if (h->prm.model == FR_DVM_ESBGK) {
-        hipLaunchKernelGGL(k_newton_es, dim3((unsigned)((A.npts + 3) / 4)), dim3(256), 0, h->stream, A);
+        const size_t shm = 4 * sizeof(double) * (size_t)fact_layout(h->vg).total;
+        A.use_fact = (shm <= 65536) && !h->es_direct;
+        hipLaunchKernelGGL(k_newton_es, dim3((unsigned)((A.npts + 3) / 4)), dim3(256), A.use_fact ? shm : 0,
+                           h->stream, A);
     } else {
         hipLaunchKernelGGL(k_newton_bgk, dim3((unsigned)((A.npts + 255) / 256)), dim3(256), 0, h->stream, A);
     }
+    int64_t nb = (A.npts + 256 * 16 - 1) / (256 * 16);
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)nb), dim3(256), 0, h->stream, A.npts, A.pt_iters, A.pt_evals,
+                       A.pt_status, A.pt_resid, A.stats, A.maxres);
     h->zvalid = 1;
     return check(h, "newton kernel");
+}
+
+// Newton on caller-supplied moment vectors (BGK form), for training targets
+// and guess evaluation.  Scratch records are allocated per call.
+int launch_newton_points(fr_dvm *h, const double *Q, int64_t n, int guess, double *z, int32_t *iters,
+                         int32_t *evals, int32_t *status, double *resid) {
+    if (n <= 0) return FR_DVM_OK;
+    if (guess == FR_DVM_GUESS_MLP && !h->d_mlp) return h->fail(FR_DVM_EINVAL, "no MLP weights set");
+    NewtonArgs A = newton_args(h, guess == FR_DVM_GUESS_MLP ? FR_DVM_GUESS_MLP : FR_DVM_GUESS_COLD);
+    double *eq = nullptr, *prim = nullptr, *zz = nullptr;
+    if (hipMalloc(&eq, sizeof(double) * kEqW * n) != hipSuccess || hipMalloc(&prim, sizeof(double) * 5 * n) != hipSuccess ||
+        (!z && hipMalloc(&zz, sizeof(double) * 5 * n) != hipSuccess)) {
+        if (eq) (void)hipFree(eq);
+        if (prim) (void)hipFree(prim);
+        return h->fail(FR_DVM_ENOMEM, "equilibrium scratch");
+    }
+    int rc = FR_DVM_OK;
+    if (A.guess == FR_DVM_GUESS_MLP) {
+        rc = ensure_dz(h, n);
+        if (!rc) rc = mlp_predict(h, Q, n, 5, h->d_mlp_dz);
+        A.dz_guess = h->d_mlp_dz;
+    }
+    if (!rc) {
+        A.npts = n;
+        A.nmom = 5;
+        A.Q = Q;
+        A.eq = eq;
+        A.prim = prim;
+        A.z = z ? z : zz;
+        A.pt_iters = iters;
+        A.pt_evals = evals;
+        A.pt_status = status;
+        A.pt_resid = resid;
+        if (!(A.mu_ref > 0)) A.mu_ref = 1.0;  // tau is not an output here
+        hipLaunchKernelGGL(k_newton_bgk, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, A);
+        rc = check(h, "newton kernel");
+    }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(eq);
+    (void)hipFree(prim);
+    if (zz) (void)hipFree(zz);
+    return rc;
 }
 
 int launch_collide(fr_dvm *h, const void *f, void *S, int accumulate) {
@@ -601,14 +985,14 @@ int launch_prim_out(fr_dvm *h, double *Qp) {
 }
 
 int launch_moments_out(fr_dvm *h, double *Q) {
-    int64_t npts = h->ne * h->ns;
+    const int64_t npts = h->ne * h->ns;
     hipLaunchKernelGGL(k_moments_out, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, h->stream, npts, h->nmom,
                        h->d_Q, Q);
     return check(h, "moments output kernel");
 }
 
 int launch_totals(fr_dvm *h, double *host_tot) {
-    int64_t npts = h->ne * h->ns;
+    const int64_t npts = h->ne * h->ns;
     hipLaunchKernelGGL(k_totals, dim3(1), dim3(1024), 0, h->stream, npts, h->nmom, h->d_Q, h->d_wq3J, h->d_tot);
     int rc = check(h, "totals kernel");
     if (rc) return rc;

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -256,10 +257,10 @@ extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vg
         for (int i = 0; i < vg.nv[d]; ++i) wax[64 * d + i] = h->wax[d][i];
     if ((rc = dev_alloc(h, &h->d_wax, 3 * 64))) return bail(rc);
     if ((rc = upload(h, h->d_wax, wax.data(), wax.size() * sizeof(double)))) return bail(rc);
-    if ((rc = dev_alloc(h, &h->d_stats, kHist + 2))) return bail(rc);
+    if ((rc = dev_alloc(h, &h->d_stats, kHist + 4))) return bail(rc);
     if ((rc = dev_alloc(h, &h->d_maxres, 1))) return bail(rc);
     if ((rc = dev_alloc(h, &h->d_tot, 8))) return bail(rc);
-    hipMemset(h->d_stats, 0, (kHist + 2) * sizeof(int64_t));
+    hipMemset(h->d_stats, 0, (kHist + 4) * sizeof(int64_t));
     hipMemset(h->d_maxres, 0, sizeof(double));
     *out = h;
     return FR_DVM_OK;
@@ -273,7 +274,7 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     if (!(p->mu_ref > 0) && p->model != FR_DVM_FREE) return h->fail(FR_DVM_EINVAL, "mu_ref must be positive");
     if (p->newton_max_iter < 1 || p->newton_max_iter > 200) return h->fail(FR_DVM_EINVAL, "newton_max_iter out of range");
     if (p->rk != FR_DVM_SSPRK3 && p->rk != FR_DVM_LSRK3_2N) return h->fail(FR_DVM_EINVAL, "unknown RK scheme");
-    if (p->guess < 0 || p->guess > 2) return h->fail(FR_DVM_EINVAL, "unknown guess mode");
+    if (p->guess < 0 || p->guess > 3) return h->fail(FR_DVM_EINVAL, "unknown guess mode");
     bool realloc_all = !h->have_params || p->precision != h->prm.precision;
     int nmom = (p->model == FR_DVM_ESBGK) ? 10 : 5;
     bool realloc_mom = !h->have_params || nmom != h->nmom;
@@ -296,11 +297,17 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
         if ((rc = dev_alloc(h, &h->d_eq, npts * kEqW))) return rc;
         if ((rc = dev_alloc(h, &h->d_z, npts * 5))) return rc;
         if ((rc = dev_alloc(h, &h->d_prim, npts * 5))) return rc;
+        if ((rc = dev_alloc(h, &h->d_pt_iters, npts))) return rc;
+        if ((rc = dev_alloc(h, &h->d_pt_evals, npts))) return rc;
+        if ((rc = dev_alloc(h, &h->d_pt_status, npts))) return rc;
+        if ((rc = dev_alloc(h, &h->d_pt_resid, npts))) return rc;
         h->zvalid = 0;
     }
     if (realloc_mom) {
         if ((rc = dev_alloc(h, &h->d_Q, npts * nmom))) return rc;
-        h->nu_pad = (int)((nu + kBlock - 1) / kBlock * kBlock);
+        // padded past the last chunk of every kernel (chunks of at most 256
+        // velocities), zero weights beyond nu
+        h->nu_pad = (int)((nu + kBlock - 1) / kBlock * kBlock + kBlock);
         std::vector<double> wpsi((size_t)h->nu_pad * nmom, 0.0);
         const VGrid &vg = h->vg;
         for (int64_t k = 0; k < nu; ++k) {
@@ -319,6 +326,10 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
         if ((rc = dev_alloc(h, &h->d_wpsi, wpsi.size()))) return rc;
         if ((rc = upload(h, h->d_wpsi, wpsi.data(), wpsi.size() * sizeof(double)))) return rc;
     }
+    // verification switch: FRDVM_ES_DIRECT=1 makes the ES Newton use the
+    // direct per-node sums instead of the factorised ones
+    const char *ev = std::getenv("FRDVM_ES_DIRECT");
+    h->es_direct = ev && ev[0] == '1';
     h->have_params = true;
     return FR_DVM_OK;
 }
@@ -371,8 +382,14 @@ extern "C" void fr_dvm_destroy(fr_dvm_t h) {
     if (!h) return;
     if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
     void *ptrs[] = {h->d_gfac, h->d_nbr, h->d_wq3J, h->d_wpsi, h->d_wax, h->d_reg, h->d_tr[0], h->d_tr[1],
-                    h->d_Q, h->d_eq, h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp};
+                    h->d_Q, h->d_eq, h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
+                    h->d_mlp_x, h->d_mlp_work, h->d_mlp_dz, h->d_pt_iters, h->d_pt_evals, h->d_pt_status,
+                    h->d_pt_resid};
     for (void *p : ptrs)
         if (p) hipFree(p);
+    for (auto &r : h->prof_recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
     delete h;
 }

@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fr_dvm.h")
 
 BGK, ESBGK, FREE = 0, 1, 2
 FP64, FP32 = 0, 1
-GUESS_COLD, GUESS_WARM, GUESS_MLP = 0, 1, 2
+GUESS_COLD, GUESS_WARM, GUESS_MLP, GUESS_MLP_WARM = 0, 1, 2, 3
 SSPRK3, LSRK3_2N = 0, 1
 NEWTON_OK, NEWTON_FALLBACK, NEWTON_NONREAL, NEWTON_ESGUARD = 0, 1, 2, 3
 
@@ -71,8 +71,17 @@ def lib():
         L.fr_dvm_moments.argtypes = [vp, vp, vp, dp]
         L.fr_dvm_rk_step.argtypes = [vp, vp, C.c_double]
         L.fr_dvm_rk_steps.argtypes = [vp, vp, C.c_double, C.c_int]
-        L.fr_dvm_newton_stats.argtypes = [vp, i64p, i64p, i64p, dp, C.c_int]
+        L.fr_dvm_newton_stats.argtypes = [vp, i64p, i64p, i64p, i64p, dp, C.c_int]
         L.fr_dvm_mlp_set_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
+        L.fr_dvm_equilibrium.argtypes = [vp, vp, C.c_int64, C.c_int, vp, vp, vp, vp, vp]
+        L.fr_mlp_param_count.argtypes = [C.c_int]
+        L.fr_mlp_param_count.restype = C.c_size_t
+        L.fr_mlp_workspace_floats.argtypes = [C.c_int, C.c_int64]
+        L.fr_mlp_workspace_floats.restype = C.c_size_t
+        L.fr_mlp_forward.argtypes = [C.c_int, vp, vp, C.c_int64, vp, vp, vp]
+        L.fr_mlp_grad.argtypes = [C.c_int, vp, vp, vp, C.c_int64, vp, vp, vp, vp]
+        L.fr_mlp_adam.argtypes = [C.c_int, vp, vp, vp, vp, C.c_int, C.c_float, vp]
+        L.fr_dvm_hbm_copy.argtypes = [vp, vp, C.c_size_t, vp]
         L.fr_dvm_profile.argtypes = [vp, C.c_int]
         L.fr_dvm_profile_read.argtypes = [vp, dp, i64p, C.c_int]
         L.fr_dvm_last_error.argtypes = [vp]
@@ -83,10 +92,61 @@ def lib():
     return _lib
 
 
+HEADERS = [HEADER, os.path.join(os.path.dirname(_HERE), "include", "fr_dvm_mlp.h")]
+
+
 def header_functions() -> list[str]:
-    """Names of the functions declared in include/fr_dvm.h."""
-    txt = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(fr_dvm_[a-z0-9_]+)\s*\(", txt)))
+    """Names of the functions declared in include/*.h."""
+    names = set()
+    for h in HEADERS:
+        names |= set(re.findall(r"\b(fr_(?:dvm|mlp)_[a-z0-9_]+)\s*\(", open(h).read()))
+    return sorted(names)
+
+
+def hbm_copy(dst, src, nbytes, stream=None):
+    """Plain device-to-device copy kernel of the library (bandwidth probe)."""
+    s = getattr(stream, "cuda_stream", stream) or 0
+    rc = lib().fr_dvm_hbm_copy(_ptr(dst), _ptr(src), int(nbytes), C.c_void_p(int(s)))
+    if rc != 0:
+        raise FrDvmError(f"fr_dvm_hbm_copy failed ({rc})")
+
+
+class Mlp:
+    """The learned-guess network's GPU kernels (include/fr_dvm_mlp.h)."""
+
+    def __init__(self, H: int = 64):
+        self.H = int(H)
+        self.n = int(lib().fr_mlp_param_count(self.H))
+
+    def workspace(self, B: int):
+        import torch
+        return torch.empty(int(lib().fr_mlp_workspace_floats(self.H, int(B))), dtype=torch.float32, device="cuda")
+
+    def forward(self, w, X, out=None, work=None):
+        import torch
+        B = X.shape[0]
+        out = torch.empty((B, 5), dtype=torch.float32, device="cuda") if out is None else out
+        work = self.workspace(B) if work is None else work
+        rc = lib().fr_mlp_forward(self.H, _ptr(w), _ptr(X), B, _ptr(out), _ptr(work), None)
+        if rc != 0:
+            raise FrDvmError(f"fr_mlp_forward failed ({rc})")
+        return out
+
+    def grad(self, w, X, T, grad=None, loss=None, work=None):
+        import torch
+        B = X.shape[0]
+        grad = torch.empty(self.n, dtype=torch.float32, device="cuda") if grad is None else grad
+        loss = torch.empty(1, dtype=torch.float32, device="cuda") if loss is None else loss
+        work = self.workspace(B) if work is None else work
+        rc = lib().fr_mlp_grad(self.H, _ptr(w), _ptr(X), _ptr(T), B, _ptr(grad), _ptr(loss), _ptr(work), None)
+        if rc != 0:
+            raise FrDvmError(f"fr_mlp_grad failed ({rc})")
+        return grad, loss
+
+    def adam(self, w, g, m, v, step, lr):
+        rc = lib().fr_mlp_adam(self.H, _ptr(w), _ptr(g), _ptr(m), _ptr(v), int(step), float(lr), None)
+        if rc != 0:
+            raise FrDvmError(f"fr_mlp_adam failed ({rc})")
 
 
 def _ptr(t):
@@ -250,10 +310,29 @@ class FrDvm:
 
     def newton_stats(self, reset=False):
         hist = np.zeros(64, np.int64)
-        nf, ng, mr = C.c_int64(), C.c_int64(), C.c_double()
+        nf, ng, ne, mr = C.c_int64(), C.c_int64(), C.c_int64(), C.c_double()
         self._check(lib().fr_dvm_newton_stats(self._h, hist.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(nf),
-                                              C.byref(ng), C.byref(mr), int(bool(reset))), "fr_dvm_newton_stats")
-        return {"hist": hist, "n_fallback": nf.value, "n_guard": ng.value, "max_resid": mr.value}
+                                              C.byref(ng), C.byref(ne), C.byref(mr), int(bool(reset))),
+                    "fr_dvm_newton_stats")
+        return {"hist": hist, "n_fallback": nf.value, "n_guard": ng.value, "n_evals": ne.value,
+                "max_resid": mr.value}
+
+    def equilibrium(self, Q, guess=GUESS_COLD):
+        """FP64 Newton for the conservative equilibria of moment vectors Q[n][5]
+        (device float64) on this handle's grid: returns z[n][5], iterations
+        (linear solves), evaluations (sum passes), status and final scaled
+        residuals (device tensors)."""
+        import torch
+        n = Q.shape[0]
+        self._check_d(Q, n * 5, "Q")
+        z = torch.empty((n, 5), dtype=torch.float64, device="cuda")
+        it = torch.empty(n, dtype=torch.int32, device="cuda")
+        ev = torch.empty(n, dtype=torch.int32, device="cuda")
+        st = torch.empty(n, dtype=torch.int32, device="cuda")
+        res = torch.empty(n, dtype=torch.float64, device="cuda")
+        self._check(lib().fr_dvm_equilibrium(self._h, _ptr(Q), n, int(guess), _ptr(z), _ptr(it), _ptr(ev), _ptr(st),
+                                             _ptr(res)), "fr_dvm_equilibrium")
+        return z, it, ev, st, res
 
     def profile(self, enable=True):
         self._check(lib().fr_dvm_profile(self._h, int(bool(enable))), "fr_dvm_profile")

@@ -1,0 +1,145 @@
+"""Learned initial guess for the conservative-equilibrium Newton solve.
+
+Training data are states the solver itself produces: for each macroscopic
+state the library's FP64 Newton (``fr_dvm_equilibrium``, cold start) gives the
+converged unknowns z*; the network learns dz = z* - z_cold from the features
+[ln rho, U/u_max, ln theta, u_max/10, n_v/32].  Forward, backward and Adam
+run in the library's HIP kernels (``fr_mlp_*``); this module only batches
+tensors and calls them.  At use, ``FrDvm.mlp_set_weights`` loads the network
+into the Newton kernel, which starts from z_cold + dz and still iterates to
+the FP64 tolerance (falling back to the cold start if the guess fails).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import frdvm
+
+Z_COLD = np.array([-1.5 * math.log(2 * math.pi), 0.0, 0.0, 0.0, 1.0])
+
+
+def _grid(umax: float, nv: int) -> dict:
+    return {"n": (nv, nv, nv), "umin": (-umax,) * 3, "umax": (umax,) * 3}
+
+
+def handle_for_grid(umax: float, nv: int, tol=1e-13, max_iter=100):
+    """A one-element handle whose only purpose is its velocity grid."""
+    import workloads as W
+    return frdvm.FrDvm(W.box_mesh(1), 1, _grid(umax, nv),
+                       {"model": frdvm.BGK, "mu_ref": 1.0, "newton_tol": tol, "newton_max_iter": max_iter})
+
+
+def features(rho, U, theta, umax, nv):
+    """Network inputs as float32 (the same formula the Newton kernel uses)."""
+    import torch
+    rho = torch.as_tensor(rho, dtype=torch.float64)
+    U = torch.as_tensor(U, dtype=torch.float64)
+    th = torch.as_tensor(theta, dtype=torch.float64)
+    um = torch.as_tensor(umax, dtype=torch.float64).reshape(-1, 1).expand(rho.shape[0], 1)
+    X = torch.cat([rho.log()[:, None], U / um, th.log()[:, None], um / 10.0,
+                   torch.full_like(um, nv / 32.0)], 1)
+    return X.float()
+
+
+def envelope(U, theta, umax, nv):
+    """Size of the discrete-velocity error of the continuous equilibrium on
+    the closed grid [-u_max, u_max]^3 with nv nodes per axis: trapezoid
+    aliasing exp(-2 pi^2 theta / du^2) plus truncation by the box
+    max_d exp(-(u_max - |U_d|)^2 / (2 theta)).  The network predicts the
+    Newton correction in units of this envelope (the same formula runs in the
+    feature kernel of the library)."""
+    U = np.asarray(U, np.float64)
+    th = np.asarray(theta, np.float64)
+    um = np.asarray(umax, np.float64)
+    du = 2.0 * um / (nv - 1)
+    gap = np.clip(um[:, None] - np.abs(U), 0.0, None)
+    tr = np.exp(-gap ** 2 / (2.0 * th[:, None])).max(1)
+    s = np.exp(-2.0 * math.pi ** 2 * th / du ** 2) + tr
+    return np.clip(s, 1e-10, 1.0)  # below 1e-10 the correction is Newton round-off
+
+
+def solve_targets(states: dict, nv: int = 32, guess=frdvm.GUESS_COLD, handles=None, weights=None):
+    """FP64 Newton on the GPU for every state (grouped by u_max).  Returns a
+    dict of numpy arrays: z* [n,5], iters (linear solves), evals (sum
+    passes), status, resid."""
+    import torch
+    import workloads as W
+    n = len(states["rho"])
+    out = {"z": np.zeros((n, 5)), "iters": np.zeros(n, np.int32), "evals": np.zeros(n, np.int32),
+           "status": np.zeros(n, np.int32), "resid": np.zeros(n)}
+    Q = W.state_moments(states["rho"], states["U"], states["theta"])
+    for um in np.unique(states["umax"]):
+        idx = np.nonzero(states["umax"] == um)[0]
+        h = handles[float(um)] if handles else handle_for_grid(float(um), nv)
+        if weights is not None:
+            h.mlp_set_weights(weights)
+        Qd = torch.as_tensor(Q[idx], dtype=torch.float64, device="cuda").contiguous()
+        res = h.equilibrium(Qd, guess)
+        for key, t in zip(("z", "iters", "evals", "status", "resid"), res):
+            out[key][idx] = t.cpu().numpy()
+    return out
+
+
+def train(X, T, H=64, steps=3000, batch=4096, lr=1e-3, seed=4, log_every=0):
+    """Adam on the GPU with cosine learning-rate decay.  X [n,7], T [n,5]
+    (unnormalised dz) float32 CUDA tensors.  Returns the flat weights (CUDA
+    float32, with the target z-score folded into the output affine) and the
+    loss history."""
+    import torch
+    mean = T.mean(0)
+    std = T.std(0).clamp_min(1e-12)
+    Tn = ((T - mean) / std).contiguous()
+    net = frdvm.Mlp(H)
+    rng = np.random.default_rng(seed)
+    w0 = np.zeros(net.n, np.float32)
+    o = 0
+    for (m, k) in [(H, 7), (H, H), (H, H), (5, H)]:
+        lim = math.sqrt(6.0 / k)
+        w0[o:o + m * k] = rng.uniform(-lim, lim, m * k)
+        o += m * k + m
+    w0[o:o + 5] = std.cpu().numpy()
+    w0[o + 5:o + 10] = mean.cpu().numpy()
+    w = torch.as_tensor(w0, device="cuda")
+    m1 = torch.zeros_like(w)
+    m2 = torch.zeros_like(w)
+    n = X.shape[0]
+    B = min(batch, n)
+    work = net.workspace(B)
+    g = torch.empty_like(w)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    hist = []
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, n, (B,), generator=gen, device="cuda")
+        xb = X[idx].contiguous()
+        tb = Tn[idx].contiguous()
+        net.grad(w, xb, tb, g, loss, work)
+        lr_t = lr * 0.5 * (1 + math.cos(math.pi * (step - 1) / steps))
+        net.adam(w, g, m1, m2, step, lr_t)
+        if log_every and (step % log_every == 0 or step == 1):
+            hist.append((step, float(loss.item())))
+    return w, hist
+
+
+def fit_guess(n_states=100_000, nv=32, H=64, steps=3000, seed=4, umax_choices=(6.0, 10.0, 14.0), extra=None):
+    """Generate states, solve them, train the network.  `extra` may add
+    solver-harvested states (dict of arrays rho, U, theta, umax).  Returns
+    (weights as numpy float32, info dict)."""
+    import torch
+    import workloads as W
+    st = W.sample_states(n_states, seed=seed, umax_choices=umax_choices, nv=nv)
+    if extra is not None:
+        for k in ("rho", "U", "theta", "umax"):
+            st[k] = np.concatenate([st[k], extra[k]])
+    sol = solve_targets(st, nv=nv)
+    ok = sol["status"] == frdvm.NEWTON_OK
+    X = features(st["rho"][ok], st["U"][ok], st["theta"][ok], st["umax"][ok], nv).cuda()
+    env = envelope(st["U"][ok], st["theta"][ok], st["umax"][ok], nv)
+    T = torch.as_tensor((sol["z"][ok] - Z_COLD) / env[:, None], dtype=torch.float32, device="cuda")
+    w, hist = train(X, T, H=H, steps=steps, seed=seed, log_every=max(steps // 10, 1))
+    info = {"n_states": int(len(ok)), "n_converged": int(ok.sum()), "reject_rate": float(st["reject_rate"]),
+            "cold_mean_iters": float(sol["iters"][ok].mean()), "loss_history": hist}
+    return w.cpu().numpy(), info

@@ -205,6 +205,60 @@ def maxwellian(prim, grid: dict, dtype=None, device="cpu", chunk_pts: int = 1 <<
 
 
 # --------------------------------------------------------------------------
+# Macroscopic states for the learned Newton guess
+# --------------------------------------------------------------------------
+
+def lattice_min_variance(U: np.ndarray, umax: float, nv: int) -> np.ndarray:
+    """Smallest sum over axes of the variance a non-negative distribution on
+    the closed uniform grid [-umax, umax] can have at mean velocity U: all
+    mass on the two nodes bracketing U_d, i.e. (U_d - u_i)(u_{i+1} - U_d)."""
+    du = 2 * umax / (nv - 1)
+    i = np.clip(np.floor((U + umax) / du), 0, nv - 2)
+    lo = -umax + i * du
+    return ((U - lo) * (lo + du - U)).sum(-1)
+
+
+def sample_states(n: int, seed: int = 4, umax_choices=(6.0, 10.0, 14.0), nv: int = 32, margin: float = 1.05):
+    """Seeded macroscopic states: rho log-normal (sigma 1), |U| uniform up to
+    0.8 u_max with a uniform direction, theta log-uniform on [0.1, 4], u_max
+    drawn from umax_choices.  States whose temperature is within `margin` of
+    the lattice bound 3 theta > min variance (not attainable by any positive
+    distribution on the grid) are rejected and redrawn.
+    Returns dict of arrays rho[n], U[n,3], theta[n], umax[n], and the
+    rejection rate."""
+    rng = np.random.default_rng(seed)
+    out = {"rho": [], "U": [], "theta": [], "umax": []}
+    drawn = kept = n_ok = 0
+    while kept < n:
+        m = 2 * (n - kept) + 16
+        rho = np.exp(rng.standard_normal(m))
+        d = rng.standard_normal((m, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        um = rng.choice(np.asarray(umax_choices, float), m)
+        U = d * (rng.uniform(0, 0.8, m) * um)[:, None]
+        th = np.exp(rng.uniform(np.log(0.1), np.log(4.0), m))
+        ok = np.array([3 * th[i] > margin * lattice_min_variance(U[i], um[i], nv) for i in range(m)])
+        drawn += m
+        n_ok += int(ok.sum())
+        take = np.nonzero(ok)[0][: n - kept]
+        for k, v in (("rho", rho), ("U", U), ("theta", th), ("umax", um)):
+            out[k].append(v[take])
+        kept += len(take)
+    res = {k: np.concatenate(v) for k, v in out.items()}
+    res["reject_rate"] = 1.0 - n_ok / drawn
+    return res
+
+
+def state_moments(rho, U, theta):
+    """Q = (rho, rho U, rho |U|^2 / 2 + 3/2 rho theta) of the continuous state."""
+    rho = np.asarray(rho)
+    U = np.asarray(U)
+    th = np.asarray(theta)
+    E = 0.5 * rho * (U * U).sum(-1) + 1.5 * rho * th
+    return np.concatenate([rho[:, None], rho[:, None] * U, E[:, None]], 1)
+
+
+# --------------------------------------------------------------------------
 # Named workloads (the shapes of the paper's runs, scaled to one GPU)
 # --------------------------------------------------------------------------
 
