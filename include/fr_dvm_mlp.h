@@ -8,8 +8,11 @@
  * starting point of that Newton solve; Newton stays the judge of the
  * residual and falls back to the cold start when the prediction fails.
  *
- * Network: 7 -> H -> H -> H -> 5, SiLU on the hidden layers, FP32.
- *   inputs  x = [ln rho, U/u_max (3), ln theta, u_max/10, n_v/32]
+ * Network: 13 -> H -> H -> H -> 5, SiLU on the hidden layers, FP32.
+ *   inputs  x = [ln rho, U/u_max (3), ln theta, u_max/10, n_v/32,
+ *                sin phi (3), cos phi (3)],  phi_d = 2 pi (U_d - umin_d)/du_d:
+ *   the phase of the bulk velocity against the grid, on which the trapezoid
+ *   aliasing error of a Gaussian depends periodically (Poisson summation)
  *   outputs y (normalised); prediction dz = y * scale + offset is added to
  *   the cold Newton unknowns z_cold = (-3/2 ln 2 pi, 0, 0, 0, 1) (BGK frame
  *   c = (u-U)/sqrt(theta)).
@@ -19,7 +22,7 @@
  * All arrays are caller-owned DEVICE float arrays unless stated; every call
  * is asynchronous on `stream` (a hipStream_t passed as void*, may be NULL).
  * Return: 0 or a negative FR_DVM_E* code (fr_dvm.h).  Batches are row
- * major: X[B][7], T[B][5].  GEMMs run on MFMA (v_mfma_f32_16x16x4_f32).
+ * major: X[B][FR_MLP_INPUTS], T[B][5].  GEMMs run on MFMA (v_mfma_f32_16x16x4_f32).
  */
 #ifndef FR_DVM_MLP_H
 #define FR_DVM_MLP_H
@@ -28,6 +31,8 @@
 #include <stdint.h>
 
 #include "fr_dvm.h"
+
+#define FR_MLP_INPUTS 13
 
 #ifdef __cplusplus
 extern "C" {
@@ -39,7 +44,7 @@ size_t fr_mlp_param_count(int H);
 /* Floats of scratch memory the forward / gradient calls need for a batch. */
 size_t fr_mlp_workspace_floats(int H, int64_t B);
 
-/* Prediction dz[B][5] (denormalised) for features X[B][7]. */
+/* Prediction dz[B][5] (denormalised) for features X[B][FR_MLP_INPUTS]. */
 int fr_mlp_forward(int H, const float *w, const float *X, int64_t B, float *dz, float *work, void *stream);
 
 /* Mean-squared-error loss L = 1/(2B) sum |y - T|^2 on normalised targets T,

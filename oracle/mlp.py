@@ -1,6 +1,6 @@
 """FP64 reference of the learned Newton initial guess (test infrastructure).
 
-A multilayer perceptron 7 -> H -> H -> H -> 5 with SiLU activations maps
+A multilayer perceptron 13 -> H -> H -> H -> 5 with SiLU activations maps
 per-point features of the macroscopic state and velocity grid to the
 correction of the Newton unknowns z over the cold guess (the continuous
 equilibrium of the moments).  The paper solves the conservative-equilibrium
@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-N_IN, N_OUT = 7, 5
+N_IN, N_OUT = 13, 5
 
 
 def n_params(H: int) -> int:
@@ -119,10 +119,17 @@ def adam_update(w, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def features(rho, U, theta, umax, nv):
-    """Network inputs: [ln rho, U/u_max (3), ln theta, u_max/10, n_v/32]."""
+    """Network inputs on the grid [-u_max, u_max]^3 with nv nodes per axis:
+    [ln rho, U/u_max (3), ln theta, u_max/10, n_v/32, sin phi (3), cos phi (3)]
+    with phi = 2 pi (U + u_max)/du, du = 2 u_max/(nv - 1): the trapezoid sum
+    of a Gaussian differs from its integral by a Fourier series in this phase
+    (Poisson summation)."""
     rho = np.asarray(rho, np.float64)
     U = np.asarray(U, np.float64)
     th = np.asarray(theta, np.float64)
     n = rho.shape[0]
+    du = 2.0 * umax / (nv - 1)
+    ph = 2.0 * np.pi * (U + umax) / du
     return np.concatenate([np.log(rho)[:, None], U / umax, np.log(th)[:, None],
-                           np.full((n, 1), umax / 10.0), np.full((n, 1), nv / 32.0)], 1)
+                           np.full((n, 1), umax / 10.0), np.full((n, 1), nv / 32.0),
+                           np.sin(ph), np.cos(ph)], 1)

@@ -159,13 +159,12 @@ extern "C" int fr_dvm_newton_stats(fr_dvm_t h, int64_t *iters_hist, int64_t *n_f
 
 extern "C" int fr_dvm_mlp_set_weights(fr_dvm_t h, const float *w, size_t n) {
     if (!h || !w) return FR_DVM_EINVAL;
-    // 7 -> H -> H -> H -> 5 plus 10 output affine floats: solve for H
+    // FR_MLP_INPUTS -> H -> H -> H -> 5 plus 10 output affine floats: solve for H
     int H = 0;
     for (int c = 1; c <= 64; ++c) {
-        size_t need = (size_t)c * 7 + c + 2 * ((size_t)c * c + c) + (size_t)5 * c + 5 + 10;
-        if (need == n) { H = c; break; }
+        if (fr_mlp_param_count(c) == n) { H = c; break; }
     }
-    if (!H) return h->fail(FR_DVM_EINVAL, "weight count does not match a 7-H-H-H-5 network with H <= 64");
+    if (!H) return h->fail(FR_DVM_EINVAL, "weight count does not match a network of fr_mlp_param_count(H), H <= 64");
     if (h->d_mlp) { hipFree(h->d_mlp); h->d_mlp = nullptr; h->owned_bytes -= h->mlp_n * sizeof(float); }
     if (hipMalloc(&h->d_mlp, n * sizeof(float)) != hipSuccess) { h->d_mlp = nullptr; return h->fail(FR_DVM_ENOMEM, "mlp"); }
     h->owned_bytes += n * sizeof(float);

@@ -14,18 +14,25 @@
 // N lanes share a velocity, a wave covers 64/N velocities.  On a
 // tensor-product Gauss element every operator factorises along lines, so the
 // x and y derivatives, traces and corrections are local to the lane's layer;
-// z lines are gathered from a per-wave LDS tile that holds the wave's
-// N^3 x (64/N) block of f.  The same tile, refilled with the stage result,
-// serves the z traces of the result and the moment reduction (lane = solution
-// point, FP64 accumulation with wave-uniform scalar weights, fixed order:
-// bitwise reproducible).  Everything is VALU FMA: the factorised contractions
-// have K = p+1 <= 4 and the kernel is HBM bound.
+// z lines are gathered from a per-wave LDS tile that holds the wave's block
+// of f, one row of N^3 points per velocity.  The same tile, refilled with the
+// stage result, serves the z traces of the result and the moment reduction
+// (lane = solution point, FP64 accumulation with wave-uniform scalar weights,
+// fixed order: bitwise reproducible).  Everything is VALU FMA: the
+// factorised contractions have K = p+1 <= 4 and the kernel is HBM bound.
 //
-// Traces: each element stores, for the velocities leaving it through a face,
-// its trace on that face ("outflow half", compact layout) into the trace
-// buffer of the next stage; the downwind neighbour reads exactly those
-// entries as its exterior state.  Two trace buffers alternate between stages.
+// Latency: the velocity axis is walked in chunks of 4 x 64/N nodes per
+// workgroup, and every HBM read of chunk c+1 (stage value, second RK
+// register, inflow traces) is issued while chunk c is computed.
+//
+// Traces: for the velocities leaving an element through a face, the element
+// writes its trace on that face ("outflow half", compact layout) into the
+// neighbour's block of the next stage's trace buffer, so each element reads
+// its exterior states from its own block.  Two trace buffers alternate
+// between stages.
 #include <hip/hip_runtime.h>
+
+#include <cstring>
 
 #include "frdvm_common.h"
 
@@ -35,18 +42,56 @@ namespace {
 
 constexpr int MODE_PRIME = 0, MODE_STAGE = 1, MODE_RESID = 2;
 
+#ifndef FRDVM_WAVES_F32
+#define FRDVM_WAVES_F32 3
+#endif
+#ifndef FRDVM_WAVES_F64
+#define FRDVM_WAVES_F64 1
+#endif
+
+// FR operators in the working precision of the kernel.
+template <typename Real>
+struct OpsR {
+    Real D[kMaxN * kMaxN];
+    Real lam[2][kMaxN];
+    Real corr[2][kMaxN];
+};
+
 struct FrArgs {
-    Ops1D ops;
+    OpsR<float> of;
+    OpsR<double> od;
     VGrid vg;
     TraceLayout tl;
-    int64_t ne;
+    float inv_nx, inv_nxy;  // 1/nv_x and 1/(nv_x nv_y) for the index split
     int nu;
-    const double *gfac;   // [ne][3]
-    const int32_t *nbr;   // [ne][6]
-    const double *wpsi;   // [nu_pad][NMOM]
+    const double *gfac;     // [ne][3]
+    const int32_t *nbr;     // [ne][6]
+    const double *wpsi;     // [nu_pad][NMOM]
     StageArgs sa;
     int do_traces, do_moments;
 };
+
+template <typename Real>
+__device__ __forceinline__ const OpsR<Real> &ops_of(const FrArgs &A);
+template <>
+__device__ __forceinline__ const OpsR<float> &ops_of<float>(const FrArgs &A) { return A.of; }
+template <>
+__device__ __forceinline__ const OpsR<double> &ops_of<double>(const FrArgs &A) { return A.od; }
+
+__device__ __forceinline__ float exp_r(float x) { return __expf(x); }
+__device__ __forceinline__ double exp_r(double x) { return exp(x); }
+
+// Element-relative access: `base` is uniform (one element's slab), `boff`
+// the lane's byte offset inside it (a slab stays below 4 GiB: at most
+// 64 solution points x 64^3 velocities x 8 bytes).
+template <typename T>
+__device__ __forceinline__ T ldb(const T *base, uint32_t boff) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ void stb(T *base, uint32_t boff, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff) = v;
+}
 
 __device__ __forceinline__ int compact_index(const VGrid &vg, int d, int side, const int iv[3]) {
     int idx[3] = {iv[0], iv[1], iv[2]};
@@ -60,6 +105,93 @@ __device__ __forceinline__ int compact_index(const VGrid &vg, int d, int side, c
     return idx[0] + ext[0] * (idx[1] + ext[1] * idx[2]);
 }
 
+// Small tables a lane chooses from by its own velocity (operator rows of the
+// inflow or outflow side, trace layout of a face, neighbour block) live in
+// LDS and are read with per-lane addresses.  A select between two uniform
+// values would need one of them copied into a vector register (one scalar
+// operand per VALU instruction), and those copies stay live for the whole
+// kernel.
+template <typename Real>
+struct LdsTab {
+    Real lam[2][kMaxN], corr[2][kMaxN];
+    int64_t nb[6];     // element offset of each neighbour's trace block
+    uint32_t cnt[6];   // trace entries per face point of each face slot
+    uint32_t fo[6];    // offset of each face slot inside a block
+};
+
+// The velocity node a lane works on in one chunk.
+struct Vel {
+    int k;  // node index (0 for a lane past the end of the grid)
+    bool act;
+    int iv[3];
+    int sgn[3];
+    double u[3];
+};
+
+__device__ __forceinline__ Vel velocity(const FrArgs &A, int k, bool lane_ok) {
+    const VGrid &vg = A.vg;
+    Vel v;
+    v.act = lane_ok && k < A.nu;
+    v.k = v.act ? k : 0;
+    // integer split through single precision; exact for node counts below
+    // 2^21 (enforced at set-up): (k + 1/2)/n stays 1/(2n) away from integers
+    const int nx = vg.nv[0], nxy = vg.nv[0] * vg.nv[1];
+    const int i2 = (int)(((float)v.k + 0.5f) * A.inv_nxy);
+    const int r2 = v.k - i2 * nxy;
+    const int i1 = (int)(((float)r2 + 0.5f) * A.inv_nx);
+    v.iv[0] = r2 - i1 * nx;
+    v.iv[1] = i1;
+    v.iv[2] = i2;
+    // The sign of each component comes from the integer split of the grid
+    // made on the host (not from the rounded value), so the compact trace
+    // slots of writer and reader always agree; a node classified as zero
+    // carries exactly zero flux.
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        v.sgn[d] = v.iv[d] >= vg.pos_start[d] ? 1 : (v.iv[d] < vg.neg_end[d] ? -1 : 0);
+        v.u[d] = v.sgn[d] == 0 ? 0.0 : __dadd_rn(vg.umin[d], __dmul_rn((double)v.iv[d], vg.du[d]));
+    }
+    return v;
+}
+
+// Traces are pushed: an element writes the trace of each velocity leaving
+// it through a face into the block of the neighbour across that face, under
+// the slot of that face (compact layout of the outflow side).  The reader
+// therefore finds all its inflow traces inside its own block: slot
+// 2d + (s ^ 1) for inflow through its face (d, s).  `TraceOff` is the lane's
+// byte offset of face point `fp0` in that block and the byte stride between
+// face points; a lane without inflow (idle, or a zero component) reads the
+// first entry of the block with stride 0 and ignores it.
+struct TraceOff {
+    uint32_t off, stride;
+};
+
+template <typename Real>
+__device__ __forceinline__ TraceOff trace_in(const FrArgs &A, const LdsTab<Real> &T, const Vel &v, int d, int fp0) {
+    TraceOff t;
+    const bool flow = v.act && v.sgn[d] != 0;
+    const int sin_ = v.sgn[d] > 0 ? 0 : 1;  // inflow face side
+    const int slot = 2 * d + (sin_ ^ 1);     // the upwind neighbour's outflow face
+    const uint32_t cnt = T.cnt[slot], fo = T.fo[slot];
+    const uint32_t idx = fo + (uint32_t)compact_index(A.vg, d, sin_ ^ 1, v.iv) +
+                         (uint32_t)fp0 * cnt;
+    t.off = flow ? idx * (uint32_t)sizeof(Real) : 0u;
+    t.stride = flow ? cnt * (uint32_t)sizeof(Real) : 0u;
+    return t;
+}
+
+// LDS tile row (one velocity): the N^3 point values followed by the N^2
+// z-face inflow traces, padded to a multiple of 16 bytes whose length in
+// dwords is 4 mod 8, so that 16-byte accesses of 8 consecutive rows hit
+// disjoint banks.
+template <typename Real>
+constexpr int tile_row(int ns, int nl) {
+    constexpr int vec = 16 / (int)sizeof(Real);
+    int t = (ns + nl + vec - 1) / vec * vec;
+    if ((t * (int)sizeof(Real) / 4) % 8 != 4) t += vec;
+    return t;
+}
+
 // The LDS tile region of a wave is private to that wave, and one wave's LDS
 // operations complete in issue order, so exchanging data through it only
 // needs the compiler kept from moving LDS accesses across this point.
@@ -69,123 +201,180 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename Real>
-__device__ __forceinline__ Real eval_g(const double *eq, const double u[3]);
-
-template <>
-__device__ __forceinline__ double eval_g<double>(const double *eq, const double u[3]) {
-    double c0 = u[0] - eq[EQ_V], c1 = u[1] - eq[EQ_V + 1], c2 = u[2] - eq[EQ_V + 2];
-    double q = eq[EQ_B] * c0 * c0 + eq[EQ_B + 1] * c1 * c1 + eq[EQ_B + 2] * c2 * c2 +
-               2.0 * (eq[EQ_B + 3] * c0 * c1 + eq[EQ_B + 4] * c0 * c2 + eq[EQ_B + 5] * c1 * c2);
-    return exp(eq[EQ_C0] - 0.5 * q);
+// Keeps the compiler from moving memory accesses (and the scheduler from
+// moving anything) across this point: bounds how many LDS values are in
+// registers at once.
+__device__ __forceinline__ void phase_fence() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
 }
 
-template <>
-__device__ __forceinline__ float eval_g<float>(const double *eq, const double u[3]) {
-    // differences of O(u_max) numbers in FP64, the quadratic form and exp in FP32
-    float c0 = (float)(u[0] - eq[EQ_V]), c1 = (float)(u[1] - eq[EQ_V + 1]), c2 = (float)(u[2] - eq[EQ_V + 2]);
-    float q = (float)eq[EQ_B] * c0 * c0 + (float)eq[EQ_B + 1] * c1 * c1 + (float)eq[EQ_B + 2] * c2 * c2 +
-              2.0f * ((float)eq[EQ_B + 3] * c0 * c1 + (float)eq[EQ_B + 4] * c0 * c2 + (float)eq[EQ_B + 5] * c1 * c2);
-    return __expf((float)eq[EQ_C0] - 0.5f * q);
+// Pins a value in a register at this point (its computation can be neither
+// sunk below nor rematerialised after it).
+template <typename T>
+__device__ __forceinline__ void keep(T &x) {
+    asm volatile("" : "+v"(x));
+}
+
+// Waves per SIMD the register allocation is held to.
+template <typename Real>
+constexpr int fr_waves() {
+    return sizeof(Real) == 4 ? FRDVM_WAVES_F32 : FRDVM_WAVES_F64;
 }
 
 template <typename Real, int P, int NMOM, int MODE>
-__global__ __launch_bounds__(kBlock) void k_fr_layer(const FrArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves<Real>()))) void k_fr_layer(
+    const FrArgs A) {
     constexpr int N = P + 1, NS = N * N * N, NL = N * N;
-    constexpr int VPW = 64 / N;       // velocities per wave
-    constexpr int VPB = 4 * VPW;      // velocities per workgroup and chunk
-    constexpr int TLD = VPW + 1;      // padded tile row
-    __shared__ double s_eq[(MODE == MODE_STAGE) ? NS * kEqW : 1];
-    constexpr size_t TILE_BYTES = sizeof(Real) * 4 * NS * TLD;
-    constexpr size_t RED_BYTES = sizeof(double) * 4 * NS * NMOM;
-    __shared__ __attribute__((aligned(16))) unsigned char s_raw[TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES];
-    Real(*tile)[NS][TLD] = reinterpret_cast<Real(*)[NS][TLD]>(s_raw);
-    double(*red)[NS][NMOM] = reinterpret_cast<double(*)[NS][NMOM]>(s_raw);
+    constexpr int VPW = 64 / N;   // velocities per wave
+    constexpr int VPB = 4 * VPW;  // velocities per workgroup and chunk
+    constexpr int TR = tile_row<Real>(NS, NL);
+    constexpr bool FLUX = MODE != MODE_PRIME;
+    constexpr bool STAGE = MODE == MODE_STAGE;
+    // equilibrium of each solution point: b (the exponent's quadratic form,
+    // -1/2 B with doubled off-diagonal terms), c0, 1/tau; and V in FP64
+    __shared__ __attribute__((aligned(16))) Real s_eb[STAGE ? NS * 8 : 1];
+    __shared__ __attribute__((aligned(16))) double s_ev[STAGE ? NS * 4 : 1];
+    __shared__ __attribute__((aligned(16))) Real tile[4][VPW][TR];
+    __shared__ __attribute__((aligned(16))) LdsTab<Real> T;
+    // running moments of each solution point, one partial sum per wave
+    __shared__ __attribute__((aligned(16))) double red[4][NS][NMOM];
 
+    const OpsR<Real> &op = ops_of<Real>(A);
     const int64_t e = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lay = lane / VPW;        // z-layer owned by this lane (N for an idle lane)
-    const int vl = lane - lay * VPW;   // velocity slot inside the wave
+    const int lay = lane / VPW;  // z-layer owned by this lane (N for an idle lane)
+    const int vl = lane - lay * VPW;
     const bool lane_ok = lay < N;
     const int l = lane_ok ? lay : 0;
-    const VGrid &vg = A.vg;
     const int nu = A.nu;
     const int64_t ebase = e * (int64_t)NS * nu;
+    const uint32_t lrow = (uint32_t)(l * NL) * (uint32_t)nu;     // offset of the layer inside the element
+    const uint32_t QB = (uint32_t)nu * (uint32_t)sizeof(Real);  // bytes between solution points
+    const int kw = wave * VPW + vl;
 
-    if (MODE == MODE_STAGE && A.sa.collide) {
-        for (int i = tid; i < NS * kEqW; i += kBlock) s_eq[i] = A.sa.eq[e * NS * kEqW + i];
+    const bool collide = STAGE && A.sa.collide;
+    if (collide) {
+        for (int s = tid; s < NS; s += kBlock) {
+            const double *q = A.sa.eq + (e * NS + s) * kEqW;
+            Real *b = &s_eb[s * 8];
+            b[0] = (Real)(-0.5 * q[EQ_B]);
+            b[1] = (Real)(-0.5 * q[EQ_B + 1]);
+            b[2] = (Real)(-0.5 * q[EQ_B + 2]);
+            b[3] = (Real)(-q[EQ_B + 3]);
+            b[4] = (Real)(-q[EQ_B + 4]);
+            b[5] = (Real)(-q[EQ_B + 5]);
+            b[6] = (Real)q[EQ_C0];
+            b[7] = (Real)q[EQ_INVTAU];
+            s_ev[s * 4] = q[EQ_V];
+            s_ev[s * 4 + 1] = q[EQ_V + 1];
+            s_ev[s * 4 + 2] = q[EQ_V + 2];
+            s_ev[s * 4 + 3] = 0.0;
+        }
     }
 
+    const double gf[3] = {A.gfac[3 * e], A.gfac[3 * e + 1], A.gfac[3 * e + 2]};
+    // tables chosen from per lane (read only after the barrier below)
+    if (tid < 2 * kMaxN) {
+        const int sd = tid / kMaxN, m = tid % kMaxN;
+        T.lam[sd][m] = op.lam[sd][m];
+        T.corr[sd][m] = op.corr[sd][m];
+    } else if (tid < 2 * kMaxN + 6) {
+        const int fc = tid - 2 * kMaxN;
+        T.nb[fc] = (int64_t)A.nbr[6 * e + fc] * A.tl.elem;
+        T.cnt[fc] = (uint32_t)A.tl.cnt[fc];
+        T.fo[fc] = (uint32_t)A.tl.face_off[fc];
+    }
     // z-direction operator entries of this lane's layer
     Real Dz[N], corrz[2];
 #pragma unroll
-    for (int m = 0; m < N; ++m) Dz[m] = (Real)A.ops.D[l * N + m];
-    corrz[0] = (Real)A.ops.corr[0][l];
-    corrz[1] = (Real)A.ops.corr[1][l];
-    const double gf[3] = {A.gfac[3 * e], A.gfac[3 * e + 1], A.gfac[3 * e + 2]};
+    for (int m = 0; m < N; ++m) Dz[m] = op.D[l * N + m];
+    corrz[0] = op.corr[0][l];
+    corrz[1] = op.corr[1][l];
+    // trace blocks: the own one (inflow of this stage) and the neighbours'
+    // (outflow of the produced value)
+    const Real *__restrict__ trE = reinterpret_cast<const Real *>(A.sa.tr_in) + (FLUX ? e * A.tl.elem : 0);
 
-    double acc[NMOM];
+    if (lane < NS) {
 #pragma unroll
-    for (int a = 0; a < NMOM; ++a) acc[a] = 0.0;
-
-    const Real *__restrict__ fin = reinterpret_cast<const Real *>(A.sa.f) + ebase + (int64_t)l * NL * nu;
-    const Real *__restrict__ trin = reinterpret_cast<const Real *>(A.sa.tr_in);
-    Real *__restrict__ trout = reinterpret_cast<Real *>(A.sa.tr_out);
-    const int nchunk = (nu + VPB - 1) / VPB;
+        for (int a = 0; a < NMOM; ++a) red[wave][lane][a] = 0.0;
+    }
+    // the equilibrium records and the lane tables are complete from here on
     __syncthreads();
 
-    // stage value of the first chunk; later chunks are prefetched one ahead
-    Real fnx[NL];
+    const Real *__restrict__ fE = reinterpret_cast<const Real *>(A.sa.f) + ebase;
+    Real *__restrict__ trout = reinterpret_cast<Real *>(A.sa.tr_out);
+    Real *__restrict__ outE = reinterpret_cast<Real *>(A.sa.fout) + ebase;
+    Real *__restrict__ dFE = reinterpret_cast<Real *>(A.sa.dF) + ebase;
+    // second register read by the stage: f^n (SSP, alpha != 0) or dF (LSRK, A != 0)
+    const bool useX = STAGE && (A.sa.scheme == 0 ? A.sa.alpha != 0.0 : A.sa.lsA != 0.0);
+    const Real *__restrict__ XE = STAGE ? (A.sa.scheme == 0 ? reinterpret_cast<const Real *>(A.sa.fn) + ebase
+                                                            : reinterpret_cast<const Real *>(A.sa.dF) + ebase)
+                                        : nullptr;
+    const int nchunk = (nu + VPB - 1) / VPB;
+
+    // The stage value and the inflow traces of chunk c+1 are requested while
+    // chunk c is computed; the second RK register of chunk c at its start.
+    // Of the z-face traces (shared by the N lanes of a velocity) each lane
+    // fetches the N points (i, j = l) and passes them on through the tile.
+    Real fc[NL], TX[N], TY[N], TZ[N];
     {
-        const int k0 = wave * VPW + vl;
-        const bool a0 = lane_ok && k0 < nu;
+        const Vel v0 = velocity(A, kw, lane_ok);
+        const uint32_t o = (lrow + (uint32_t)v0.k) * (uint32_t)sizeof(Real);
 #pragma unroll
-        for (int q = 0; q < NL; ++q) fnx[q] = a0 ? fin[(int64_t)q * nu + k0] : Real(0);
+        for (int q = 0; q < NL; ++q) fc[q] = ldb(fE, o + q * QB);
+        if (FLUX) {
+            const TraceOff sx = trace_in<Real>(A, T, v0, 0, N * l);
+            const TraceOff sy = trace_in<Real>(A, T, v0, 1, N * l);
+            const TraceOff sz = trace_in<Real>(A, T, v0, 2, N * l);
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                TX[a] = ldb(trE, sx.off + a * sx.stride);
+                TY[a] = ldb(trE, sy.off + a * sy.stride);
+                TZ[a] = ldb(trE, sz.off + a * sz.stride);
+            }
+        }
     }
 
     for (int ch = 0; ch < nchunk; ++ch) {
-        const int k = ch * VPB + wave * VPW + vl;
-        const bool act = lane_ok && k < nu;
-        const int kk = act ? k : 0;
+        const Vel v = velocity(A, ch * VPB + kw, lane_ok);
+        const uint32_t o = (lrow + (uint32_t)v.k) * (uint32_t)sizeof(Real);
+        TraceOff nx{0u, 0u}, ny{0u, 0u}, nz{0u, 0u};
         Real f[NL];
-#pragma unroll
-        for (int q = 0; q < NL; ++q) f[q] = fnx[q];
         {
-            const int k1 = k + VPB;
-            const bool a1 = lane_ok && k1 < nu;
+            const Vel vn = velocity(A, (ch + 1) * VPB + kw, lane_ok);
+            const uint32_t on = (lrow + (uint32_t)vn.k) * (uint32_t)sizeof(Real);
 #pragma unroll
-            for (int q = 0; q < NL; ++q) fnx[q] = a1 ? fin[(int64_t)q * nu + k1] : Real(0);
+            for (int q = 0; q < NL; ++q) {
+                f[q] = fc[q];
+                fc[q] = ldb(fE, on + q * QB);
+            }
+            if (FLUX) {
+                nx = trace_in<Real>(A, T, vn, 0, N * l);
+                ny = trace_in<Real>(A, T, vn, 1, N * l);
+                nz = trace_in<Real>(A, T, vn, 2, N * l);
+            }
         }
-        int iv[3];
-        iv[0] = kk % vg.nv[0];
-        iv[1] = (kk / vg.nv[0]) % vg.nv[1];
-        iv[2] = kk / (vg.nv[0] * vg.nv[1]);
-        // The sign of each velocity component is taken from the integer split
-        // of the grid computed on the host (not from the rounded value), so
-        // the compact trace slots of writer and reader always agree; a node
-        // classified as zero carries exactly zero flux.
-        double u[3];
-        int sgn[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            sgn[d] = iv[d] >= vg.pos_start[d] ? 1 : (iv[d] < vg.neg_end[d] ? -1 : 0);
-            u[d] = sgn[d] == 0 ? 0.0 : __dadd_rn(vg.umin[d], __dmul_rn((double)iv[d], vg.du[d]));
-        }
+        Real X[NL];
 
-        if (MODE != MODE_PRIME) {
-            // publish the stage value for the z-line gathers
+        if (FLUX) {
+            // publish the stage value and this lane's z-face traces
             wave_sync();
             if (lane_ok) {
 #pragma unroll
-                for (int q = 0; q < NL; ++q) tile[wave][l * NL + q][vl] = f[q];
+                for (int q = 0; q < NL; ++q) tile[wave][vl][l * NL + q] = f[q];
+#pragma unroll
+                for (int a = 0; a < N; ++a) tile[wave][vl][NS + N * l + a] = TZ[a];
             }
             wave_sync();
+#pragma unroll
+            for (int a = 0; a < N; ++a) TZ[a] = ldb(trE, nz.off + a * nz.stride);
             Real r[NL];
 #pragma unroll
             for (int q = 0; q < NL; ++q) r[q] = Real(0);
-            const Real ax = (Real)(gf[0] * u[0]), ay = (Real)(gf[1] * u[1]), az = (Real)(gf[2] * u[2]);
+            const Real ax = (Real)(gf[0] * v.u[0]), ay = (Real)(gf[1] * v.u[1]), az = (Real)(gf[2] * v.u[2]);
             // x and y derivatives inside the layer
 #pragma unroll
             for (int j = 0; j < N; ++j)
@@ -194,114 +383,132 @@ __global__ __launch_bounds__(kBlock) void k_fr_layer(const FrArgs A) {
                     Real tx = Real(0), ty = Real(0);
 #pragma unroll
                     for (int m = 0; m < N; ++m) {
-                        tx += (Real)A.ops.D[i * N + m] * f[m + N * j];
-                        ty += (Real)A.ops.D[j * N + m] * f[i + N * m];
+                        tx += op.D[i * N + m] * f[m + N * j];
+                        ty += op.D[j * N + m] * f[i + N * m];
                     }
                     r[i + N * j] += ax * tx + ay * ty;
                 }
             // z lines: derivative and the inflow correction of the z faces
-            const int zin = sgn[2] > 0 ? 0 : 1;
-            const bool zflow = act && sgn[2] != 0;
-            int64_t zbase = 0, zcnt = 0;
-            Real unz = Real(0);
-            if (zflow) {
-                const int nface = 4 + (zin ^ 1);
-                zcnt = A.tl.cnt[nface];
-                zbase = (int64_t)A.nbr[6 * e + 4 + zin] * A.tl.elem + A.tl.face_off[nface] + compact_index(vg, 2, zin ^ 1, iv);
-                unz = (Real)((zin ? 1.0 : -1.0) * gf[2] * u[2]);
-            }
+            {
+                const int zin = v.sgn[2] > 0 ? 0 : 1;
+                const bool zflow = v.act && v.sgn[2] != 0;
+                const Real unz = (Real)((zin ? 1.0 : -1.0) * gf[2] * v.u[2]);
+                const Real cz = zflow ? (zin ? corrz[1] : corrz[0]) * unz : Real(0);
+                Real lz[N];
 #pragma unroll
-            for (int q = 0; q < NL; ++q) {
-                Real g[N];
+                for (int m = 0; m < N; ++m) lz[m] = T.lam[zin][m];
+                // one layer row of the tile at a time (bounded register use):
+                // derivative straight into r, the interior z trace into fmz
+                Real fmz[NL];
 #pragma unroll
-                for (int m = 0; m < N; ++m) g[m] = tile[wave][m * NL + q][vl];
-                Real t = Real(0);
+                for (int m = 0; m < N; ++m) {
+                    const Real azd = az * Dz[m];
 #pragma unroll
-                for (int m = 0; m < N; ++m) t += Dz[m] * g[m];
-                r[q] += az * t;
-                if (zflow) {
-                    Real fm = Real(0);
-#pragma unroll
-                    for (int m = 0; m < N; ++m) fm += (Real)A.ops.lam[zin][m] * g[m];
-                    const Real fp = trin[zbase + q * zcnt];
-                    r[q] += corrz[zin] * (unz * (fp - fm));
+                    for (int q = 0; q < NL; ++q) {
+                        const Real g = tile[wave][vl][m * NL + q];
+                        r[q] = fma(azd, g, r[q]);
+                        fmz[q] = m == 0 ? lz[0] * g : fma(lz[m], g, fmz[q]);
+                        keep(r[q]);
+                        keep(fmz[q]);
+                    }
+                    phase_fence();
                 }
+#pragma unroll
+                for (int q = 0; q < NL; ++q) {
+                    const Real fp = zflow ? tile[wave][vl][NS + q] : fmz[q];
+                    r[q] = fma(cz, fp - fmz[q], r[q]);
+                }
+                phase_fence();
+            }
+            if (useX) {
+#pragma unroll
+                for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
             }
             // x faces: face points (j, l); y faces: face points (i, l)
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
-                if (act && sgn[d] != 0) {
-                    const int sin_ = sgn[d] > 0 ? 0 : 1;
-                    const int nface = 2 * d + (sin_ ^ 1);
-                    const int64_t cnt = A.tl.cnt[nface];
-                    const int64_t base = (int64_t)A.nbr[6 * e + 2 * d + sin_] * A.tl.elem + A.tl.face_off[nface] +
-                                         compact_index(vg, d, sin_ ^ 1, iv);
-                    const Real un = (Real)((sin_ ? 1.0 : -1.0) * gf[d] * u[d]);
+                const bool flow = v.act && v.sgn[d] != 0;
+                const int sin_ = v.sgn[d] > 0 ? 0 : 1;
+                const Real un = (Real)((sin_ ? 1.0 : -1.0) * gf[d] * v.u[d]);
+                const TraceOff sn = d == 0 ? nx : ny;
 #pragma unroll
-                    for (int a = 0; a < N; ++a) {
-                        const Real fp = trin[base + (a + N * l) * cnt];
-                        Real fm = Real(0);
+                for (int a = 0; a < N; ++a) {
+                    Real fm = Real(0);
 #pragma unroll
-                        for (int m = 0; m < N; ++m)
-                            fm += (Real)A.ops.lam[sin_][m] * (d == 0 ? f[m + N * a] : f[a + N * m]);
-                        const Real jmp = un * (fp - fm);
+                    for (int m = 0; m < N; ++m)
+                        fm += T.lam[sin_][m] * (d == 0 ? f[m + N * a] : f[a + N * m]);
+                    Real &tin = d == 0 ? TX[a] : TY[a];
+                    const Real jmp = flow ? un * (tin - fm) : Real(0);
+                    tin = ldb(trE, sn.off + a * sn.stride);
 #pragma unroll
-                        for (int m = 0; m < N; ++m)
-                            r[d == 0 ? m + N * a : a + N * m] += (Real)A.ops.corr[sin_][m] * jmp;
-                    }
+                    for (int m = 0; m < N; ++m)
+                        r[d == 0 ? m + N * a : a + N * m] += T.corr[sin_][m] * jmp;
                 }
             }
-            Real *__restrict__ out = reinterpret_cast<Real *>(A.sa.fout) + ebase + (int64_t)l * NL * nu;
             if (MODE == MODE_RESID) {
-                if (act) {
+                if (v.act) {
 #pragma unroll
-                    for (int q = 0; q < NL; ++q) out[(int64_t)q * nu + k] = -r[q];
+                    for (int q = 0; q < NL; ++q) stb(outE, o + q * QB, -r[q]);
                 }
                 continue;
             }
             // collision source and the Runge-Kutta combination, point by point
-            const Real *__restrict__ fnp = reinterpret_cast<const Real *>(A.sa.fn) + ebase + (int64_t)l * NL * nu;
-            Real *__restrict__ dF = reinterpret_cast<Real *>(A.sa.dF) + ebase + (int64_t)l * NL * nu;
             const Real dt = (Real)A.sa.dt;
 #pragma unroll
             for (int q = 0; q < NL; ++q) {
+                const Real fq = tile[wave][vl][l * NL + q];  // stage value (also in f until here)
                 Real L = -r[q];
-                if (A.sa.collide) {
-                    const double *eq = &s_eq[(l * NL + q) * kEqW];
-                    const Real gq = eval_g<Real>(eq, u);
-                    L += (gq - f[q]) * (Real)eq[EQ_INVTAU];
+                if (collide) {
+                    const int s = l * NL + q;
+                    const Real *b = &s_eb[s * 8];
+                    const double *V = &s_ev[s * 4];
+                    // differences of O(u_max) numbers in FP64, the quadratic form in Real
+                    const Real c0 = (Real)(v.u[0] - V[0]), c1 = (Real)(v.u[1] - V[1]), c2 = (Real)(v.u[2] - V[2]);
+                    Real t0 = b[0] * c0;
+                    t0 = fma(b[3], c1, t0);
+                    t0 = fma(b[4], c2, t0);
+                    Real t1 = b[1] * c1;
+                    t1 = fma(b[5], c2, t1);
+                    const Real t2 = b[2] * c2;
+                    Real E = fma(c0, t0, b[6]);
+                    E = fma(c1, t1, E);
+                    E = fma(c2, t2, E);
+                    L += (exp_r(E) - fq) * b[7];
                 }
                 Real fo;
                 if (A.sa.scheme == 0) {
-                    fo = (Real)A.sa.beta * (f[q] + dt * L);
-                    if (A.sa.alpha != 0.0 && act) fo += (Real)A.sa.alpha * fnp[(int64_t)q * nu + k];
+                    fo = (Real)A.sa.beta * (fq + dt * L);
+                    if (useX) fo += (Real)A.sa.alpha * X[q];
                 } else {
                     Real dd = dt * L;
-                    if (A.sa.lsA != 0.0 && act) dd += (Real)A.sa.lsA * dF[(int64_t)q * nu + k];
-                    if (act) dF[(int64_t)q * nu + k] = dd;
-                    fo = f[q] + (Real)A.sa.lsB * dd;
+                    if (useX) dd += (Real)A.sa.lsA * X[q];
+                    if (v.act) stb(dFE, o + q * QB, dd);
+                    fo = fq + (Real)A.sa.lsB * dd;
                 }
-                f[q] = act ? fo : Real(0);
-                if (act) out[(int64_t)q * nu + k] = fo;
+                f[q] = v.act ? fo : Real(0);
+                if (v.act) stb(outE, o + q * QB, fo);
+                if (q % 4 == 3) phase_fence();
             }
         }
 
-        // outflow traces of the produced value on the x and y faces
-        if (A.do_traces && act) {
+        // outflow traces of the produced value on the x and y faces, into
+        // the neighbours' blocks
+        if (A.do_traces && v.act) {
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
-                if (sgn[d] != 0) {
-                    const int side = sgn[d] > 0 ? 1 : 0;
+                if (v.sgn[d] != 0) {
+                    const int side = v.sgn[d] > 0 ? 1 : 0;
                     const int face = 2 * d + side;
-                    const int64_t cnt = A.tl.cnt[face];
-                    const int64_t base = e * A.tl.elem + A.tl.face_off[face] + compact_index(vg, d, side, iv);
+                    const int cnt = (int)T.cnt[face];
+                    Real *tp = trout + T.nb[face] + T.fo[face] + compact_index(A.vg, d, side, v.iv) +
+                               (int64_t)(N * l) * cnt;
 #pragma unroll
                     for (int a = 0; a < N; ++a) {
                         Real t = Real(0);
 #pragma unroll
                         for (int m = 0; m < N; ++m)
-                            t += (Real)A.ops.lam[side][m] * (d == 0 ? f[m + N * a] : f[a + N * m]);
-                        trout[base + (a + N * l) * cnt] = t;
+                            t += T.lam[side][m] * (d == 0 ? f[m + N * a] : f[a + N * m]);
+                        tp[a * cnt] = t;
                     }
                 }
             }
@@ -312,43 +519,47 @@ __global__ __launch_bounds__(kBlock) void k_fr_layer(const FrArgs A) {
             wave_sync();
             if (lane_ok) {
 #pragma unroll
-                for (int q = 0; q < NL; ++q) tile[wave][l * NL + q][vl] = f[q];
+                for (int q = 0; q < NL; ++q) tile[wave][vl][l * NL + q] = f[q];
             }
             wave_sync();
-            if (A.do_traces && act && sgn[2] != 0) {
+            if (A.do_traces && v.act && v.sgn[2] != 0) {
                 // this lane writes the z-face points (i, j = l)
-                const int side = sgn[2] > 0 ? 1 : 0;
+                const int side = v.sgn[2] > 0 ? 1 : 0;
                 const int face = 4 + side;
-                const int64_t cnt = A.tl.cnt[face];
-                const int64_t base = e * A.tl.elem + A.tl.face_off[face] + compact_index(vg, 2, side, iv);
+                const int cnt = (int)T.cnt[face];
+                Real *tp = trout + T.nb[face] + T.fo[face] + compact_index(A.vg, 2, side, v.iv) +
+                           (int64_t)(N * l) * cnt;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     const int q = i + N * l;
                     Real t = Real(0);
 #pragma unroll
-                    for (int m = 0; m < N; ++m) t += (Real)A.ops.lam[side][m] * tile[wave][m * NL + q][vl];
-                    trout[base + q * cnt] = t;
+                    for (int m = 0; m < N; ++m) t += T.lam[side][m] * tile[wave][vl][m * NL + q];
+                    tp[i * cnt] = t;
                 }
             }
             if (A.do_moments && lane < NS) {
                 const int kb = ch * VPB + wave * VPW;
-                const double *__restrict__ wp = A.wpsi + (int64_t)kb * NMOM;
+                // wave-uniform weights through the scalar cache (the table is
+                // never written by the kernel)
+                const __attribute__((address_space(4))) double *wp =
+                    (const __attribute__((address_space(4))) double *)(A.wpsi + (int64_t)kb * NMOM);
+                double acc[NMOM];
+#pragma unroll
+                for (int a = 0; a < NMOM; ++a) acc[a] = 0.0;
 #pragma unroll 4
                 for (int j = 0; j < VPW; ++j) {
-                    const double v = (double)tile[wave][lane][j];
+                    const double x = (double)tile[wave][j][lane];
 #pragma unroll
-                    for (int a = 0; a < NMOM; ++a) acc[a] += wp[j * NMOM + a] * v;
+                    for (int a = 0; a < NMOM; ++a) acc[a] += wp[j * NMOM + a] * x;
                 }
+#pragma unroll
+                for (int a = 0; a < NMOM; ++a) red[wave][lane][a] += acc[a];
             }
         }
     }
 
     if (A.do_moments) {
-        __syncthreads();
-        if (lane < NS) {
-#pragma unroll
-            for (int a = 0; a < NMOM; ++a) red[wave][lane][a] = acc[a];
-        }
         __syncthreads();
         for (int i = tid; i < NS * NMOM; i += kBlock) {
             const int s = i / NMOM, a = i % NMOM;
@@ -391,10 +602,22 @@ __global__ __launch_bounds__(256) void k_copy16(uint4 *__restrict__ dst, const u
 
 int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_moments) {
     FrArgs A;
-    A.ops = h->ops;
+    std::memset(&A, 0, sizeof(A));
+    for (int i = 0; i < kMaxN * kMaxN; ++i) {
+        A.od.D[i] = h->ops.D[i];
+        A.of.D[i] = (float)h->ops.D[i];
+    }
+    for (int s = 0; s < 2; ++s)
+        for (int m = 0; m < kMaxN; ++m) {
+            A.od.lam[s][m] = h->ops.lam[s][m];
+            A.of.lam[s][m] = (float)h->ops.lam[s][m];
+            A.od.corr[s][m] = h->ops.corr[s][m];
+            A.of.corr[s][m] = (float)h->ops.corr[s][m];
+        }
     A.vg = h->vg;
+    A.inv_nx = 1.0f / (float)h->vg.nv[0];
+    A.inv_nxy = 1.0f / (float)(h->vg.nv[0] * h->vg.nv[1]);
     A.tl = h->tl;
-    A.ne = h->ne;
     A.nu = h->vg.nu;
     A.gfac = h->d_gfac;
     A.nbr = h->d_nbr;

@@ -125,7 +125,7 @@ struct Layout {
 
 Layout layout(int H) {
     Layout L;
-    int ins[4] = {7, H, H, H}, outs[4] = {H, H, H, 5};
+    int ins[4] = {FR_MLP_INPUTS, H, H, H}, outs[4] = {H, H, H, 5};
     size_t o = 0;
     for (int l = 0; l < 4; ++l) {
         L.in[l] = ins[l];

@@ -211,9 +211,11 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// ES sums over all velocity nodes: lane-strided, butterfly reduced.
+// ES sums over all velocity nodes: lane-strided, butterfly reduced.  With
+// jac == false only the residual sums S0, Sc and the trace of Scc (stored in
+// Scc[0]) are formed.
 __device__ void sums_es(const NewtonArgs &A, int lane, const double U[3], double ist, double wscale,
-                        const double Am[3][3], const double z[5], Sums &s) {
+                        const double Am[3][3], const double z[5], Sums &s, bool jac) {
     double acc[18];
 #pragma unroll
     for (int a = 0; a < 18; ++a) acc[a] = 0.0;
@@ -228,9 +230,13 @@ __device__ void sums_es(const NewtonArgs &A, int lane, const double U[3], double
         const double w = A.wax[i] * A.wax[64 + j] * A.wax[128 + l] * wscale;
         const double ev = w * exp(z[0] + z[1] * c0 + z[2] * c1 + z[3] * c2 - 0.5 * z[4] * q);
         const double cc = c0 * c0 + c1 * c1 + c2 * c2;
-        const double eq_ = ev * q, ec = ev * cc;
         acc[0] += ev;
         acc[1] += ev * c0; acc[2] += ev * c1; acc[3] += ev * c2;
+        if (!jac) {
+            acc[4] += ev * cc;
+            continue;
+        }
+        const double eq_ = ev * q, ec = ev * cc;
         acc[4] += ev * c0 * c0; acc[5] += ev * c1 * c1; acc[6] += ev * c2 * c2;
         acc[7] += ev * c0 * c1; acc[8] += ev * c0 * c2; acc[9] += ev * c1 * c2;
         acc[10] += eq_;
@@ -241,6 +247,11 @@ __device__ void sums_es(const NewtonArgs &A, int lane, const double U[3], double
     s.S0 = wave_sum(acc[0]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) s.Sc[d] = wave_sum(acc[1 + d]);
+    if (!jac) {
+        s.Scc[0] = wave_sum(acc[4]);
+        s.Scc[1] = s.Scc[2] = 0.0;
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < 6; ++a) s.Scc[a] = wave_sum(acc[4 + a]);
     s.Sq = wave_sum(acc[10]);
@@ -300,96 +311,150 @@ __device__ __forceinline__ void lds_wave_sync() {
 }
 
 // Returns false (and leaves s untouched) when a factor exponent exceeds the
-// safe range; the caller then uses the direct sum.
+// safe range; the caller then uses the direct sum.  jac as for sums_es.
 __device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const double U[3], double ist,
-                             const double Am[3][3], const double z[5], Sums &s) {
+                             const double Am[3][3], const double z[5], Sums &s, bool jac) {
     const VGrid &vg = A.vg;
     const FactLayout L = fact_layout(vg);
     const double hz = 0.5 * z[4];
     double amax = -1e300;
     lds_wave_sync();  // previous evaluation's readers are done with the tables
-    for (int t = lane; t < L.n0 + L.n1 + L.n2; t += 64) {
-        const int d = t < L.n0 ? 0 : (t < L.n0 + L.n1 ? 1 : 2);
-        const int i = t - (d == 0 ? 0 : (d == 1 ? L.n0 : L.n0 + L.n1));
-        const double c = (gridu(vg, d, i) - U[d]) * ist;
-        double arg = c * (z[1 + d] - hz * Am[d][d] * c);
-        if (d == 0) arg += z[0];
-        amax = fmax(amax, arg);
-        const double v = A.wax[64 * d + i] * ist * exp(arg);
-        if (d == 0) {
-            tb[L.c0 + i] = c;
-            tb[L.X + i] = v;
-        } else if (d == 1) {
-            tb[L.c1 + i] = c;
-            tb[L.Y + i] = v;
-        } else {
-            tb[L.c2 + i] = c;
-            double p = v;
+    // one-axis factors, axis by axis (an axis index varying across lanes would
+    // put the small per-point arrays U, z, Am into scratch memory)
 #pragma unroll
-            for (int e = 0; e < 5; ++e) { tb[L.Zc + 5 * i + e] = p; p *= c; }
+    for (int d = 0; d < 3; ++d) {
+        const int nd = d == 0 ? L.n0 : (d == 1 ? L.n1 : L.n2);
+        const int oc = d == 0 ? L.c0 : (d == 1 ? L.c1 : L.c2);
+        for (int i = lane; i < nd; i += 64) {
+            const double c = (gridu(vg, d, i) - U[d]) * ist;
+            double arg = c * (z[1 + d] - hz * Am[d][d] * c);
+            if (d == 0) arg += z[0];
+            amax = fmax(amax, arg);
+            const double v = A.wax[64 * d + i] * ist * exp(arg);
+            tb[oc + i] = c;
+            if (d == 0) {
+                tb[L.X + i] = v;
+            } else if (d == 1) {
+                tb[L.Y + i] = v;
+            } else {
+                double p = v;
+#pragma unroll
+                for (int e = 0; e < 5; ++e) { tb[L.Zc + 5 * i + e] = p; p *= c; }
+            }
         }
     }
     lds_wave_sync();
+    // Two-axis factors exp(k c_a c_b): along a row the exponent is affine in
+    // the node index (uniform grid), so one lane fills a row by a geometric
+    // recurrence from its larger end (2 exponentials per row; values only
+    // shrink along the recurrence, so an underflow is a true underflow).
     const double k01 = -z[4] * Am[0][1], k02 = -z[4] * Am[0][2], k12 = -z[4] * Am[1][2];
-    const int nP = L.n0 * L.n1, nQ = L.n0 * L.n2, nR = L.n1 * L.n2;
-    for (int t = lane; t < nP + nQ + nR; t += 64) {
-        if (t < nP) {
-            const int i = t % L.n0, j = t / L.n0;
-            const double arg = k01 * tb[L.c0 + i] * tb[L.c1 + j];
-            amax = fmax(amax, arg);
-            tb[L.P + i * L.ld1 + j] = exp(arg);
-        } else if (t < nP + nQ) {
-            const int u = t - nP, i = u % L.n0, l = u / L.n0;
-            const double arg = k02 * tb[L.c0 + i] * tb[L.c2 + l];
-            amax = fmax(amax, arg);
-            tb[L.Q + i * L.ld2 + l] = exp(arg);
+    for (int t = lane; t < 2 * L.n0 + L.n1; t += 64) {
+        double kc, *dst;
+        const double *cb;
+        int nb;
+        if (t < L.n0) {
+            kc = k01 * tb[L.c0 + t];
+            cb = tb + L.c1;
+            nb = L.n1;
+            dst = tb + L.P + t * L.ld1;
+        } else if (t < 2 * L.n0) {
+            kc = k02 * tb[L.c0 + t - L.n0];
+            cb = tb + L.c2;
+            nb = L.n2;
+            dst = tb + L.Q + (t - L.n0) * L.ld2;
         } else {
-            const int u = t - nP - nQ, j = u % L.n1, l = u / L.n1;
-            const double arg = k12 * tb[L.c1 + j] * tb[L.c2 + l];
-            amax = fmax(amax, arg);
-            tb[L.R + j * L.ld2 + l] = exp(arg);
+            kc = k12 * tb[L.c1 + t - 2 * L.n0];
+            cb = tb + L.c2;
+            nb = L.n2;
+            dst = tb + L.R + (t - 2 * L.n0) * L.ld2;
+        }
+        const double a0 = kc * cb[0], a1 = kc * cb[nb - 1];
+        amax = fmax(amax, fmax(a0, a1));
+        const double step = nb > 1 ? fabs(a1 - a0) / (nb - 1) : 0.0;
+        const double ratio = exp(-step);
+        const bool up = a1 > a0;  // the larger end is the last node
+        double v = exp(up ? a1 : a0);
+        for (int m = 0; m < nb; ++m) {
+            dst[up ? nb - 1 - m : m] = v;
+            v *= ratio;
         }
     }
     lds_wave_sync();
     if (wave_max(amax) > 600.0) return false;
     // Per pair (i,j) the c2 dependence is carried by T_e = sum_l Z c2^e Q R;
     // with q = qa + qb c2 + A22 c2^2 and |c|^2 = r2 + c2^2 (qa, qb, r2 from
-    // c0, c1) every one of the 18 sums is a short combination of T_0..T_4.
+    // c0, c1) every one of the 18 sums is a short combination of T_0..T_4
+    // (T_0..T_2 for the residual sums).  A lane takes four pairs at a time
+    // and walks l once for all four (the Z row is read once per l).
+    constexpr int B = 4;
     double acc[18];
 #pragma unroll
     for (int a = 0; a < 18; ++a) acc[a] = 0.0;
     const double a00 = Am[0][0], a11 = Am[1][1], a22 = Am[2][2];
     const double t01 = 2.0 * Am[0][1], t02 = 2.0 * Am[0][2], t12 = 2.0 * Am[1][2];
-    for (int p = lane; p < nP; p += 64) {
-        const int i = p % L.n0, j = p / L.n0;
-        double T0 = 0, T1 = 0, T2 = 0, T3 = 0, T4 = 0;
-        const double *Qi = tb + L.Q + i * L.ld2;
-        const double *Rj = tb + L.R + j * L.ld2;
-        for (int l = 0; l < L.n2; ++l) {
-            const double qr = Qi[l] * Rj[l];
-            const double *zc = tb + L.Zc + 5 * l;
-            T0 += zc[0] * qr; T1 += zc[1] * qr; T2 += zc[2] * qr; T3 += zc[3] * qr; T4 += zc[4] * qr;
+    const int nP = L.n0 * L.n1;
+    const int ne = jac ? 5 : 3;
+    for (int p0 = lane; p0 < nP; p0 += 64 * B) {
+        int qo[B], ro[B];
+        double T[B][5];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int p = p0 + 64 * b < nP ? p0 + 64 * b : p0;
+            qo[b] = L.Q + (p % L.n0) * L.ld2;
+            ro[b] = L.R + (p / L.n0) * L.ld2;
+#pragma unroll
+            for (int e = 0; e < 5; ++e) T[b][e] = 0.0;
         }
-        const double c0 = tb[L.c0 + i], c1 = tb[L.c1 + j];
-        const double b = tb[L.X + i] * tb[L.Y + j] * tb[L.P + i * L.ld1 + j];
-        const double qa = c0 * (a00 * c0 + t01 * c1) + a11 * c1 * c1, qb = t02 * c0 + t12 * c1;
-        const double r2 = c0 * c0 + c1 * c1;
-        const double q0 = qa * T0 + qb * T1 + a22 * T2;      // sum q
-        const double q1 = qa * T1 + qb * T2 + a22 * T3;      // sum c2 q
-        const double q2 = qa * T2 + qb * T3 + a22 * T4;      // sum c2^2 q
-        const double s2 = r2 * T0 + T2;                      // sum |c|^2
-        acc[0] += b * T0;
-        acc[1] += b * c0 * T0; acc[2] += b * c1 * T0; acc[3] += b * T1;
-        acc[4] += b * c0 * c0 * T0; acc[5] += b * c1 * c1 * T0; acc[6] += b * T2;
-        acc[7] += b * c0 * c1 * T0; acc[8] += b * c0 * T1; acc[9] += b * c1 * T1;
-        acc[10] += b * q0;
-        acc[11] += b * c0 * q0; acc[12] += b * c1 * q0; acc[13] += b * q1;
-        acc[14] += b * c0 * s2; acc[15] += b * c1 * s2; acc[16] += b * (r2 * T1 + T3);
-        acc[17] += b * (r2 * q0 + q2);
+        for (int l = 0; l < L.n2; ++l) {
+            const double *zc = tb + L.Zc + 5 * l;
+            double zl[5];
+#pragma unroll
+            for (int e = 0; e < 5; ++e) zl[e] = e < ne ? zc[e] : 0.0;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const double qr = tb[qo[b] + l] * tb[ro[b] + l];
+#pragma unroll
+                for (int e = 0; e < 5; ++e)
+                    if (e < ne) T[b][e] += zl[e] * qr;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int p = p0 + 64 * b;
+            if (p >= nP) break;
+            const int i = p % L.n0, j = p / L.n0;
+            const double T0 = T[b][0], T1 = T[b][1], T2 = T[b][2], T3 = T[b][3], T4 = T[b][4];
+            const double c0 = tb[L.c0 + i], c1 = tb[L.c1 + j];
+            const double bb = tb[L.X + i] * tb[L.Y + j] * tb[L.P + i * L.ld1 + j];
+            const double r2 = c0 * c0 + c1 * c1;
+            acc[0] += bb * T0;
+            acc[1] += bb * c0 * T0; acc[2] += bb * c1 * T0; acc[3] += bb * T1;
+            if (!jac) {
+                acc[4] += bb * (r2 * T0 + T2);
+                continue;
+            }
+            const double qa = c0 * (a00 * c0 + t01 * c1) + a11 * c1 * c1, qb = t02 * c0 + t12 * c1;
+            const double q0 = qa * T0 + qb * T1 + a22 * T2;      // sum q
+            const double q1 = qa * T1 + qb * T2 + a22 * T3;      // sum c2 q
+            const double q2 = qa * T2 + qb * T3 + a22 * T4;      // sum c2^2 q
+            const double s2 = r2 * T0 + T2;                      // sum |c|^2
+            acc[4] += bb * c0 * c0 * T0; acc[5] += bb * c1 * c1 * T0; acc[6] += bb * T2;
+            acc[7] += bb * c0 * c1 * T0; acc[8] += bb * c0 * T1; acc[9] += bb * c1 * T1;
+            acc[10] += bb * q0;
+            acc[11] += bb * c0 * q0; acc[12] += bb * c1 * q0; acc[13] += bb * q1;
+            acc[14] += bb * c0 * s2; acc[15] += bb * c1 * s2; acc[16] += bb * (r2 * T1 + T3);
+            acc[17] += bb * (r2 * q0 + q2);
+        }
     }
     s.S0 = wave_sum(acc[0]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) s.Sc[d] = wave_sum(acc[1 + d]);
+    if (!jac) {
+        s.Scc[0] = wave_sum(acc[4]);
+        s.Scc[1] = s.Scc[2] = 0.0;
+        return true;
+    }
 #pragma unroll
     for (int a = 0; a < 6; ++a) s.Scc[a] = wave_sum(acc[4 + a]);
     s.Sq = wave_sum(acc[10]);
@@ -535,14 +600,28 @@ __device__ bool alt_start(const NewtonArgs &A, int64_t pt, const double zc[5], d
     return ok && z[4] > 0.0;
 }
 
+// Residual rows psi = (1, c, |c|^2/2) against the targets (1, 0, 0, 0, 3/2).
+__device__ __forceinline__ void residual(const Sums &s, double r[5]) {
+    r[0] = s.S0 - 1.0;
+    r[1] = s.Sc[0];
+    r[2] = s.Sc[1];
+    r[3] = s.Sc[2];
+    r[4] = 0.5 * (s.Scc[0] + s.Scc[1] + s.Scc[2]) - 1.5;
+}
+
+// Below this residual norm the iteration keeps its Jacobian (chord steps)
+// and evaluates only the residual sums; from a start this close the chord
+// contraction factor is of the order of the distance to the root.
+constexpr double kChord = 1e-5;
+
 // Damped Newton from the better of the cold start and the alternative start.
 // Returns 1 on convergence; z, res, iterations (linear solves) and evals
 // (sum passes) are outputs.
 template <typename SumsFn>
 __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const double zc[5], double z[5],
                             double &res, int &iters, int &evals) {
-    // The state is kept as the 18 raw sums (the Jacobian is assembled from
-    // them right before each solve) to keep register pressure low.
+    // s: full sums at the point of the current Jacobian (assembled right
+    // before each solve, to keep register pressure low); r: residual at z.
     double r[5], J[5][5];
     Sums s;
     // the alternative start is tried first; the cold start is evaluated too
@@ -552,14 +631,14 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const 
 #pragma unroll
         for (int a = 0; a < 5; ++a) z[a] = zc[a];
     }
-    sums(z, s);
-    assemble(s, r, J);
+    sums(z, s, true);
+    residual(s, r);
     evals = 1;
     if (have_alt && !(norm2_5(r) <= 1e-2)) {
         Sums sc;
-        double rc[5], Jc[5][5];
-        sums(zc, sc);
-        assemble(sc, rc, Jc);
+        double rc[5];
+        sums(zc, sc, true);
+        residual(sc, rc);
         ++evals;
         if (!(norm2_5(r) <= norm2_5(rc))) {
             s = sc;
@@ -570,11 +649,11 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const 
     int conv = 0, it;
     for (it = 0; it < A.max_iter; ++it) {
         const double rn = norm2_5(r), ri = normi_5(r);
-        double rhs[5] = {-r[0], -r[1], -r[2], -r[3], -r[4]}, dz[5];
-        assemble(s, r, J);
+        double rhs[5] = {-r[0], -r[1], -r[2], -r[3], -r[4]}, dz[5], rdum[5];
+        assemble(s, rdum, J);
         const bool ok = solve5(J, rhs, dz);
         if (ok && ri <= A.tol) {
-            // converged: one extra full step makes the result path independent
+            // converged: one extra step makes the result path independent
 #pragma unroll
             for (int a = 0; a < 5; ++a) z[a] += dz[a];
             res = ri;
@@ -583,17 +662,17 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const 
             break;
         }
         if (!ok) break;
-        double alpha = 1.0, zt[5];
+        const bool chord = rn <= kChord;
+        double alpha = 1.0, zt[5], rt[5];
         Sums st;
         bool acc = false;
         for (int hh = 0; hh < 40; ++hh) {
 #pragma unroll
             for (int a = 0; a < 5; ++a) zt[a] = z[a] + alpha * dz[a];
             if (zt[4] > 0.0) {
-                sums(zt, st);
+                sums(zt, st, !chord);
                 ++evals;
-                const double c2 = st.Scc[0] + st.Scc[1] + st.Scc[2];
-                const double rt[5] = {st.S0 - 1.0, st.Sc[0], st.Sc[1], st.Sc[2], 0.5 * c2 - 1.5};
+                residual(st, rt);
                 if (norm2_5(rt) < (1.0 - 1e-4 * alpha) * rn) { acc = true; break; }
             }
             alpha *= 0.5;
@@ -603,11 +682,16 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const 
             if (ri <= 100.0 * A.tol) { res = ri; conv = 1; ++it; }
             break;
         }
-        s = st;
 #pragma unroll
-        for (int a = 0; a < 5; ++a) z[a] = zt[a];
-        r[0] = s.S0 - 1.0; r[1] = s.Sc[0]; r[2] = s.Sc[1]; r[3] = s.Sc[2];
-        r[4] = 0.5 * (s.Scc[0] + s.Scc[1] + s.Scc[2]) - 1.5;
+        for (int a = 0; a < 5; ++a) { z[a] = zt[a]; r[a] = rt[a]; }
+        if (!chord) {
+            s = st;
+        } else if (norm2_5(rt) > 1e-2 * rn) {
+            // slow chord contraction: refresh the Jacobian at the new point
+            sums(z, s, true);
+            ++evals;
+            residual(s, r);
+        }
     }
     iters = it;
     if (!conv) {
@@ -636,7 +720,7 @@ __global__ __launch_bounds__(256) void k_newton_bgk(const NewtonArgs A) {
     const double ist = 1.0 / sqrt(th);
     const double zc[5] = {-1.5 * log(kTwoPi), 0.0, 0.0, 0.0, 1.0};
     double z[5];
-    auto fn = [&](const double zz[5], Sums &s) { sums_bgk(A, U, ist, zz, s); };
+    auto fn = [&](const double zz[5], Sums &s, bool) { sums_bgk(A, U, ist, zz, s); };
     double res;
     int iters, evals;
     const int conv = newton_solve(A, fn, pt, zc, z, res, iters, evals);
@@ -645,7 +729,11 @@ __global__ __launch_bounds__(256) void k_newton_bgk(const NewtonArgs A) {
     record_stats(A, pt, iters, evals, conv ? FR_DVM_NEWTON_OK : FR_DVM_NEWTON_FALLBACK, res);
 }
 
-__global__ __launch_bounds__(256) void k_newton_es(const NewtonArgs A) {
+#ifndef FRDVM_WAVES_ES
+#define FRDVM_WAVES_ES 1
+#endif
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FRDVM_WAVES_ES))) void k_newton_es(
+    const NewtonArgs A) {
     const int lane = threadIdx.x & 63;
     const int64_t pt = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (pt >= A.npts) return;  // whole waves exit together
@@ -690,8 +778,9 @@ __global__ __launch_bounds__(256) void k_newton_es(const NewtonArgs A) {
     const double wscale = ist * ist * ist;
     extern __shared__ double es_tables[];
     double *tb = es_tables + (threadIdx.x >> 6) * (A.use_fact ? fact_layout(A.vg).total : 0);
-    auto fn = [&](const double zz[5], Sums &s) {
-        if (!(A.use_fact && sums_es_fact(A, lane, tb, U, ist, Am, zz, s))) sums_es(A, lane, U, ist, wscale, Am, zz, s);
+    auto fn = [&](const double zz[5], Sums &s, bool jac) {
+        if (!(A.use_fact && sums_es_fact(A, lane, tb, U, ist, Am, zz, s, jac)))
+            sums_es(A, lane, U, ist, wscale, Am, zz, s, jac);
     };
     double res;
     int iters, evals;
@@ -722,9 +811,10 @@ __global__ void k_mlp_scale(int64_t n, const float *__restrict__ env, float *__r
 }
 
 // Features of the learned guess from the moments: [ln rho, U/u_max, ln theta,
-// u_max/10, n_v/32] (FP32) and the correction envelope; non-realizable
+// u_max/10, n_v/32, sin and cos of the grid phase 2 pi (U - umin)/du] (FP32)
+// and the correction envelope; non-realizable
 // points get zeros (Newton marks them).
-__global__ void k_mlp_features(int64_t npts, int nmom, const double *__restrict__ Q, double umax, double nv,
+__global__ void k_mlp_features(int64_t npts, int nmom, const double *__restrict__ Q, const VGrid vg, double umax,
                                double du, float *__restrict__ X, float *__restrict__ env) {
     const int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pt >= npts) return;
@@ -733,9 +823,9 @@ __global__ void k_mlp_features(int64_t npts, int nmom, const double *__restrict_
     const double U[3] = {q[1] / rho, q[2] / rho, q[3] / rho};
     const double E = nmom == 5 ? q[4] : 0.5 * (q[4] + q[5] + q[6]);
     const double th = (2.0 / 3.0) * (E / rho - 0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
-    float *x = X + pt * 7;
+    float *x = X + pt * FR_MLP_INPUTS;
     if (!(rho > 0.0) || !(th > 0.0)) {
-        for (int a = 0; a < 7; ++a) x[a] = 0.f;
+        for (int a = 0; a < FR_MLP_INPUTS; ++a) x[a] = 0.f;
         env[pt] = 0.f;
         return;
     }
@@ -746,7 +836,13 @@ __global__ void k_mlp_features(int64_t npts, int nmom, const double *__restrict_
     x[3] = (float)(U[2] / umax);
     x[4] = (float)log(th);
     x[5] = (float)(umax / 10.0);
-    x[6] = (float)(nv / 32.0);
+    x[6] = (float)(vg.nv[0] / 32.0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double ph = vg.du[d] > 0.0 ? kTwoPi * (U[d] - vg.umin[d]) / vg.du[d] : 0.0;
+        x[7 + d] = (float)sin(ph);
+        x[10 + d] = (float)cos(ph);
+    }
 }
 
 __global__ void k_collide(const VGrid vg, const double *__restrict__ eqs, const void *fv, void *Sv, int accumulate,
@@ -859,7 +955,7 @@ double grid_umax(const VGrid &vg) {
 int mlp_predict(fr_dvm *h, const double *Q, int64_t n, int nmom, float *dz) {
     const int64_t batch = 65536;
     const int64_t nb = n < batch ? n : batch;
-    const size_t need_x = (size_t)nb * 8, need_w = fr_mlp_workspace_floats(h->mlp_hidden, nb);
+    const size_t need_x = (size_t)nb * (FR_MLP_INPUTS + 1), need_w = fr_mlp_workspace_floats(h->mlp_hidden, nb);
     if (h->mlp_x_n < need_x || h->mlp_work_n < need_w) {
         if (h->d_mlp_x) (void)hipFree(h->d_mlp_x);
         if (h->d_mlp_work) (void)hipFree(h->d_mlp_work);
@@ -873,11 +969,11 @@ int mlp_predict(fr_dvm *h, const double *Q, int64_t n, int nmom, float *dz) {
     }
     const double umax = grid_umax(h->vg);
     const double du = std::fmax(h->vg.du[0], std::fmax(h->vg.du[1], h->vg.du[2]));
-    float *env = h->d_mlp_x + (size_t)nb * 7;
+    float *env = h->d_mlp_x + (size_t)nb * FR_MLP_INPUTS;
     for (int64_t b0 = 0; b0 < n; b0 += batch) {
         const int64_t m = (n - b0) < batch ? (n - b0) : batch;
         hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, h->stream, m, nmom,
-                           Q + b0 * nmom, umax, (double)h->vg.nv[0], du, h->d_mlp_x, env);
+                           Q + b0 * nmom, h->vg, umax, du, h->d_mlp_x, env);
         int rc = fr_mlp_forward(h->mlp_hidden, h->d_mlp, h->d_mlp_x, m, dz + b0 * 5, h->d_mlp_work, h->stream);
         if (rc) return h->fail(rc, "MLP forward");
         hipLaunchKernelGGL(k_mlp_scale, dim3((unsigned)((m * 5 + 255) / 256)), dim3(256), 0, h->stream, m, env,

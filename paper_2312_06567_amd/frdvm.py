@@ -19,6 +19,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fr_dvm.h")
 BGK, ESBGK, FREE = 0, 1, 2
 FP64, FP32 = 0, 1
 GUESS_COLD, GUESS_WARM, GUESS_MLP, GUESS_MLP_WARM = 0, 1, 2, 3
+MLP_INPUTS = 13  # FR_MLP_INPUTS of fr_dvm_mlp.h
 SSPRK3, LSRK3_2N = 0, 1
 NEWTON_OK, NEWTON_FALLBACK, NEWTON_NONREAL, NEWTON_ESGUARD = 0, 1, 2, 3
 
@@ -124,6 +125,8 @@ class Mlp:
 
     def forward(self, w, X, out=None, work=None):
         import torch
+        if X.dim() != 2 or X.shape[1] != MLP_INPUTS:
+            raise FrDvmError(f"features must be [B, {MLP_INPUTS}]")
         B = X.shape[0]
         out = torch.empty((B, 5), dtype=torch.float32, device="cuda") if out is None else out
         work = self.workspace(B) if work is None else work
@@ -134,6 +137,8 @@ class Mlp:
 
     def grad(self, w, X, T, grad=None, loss=None, work=None):
         import torch
+        if X.dim() != 2 or X.shape[1] != MLP_INPUTS:
+            raise FrDvmError(f"features must be [B, {MLP_INPUTS}]")
         B = X.shape[0]
         grad = torch.empty(self.n, dtype=torch.float32, device="cuda") if grad is None else grad
         loss = torch.empty(1, dtype=torch.float32, device="cuda") if loss is None else loss

@@ -32,14 +32,19 @@ def handle_for_grid(umax: float, nv: int, tol=1e-13, max_iter=100):
 
 
 def features(rho, U, theta, umax, nv):
-    """Network inputs as float32 (the same formula the Newton kernel uses)."""
+    """Network inputs as float32, the formula of the library's feature kernel
+    for the grid [-u_max, u_max]^3 with nv nodes per axis: [ln rho, U/u_max,
+    ln theta, u_max/10, n_v/32, sin phi, cos phi] with the grid phase
+    phi = 2 pi (U + u_max)/du of the bulk velocity."""
     import torch
     rho = torch.as_tensor(rho, dtype=torch.float64)
     U = torch.as_tensor(U, dtype=torch.float64)
     th = torch.as_tensor(theta, dtype=torch.float64)
     um = torch.as_tensor(umax, dtype=torch.float64).reshape(-1, 1).expand(rho.shape[0], 1)
+    du = 2.0 * um / (nv - 1)
+    ph = 2.0 * math.pi * (U + um) / du
     X = torch.cat([rho.log()[:, None], U / um, th.log()[:, None], um / 10.0,
-                   torch.full_like(um, nv / 32.0)], 1)
+                   torch.full_like(um, nv / 32.0), ph.sin(), ph.cos()], 1)
     return X.float()
 
 
@@ -95,7 +100,7 @@ def train(X, T, H=64, steps=3000, batch=4096, lr=1e-3, seed=4, log_every=0):
     rng = np.random.default_rng(seed)
     w0 = np.zeros(net.n, np.float32)
     o = 0
-    for (m, k) in [(H, 7), (H, H), (H, H), (5, H)]:
+    for (m, k) in [(H, frdvm.MLP_INPUTS), (H, H), (H, H), (5, H)]:
         lim = math.sqrt(6.0 / k)
         w0[o:o + m * k] = rng.uniform(-lim, lim, m * k)
         o += m * k + m

@@ -5,6 +5,8 @@ import os
 
 import pytest
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
 
 def test_library_exports_every_header_symbol():
     from paper_2312_06567_amd import frdvm
@@ -34,3 +36,15 @@ def test_oracle_and_library_share_no_code():
             assert "import paper_2312_06567_amd" not in txt
             assert "from paper_2312_06567_amd" not in txt
             assert "frdvm_common" not in txt and "fr_dvm.h" not in txt
+
+
+def test_mlp_input_width_agrees_everywhere():
+    """FR_MLP_INPUTS of the header, the binding constant, the library's
+    parameter count and the oracle network describe the same network."""
+    import re
+    from oracle import mlp as omlp
+    from paper_2312_06567_amd import frdvm
+    hdr = open(os.path.join(ROOT, "include", "fr_dvm_mlp.h")).read()
+    n_in = int(re.search(r"#define FR_MLP_INPUTS (\d+)", hdr).group(1))
+    assert n_in == frdvm.MLP_INPUTS == omlp.N_IN
+    assert frdvm.lib().fr_mlp_param_count(64) == omlp.n_params(64)

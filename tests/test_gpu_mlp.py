@@ -33,7 +33,7 @@ def _rand_net(H, seed):
 def test_forward_matches_oracle(F, H, B):
     rng = np.random.default_rng(1)
     w = _rand_net(H, 2)
-    X = rng.standard_normal((B, 7))
+    X = rng.standard_normal((B, omlp.N_IN))
     ref = omlp.predict(w, X, H)
     net = F.Mlp(H)
     got = net.forward(torch.as_tensor(w, dtype=torch.float32).cuda(),
@@ -47,7 +47,7 @@ def test_gradient_matches_oracle(F, H, B):
     to central finite differences): relative L2 <= 1e-3 per layer."""
     rng = np.random.default_rng(3)
     w = _rand_net(H, 4)
-    X = rng.standard_normal((B, 7))
+    X = rng.standard_normal((B, omlp.N_IN))
     T = rng.standard_normal((B, 5))
     loss_ref, g_ref = omlp.loss_and_grad(w, X, T, H)
     net = F.Mlp(H)
