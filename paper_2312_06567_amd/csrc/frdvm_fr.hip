@@ -228,6 +228,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     constexpr int N = P + 1, NS = N * N * N, NL = N * N;
     constexpr int VPW = 64 / N;   // velocities per wave
     constexpr int VPB = 4 * VPW;  // velocities per workgroup and chunk
+
     constexpr int TR = tile_row<Real>(NS, NL);
     constexpr bool FLUX = MODE != MODE_PRIME;
     constexpr bool STAGE = MODE == MODE_STAGE;
@@ -253,7 +254,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     const int64_t ebase = e * (int64_t)NS * nu;
     const uint32_t lrow = (uint32_t)(l * NL) * (uint32_t)nu;     // offset of the layer inside the element
     const uint32_t QB = (uint32_t)nu * (uint32_t)sizeof(Real);  // bytes between solution points
-    const int kw = wave * VPW + vl;
+    // first velocity of this wave in chunk ch
+    auto kbase = [&](int ch) { return ch * VPB + wave * VPW; };
 
     const bool collide = STAGE && A.sa.collide;
     if (collide) {
@@ -321,7 +323,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     // fetches the N points (i, j = l) and passes them on through the tile.
     Real fc[NL], TX[N], TY[N], TZ[N];
     {
-        const Vel v0 = velocity(A, kw, lane_ok);
+        const Vel v0 = velocity(A, kbase(0) + vl, lane_ok);
         const uint32_t o = (lrow + (uint32_t)v0.k) * (uint32_t)sizeof(Real);
 #pragma unroll
         for (int q = 0; q < NL; ++q) fc[q] = ldb(fE, o + q * QB);
@@ -339,12 +341,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     }
 
     for (int ch = 0; ch < nchunk; ++ch) {
-        const Vel v = velocity(A, ch * VPB + kw, lane_ok);
+        const Vel v = velocity(A, kbase(ch) + vl, lane_ok);
         const uint32_t o = (lrow + (uint32_t)v.k) * (uint32_t)sizeof(Real);
         TraceOff nx{0u, 0u}, ny{0u, 0u}, nz{0u, 0u};
         Real f[NL];
         {
-            const Vel vn = velocity(A, (ch + 1) * VPB + kw, lane_ok);
+            const Vel vn = velocity(A, kbase(ch + 1) + vl, lane_ok);
             const uint32_t on = (lrow + (uint32_t)vn.k) * (uint32_t)sizeof(Real);
 #pragma unroll
             for (int q = 0; q < NL; ++q) {
@@ -539,7 +541,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                 }
             }
             if (A.do_moments && lane < NS) {
-                const int kb = ch * VPB + wave * VPW;
+                const int kb = kbase(ch);
                 // wave-uniform weights through the scalar cache (the table is
                 // never written by the kernel)
                 const __attribute__((address_space(4))) double *wp =

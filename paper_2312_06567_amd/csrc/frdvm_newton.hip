@@ -205,9 +205,13 @@ __device__ void sums_bgk(const NewtonArgs &A, const double U[3], double ist, con
     s.Sc2q = K * t4;
 }
 
+// ES sums: kLpp lanes per solution point (two points per wave), reduced by
+// a butterfly inside each half-wave.
+constexpr int kLpp = 32;
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int o = kLpp / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kLpp);
     return v;
 }
 
@@ -220,7 +224,7 @@ __device__ void sums_es(const NewtonArgs &A, int lane, const double U[3], double
 #pragma unroll
     for (int a = 0; a < 18; ++a) acc[a] = 0.0;
     const VGrid &vg = A.vg;
-    for (int k = lane; k < vg.nu; k += 64) {
+    for (int k = lane; k < vg.nu; k += kLpp) {
         const int i = k % vg.nv[0], j = (k / vg.nv[0]) % vg.nv[1], l = k / (vg.nv[0] * vg.nv[1]);
         const double c0 = (gridu(vg, 0, i) - U[0]) * ist;
         const double c1 = (gridu(vg, 1, j) - U[1]) * ist;
@@ -300,7 +304,7 @@ __host__ __device__ inline FactLayout fact_layout(const VGrid &vg) {
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    for (int o = kLpp / 2; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kLpp));
     return v;
 }
 
@@ -325,7 +329,7 @@ __device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const do
     for (int d = 0; d < 3; ++d) {
         const int nd = d == 0 ? L.n0 : (d == 1 ? L.n1 : L.n2);
         const int oc = d == 0 ? L.c0 : (d == 1 ? L.c1 : L.c2);
-        for (int i = lane; i < nd; i += 64) {
+        for (int i = lane; i < nd; i += kLpp) {
             const double c = (gridu(vg, d, i) - U[d]) * ist;
             double arg = c * (z[1 + d] - hz * Am[d][d] * c);
             if (d == 0) arg += z[0];
@@ -349,7 +353,7 @@ __device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const do
     // recurrence from its larger end (2 exponentials per row; values only
     // shrink along the recurrence, so an underflow is a true underflow).
     const double k01 = -z[4] * Am[0][1], k02 = -z[4] * Am[0][2], k12 = -z[4] * Am[1][2];
-    for (int t = lane; t < 2 * L.n0 + L.n1; t += 64) {
+    for (int t = lane; t < 2 * L.n0 + L.n1; t += kLpp) {
         double kc, *dst;
         const double *cb;
         int nb;
@@ -395,12 +399,12 @@ __device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const do
     const double t01 = 2.0 * Am[0][1], t02 = 2.0 * Am[0][2], t12 = 2.0 * Am[1][2];
     const int nP = L.n0 * L.n1;
     const int ne = jac ? 5 : 3;
-    for (int p0 = lane; p0 < nP; p0 += 64 * B) {
+    for (int p0 = lane; p0 < nP; p0 += kLpp * B) {
         int qo[B], ro[B];
         double T[B][5];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int p = p0 + 64 * b < nP ? p0 + 64 * b : p0;
+            const int p = p0 + kLpp * b < nP ? p0 + kLpp * b : p0;
             qo[b] = L.Q + (p % L.n0) * L.ld2;
             ro[b] = L.R + (p / L.n0) * L.ld2;
 #pragma unroll
@@ -421,7 +425,7 @@ __device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const do
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const int p = p0 + 64 * b;
+            const int p = p0 + kLpp * b;
             if (p >= nP) break;
             const int i = p % L.n0, j = p / L.n0;
             const double T0 = T[b][0], T1 = T[b][1], T2 = T[b][2], T3 = T[b][3], T4 = T[b][4];
@@ -730,13 +734,20 @@ __global__ __launch_bounds__(256) void k_newton_bgk(const NewtonArgs A) {
 }
 
 #ifndef FRDVM_WAVES_ES
-#define FRDVM_WAVES_ES 1
+#define FRDVM_WAVES_ES 2
 #endif
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FRDVM_WAVES_ES))) void k_newton_es(
+// One solution point per kLpp lanes: two per wave, four per 128-thread
+// workgroup (the per-point LDS tables of four points fit three workgroups
+// per CU).
+constexpr int kEsBlock = 128;
+constexpr int kEsPts = kEsBlock / kLpp;
+
+__global__ __launch_bounds__(kEsBlock) __attribute__((amdgpu_waves_per_eu(FRDVM_WAVES_ES))) void k_newton_es(
     const NewtonArgs A) {
-    const int lane = threadIdx.x & 63;
-    const int64_t pt = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (pt >= A.npts) return;  // whole waves exit together
+    const int lane = threadIdx.x % kLpp;
+    const int slot = threadIdx.x / kLpp;
+    const int64_t pt = (int64_t)blockIdx.x * kEsPts + slot;
+    if (pt >= A.npts) return;  // a point's lanes exit together
     const double *Q = A.Q + pt * A.nmom;
     const double rho = Q[0];
     const double irho = 1.0 / rho;
@@ -777,7 +788,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FRDVM_WAVES
     double z[5];
     const double wscale = ist * ist * ist;
     extern __shared__ double es_tables[];
-    double *tb = es_tables + (threadIdx.x >> 6) * (A.use_fact ? fact_layout(A.vg).total : 0);
+    double *tb = es_tables + slot * (A.use_fact ? fact_layout(A.vg).total : 0);
     auto fn = [&](const double zz[5], Sums &s, bool jac) {
         if (!(A.use_fact && sums_es_fact(A, lane, tb, U, ist, Am, zz, s, jac)))
             sums_es(A, lane, U, ist, wscale, Am, zz, s, jac);
@@ -1010,9 +1021,10 @@ int launch_newton(fr_dvm *h, int guess) {
     A.pt_resid = h->d_pt_resid;
     ProfScope ps(h, 1);
     if (h->prm.model == FR_DVM_ESBGK) {
-        const size_t shm = 4 * sizeof(double) * (size_t)fact_layout(h->vg).total;
+        const size_t shm = kEsPts * sizeof(double) * (size_t)fact_layout(h->vg).total;
         A.use_fact = (shm <= 65536) && !h->es_direct;
-        hipLaunchKernelGGL(k_newton_es, dim3((unsigned)((A.npts + 3) / 4)), dim3(256), A.use_fact ? shm : 0,
+        hipLaunchKernelGGL(k_newton_es, dim3((unsigned)((A.npts + kEsPts - 1) / kEsPts)), dim3(kEsBlock),
+                           A.use_fact ? shm : 0,
                            h->stream, A);
     } else {
         hipLaunchKernelGGL(k_newton_bgk, dim3((unsigned)((A.npts + 255) / 256)), dim3(256), 0, h->stream, A);
