@@ -78,9 +78,9 @@ struct fr_dvm {
     double *d_gfac = nullptr;    // [ne][3]
     int32_t *d_nbr = nullptr;    // [ne][6]
     double *d_wq3J = nullptr;    // [ne*ns] Gauss weight x |J| per solution point
-    double *d_wpsi = nullptr;    // [nu_pad][nmom] velocity weight x collision invariant
+    double *d_wx3 = nullptr;     // [nv_x][3] moment weights along x: w, w u_x, w u_x^2
+    double *d_wrow = nullptr;    // [nv_y nv_z][6] per (y,z) row: W, W u_y, W u_z, W u_y^2, W u_z^2, W u_y u_z
     double *d_wax = nullptr;     // [3][64] 1-D weights
-    int nu_pad = 0;
 
     // parameters
     fr_dvm_params prm{};

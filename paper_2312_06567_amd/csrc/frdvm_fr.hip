@@ -43,10 +43,10 @@ namespace {
 constexpr int MODE_PRIME = 0, MODE_STAGE = 1, MODE_RESID = 2;
 
 #ifndef FRDVM_WAVES_F32
-#define FRDVM_WAVES_F32 3
+#define FRDVM_WAVES_F32 4
 #endif
 #ifndef FRDVM_WAVES_F64
-#define FRDVM_WAVES_F64 1
+#define FRDVM_WAVES_F64 2
 #endif
 
 // FR operators in the working precision of the kernel.
@@ -66,7 +66,8 @@ struct FrArgs {
     int nu;
     const double *gfac;     // [ne][3]
     const int32_t *nbr;     // [ne][6]
-    const double *wpsi;     // [nu_pad][NMOM]
+    const double *wx3;      // [nv_x][3] moment weights along x
+    const double *wrow;     // [nv_y nv_z][6] moment weights of a (y, z) row
     StageArgs sa;
     int do_traces, do_moments;
 };
@@ -78,8 +79,23 @@ __device__ __forceinline__ const OpsR<float> &ops_of<float>(const FrArgs &A) { r
 template <>
 __device__ __forceinline__ const OpsR<double> &ops_of<double>(const FrArgs &A) { return A.od; }
 
-__device__ __forceinline__ float exp_r(float x) { return __expf(x); }
-__device__ __forceinline__ double exp_r(double x) { return exp(x); }
+// exp of an exponent held in FP64, returned in the working precision.  For
+// FP32 the reduction to 2^n 2^r, |r| <= 1/2, is done in FP64 and only 2^r is
+// taken in FP32: the result carries the ~1 ulp error of the hardware exp2
+// and no error proportional to |E| (an FP32 exponent of a few units would
+// bias every equilibrium value of a point by ~1e-7 and spoil conservation).
+template <typename Real>
+__device__ __forceinline__ Real exp_r(double E);
+template <>
+__device__ __forceinline__ float exp_r<float>(double E) {
+    const double e2 = E * 1.4426950408889634074;  // log2(e)
+    const double n = rint(e2);
+    return ldexpf(__builtin_amdgcn_exp2f((float)(e2 - n)), (int)n);
+}
+template <>
+__device__ __forceinline__ double exp_r<double>(double E) {
+    return exp(E);
+}
 
 // Element-relative access: `base` is uniform (one element's slab), `boff`
 // the lane's byte offset inside it (a slab stays below 4 GiB: at most
@@ -216,14 +232,15 @@ __device__ __forceinline__ void keep(T &x) {
     asm volatile("" : "+v"(x));
 }
 
-// Waves per SIMD the register allocation is held to.
-template <typename Real>
+// Waves per SIMD the register allocation is held to (the prime pass keeps
+// little state and is given more).
+template <typename Real, int MODE>
 constexpr int fr_waves() {
-    return sizeof(Real) == 4 ? FRDVM_WAVES_F32 : FRDVM_WAVES_F64;
+    return MODE == MODE_PRIME ? 4 : (sizeof(Real) == 4 ? FRDVM_WAVES_F32 : FRDVM_WAVES_F64);
 }
 
 template <typename Real, int P, int NMOM, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves<Real>()))) void k_fr_layer(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves<Real, MODE>()))) void k_fr_layer(
     const FrArgs A) {
     constexpr int N = P + 1, NS = N * N * N, NL = N * N;
     constexpr int VPW = 64 / N;   // velocities per wave
@@ -233,8 +250,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     constexpr bool FLUX = MODE != MODE_PRIME;
     constexpr bool STAGE = MODE == MODE_STAGE;
     // equilibrium of each solution point: b (the exponent's quadratic form,
-    // -1/2 B with doubled off-diagonal terms), c0, 1/tau; and V in FP64
-    __shared__ __attribute__((aligned(16))) Real s_eb[STAGE ? NS * 8 : 1];
+    // -1/2 B with doubled off-diagonal terms), c0, 1/tau; and V; all FP64
+    // (the exponent is formed in FP64 in both precisions)
+    __shared__ __attribute__((aligned(16))) double s_eb[STAGE ? NS * 8 : 1];
     __shared__ __attribute__((aligned(16))) double s_ev[STAGE ? NS * 4 : 1];
     __shared__ __attribute__((aligned(16))) Real tile[4][VPW][TR];
     __shared__ __attribute__((aligned(16))) LdsTab<Real> T;
@@ -261,15 +279,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     if (collide) {
         for (int s = tid; s < NS; s += kBlock) {
             const double *q = A.sa.eq + (e * NS + s) * kEqW;
-            Real *b = &s_eb[s * 8];
-            b[0] = (Real)(-0.5 * q[EQ_B]);
-            b[1] = (Real)(-0.5 * q[EQ_B + 1]);
-            b[2] = (Real)(-0.5 * q[EQ_B + 2]);
-            b[3] = (Real)(-q[EQ_B + 3]);
-            b[4] = (Real)(-q[EQ_B + 4]);
-            b[5] = (Real)(-q[EQ_B + 5]);
-            b[6] = (Real)q[EQ_C0];
-            b[7] = (Real)q[EQ_INVTAU];
+            double *b = &s_eb[s * 8];
+            b[0] = -0.5 * q[EQ_B];
+            b[1] = -0.5 * q[EQ_B + 1];
+            b[2] = -0.5 * q[EQ_B + 2];
+            b[3] = -q[EQ_B + 3];
+            b[4] = -q[EQ_B + 4];
+            b[5] = -q[EQ_B + 5];
+            b[6] = q[EQ_C0];
+            b[7] = q[EQ_INVTAU];
             s_ev[s * 4] = q[EQ_V];
             s_ev[s * 4 + 1] = q[EQ_V + 1];
             s_ev[s * 4 + 2] = q[EQ_V + 2];
@@ -343,109 +361,104 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     for (int ch = 0; ch < nchunk; ++ch) {
         const Vel v = velocity(A, kbase(ch) + vl, lane_ok);
         const uint32_t o = (lrow + (uint32_t)v.k) * (uint32_t)sizeof(Real);
-        TraceOff nx{0u, 0u}, ny{0u, 0u}, nz{0u, 0u};
-        Real f[NL];
+        // Publish the stage value (and, for the residual, this lane's z-face
+        // traces) to the tile; every later use of the stage value reads it
+        // there, so its registers take the next chunk's loads right away.
+        wave_sync();
+        if (lane_ok) {
+#pragma unroll
+            for (int q = 0; q < NL; ++q) tile[wave][vl][l * NL + q] = fc[q];
+            if (FLUX) {
+#pragma unroll
+                for (int a = 0; a < N; ++a) tile[wave][vl][NS + N * l + a] = TZ[a];
+            }
+        }
+        wave_sync();
+        TraceOff nx{0u, 0u}, ny{0u, 0u};
         {
             const Vel vn = velocity(A, kbase(ch + 1) + vl, lane_ok);
             const uint32_t on = (lrow + (uint32_t)vn.k) * (uint32_t)sizeof(Real);
 #pragma unroll
-            for (int q = 0; q < NL; ++q) {
-                f[q] = fc[q];
-                fc[q] = ldb(fE, on + q * QB);
-            }
+            for (int q = 0; q < NL; ++q) fc[q] = ldb(fE, on + q * QB);
             if (FLUX) {
                 nx = trace_in<Real>(A, T, vn, 0, N * l);
                 ny = trace_in<Real>(A, T, vn, 1, N * l);
-                nz = trace_in<Real>(A, T, vn, 2, N * l);
+                const TraceOff nz = trace_in<Real>(A, T, vn, 2, N * l);
+#pragma unroll
+                for (int a = 0; a < N; ++a) TZ[a] = ldb(trE, nz.off + a * nz.stride);
             }
         }
-        Real X[NL];
+        const Real *trow = &tile[wave][vl][l * NL];  // this lane's layer of the stage value
+        Real f[NL];  // the produced value (stage) or the stage value itself (prime)
 
         if (FLUX) {
-            // publish the stage value and this lane's z-face traces
-            wave_sync();
-            if (lane_ok) {
-#pragma unroll
-                for (int q = 0; q < NL; ++q) tile[wave][vl][l * NL + q] = f[q];
-#pragma unroll
-                for (int a = 0; a < N; ++a) tile[wave][vl][NS + N * l + a] = TZ[a];
-            }
-            wave_sync();
-#pragma unroll
-            for (int a = 0; a < N; ++a) TZ[a] = ldb(trE, nz.off + a * nz.stride);
             Real r[NL];
 #pragma unroll
             for (int q = 0; q < NL; ++q) r[q] = Real(0);
             const Real ax = (Real)(gf[0] * v.u[0]), ay = (Real)(gf[1] * v.u[1]), az = (Real)(gf[2] * v.u[2]);
-            // x and y derivatives inside the layer
-#pragma unroll
-            for (int j = 0; j < N; ++j)
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    Real tx = Real(0), ty = Real(0);
-#pragma unroll
-                    for (int m = 0; m < N; ++m) {
-                        tx += op.D[i * N + m] * f[m + N * j];
-                        ty += op.D[j * N + m] * f[i + N * m];
-                    }
-                    r[i + N * j] += ax * tx + ay * ty;
-                }
-            // z lines: derivative and the inflow correction of the z faces
-            {
-                const int zin = v.sgn[2] > 0 ? 0 : 1;
-                const bool zflow = v.act && v.sgn[2] != 0;
-                const Real unz = (Real)((zin ? 1.0 : -1.0) * gf[2] * v.u[2]);
-                const Real cz = zflow ? (zin ? corrz[1] : corrz[0]) * unz : Real(0);
-                Real lz[N];
-#pragma unroll
-                for (int m = 0; m < N; ++m) lz[m] = T.lam[zin][m];
-                // one layer row of the tile at a time (bounded register use):
-                // derivative straight into r, the interior z trace into fmz
-                Real fmz[NL];
-#pragma unroll
-                for (int m = 0; m < N; ++m) {
-                    const Real azd = az * Dz[m];
-#pragma unroll
-                    for (int q = 0; q < NL; ++q) {
-                        const Real g = tile[wave][vl][m * NL + q];
-                        r[q] = fma(azd, g, r[q]);
-                        fmz[q] = m == 0 ? lz[0] * g : fma(lz[m], g, fmz[q]);
-                        keep(r[q]);
-                        keep(fmz[q]);
-                    }
-                    phase_fence();
-                }
-#pragma unroll
-                for (int q = 0; q < NL; ++q) {
-                    const Real fp = zflow ? tile[wave][vl][NS + q] : fmz[q];
-                    r[q] = fma(cz, fp - fmz[q], r[q]);
-                }
-                phase_fence();
-            }
-            if (useX) {
-#pragma unroll
-                for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
-            }
-            // x faces: face points (j, l); y faces: face points (i, l)
+            // x lines (rows j) then y lines (columns i) of the layer: the
+            // derivative and the inflow correction of the x / y faces
+            // (face points (j, l) / (i, l))
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
                 const bool flow = v.act && v.sgn[d] != 0;
                 const int sin_ = v.sgn[d] > 0 ? 0 : 1;
                 const Real un = (Real)((sin_ ? 1.0 : -1.0) * gf[d] * v.u[d]);
+                const Real ad = d == 0 ? ax : ay;
                 const TraceOff sn = d == 0 ? nx : ny;
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
+                    Real g[N];
+#pragma unroll
+                    for (int m = 0; m < N; ++m) g[m] = trow[d == 0 ? m + N * a : a + N * m];
                     Real fm = Real(0);
 #pragma unroll
-                    for (int m = 0; m < N; ++m)
-                        fm += T.lam[sin_][m] * (d == 0 ? f[m + N * a] : f[a + N * m]);
+                    for (int m = 0; m < N; ++m) fm += T.lam[sin_][m] * g[m];
                     Real &tin = d == 0 ? TX[a] : TY[a];
                     const Real jmp = flow ? un * (tin - fm) : Real(0);
                     tin = ldb(trE, sn.off + a * sn.stride);
 #pragma unroll
-                    for (int m = 0; m < N; ++m)
-                        r[d == 0 ? m + N * a : a + N * m] += T.corr[sin_][m] * jmp;
+                    for (int i = 0; i < N; ++i) {
+                        Real t = Real(0);
+#pragma unroll
+                        for (int m = 0; m < N; ++m) t += op.D[i * N + m] * g[m];
+                        Real &ri = r[d == 0 ? i + N * a : a + N * i];
+                        ri = fma(ad, t, ri);
+                        ri = fma(T.corr[sin_][i], jmp, ri);
+                        keep(ri);
+                    }
+                    phase_fence();
                 }
+            }
+            Real X[NL];
+            if (useX) {
+#pragma unroll
+                for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
+            }
+            // z lines: derivative and inflow correction of the z faces in one
+            // pass over the tile rows, r += sum_m (az Dz[m] - cz lam[m]) f_m,
+            // then r += cz f+ (the interior trace folded into the coefficients)
+            {
+                const int zin = v.sgn[2] > 0 ? 0 : 1;
+                const bool zflow = v.act && v.sgn[2] != 0;
+                const Real unz = (Real)((zin ? 1.0 : -1.0) * gf[2] * v.u[2]);
+                const Real cz = zflow ? (zin ? corrz[1] : corrz[0]) * unz : Real(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const Real cm = az * Dz[m] - cz * T.lam[zin][m];
+#pragma unroll
+                    for (int q = 0; q < NL; ++q) {
+                        r[q] = fma(cm, tile[wave][vl][m * NL + q], r[q]);
+                        keep(r[q]);
+                    }
+                    phase_fence();
+                }
+#pragma unroll
+                for (int q = 0; q < NL; ++q) {
+                    const Real fp = zflow ? tile[wave][vl][NS + q] : Real(0);
+                    r[q] = fma(cz, fp, r[q]);
+                }
+                phase_fence();
             }
             if (MODE == MODE_RESID) {
                 if (v.act) {
@@ -458,24 +471,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
             const Real dt = (Real)A.sa.dt;
 #pragma unroll
             for (int q = 0; q < NL; ++q) {
-                const Real fq = tile[wave][vl][l * NL + q];  // stage value (also in f until here)
+                const Real fq = trow[q];
                 Real L = -r[q];
                 if (collide) {
                     const int s = l * NL + q;
-                    const Real *b = &s_eb[s * 8];
+                    const double *b = &s_eb[s * 8];
                     const double *V = &s_ev[s * 4];
-                    // differences of O(u_max) numbers in FP64, the quadratic form in Real
-                    const Real c0 = (Real)(v.u[0] - V[0]), c1 = (Real)(v.u[1] - V[1]), c2 = (Real)(v.u[2] - V[2]);
-                    Real t0 = b[0] * c0;
+                    const double c0 = v.u[0] - V[0], c1 = v.u[1] - V[1], c2 = v.u[2] - V[2];
+                    double t0 = b[0] * c0;
                     t0 = fma(b[3], c1, t0);
                     t0 = fma(b[4], c2, t0);
-                    Real t1 = b[1] * c1;
+                    double t1 = b[1] * c1;
                     t1 = fma(b[5], c2, t1);
-                    const Real t2 = b[2] * c2;
-                    Real E = fma(c0, t0, b[6]);
+                    const double t2 = b[2] * c2;
+                    double E = fma(c0, t0, b[6]);
                     E = fma(c1, t1, E);
                     E = fma(c2, t2, E);
-                    L += (exp_r(E) - fq) * b[7];
+                    L += (exp_r<Real>(E) - fq) * (Real)b[7];
                 }
                 Real fo;
                 if (A.sa.scheme == 0) {
@@ -491,6 +503,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                 if (v.act) stb(outE, o + q * QB, fo);
                 if (q % 4 == 3) phase_fence();
             }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NL; ++q) f[q] = trow[q];
         }
 
         // outflow traces of the produced value on the x and y faces, into
@@ -516,14 +531,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
             }
         }
 
-        // tile of the produced value: z traces and the moment reduction
+        // tile of the produced value (the prime pass left the value there):
+        // z traces and the moment reduction
         if (A.do_moments || A.do_traces) {
-            wave_sync();
-            if (lane_ok) {
+            if (FLUX) {
+                wave_sync();
+                if (lane_ok) {
 #pragma unroll
-                for (int q = 0; q < NL; ++q) tile[wave][vl][l * NL + q] = f[q];
+                    for (int q = 0; q < NL; ++q) tile[wave][vl][l * NL + q] = f[q];
+                }
+                wave_sync();
             }
-            wave_sync();
             if (A.do_traces && v.act && v.sgn[2] != 0) {
                 // this lane writes the z-face points (i, j = l)
                 const int side = v.sgn[2] > 0 ? 1 : 0;
@@ -541,22 +559,52 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                 }
             }
             if (A.do_moments && lane < NS) {
+                // Moments of this wave's velocities (lane = solution point).
+                // Along an x-row only w_x varies with the node; each row
+                // segment is summed as (sum w_x f, sum w_x u_x f, sum w_x u_x^2 f)
+                // and closed with the row's (y, z) weights: 3 FMA per node
+                // instead of one per moment.  Weights are wave-uniform and
+                // read through the scalar cache (never written by the kernel).
+                typedef const __attribute__((address_space(4))) double cdouble;
+                cdouble *wx3 = (cdouble *)A.wx3;
+                cdouble *wrow = (cdouble *)A.wrow;
                 const int kb = kbase(ch);
-                // wave-uniform weights through the scalar cache (the table is
-                // never written by the kernel)
-                const __attribute__((address_space(4))) double *wp =
-                    (const __attribute__((address_space(4))) double *)(A.wpsi + (int64_t)kb * NMOM);
-                double acc[NMOM];
+                const int nx = A.vg.nv[0];
+                const int jn = nu - kb < VPW ? nu - kb : VPW;
+                int ix = kb % nx, row = kb / nx;
+                double M[NMOM], a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
-                for (int a = 0; a < NMOM; ++a) acc[a] = 0.0;
-#pragma unroll 4
-                for (int j = 0; j < VPW; ++j) {
+                for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
+                for (int j = 0; j < jn; ++j) {
                     const double x = (double)tile[wave][j][lane];
-#pragma unroll
-                    for (int a = 0; a < NMOM; ++a) acc[a] += wp[j * NMOM + a] * x;
+                    a0 = fma(wx3[3 * ix], x, a0);
+                    a1 = fma(wx3[3 * ix + 1], x, a1);
+                    a2 = fma(wx3[3 * ix + 2], x, a2);
+                    if (++ix == nx || j == jn - 1) {
+                        cdouble *wr = wrow + 6 * row;
+                        M[0] = fma(wr[0], a0, M[0]);
+                        M[1] = fma(wr[0], a1, M[1]);
+                        M[2] = fma(wr[1], a0, M[2]);
+                        M[3] = fma(wr[2], a0, M[3]);
+                        if constexpr (NMOM == 5) {
+                            M[4] = fma(0.5, fma(wr[0], a2, (wr[3] + wr[4]) * a0), M[4]);
+                        } else {
+                            M[4] = fma(wr[0], a2, M[4]);
+                            M[5] = fma(wr[3], a0, M[5]);
+                            M[6] = fma(wr[4], a0, M[6]);
+                            M[7] = fma(wr[1], a1, M[7]);
+                            M[8] = fma(wr[2], a1, M[8]);
+                            M[9] = fma(wr[5], a0, M[9]);
+                        }
+                        a0 = a1 = a2 = 0.0;
+                        if (ix == nx) {
+                            ix = 0;
+                            ++row;
+                        }
+                    }
                 }
 #pragma unroll
-                for (int a = 0; a < NMOM; ++a) red[wave][lane][a] += acc[a];
+                for (int a = 0; a < NMOM; ++a) red[wave][lane][a] += M[a];
             }
         }
     }
@@ -623,7 +671,8 @@ int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int 
     A.nu = h->vg.nu;
     A.gfac = h->d_gfac;
     A.nbr = h->d_nbr;
-    A.wpsi = h->d_wpsi;
+    A.wx3 = h->d_wx3;
+    A.wrow = h->d_wrow;
     A.sa = sa;
     A.do_traces = do_traces;
     A.do_moments = do_moments;

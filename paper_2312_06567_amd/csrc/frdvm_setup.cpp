@@ -305,26 +305,29 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     }
     if (realloc_mom) {
         if ((rc = dev_alloc(h, &h->d_Q, npts * nmom))) return rc;
-        // padded past the last chunk of every kernel (chunks of at most 256
-        // velocities), zero weights beyond nu
-        h->nu_pad = (int)((nu + kBlock - 1) / kBlock * kBlock + kBlock);
-        std::vector<double> wpsi((size_t)h->nu_pad * nmom, 0.0);
+        // moment weights on the tensor velocity grid: along x per node
+        // (w_x, w_x u_x, w_x u_x^2), per (y, z) row (W, W u_y, W u_z, W u_y^2,
+        // W u_z^2, W u_y u_z) with W = w_y w_z
         const VGrid &vg = h->vg;
-        for (int64_t k = 0; k < nu; ++k) {
-            int i = (int)(k % vg.nv[0]), j = (int)((k / vg.nv[0]) % vg.nv[1]), l = (int)(k / ((int64_t)vg.nv[0] * vg.nv[1]));
-            double ux = vg.umin[0] + i * vg.du[0], uy = vg.umin[1] + j * vg.du[1], uz = vg.umin[2] + l * vg.du[2];
-            double w = h->wax[0][i] * h->wax[1][j] * h->wax[2][l];
-            double *o = &wpsi[(size_t)k * nmom];
-            o[0] = w; o[1] = w * ux; o[2] = w * uy; o[3] = w * uz;
-            if (nmom == 5) {
-                o[4] = 0.5 * w * (ux * ux + uy * uy + uz * uz);
-            } else {
-                o[4] = w * ux * ux; o[5] = w * uy * uy; o[6] = w * uz * uz;
-                o[7] = w * ux * uy; o[8] = w * ux * uz; o[9] = w * uy * uz;
-            }
+        std::vector<double> wx3((size_t)3 * vg.nv[0]), wrow((size_t)6 * vg.nv[1] * vg.nv[2]);
+        for (int i = 0; i < vg.nv[0]; ++i) {
+            const double ux = vg.umin[0] + i * vg.du[0], w = h->wax[0][i];
+            wx3[3 * i] = w;
+            wx3[3 * i + 1] = w * ux;
+            wx3[3 * i + 2] = w * ux * ux;
         }
-        if ((rc = dev_alloc(h, &h->d_wpsi, wpsi.size()))) return rc;
-        if ((rc = upload(h, h->d_wpsi, wpsi.data(), wpsi.size() * sizeof(double)))) return rc;
+        for (int l = 0; l < vg.nv[2]; ++l)
+            for (int j = 0; j < vg.nv[1]; ++j) {
+                const double uy = vg.umin[1] + j * vg.du[1], uz = vg.umin[2] + l * vg.du[2];
+                const double W = h->wax[1][j] * h->wax[2][l];
+                double *o = &wrow[(size_t)6 * (j + (size_t)vg.nv[1] * l)];
+                o[0] = W; o[1] = W * uy; o[2] = W * uz;
+                o[3] = W * uy * uy; o[4] = W * uz * uz; o[5] = W * uy * uz;
+            }
+        if ((rc = dev_alloc(h, &h->d_wx3, wx3.size()))) return rc;
+        if ((rc = upload(h, h->d_wx3, wx3.data(), wx3.size() * sizeof(double)))) return rc;
+        if ((rc = dev_alloc(h, &h->d_wrow, wrow.size()))) return rc;
+        if ((rc = upload(h, h->d_wrow, wrow.data(), wrow.size() * sizeof(double)))) return rc;
     }
     // verification switch: FRDVM_ES_DIRECT=1 makes the ES Newton use the
     // direct per-node sums instead of the factorised ones
@@ -381,7 +384,7 @@ extern "C" const char *fr_dvm_last_error(fr_dvm_t h) { return h ? h->err.c_str()
 extern "C" void fr_dvm_destroy(fr_dvm_t h) {
     if (!h) return;
     if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
-    void *ptrs[] = {h->d_gfac, h->d_nbr, h->d_wq3J, h->d_wpsi, h->d_wax, h->d_reg, h->d_tr[0], h->d_tr[1],
+    void *ptrs[] = {h->d_gfac, h->d_nbr, h->d_wq3J, h->d_wx3, h->d_wrow, h->d_wax, h->d_reg, h->d_tr[0], h->d_tr[1],
                     h->d_Q, h->d_eq, h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
                     h->d_mlp_x, h->d_mlp_work, h->d_mlp_dz, h->d_pt_iters, h->d_pt_evals, h->d_pt_status,
                     h->d_pt_resid};

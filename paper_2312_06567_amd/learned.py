@@ -148,3 +148,51 @@ def fit_guess(n_states=100_000, nv=32, H=64, steps=3000, seed=4, umax_choices=(6
     info = {"n_states": int(len(ok)), "n_converged": int(ok.sum()), "reject_rate": float(st["reject_rate"]),
             "cold_mean_iters": float(sol["iters"][ok].mean()), "loss_history": hist}
     return w.cpu().numpy(), info
+
+
+def evaluate(weights, n_states=100_000, nv=32, seed=99, umax_choices=(6.0, 10.0, 14.0)):
+    """Newton from the cold start and from the learned start on held-out
+    states: mean linear solves and sum passes, both overall and on the states
+    the cold start needs >= 5 solves for, fallbacks, largest final residual
+    and the largest difference of the converged unknowns."""
+    st = W_sample(n_states, seed, umax_choices, nv)
+    a = solve_targets(st, nv=nv, guess=frdvm.GUESS_COLD)
+    b = solve_targets(st, nv=nv, guess=frdvm.GUESS_MLP, weights=weights)
+    ok = (a["status"] == frdvm.NEWTON_OK) & (b["status"] == frdvm.NEWTON_OK)
+    hard = ok & (a["iters"] >= 5)
+    return {"n_states": int(n_states), "both_converged": int(ok.sum()),
+            "cold_solves": float(a["iters"][ok].mean()), "learned_solves": float(b["iters"][ok].mean()),
+            "cold_passes": float(a["evals"][ok].mean()), "learned_passes": float(b["evals"][ok].mean()),
+            "hard_states": int(hard.sum()), "cold_solves_hard": float(a["iters"][hard].mean()),
+            "learned_solves_hard": float(b["iters"][hard].mean()),
+            "fallback_cold": int((a["status"] == frdvm.NEWTON_FALLBACK).sum()),
+            "fallback_learned": int((b["status"] == frdvm.NEWTON_FALLBACK).sum()),
+            "max_resid_cold": float(a["resid"][ok].max()), "max_resid_learned": float(b["resid"][ok].max()),
+            "max_dz_between_roots": float(np.abs(a["z"][ok] - b["z"][ok]).max())}
+
+
+def W_sample(n, seed, umax_choices, nv):
+    import workloads as W
+    return W.sample_states(n, seed=seed, umax_choices=umax_choices, nv=nv)
+
+
+if __name__ == "__main__":
+    # Learned-start study on the 32^3 grids with u_max in {6, 10, 14}: train on
+    # solver-solved states, evaluate on held-out ones; prints one JSON line.
+    import argparse
+    import json
+    import time
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=1_000_000)
+    ap.add_argument("--test", type=int, default=200_000)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--hidden", type=int, default=64)
+    args = ap.parse_args()
+    t0 = time.perf_counter()
+    w, info = fit_guess(n_states=args.train, H=args.hidden, steps=args.steps, seed=4)
+    t1 = time.perf_counter()
+    ev = evaluate(w, n_states=args.test)
+    out = {"train_states": args.train, "train_steps": args.steps, "hidden": args.hidden,
+           "train_seconds": t1 - t0, "final_loss": info["loss_history"][-1][1] if info["loss_history"] else None,
+           "reject_rate": info["reject_rate"], **ev}
+    print(json.dumps(out), flush=True)
