@@ -50,13 +50,14 @@ def stage_values_per_dof(p: int, rk: int, stage: int, last: bool) -> float:
     traces (3/(p+1) values per DOF) and, unless it is the last stage of the
     call, write the result's own outflow traces (3/(p+1)); SSP-RK3 reads f^n
     in stages 2 and 3; the low-storage scheme reads dF in stages 2 and 3 and
-    writes it in every stage.  (Moments and equilibrium records are per
-    solution point, not per DOF: below 0.1 % at 20^3 velocities.)"""
+    writes it in stages 1 and 2 (after stage 3 it is dead).  (Moments and
+    equilibrium records are per solution point, not per DOF: below 0.1 % at
+    20^3 velocities.)"""
     tr = 3.0 / (p + 1)
     v = 2.0 + tr + (0.0 if last else tr)
     if stage > 0:
         v += 1.0
-    if rk == 1:
+    if rk == 1 and stage < 2:
         v += 1.0
     return v
 

@@ -112,10 +112,15 @@ typedef struct {
     int32_t rk;           /* FR_DVM_SSPRK3 | FR_DVM_LSRK3_2N */
     double farfield[5];   /* rho, Ux, Uy, Uz, theta of the farfield Maxwellian (bc 1) */
     double theta_wall;    /* diffuse wall temperature (bc 2), wall at rest */
+    int32_t overlap;      /* rk_step(s): 1 = the Newton solve of the next stage runs
+                             on a second library-owned stream, half of the elements
+                             at a time, while the current stage still streams the
+                             other half; 0 = one stream, stage and Newton in turn.
+                             Results are identical. */
 } fr_dvm_params;
 
 /* Fill p with defaults: BGK, Pr 1, mu_ref 1e-3, theta_ref 1, omega 0.81,
- * FP64, tol 1e-13, 50 iterations, cold guess, SSP-RK3. */
+ * FP64, tol 1e-13, 50 iterations, cold guess, SSP-RK3, overlap 0. */
 void fr_dvm_default_params(fr_dvm_params *p);
 
 /* Create a handle for a mesh, FR order p (solution points (p+1)^3 per

@@ -85,6 +85,53 @@ extern "C" int fr_dvm_collide(fr_dvm_t h, const void *f, void *S, double *Qp, in
     return FR_DVM_OK;
 }
 
+namespace {
+
+// Arguments of RK stage st (0..2) of the handle's scheme, f updated in place.
+StageArgs stage_args(fr_dvm *h, void *f, double dt, int st, int collide) {
+    StageArgs a = blank();
+    a.dt = dt;
+    a.collide = collide;
+    a.eq = h->d_eq;
+    a.tr_in = h->d_tr[h->cur_tr];
+    a.tr_out = h->d_tr[h->cur_tr ^ 1];
+    a.Q = h->d_Q;
+    if (h->prm.rk == FR_DVM_SSPRK3) {
+        static const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
+        a.scheme = 0;
+        a.alpha = al[st];
+        a.beta = be[st];
+        a.f = st == 0 ? f : h->d_reg;
+        a.fn = f;
+        a.fout = st == 2 ? f : h->d_reg;
+    } else {
+        static const double lA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0}, lB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+        a.scheme = 1;
+        a.lsA = lA[st];
+        a.lsB = lB[st];
+        a.keep_dF = st < 2;
+        a.f = f;
+        a.fout = f;
+        a.dF = h->d_reg;
+    }
+    return a;
+}
+
+int ensure_aux(fr_dvm *h) {
+    if (h->aux) return FR_DVM_OK;
+    if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) {
+        h->aux = nullptr;
+        return h->fail(FR_DVM_EHIP, "second stream");
+    }
+    for (int i = 0; i < 2; ++i)
+        if (hipEventCreateWithFlags(&h->ev_stage[i], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_newton[i], hipEventDisableTiming) != hipSuccess)
+            return h->fail(FR_DVM_EHIP, "stream events");
+    return FR_DVM_OK;
+}
+
+}  // namespace
+
 extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
     int rc = ready(h);
     if (rc) return rc;
@@ -96,40 +143,49 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
     // of its result for the next stage)
     if ((rc = prime(h, f, 1, collide))) return rc;
     const int guess = guess_mode(h);
-    for (int step = 0; step < nsteps; ++step) {
-        for (int st = 0; st < 3; ++st) {
-            if (collide && (rc = launch_newton(h, guess))) return rc;
-            StageArgs a = blank();
-            a.dt = dt;
-            a.collide = collide;
-            a.eq = h->d_eq;
-            a.tr_in = h->d_tr[h->cur_tr];
-            a.tr_out = h->d_tr[h->cur_tr ^ 1];
-            a.Q = h->d_Q;
-            if (h->prm.rk == FR_DVM_SSPRK3) {
-                static const double al[3] = {0.0, 0.75, 1.0 / 3.0}, be[3] = {1.0, 0.25, 2.0 / 3.0};
-                a.scheme = 0;
-                a.alpha = al[st];
-                a.beta = be[st];
-                a.f = st == 0 ? f : h->d_reg;
-                a.fn = f;
-                a.fout = st == 2 ? f : h->d_reg;
-            } else {
-                static const double lA[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0}, lB[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
-                a.scheme = 1;
-                a.lsA = lA[st];
-                a.lsB = lB[st];
-                a.f = f;
-                a.fout = f;
-                a.dF = h->d_reg;
+    if (collide && (rc = launch_newton(h, guess))) return rc;
+    // Overlap: the elements are taken in two halves (z slabs).  Stage k of
+    // half 0, then of half 1, on the handle's stream; as soon as stage k of a
+    // half is done, the Newton solve for stage k+1 of that half runs on the
+    // second stream, alongside the stage launch of the other half.  Stage k+1
+    // of a half waits for that half's Newton; it follows stage k of both
+    // halves on its own stream (the neighbour traces it reads).  Per point
+    // the work and its order are those of the single-stream path.
+    // (decided after the first solve: a learned-then-warm start is warm from here on)
+    const bool split = h->prm.overlap && collide && h->ne >= 2 && newton_part_ok(h, guess);
+    if (split && (rc = ensure_aux(h))) return rc;
+    const int64_t eh[3] = {0, h->ne / 2, h->ne};
+    const int nst = 3 * nsteps;
+    for (int k = 0; k < nst; ++k) {
+        const int st = k % 3;
+        const int last = k == nst - 1;
+        StageArgs a = stage_args(h, f, dt, st, collide);
+        const int traces = last ? 0 : 1, moments = (last || !collide) ? 0 : 1;
+        if (!split) {
+            if (k > 0 && collide && (rc = launch_newton(h, guess))) return rc;
+            ProfScope ps(h, 0);
+            if ((rc = launch_fr_axis(h, 1, a, traces, moments))) return rc;
+        } else {
+            for (int half = 0; half < 2; ++half) {
+                if (k > 0 && hipStreamWaitEvent(h->stream, h->ev_newton[half], 0) != hipSuccess)
+                    return h->fail(FR_DVM_EHIP, "stream wait");
+                a.e0 = eh[half];
+                a.ecount = eh[half + 1] - eh[half];
+                {
+                    ProfScope ps(h, 0);
+                    if ((rc = launch_fr_axis(h, 1, a, traces, moments))) return rc;
+                }
+                if (last) continue;
+                if (hipEventRecord(h->ev_stage[half], h->stream) != hipSuccess ||
+                    hipStreamWaitEvent(h->aux, h->ev_stage[half], 0) != hipSuccess)
+                    return h->fail(FR_DVM_EHIP, "stream event");
+                if ((rc = launch_newton_part(h, guess, eh[half] * h->ns, (eh[half + 1] - eh[half]) * h->ns, h->aux)))
+                    return rc;
+                if (hipEventRecord(h->ev_newton[half], h->aux) != hipSuccess)
+                    return h->fail(FR_DVM_EHIP, "stream event");
             }
-            const int last = (step == nsteps - 1) && (st == 2);
-            {
-                ProfScope ps(h, 0);
-                if ((rc = launch_fr_axis(h, 1, a, last ? 0 : 1, (last || !collide) ? 0 : 1))) return rc;
-            }
-            h->cur_tr ^= 1;
         }
+        h->cur_tr ^= 1;
     }
     return FR_DVM_OK;
 }

@@ -59,6 +59,10 @@ struct fr_dvm {
     std::string err;
     hipStream_t stream = nullptr;
     int device = 0;
+    // second stream for the Newton solves overlapped with the stage launches,
+    // and the events that order the two (stage half done, Newton half done)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_stage[2] = {nullptr, nullptr}, ev_newton[2] = {nullptr, nullptr};
 
     // discretisation
     int p = 0, n = 0, ns = 0, nfp = 0;
@@ -128,14 +132,16 @@ namespace frdvm {
 struct ProfScope {
     fr_dvm *h;
     int kind;
+    hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(fr_dvm *h_, int k) : h(h_), kind(k) {
+    // s: the stream the timed launches go to (nullptr: the handle's stream)
+    ProfScope(fr_dvm *h_, int k, hipStream_t s_ = nullptr) : h(h_), kind(k), s(s_ ? s_ : h_->stream) {
         if (h->prof && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
-            (void)hipEventRecord(a, h->stream);
+            (void)hipEventRecord(a, s);
     }
     ~ProfScope() {
         if (a && b) {
-            (void)hipEventRecord(b, h->stream);
+            (void)hipEventRecord(b, s);
             h->prof_recs.push_back({kind, a, b});
         }
     }
@@ -159,12 +165,18 @@ struct StageArgs {
     double dt, alpha, beta;  // SSP: fout = alpha fn + beta (f + dt L)
     double lsA, lsB;         // LSRK: dF = lsA dF + dt L; fout = f + lsB dF
     int scheme;              // 0 SSP, 1 LSRK
+    int keep_dF;             // LSRK: store dF (not after the last stage of a step, where it is dead)
     int collide;             // include the collision source
+    int64_t e0, ecount;      // element range [e0, e0 + ecount); ecount 0: all elements
 };
 int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);
 
 // ---- launchers (frdvm_newton.hip) ----
 int launch_newton(fr_dvm *h, int guess);
+// Newton over the points [p0, p0 + np) on stream s (warm or cold start only;
+// newton_part_ok tells whether the handle's start allows it).
+int newton_part_ok(fr_dvm *h, int guess);
+int launch_newton_part(fr_dvm *h, int guess, int64_t p0, int64_t np, hipStream_t s);
 int launch_newton_points(fr_dvm *h, const double *Q, int64_t n, int guess, double *z, int32_t *iters, int32_t *evals,
                          int32_t *status, double *resid);
 int launch_collide(fr_dvm *h, const void *f, void *S, int accumulate);

@@ -42,8 +42,12 @@ namespace {
 
 constexpr int MODE_PRIME = 0, MODE_STAGE = 1, MODE_RESID = 2;
 
+// Register targets (waves per SIMD) of the stage kernel.  FP32: the LDS of a
+// workgroup (48 KB at p = 3 with the ES moments) admits three workgroups of
+// four waves per CU, i.e. 3 waves/SIMD; a target above what LDS admits is
+// not honoured and leaves the kernel at 2.  FP64: LDS admits two.
 #ifndef FRDVM_WAVES_F32
-#define FRDVM_WAVES_F32 4
+#define FRDVM_WAVES_F32 3
 #endif
 #ifndef FRDVM_WAVES_F64
 #define FRDVM_WAVES_F64 2
@@ -260,7 +264,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     __shared__ __attribute__((aligned(16))) double red[4][NS][NMOM];
 
     const OpsR<Real> &op = ops_of<Real>(A);
-    const int64_t e = blockIdx.x;
+    const int64_t e = A.sa.e0 + blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -496,7 +500,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                 } else {
                     Real dd = dt * L;
                     if (useX) dd += (Real)A.sa.lsA * X[q];
-                    if (v.act) stb(dFE, o + q * QB, dd);
+                    if (v.act && A.sa.keep_dF) stb(dFE, o + q * QB, dd);
                     fo = fq + (Real)A.sa.lsB * dd;
                 }
                 f[q] = v.act ? fo : Real(0);
@@ -620,7 +624,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
 
 template <typename Real, int P, int NMOM>
 int launch_p(fr_dvm *h, int mode, const FrArgs &A) {
-    dim3 grid((unsigned)h->ne), block(kBlock);
+    dim3 grid((unsigned)(A.sa.ecount ? A.sa.ecount : h->ne)), block(kBlock);
     if (mode == MODE_PRIME)
         hipLaunchKernelGGL((k_fr_layer<Real, P, NMOM, MODE_PRIME>), grid, block, 0, h->stream, A);
     else if (mode == MODE_STAGE)
@@ -642,15 +646,26 @@ int launch_np(fr_dvm *h, int mode, const FrArgs &A) {
     return h->fail(FR_DVM_EUNSUPPORTED, "order");
 }
 
-// Streaming copy with 16-byte accesses, grid-stride.
+// Streaming copy with 16-byte accesses, grid-stride, four loads in flight
+// per lane before the stores.
 __global__ __launch_bounds__(256) void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * st < n; i += 4 * st) {
+        const uint4 a = src[i], b = src[i + st], c = src[i + 2 * st], d = src[i + 3 * st];
+        dst[i] = a;
+        dst[i + st] = b;
+        dst[i + 2 * st] = c;
+        dst[i + 3 * st] = d;
+    }
+    for (; i < n; i += st) dst[i] = src[i];
 }
 
 }  // namespace
 
 int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_moments) {
+    if (sa.ecount < 0 || sa.e0 < 0 || (sa.ecount ? sa.e0 + sa.ecount > h->ne : sa.e0 != 0))
+        return h->fail(FR_DVM_EINVAL, "element range");
     FrArgs A;
     std::memset(&A, 0, sizeof(A));
     for (int i = 0; i < kMaxN * kMaxN; ++i) {
@@ -690,8 +705,8 @@ extern "C" int fr_dvm_hbm_copy(void *dst, const void *src, size_t nbytes, void *
     if (d < s + nbytes && s < d + nbytes) return FR_DVM_EINVAL;
     int64_t n = (int64_t)(nbytes / 16);
     if (n == 0) return FR_DVM_OK;
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;
+    int64_t blocks = (n + 1023) / 1024;
+    if (blocks > 256 * 32) blocks = 256 * 32;
     hipLaunchKernelGGL(frdvm::k_copy16, dim3((unsigned)blocks), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
                        static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), n);
     return hipGetLastError() == hipSuccess ? FR_DVM_OK : FR_DVM_EHIP;

@@ -18,8 +18,9 @@
 // BGK kernel: one thread per point.  On a tensor velocity grid the BGK
 // exponential factorises per axis, so each Newton iteration costs 3 n_v
 // exponentials and 1-D power sums instead of n_v^3 terms.
-// ES kernel: one wave64 per point, lanes over velocity nodes, butterfly
-// reduction of the 18 sums (lane-symmetric: every lane gets the same bits).
+// ES kernel: 32 lanes per point (two points per wave), lanes over velocity
+// nodes or node pairs, butterfly reduction of the 18 sums (lane-symmetric:
+// every lane gets the same bits); the iteration state lives in LDS.
 // Starting points: cold (continuous equilibrium of the moments), warm (the
 // previous solution at the point) or learned (cold + a correction predicted
 // by the MLP kernels; the start with the smaller residual is kept, so the
@@ -267,18 +268,21 @@ __device__ void sums_es(const NewtonArgs &A, int lane, const double U[3], double
 }
 
 // ---- factorised ES sums -------------------------------------------------
-// On a tensor grid the exponent z0 + z.c - z4 c^T A c / 2 splits into one-axis
-// terms and three two-axis cross terms, so e = X(i) Y(j) Z(l) P(i,j) Q(i,l)
-// R(j,l): 3n + 3n^2 exponentials per evaluation instead of n^3; the sums
-// follow from T_e(i,j) = sum_l Z c2^e Q R and the pair sums, reduced over the
-// wave.
+// On a tensor grid the exponent z0 + z.c - z4 c^T A c / 2 splits into the
+// one-axis factors X(i), Y(j), Z(l) and the cross factors exp(k01 c0 c1),
+// exp(k02 c0 c2), exp(k12 c1 c2) (k_ab = -z4 A_ab).  The first cross factor
+// is tabulated, P(i,j).  The product of the other two,
+// G(i,j,l) = exp((k02 c0_i + k12 c1_j) c2_l), is geometric in l on a uniform
+// grid with start G0(i) H0(j) and ratio Ra(i) Rb(j), so it is generated along
+// l and needs no table: 3n + 3n + n + 2n exponentials per evaluation.  The
+// sums follow from T_e(i,j) = sum_l Z c2^e G and the pair sums, reduced over
+// the lanes of the point.
 
-
-// Layout of one wave's table region (doubles); rows of the pair tables are
-// padded to an odd length to spread LDS banks.
+// Layout of one point's table region (doubles); rows of P are padded to an
+// odd length to spread LDS banks.
 struct FactLayout {
-    int n0, n1, n2, ld1, ld2;  // ld1 = row length of P (over j), ld2 of Q and R (over l)
-    int c0, c1, c2, X, Y, Zc, P, Q, R, total;
+    int n0, n1, n2, ld1;  // ld1 = row length of P (over j)
+    int c0, c1, c2, X, Y, Zc, P, G0, Ra, H0, Rb, total;
 };
 
 __host__ __device__ inline FactLayout fact_layout(const VGrid &vg) {
@@ -287,7 +291,6 @@ __host__ __device__ inline FactLayout fact_layout(const VGrid &vg) {
     L.n1 = vg.nv[1];
     L.n2 = vg.nv[2];
     L.ld1 = L.n1 | 1;
-    L.ld2 = L.n2 | 1;
     int o = 0;
     L.c0 = o; o += L.n0;
     L.c1 = o; o += L.n1;
@@ -296,8 +299,10 @@ __host__ __device__ inline FactLayout fact_layout(const VGrid &vg) {
     L.Y = o; o += L.n1;
     L.Zc = o; o += 5 * L.n2;
     L.P = o; o += L.n0 * L.ld1;
-    L.Q = o; o += L.n0 * L.ld2;
-    L.R = o; o += L.n1 * L.ld2;
+    L.G0 = o; o += L.n0;
+    L.Ra = o; o += L.n0;
+    L.H0 = o; o += L.n1;
+    L.Rb = o; o += L.n1;
     L.total = o;
     return L;
 }
@@ -314,16 +319,108 @@ __device__ __forceinline__ void lds_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Quadratic-form entries a pair finish needs: A00, A11, A22, 2A01, 2A02, 2A12.
+struct QuadA {
+    double a00, a11, a22, t01, t02, t12;
+};
+
+// B pairs p0 + kLpp b (all < n0 n1) of one lane: T_e = sum_l Z c2^e G for
+// e < NE (5 for the full sums, 3 for the residual sums), then the pairs'
+// contributions to the 18 (5) sums.  Returns the largest |exponent| of G
+// over the pairs (G is exact at both ends of l, hence everywhere between).
+template <int B, int NE>
+__device__ __forceinline__ double pair_block(const FactLayout &L, const double *tb, int p0, double k02, double k12,
+                                             const QuadA &q, double acc[18]) {
+    constexpr bool JAC = NE == 5;
+    double g[B], gr[B], T[B][NE];
+    int ii[B], jj[B];
+    double gmax = 0.0;
+    const double c2a = tb[L.c2], c2b = tb[L.c2 + L.n2 - 1];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int p = p0 + kLpp * b;
+        ii[b] = p % L.n0;
+        jj[b] = p / L.n0;
+        const double kap = k02 * tb[L.c0 + ii[b]] + k12 * tb[L.c1 + jj[b]];
+        gmax = fmax(gmax, fmax(fabs(kap * c2a), fabs(kap * c2b)));
+        g[b] = tb[L.G0 + ii[b]] * tb[L.H0 + jj[b]];
+        gr[b] = tb[L.Ra + ii[b]] * tb[L.Rb + jj[b]];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) T[b][e] = 0.0;
+    }
+    for (int l = 0; l < L.n2; ++l) {
+        const double *zc = tb + L.Zc + 5 * l;
+        double zl[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) zl[e] = zc[e];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) T[b][e] = fma(zl[e], g[b], T[b][e]);
+            g[b] *= gr[b];
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int i = ii[b], j = jj[b];
+        const double T0 = T[b][0], T1 = T[b][1], T2 = T[b][2];
+        const double c0 = tb[L.c0 + i], c1 = tb[L.c1 + j];
+        const double bb = tb[L.X + i] * tb[L.Y + j] * tb[L.P + i * L.ld1 + j];
+        const double r2 = c0 * c0 + c1 * c1;
+        acc[0] += bb * T0;
+        acc[1] += bb * c0 * T0; acc[2] += bb * c1 * T0; acc[3] += bb * T1;
+        if constexpr (!JAC) {
+            acc[4] += bb * (r2 * T0 + T2);
+        } else {
+            const double T3 = T[b][NE > 3 ? 3 : 0], T4 = T[b][NE > 4 ? 4 : 0];
+            const double qa = c0 * (q.a00 * c0 + q.t01 * c1) + q.a11 * c1 * c1, qb = q.t02 * c0 + q.t12 * c1;
+            const double q0 = qa * T0 + qb * T1 + q.a22 * T2;    // sum q
+            const double q1 = qa * T1 + qb * T2 + q.a22 * T3;    // sum c2 q
+            const double q2 = qa * T2 + qb * T3 + q.a22 * T4;    // sum c2^2 q
+            const double s2 = r2 * T0 + T2;                      // sum |c|^2
+            acc[4] += bb * c0 * c0 * T0; acc[5] += bb * c1 * c1 * T0; acc[6] += bb * T2;
+            acc[7] += bb * c0 * c1 * T0; acc[8] += bb * c0 * T1; acc[9] += bb * c1 * T1;
+            acc[10] += bb * q0;
+            acc[11] += bb * c0 * q0; acc[12] += bb * c1 * q0; acc[13] += bb * q1;
+            acc[14] += bb * c0 * s2; acc[15] += bb * c1 * s2; acc[16] += bb * (r2 * T1 + T3);
+            acc[17] += bb * (r2 * q0 + q2);
+        }
+    }
+    return gmax;
+}
+
+// All n0 n1 pairs of the point: full passes of four pairs per lane, then the
+// remainder one pair per lane.
+template <int NE>
+__device__ __forceinline__ double pair_sums(const FactLayout &L, const double *tb, int lane, double k02, double k12,
+                                            const QuadA &q, double acc[18]) {
+    const int nP = L.n0 * L.n1;
+    const int full = nP / (2 * kLpp) * (2 * kLpp);
+    double gmax = 0.0;
+    for (int p0 = lane; p0 < full; p0 += 2 * kLpp) gmax = fmax(gmax, pair_block<2, NE>(L, tb, p0, k02, k12, q, acc));
+    for (int p0 = full + lane; p0 < nP; p0 += kLpp) gmax = fmax(gmax, pair_block<1, NE>(L, tb, p0, k02, k12, q, acc));
+    return gmax;
+}
+
 // Returns false (and leaves s untouched) when a factor exponent exceeds the
 // safe range; the caller then uses the direct sum.  jac as for sums_es.
 __device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const double U[3], double ist,
                              const double Am[3][3], const double z[5], Sums &s, bool jac) {
+    // per-evaluation values: nothing derived from the lane or the frame is
+    // hoisted out of the caller's Newton loop (it would stay live across it)
+    asm volatile("" : "+v"(lane), "+v"(ist));
     const VGrid &vg = A.vg;
     const FactLayout L = fact_layout(vg);
     const double hz = 0.5 * z[4];
+    const double k01 = -z[4] * Am[0][1], k02 = -z[4] * Am[0][2], k12 = -z[4] * Am[1][2];
+    // c2 at the first node and the c2 spacing (the G recurrence runs along l)
+    const double c2a = (gridu(vg, 2, 0) - U[2]) * ist, dl2 = vg.du[2] * ist;
+    // largest exponent of a direct factor (X, Y, Z, P: an underflow there is
+    // a true underflow) and largest |exponent| of a G factor (its start and
+    // ratio tables must neither overflow nor underflow)
     double amax = -1e300;
     lds_wave_sync();  // previous evaluation's readers are done with the tables
-    // one-axis factors, axis by axis (an axis index varying across lanes would
+    // one-axis tables, axis by axis (an axis index varying across lanes would
     // put the small per-point arrays U, z, Am into scratch memory)
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -338,8 +435,16 @@ __device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const do
             tb[oc + i] = c;
             if (d == 0) {
                 tb[L.X + i] = v;
+                const double g0 = k02 * c * c2a, gr = k02 * c * dl2;
+                amax = fmax(amax, fmax(fabs(g0), fabs(gr)));
+                tb[L.G0 + i] = exp(g0);
+                tb[L.Ra + i] = exp(gr);
             } else if (d == 1) {
                 tb[L.Y + i] = v;
+                const double h0 = k12 * c * c2a, hr = k12 * c * dl2;
+                amax = fmax(amax, fmax(fabs(h0), fabs(hr)));
+                tb[L.H0 + i] = exp(h0);
+                tb[L.Rb + i] = exp(hr);
             } else {
                 double p = v;
 #pragma unroll
@@ -348,32 +453,15 @@ __device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const do
         }
     }
     lds_wave_sync();
-    // Two-axis factors exp(k c_a c_b): along a row the exponent is affine in
-    // the node index (uniform grid), so one lane fills a row by a geometric
-    // recurrence from its larger end (2 exponentials per row; values only
-    // shrink along the recurrence, so an underflow is a true underflow).
-    const double k01 = -z[4] * Am[0][1], k02 = -z[4] * Am[0][2], k12 = -z[4] * Am[1][2];
-    for (int t = lane; t < 2 * L.n0 + L.n1; t += kLpp) {
-        double kc, *dst;
-        const double *cb;
-        int nb;
-        if (t < L.n0) {
-            kc = k01 * tb[L.c0 + t];
-            cb = tb + L.c1;
-            nb = L.n1;
-            dst = tb + L.P + t * L.ld1;
-        } else if (t < 2 * L.n0) {
-            kc = k02 * tb[L.c0 + t - L.n0];
-            cb = tb + L.c2;
-            nb = L.n2;
-            dst = tb + L.Q + (t - L.n0) * L.ld2;
-        } else {
-            kc = k12 * tb[L.c1 + t - 2 * L.n0];
-            cb = tb + L.c2;
-            nb = L.n2;
-            dst = tb + L.R + (t - 2 * L.n0) * L.ld2;
-        }
-        const double a0 = kc * cb[0], a1 = kc * cb[nb - 1];
+    // P(i,j) = exp(k01 c0_i c1_j): along a row the exponent is affine in j,
+    // so one lane fills a row by a geometric recurrence from its larger end
+    // (2 exponentials per row; values only shrink along the recurrence, so an
+    // underflow is a true underflow).
+    for (int i = lane; i < L.n0; i += kLpp) {
+        const double kc = k01 * tb[L.c0 + i];
+        const int nb = L.n1;
+        double *dst = tb + L.P + i * L.ld1;
+        const double a0 = kc * tb[L.c1], a1 = kc * tb[L.c1 + nb - 1];
         amax = fmax(amax, fmax(a0, a1));
         const double step = nb > 1 ? fabs(a1 - a0) / (nb - 1) : 0.0;
         const double ratio = exp(-step);
@@ -385,72 +473,12 @@ __device__ bool sums_es_fact(const NewtonArgs &A, int lane, double *tb, const do
         }
     }
     lds_wave_sync();
-    if (wave_max(amax) > 600.0) return false;
-    // Per pair (i,j) the c2 dependence is carried by T_e = sum_l Z c2^e Q R;
-    // with q = qa + qb c2 + A22 c2^2 and |c|^2 = r2 + c2^2 (qa, qb, r2 from
-    // c0, c1) every one of the 18 sums is a short combination of T_0..T_4
-    // (T_0..T_2 for the residual sums).  A lane takes four pairs at a time
-    // and walks l once for all four (the Z row is read once per l).
-    constexpr int B = 4;
+    const QuadA q = {Am[0][0], Am[1][1], Am[2][2], 2.0 * Am[0][1], 2.0 * Am[0][2], 2.0 * Am[1][2]};
     double acc[18];
 #pragma unroll
     for (int a = 0; a < 18; ++a) acc[a] = 0.0;
-    const double a00 = Am[0][0], a11 = Am[1][1], a22 = Am[2][2];
-    const double t01 = 2.0 * Am[0][1], t02 = 2.0 * Am[0][2], t12 = 2.0 * Am[1][2];
-    const int nP = L.n0 * L.n1;
-    const int ne = jac ? 5 : 3;
-    for (int p0 = lane; p0 < nP; p0 += kLpp * B) {
-        int qo[B], ro[B];
-        double T[B][5];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int p = p0 + kLpp * b < nP ? p0 + kLpp * b : p0;
-            qo[b] = L.Q + (p % L.n0) * L.ld2;
-            ro[b] = L.R + (p / L.n0) * L.ld2;
-#pragma unroll
-            for (int e = 0; e < 5; ++e) T[b][e] = 0.0;
-        }
-        for (int l = 0; l < L.n2; ++l) {
-            const double *zc = tb + L.Zc + 5 * l;
-            double zl[5];
-#pragma unroll
-            for (int e = 0; e < 5; ++e) zl[e] = e < ne ? zc[e] : 0.0;
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                const double qr = tb[qo[b] + l] * tb[ro[b] + l];
-#pragma unroll
-                for (int e = 0; e < 5; ++e)
-                    if (e < ne) T[b][e] += zl[e] * qr;
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const int p = p0 + kLpp * b;
-            if (p >= nP) break;
-            const int i = p % L.n0, j = p / L.n0;
-            const double T0 = T[b][0], T1 = T[b][1], T2 = T[b][2], T3 = T[b][3], T4 = T[b][4];
-            const double c0 = tb[L.c0 + i], c1 = tb[L.c1 + j];
-            const double bb = tb[L.X + i] * tb[L.Y + j] * tb[L.P + i * L.ld1 + j];
-            const double r2 = c0 * c0 + c1 * c1;
-            acc[0] += bb * T0;
-            acc[1] += bb * c0 * T0; acc[2] += bb * c1 * T0; acc[3] += bb * T1;
-            if (!jac) {
-                acc[4] += bb * (r2 * T0 + T2);
-                continue;
-            }
-            const double qa = c0 * (a00 * c0 + t01 * c1) + a11 * c1 * c1, qb = t02 * c0 + t12 * c1;
-            const double q0 = qa * T0 + qb * T1 + a22 * T2;      // sum q
-            const double q1 = qa * T1 + qb * T2 + a22 * T3;      // sum c2 q
-            const double q2 = qa * T2 + qb * T3 + a22 * T4;      // sum c2^2 q
-            const double s2 = r2 * T0 + T2;                      // sum |c|^2
-            acc[4] += bb * c0 * c0 * T0; acc[5] += bb * c1 * c1 * T0; acc[6] += bb * T2;
-            acc[7] += bb * c0 * c1 * T0; acc[8] += bb * c0 * T1; acc[9] += bb * c1 * T1;
-            acc[10] += bb * q0;
-            acc[11] += bb * c0 * q0; acc[12] += bb * c1 * q0; acc[13] += bb * q1;
-            acc[14] += bb * c0 * s2; acc[15] += bb * c1 * s2; acc[16] += bb * (r2 * T1 + T3);
-            acc[17] += bb * (r2 * q0 + q2);
-        }
-    }
+    const double gmax = jac ? pair_sums<5>(L, tb, lane, k02, k12, q, acc) : pair_sums<3>(L, tb, lane, k02, k12, q, acc);
+    if (wave_max(fmax(amax, gmax)) > 600.0) return false;
     s.S0 = wave_sum(acc[0]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) s.Sc[d] = wave_sum(acc[1 + d]);
@@ -706,6 +734,129 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const 
     return conv;
 }
 
+// The same iteration as newton_solve, written as one loop around a single
+// evaluation of the sums: the two points of a wave evaluate together in
+// whatever phase each is (start, cold start, line-search trial, Jacobian
+// refresh), and the sums code is emitted once.  The sums at the current
+// Jacobian (s) and at the point under evaluation (st) are held by the
+// caller, in LDS, and so is the iteration's state: the start zc, the iterate
+// z, the point under evaluation ze, its residual r and the step dz (the
+// sums need most of the register file).
+template <typename SumsFn>
+__device__ int newton_solve_es(const NewtonArgs &A, SumsFn sums, int64_t pt, const double *zc, double *z,
+                               double *ze, double *r, double *dz, Sums &s, Sums &st, double &res, int &iters,
+                               int &evals) {
+    enum { kStart, kCold, kTrial, kRefresh };
+    double za[5];
+    const bool have_alt = A.guess != FR_DVM_GUESS_COLD && alt_start(A, pt, zc, za);
+#pragma unroll
+    for (int a = 0; a < 5; ++a) z[a] = have_alt ? za[a] : zc[a];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) { ze[a] = z[a]; r[a] = 0.0; dz[a] = 0.0; }
+    int phase = kStart, it = 0, hh = 0, conv = 0;
+    bool jac = true, chord = false;
+    double alpha = 1.0, rn = 0.0, ri = 0.0;
+    evals = 0;
+    for (;;) {
+        Sums &tg = (phase == kStart || phase == kRefresh) ? s : st;
+        sums(ze, tg, jac);
+        ++evals;
+        double re[5];
+        residual(tg, re);
+        if (phase == kStart) {
+#pragma unroll
+            for (int a = 0; a < 5; ++a) r[a] = re[a];
+            if (have_alt && !(norm2_5(r) <= 1e-2)) {
+                // the alternative start is not already close: evaluate the
+                // cold start too and keep the better one
+                phase = kCold;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) ze[a] = zc[a];
+                continue;
+            }
+        } else if (phase == kCold) {
+            if (!(norm2_5(r) <= norm2_5(re))) {
+                s = st;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) { z[a] = zc[a]; r[a] = re[a]; }
+            }
+        } else if (phase == kTrial) {
+            const double rt = norm2_5(re);
+            if (rt < (1.0 - 1e-4 * alpha) * rn) {
+#pragma unroll
+                for (int a = 0; a < 5; ++a) { z[a] = ze[a]; r[a] = re[a]; }
+                if (!chord) {
+                    s = st;
+                } else if (rt > 1e-2 * rn) {
+                    // slow chord contraction: refresh the Jacobian at z (= ze)
+                    phase = kRefresh;
+                    jac = true;
+                    continue;
+                }
+                ++it;
+            } else {
+                // rejected: halve the step until the trial is admissible
+                do {
+                    alpha *= 0.5;
+                    ++hh;
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) ze[a] = z[a] + alpha * dz[a];
+                } while (hh < 40 && !(ze[4] > 0.0));
+                if (hh < 40) continue;
+                // stagnation at the rounding floor of the FP64 sums
+                if (ri <= 100.0 * A.tol) { res = ri; conv = 1; ++it; }
+                break;
+            }
+        } else {  // kRefresh
+#pragma unroll
+            for (int a = 0; a < 5; ++a) r[a] = re[a];
+            ++it;
+        }
+        // Newton step from z with the Jacobian of s
+        if (it >= A.max_iter) break;
+        rn = norm2_5(r);
+        ri = normi_5(r);
+        double J[5][5], rdum[5];
+        double rhs[5] = {-r[0], -r[1], -r[2], -r[3], -r[4]};
+        assemble(s, rdum, J);
+        const bool ok = solve5(J, rhs, dz);
+        if (ok && ri <= A.tol) {
+            // converged: one extra step makes the result path independent
+#pragma unroll
+            for (int a = 0; a < 5; ++a) z[a] += dz[a];
+            res = ri;
+            conv = 1;
+            ++it;
+            break;
+        }
+        if (!ok) break;
+        chord = rn <= kChord;
+        alpha = 1.0;
+        hh = 0;
+#pragma unroll
+        for (int a = 0; a < 5; ++a) ze[a] = z[a] + alpha * dz[a];
+        while (hh < 40 && !(ze[4] > 0.0)) {
+            alpha *= 0.5;
+            ++hh;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) ze[a] = z[a] + alpha * dz[a];
+        }
+        if (hh == 40) {
+            if (ri <= 100.0 * A.tol) { res = ri; conv = 1; ++it; }
+            break;
+        }
+        phase = kTrial;
+        jac = !chord;
+    }
+    iters = it;
+    if (!conv) {
+        res = normi_5(r);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) z[a] = zc[a];
+    }
+    return conv;
+}
+
 __global__ __launch_bounds__(256) void k_newton_bgk(const NewtonArgs A) {
     const int64_t pt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pt >= A.npts) return;
@@ -734,13 +885,21 @@ __global__ __launch_bounds__(256) void k_newton_bgk(const NewtonArgs A) {
 }
 
 #ifndef FRDVM_WAVES_ES
-#define FRDVM_WAVES_ES 2
+#define FRDVM_WAVES_ES 3
 #endif
 // One solution point per kLpp lanes: two per wave, four per 128-thread
-// workgroup (the per-point LDS tables of four points fit three workgroups
-// per CU).
+// workgroup (about 6 KB of LDS per point at 20^3 velocities, so LDS admits
+// six workgroups per CU and registers decide the occupancy).
 constexpr int kEsBlock = 128;
 constexpr int kEsPts = kEsBlock / kLpp;
+constexpr int kSumsD = (int)(sizeof(Sums) / sizeof(double));
+constexpr int kStateD = 38;  // U[3], A[3][3], zc, z, ze, r, dz [5] each, pad
+
+// LDS doubles per point of k_newton_es: two sum sets, the iteration state,
+// then the factor tables.
+__host__ __device__ inline int es_slot_doubles(const VGrid &vg, int use_fact) {
+    return 2 * kSumsD + kStateD + (use_fact ? fact_layout(vg).total : 0);
+}
 
 __global__ __launch_bounds__(kEsBlock) __attribute__((amdgpu_waves_per_eu(FRDVM_WAVES_ES))) void k_newton_es(
     const NewtonArgs A) {
@@ -787,17 +946,33 @@ __global__ __launch_bounds__(kEsBlock) __attribute__((amdgpu_waves_per_eu(FRDVM_
     const double zc[5] = {-1.5 * log(kTwoPi) + 0.5 * log(det3(Am)), 0.0, 0.0, 0.0, 1.0};
     double z[5];
     const double wscale = ist * ist * ist;
-    extern __shared__ double es_tables[];
-    double *tb = es_tables + slot * (A.use_fact ? fact_layout(A.vg).total : 0);
-    auto fn = [&](const double zz[5], Sums &s, bool jac) {
-        if (!(A.use_fact && sums_es_fact(A, lane, tb, U, ist, Am, zz, s, jac)))
-            sums_es(A, lane, U, ist, wscale, Am, zz, s, jac);
+    // per point: the two sum sets of the iteration, the iteration state and
+    // the point's frame (U, A), then the factor tables
+    extern __shared__ double es_lds[];
+    double *sl = es_lds + slot * es_slot_doubles(A.vg, A.use_fact);
+    Sums &s_cur = *reinterpret_cast<Sums *>(sl);
+    Sums &s_try = *reinterpret_cast<Sums *>(sl + kSumsD);
+    double *ns = sl + 2 * kSumsD;
+    double *Us = ns, *zcs = ns + 12, *zs = ns + 17, *zes = ns + 22, *rs = ns + 27, *dzs = ns + 32;
+    double(*Ams)[3] = reinterpret_cast<double(*)[3]>(ns + 3);
+    double *tb = ns + kStateD;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        Us[d] = U[d];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Ams[d][b] = Am[d][b];
+    }
+#pragma unroll
+    for (int a = 0; a < 5; ++a) zcs[a] = zc[a];
+    auto fn = [&](const double *zz, Sums &s, bool jac) {
+        if (!(A.use_fact && sums_es_fact(A, lane, tb, Us, ist, Ams, zz, s, jac)))
+            sums_es(A, lane, Us, ist, wscale, Ams, zz, s, jac);
     };
     double res;
     int iters, evals;
-    const int conv = newton_solve(A, fn, pt, zc, z, res, iters, evals);
+    const int conv = newton_solve_es(A, fn, pt, zcs, zs, zes, rs, dzs, s_cur, s_try, res, iters, evals);
     if (lane == 0) {
-        write_point(A, pt, rho, U, th, Am, z, inv_tau, res);
+        write_point(A, pt, rho, Us, th, Ams, zs, inv_tau, res);
         record_stats(A, pt, iters, evals, conv ? status : FR_DVM_NEWTON_FALLBACK, res);
     }
 }
@@ -1004,6 +1179,39 @@ int ensure_dz(fr_dvm *h, int64_t n) {
 
 }  // namespace
 
+namespace {
+
+// The Newton kernel and its statistics over the points [p0, p0 + np) on
+// stream s: every per-point array of A is offset to p0, so the kernels see a
+// contiguous range starting at their point 0.
+int newton_run(fr_dvm *h, NewtonArgs A, int64_t p0, int64_t np, hipStream_t s) {
+    A.npts = np;
+    A.Q += p0 * A.nmom;
+    A.eq += p0 * kEqW;
+    A.z += p0 * 5;
+    A.prim += p0 * 5;
+    if (A.dz_guess) A.dz_guess += p0 * 5;
+    A.pt_iters = h->d_pt_iters + p0;
+    A.pt_evals = h->d_pt_evals + p0;
+    A.pt_status = h->d_pt_status + p0;
+    A.pt_resid = h->d_pt_resid + p0;
+    ProfScope ps(h, 1, s);
+    if (h->prm.model == FR_DVM_ESBGK) {
+        A.use_fact = (kEsPts * sizeof(double) * (size_t)es_slot_doubles(h->vg, 1) <= 65536) && !h->es_direct;
+        const size_t shm = kEsPts * sizeof(double) * (size_t)es_slot_doubles(h->vg, A.use_fact);
+        hipLaunchKernelGGL(k_newton_es, dim3((unsigned)((A.npts + kEsPts - 1) / kEsPts)), dim3(kEsBlock), shm, s, A);
+    } else {
+        hipLaunchKernelGGL(k_newton_bgk, dim3((unsigned)((A.npts + 255) / 256)), dim3(256), 0, s, A);
+    }
+    int64_t nb = (A.npts + 256 * 16 - 1) / (256 * 16);
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)nb), dim3(256), 0, s, A.npts, A.pt_iters, A.pt_evals,
+                       A.pt_status, A.pt_resid, A.stats, A.maxres);
+    return check(h, "newton kernel");
+}
+
+}  // namespace
+
 int launch_newton(fr_dvm *h, int guess) {
     // learned start where no previous solution exists, warm start afterwards
     if (guess == FR_DVM_GUESS_MLP_WARM) guess = h->zvalid ? FR_DVM_GUESS_WARM : FR_DVM_GUESS_MLP;
@@ -1015,26 +1223,22 @@ int launch_newton(fr_dvm *h, int guess) {
         if (rc) return rc;
         A.dz_guess = h->d_mlp_dz;
     }
-    A.pt_iters = h->d_pt_iters;
-    A.pt_evals = h->d_pt_evals;
-    A.pt_status = h->d_pt_status;
-    A.pt_resid = h->d_pt_resid;
-    ProfScope ps(h, 1);
-    if (h->prm.model == FR_DVM_ESBGK) {
-        const size_t shm = kEsPts * sizeof(double) * (size_t)fact_layout(h->vg).total;
-        A.use_fact = (shm <= 65536) && !h->es_direct;
-        hipLaunchKernelGGL(k_newton_es, dim3((unsigned)((A.npts + kEsPts - 1) / kEsPts)), dim3(kEsBlock),
-                           A.use_fact ? shm : 0,
-                           h->stream, A);
-    } else {
-        hipLaunchKernelGGL(k_newton_bgk, dim3((unsigned)((A.npts + 255) / 256)), dim3(256), 0, h->stream, A);
-    }
-    int64_t nb = (A.npts + 256 * 16 - 1) / (256 * 16);
-    if (nb > 1024) nb = 1024;
-    hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)nb), dim3(256), 0, h->stream, A.npts, A.pt_iters, A.pt_evals,
-                       A.pt_status, A.pt_resid, A.stats, A.maxres);
-    h->zvalid = 1;
-    return check(h, "newton kernel");
+    const int rc = newton_run(h, A, 0, A.npts, h->stream);
+    if (!rc) h->zvalid = 1;
+    return rc;
+}
+
+int newton_part_ok(fr_dvm *h, int guess) {
+    if (guess == FR_DVM_GUESS_MLP_WARM) guess = h->zvalid ? FR_DVM_GUESS_WARM : FR_DVM_GUESS_MLP;
+    return newton_args(h, guess).guess != FR_DVM_GUESS_MLP;
+}
+
+int launch_newton_part(fr_dvm *h, int guess, int64_t p0, int64_t np, hipStream_t s) {
+    if (guess == FR_DVM_GUESS_MLP_WARM) guess = h->zvalid ? FR_DVM_GUESS_WARM : FR_DVM_GUESS_MLP;
+    NewtonArgs A = newton_args(h, guess);
+    if (A.guess == FR_DVM_GUESS_MLP) return h->fail(FR_DVM_EINVAL, "learned start needs all points");
+    if (p0 < 0 || np < 0 || p0 + np > A.npts) return h->fail(FR_DVM_EINVAL, "point range");
+    return newton_run(h, A, p0, np, s);
 }
 
 // Newton on caller-supplied moment vectors (BGK form), for training targets

@@ -137,6 +137,7 @@ extern "C" void fr_dvm_default_params(fr_dvm_params *p) {
     p->farfield[0] = 1.0;
     p->farfield[4] = 1.0;
     p->theta_wall = 1.0;
+    p->overlap = 0;
 }
 
 extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out) {
@@ -275,6 +276,7 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     if (p->newton_max_iter < 1 || p->newton_max_iter > 200) return h->fail(FR_DVM_EINVAL, "newton_max_iter out of range");
     if (p->rk != FR_DVM_SSPRK3 && p->rk != FR_DVM_LSRK3_2N) return h->fail(FR_DVM_EINVAL, "unknown RK scheme");
     if (p->guess < 0 || p->guess > 3) return h->fail(FR_DVM_EINVAL, "unknown guess mode");
+    if (p->overlap != 0 && p->overlap != 1) return h->fail(FR_DVM_EINVAL, "overlap must be 0 or 1");
     bool realloc_all = !h->have_params || p->precision != h->prm.precision;
     int nmom = (p->model == FR_DVM_ESBGK) ? 10 : 5;
     bool realloc_mom = !h->have_params || nmom != h->nmom;
@@ -393,6 +395,14 @@ extern "C" void fr_dvm_destroy(fr_dvm_t h) {
     for (auto &r : h->prof_recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
+    }
+    if (h->aux) {
+        (void)hipStreamSynchronize(h->aux);
+        (void)hipStreamDestroy(h->aux);
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (h->ev_stage[i]) (void)hipEventDestroy(h->ev_stage[i]);
+        if (h->ev_newton[i]) (void)hipEventDestroy(h->ev_newton[i]);
     }
     delete h;
 }

@@ -44,7 +44,7 @@ class _Params(C.Structure):
                 ("theta_ref", C.c_double), ("omega", C.c_double), ("visc_law", C.c_int32),
                 ("theta_s", C.c_double), ("precision", C.c_int32), ("newton_tol", C.c_double),
                 ("newton_max_iter", C.c_int32), ("guess", C.c_int32), ("rk", C.c_int32),
-                ("farfield", C.c_double * 5), ("theta_wall", C.c_double)]
+                ("farfield", C.c_double * 5), ("theta_wall", C.c_double), ("overlap", C.c_int32)]
 
 
 _lib = None
