@@ -392,6 +392,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                 for (int a = 0; a < N; ++a) TZ[a] = ldb(trE, nz.off + a * nz.stride);
             }
         }
+        // the second RK register of this chunk, requested before the x/y/z
+        // passes so that they cover its latency (its registers are live in
+        // the RK update anyway, where the register peak is)
+        Real X[NL];
+        if (useX) {
+#pragma unroll
+            for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
+        }
         const Real *trow = &tile[wave][vl][l * NL];  // this lane's layer of the stage value
         Real f[NL];  // the produced value (stage) or the stage value itself (prime)
 
@@ -433,11 +441,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                     }
                     phase_fence();
                 }
-            }
-            Real X[NL];
-            if (useX) {
-#pragma unroll
-                for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
             }
             // z lines: derivative and inflow correction of the z faces in one
             // pass over the tile rows, r += sum_m (az Dz[m] - cz lam[m]) f_m,
