@@ -17,7 +17,6 @@ constexpr int kMaxP = 3;
 constexpr int kMaxN = kMaxP + 1;
 constexpr int kEqW = 12;   // per-point equilibrium record (see EqRec below)
 constexpr int kHist = 64;  // Newton iteration histogram bins
-constexpr int kBlock = 256;
 
 // Per-point equilibrium record written by the Newton kernels and read by the
 // collision (fused or stand-alone):

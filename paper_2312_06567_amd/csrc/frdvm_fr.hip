@@ -9,21 +9,23 @@
 // function.  The collision source (g(Q') - f)/tau follows Section
 // "Governing equations"; Q' comes from the Newton kernels.
 //
-// Work decomposition: one workgroup (4 wave64) per element.  A lane owns one
-// velocity node and one z-layer of the element's N^3 Gauss points (N = p+1):
-// N lanes share a velocity, a wave covers 64/N velocities.  On a
-// tensor-product Gauss element every operator factorises along lines, so the
-// x and y derivatives, traces and corrections are local to the lane's layer;
-// z lines are gathered from a per-wave LDS tile that holds the wave's block
-// of f, one row of N^3 points per velocity.  The same tile, refilled with the
-// stage result, serves the z traces of the result and the moment reduction
-// (lane = solution point, FP64 accumulation with wave-uniform scalar weights,
-// fixed order: bitwise reproducible).  Everything is VALU FMA: the
-// factorised contractions have K = p+1 <= 4 and the kernel is HBM bound.
+// Work decomposition: one workgroup per element, one wave64 per z-layer of
+// the element's N^3 Gauss points (N = p+1), one lane per velocity node: the
+// velocity axis is walked in chunks of 64 nodes, so every access to f, the
+// RK registers and the traces is a run of 64 consecutive velocities (256 B
+// in FP32) per solution point.  On a tensor-product Gauss element every
+// operator factorises along lines: the x and y lines lie in the lane's own
+// layer; z lines cross the layers and are read from a workgroup LDS tile of
+// the chunk's stage value.  A second tile takes the produced value for the z
+// traces and the moment reduction (lane = solution point, FP64 accumulation
+// with scalar-cache weights, fixed order: bitwise reproducible).  The
+// equilibrium record of a point is uniform over a wave and is read through
+// the scalar cache.  Everything is VALU FMA: the factorised contractions
+// have K = p+1 <= 4 and the kernel is HBM bound.
 //
-// Latency: the velocity axis is walked in chunks of 4 x 64/N nodes per
-// workgroup, and every HBM read of chunk c+1 (stage value, second RK
-// register, inflow traces) is issued while chunk c is computed.
+// Latency: every HBM read of chunk c+1 (stage value, inflow traces) is
+// issued while chunk c is computed, the second RK register of chunk c at
+// its start.
 //
 // Traces: for the velocities leaving an element through a face, the element
 // writes its trace on that face ("outflow half", compact layout) into the
@@ -41,6 +43,7 @@ namespace frdvm {
 namespace {
 
 constexpr int MODE_PRIME = 0, MODE_STAGE = 1, MODE_RESID = 2;
+constexpr int kChunk = 64;  // velocities per chunk: one per lane of a wave
 
 // Register targets (waves per SIMD) of the stage kernel.  FP32: the LDS of a
 // workgroup (48 KB at p = 3 with the ES moments) admits three workgroups of
@@ -200,27 +203,6 @@ __device__ __forceinline__ TraceOff trace_in(const FrArgs &A, const LdsTab<Real>
     return t;
 }
 
-// LDS tile row (one velocity): the N^3 point values followed by the N^2
-// z-face inflow traces, padded to a multiple of 16 bytes whose length in
-// dwords is 4 mod 8, so that 16-byte accesses of 8 consecutive rows hit
-// disjoint banks.
-template <typename Real>
-constexpr int tile_row(int ns, int nl) {
-    constexpr int vec = 16 / (int)sizeof(Real);
-    int t = (ns + nl + vec - 1) / vec * vec;
-    if ((t * (int)sizeof(Real) / 4) % 8 != 4) t += vec;
-    return t;
-}
-
-// The LDS tile region of a wave is private to that wave, and one wave's LDS
-// operations complete in issue order, so exchanging data through it only
-// needs the compiler kept from moving LDS accesses across this point.
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Keeps the compiler from moving memory accesses (and the scheduler from
 // moving anything) across this point: bounds how many LDS values are in
 // registers at once.
@@ -243,45 +225,61 @@ constexpr int fr_waves() {
     return MODE == MODE_PRIME ? 4 : (sizeof(Real) == 4 ? FRDVM_WAVES_F32 : FRDVM_WAVES_F64);
 }
 
-template <typename Real, int P, int NMOM, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves<Real, MODE>()))) void k_fr_layer(
-    const FrArgs A) {
-    constexpr int N = P + 1, NS = N * N * N, NL = N * N;
-    constexpr int VPW = 64 / N;   // velocities per wave
-    constexpr int VPB = 4 * VPW;  // velocities per workgroup and chunk
+// LDS tiles: one row of kChunk velocities per solution point, padded by one
+// element so that the moment pass (lane = solution point, reading along its
+// row) hits distinct banks; written and read elsewhere with lane = velocity.
+constexpr int kTileLd = kChunk + 1;
+template <typename Real>
+__device__ __forceinline__ int tix(int row, int col) {
+    return row * kTileLd + col;
+}
 
-    constexpr int TR = tile_row<Real>(NS, NL);
+template <typename Real, int P, int NMOM, int MODE>
+__global__ __launch_bounds__(kChunk *(P + 1)) __attribute__((amdgpu_waves_per_eu(fr_waves<Real, MODE>()))) void
+k_fr_layer(const FrArgs A) {
+    constexpr int N = P + 1, NS = N * N * N, NL = N * N;
+    constexpr int NT = kChunk * N;                  // threads: one wave per z-layer
+    constexpr int VPM = (kChunk + N - 1) / N;       // chunk velocities per wave in the moment pass
     constexpr bool FLUX = MODE != MODE_PRIME;
     constexpr bool STAGE = MODE == MODE_STAGE;
-    // equilibrium of each solution point: b (the exponent's quadratic form,
-    // -1/2 B with doubled off-diagonal terms), c0, 1/tau; and V; all FP64
-    // (the exponent is formed in FP64 in both precisions)
-    __shared__ __attribute__((aligned(16))) double s_eb[STAGE ? NS * 8 : 1];
-    __shared__ __attribute__((aligned(16))) double s_ev[STAGE ? NS * 4 : 1];
-    __shared__ __attribute__((aligned(16))) Real tile[4][VPW][TR];
+    // the chunk's stage value (all layers, for the z lines) and z-face inflow
+    // traces; the produced value (for the z traces and the moments).  The
+    // prime pass uses the two value tiles alternately, chunk by chunk.  The
+    // moment partial sums of the waves reuse the tiles after the loop.
+    constexpr int TS = NS * kTileLd, TZ_ = FLUX ? NL * kTileLd : 1, TP = NS * kTileLd;
+    constexpr int TBYTES = (TS + TZ_ + TP) * (int)sizeof(Real);
+    constexpr int RBYTES = N * NS * NMOM * (int)sizeof(double);
+    __shared__ __attribute__((aligned(16))) char s_tiles[TBYTES > RBYTES ? TBYTES : RBYTES];
+    Real *const tS = reinterpret_cast<Real *>(s_tiles);
+    Real *const tZ = tS + TS;
+    Real *const tP = tZ + TZ_;
+    double *const red = reinterpret_cast<double *>(s_tiles);
     __shared__ __attribute__((aligned(16))) LdsTab<Real> T;
-    // running moments of each solution point, one partial sum per wave
-    __shared__ __attribute__((aligned(16))) double red[4][NS][NMOM];
+    // equilibrium records staged per workgroup (b: the exponent's quadratic
+    // form, -1/2 B with doubled off-diagonal terms, c0, 1/tau; V), read with
+    // a wave-uniform address
+    constexpr bool EQ_LDS = STAGE;
+    __shared__ __attribute__((aligned(16))) double s_eb[EQ_LDS ? NS * 8 : 1];
+    __shared__ __attribute__((aligned(16))) double s_ev[EQ_LDS ? NS * 4 : 1];
 
     const OpsR<Real> &op = ops_of<Real>(A);
     const int64_t e = A.sa.e0 + blockIdx.x;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lay = lane / VPW;  // z-layer owned by this lane (N for an idle lane)
-    const int vl = lane - lay * VPW;
-    const bool lane_ok = lay < N;
-    const int l = lane_ok ? lay : 0;
+    const int vl = tid & (kChunk - 1);                       // velocity of the chunk (lane)
+    const int l = __builtin_amdgcn_readfirstlane(tid >> 6);  // z-layer of the wave
     const int nu = A.nu;
     const int64_t ebase = e * (int64_t)NS * nu;
     const uint32_t lrow = (uint32_t)(l * NL) * (uint32_t)nu;     // offset of the layer inside the element
     const uint32_t QB = (uint32_t)nu * (uint32_t)sizeof(Real);  // bytes between solution points
-    // first velocity of this wave in chunk ch
-    auto kbase = [&](int ch) { return ch * VPB + wave * VPW; };
 
     const bool collide = STAGE && A.sa.collide;
-    if (collide) {
-        for (int s = tid; s < NS; s += kBlock) {
+    // equilibrium records of this wave's layer: c0, V, B, 1/tau per point,
+    // wave-uniform, read through the scalar cache (written by the previous
+    // launch)
+    typedef const __attribute__((address_space(4))) double cdouble;
+    cdouble *eqL = (cdouble *)(A.sa.eq + (e * NS + l * NL) * kEqW);
+    if (EQ_LDS && collide) {
+        for (int s = tid; s < NS; s += NT) {
             const double *q = A.sa.eq + (e * NS + s) * kEqW;
             double *b = &s_eb[s * 8];
             b[0] = -0.5 * q[EQ_B];
@@ -311,7 +309,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
         T.cnt[fc] = (uint32_t)A.tl.cnt[fc];
         T.fo[fc] = (uint32_t)A.tl.face_off[fc];
     }
-    // z-direction operator entries of this lane's layer
+    // z-direction operator entries of this wave's layer
     Real Dz[N], corrz[2];
 #pragma unroll
     for (int m = 0; m < N; ++m) Dz[m] = op.D[l * N + m];
@@ -320,12 +318,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     // trace blocks: the own one (inflow of this stage) and the neighbours'
     // (outflow of the produced value)
     const Real *__restrict__ trE = reinterpret_cast<const Real *>(A.sa.tr_in) + (FLUX ? e * A.tl.elem : 0);
-
-    if (lane < NS) {
+    // running moments of the solution point tid % 64 over this wave's share
+    // of every chunk (one partial per wave, added in wave order at the end)
+    double Mrun[NMOM];
 #pragma unroll
-        for (int a = 0; a < NMOM; ++a) red[wave][lane][a] = 0.0;
-    }
-    // the equilibrium records and the lane tables are complete from here on
+    for (int a = 0; a < NMOM; ++a) Mrun[a] = 0.0;
+    // the lane tables (and the staged records) are complete from here on
     __syncthreads();
 
     const Real *__restrict__ fE = reinterpret_cast<const Real *>(A.sa.f) + ebase;
@@ -337,15 +335,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     const Real *__restrict__ XE = STAGE ? (A.sa.scheme == 0 ? reinterpret_cast<const Real *>(A.sa.fn) + ebase
                                                             : reinterpret_cast<const Real *>(A.sa.dF) + ebase)
                                         : nullptr;
-    const int nchunk = (nu + VPB - 1) / VPB;
+    const int nchunk = (nu + kChunk - 1) / kChunk;
 
     // The stage value and the inflow traces of chunk c+1 are requested while
-    // chunk c is computed; the second RK register of chunk c at its start.
-    // Of the z-face traces (shared by the N lanes of a velocity) each lane
-    // fetches the N points (i, j = l) and passes them on through the tile.
+    // chunk c is computed.  Of the z-face traces (N^2 points per velocity,
+    // needed by every layer) the wave of layer l fetches the points (i, l)
+    // and passes them on through the tile.
     Real fc[NL], TX[N], TY[N], TZ[N];
     {
-        const Vel v0 = velocity(A, kbase(0) + vl, lane_ok);
+        const Vel v0 = velocity(A, vl, true);
         const uint32_t o = (lrow + (uint32_t)v0.k) * (uint32_t)sizeof(Real);
 #pragma unroll
         for (int q = 0; q < NL; ++q) fc[q] = ldb(fE, o + q * QB);
@@ -363,24 +361,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
     }
 
     for (int ch = 0; ch < nchunk; ++ch) {
-        const Vel v = velocity(A, kbase(ch) + vl, lane_ok);
+        const Vel v = velocity(A, ch * kChunk + vl, true);
         const uint32_t o = (lrow + (uint32_t)v.k) * (uint32_t)sizeof(Real);
-        // Publish the stage value (and, for the residual, this lane's z-face
-        // traces) to the tile; every later use of the stage value reads it
-        // there, so its registers take the next chunk's loads right away.
-        wave_sync();
-        if (lane_ok) {
+        // tile taking the stage value of the chunk, and tile read by the z
+        // traces and the moment pass (the same, alternating, for the prime pass)
+        Real *const tpub = FLUX ? tS : ((ch & 1) ? tP : tS);
+        Real *const tout = FLUX ? tP : tpub;
+        // Publish the stage value (the prime pass: into the tile its z traces
+        // and moments read) and this wave's z-face traces; every later use of
+        // the stage value reads the tile, so its registers take the next
+        // chunk's loads right away.
 #pragma unroll
-            for (int q = 0; q < NL; ++q) tile[wave][vl][l * NL + q] = fc[q];
-            if (FLUX) {
+        for (int q = 0; q < NL; ++q) tpub[tix<Real>(l * NL + q, vl)] = fc[q];
+        if (FLUX) {
 #pragma unroll
-                for (int a = 0; a < N; ++a) tile[wave][vl][NS + N * l + a] = TZ[a];
-            }
+            for (int a = 0; a < N; ++a) tZ[tix<Real>(N * l + a, vl)] = TZ[a];
         }
-        wave_sync();
         TraceOff nx{0u, 0u}, ny{0u, 0u};
         {
-            const Vel vn = velocity(A, kbase(ch + 1) + vl, lane_ok);
+            const Vel vn = velocity(A, (ch + 1) * kChunk + vl, true);
             const uint32_t on = (lrow + (uint32_t)vn.k) * (uint32_t)sizeof(Real);
 #pragma unroll
             for (int q = 0; q < NL; ++q) fc[q] = ldb(fE, on + q * QB);
@@ -393,15 +392,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
             }
         }
         // the second RK register of this chunk, requested before the x/y/z
-        // passes so that they cover its latency (its registers are live in
-        // the RK update anyway, where the register peak is)
+        // passes so that they cover its latency
         Real X[NL];
         if (useX) {
 #pragma unroll
             for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
         }
-        const Real *trow = &tile[wave][vl][l * NL];  // this lane's layer of the stage value
-        Real f[NL];  // the produced value (stage) or the stage value itself (prime)
+        if (FLUX) __syncthreads();  // the chunk's stage value of every layer is in the tile
+        Real f[NL];  // the produced value (stage and residual modes)
 
         if (FLUX) {
             Real r[NL];
@@ -422,7 +420,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                 for (int a = 0; a < N; ++a) {
                     Real g[N];
 #pragma unroll
-                    for (int m = 0; m < N; ++m) g[m] = trow[d == 0 ? m + N * a : a + N * m];
+                    for (int m = 0; m < N; ++m) g[m] = tS[tix<Real>(l * NL + (d == 0 ? m + N * a : a + N * m), vl)];
                     Real fm = Real(0);
 #pragma unroll
                     for (int m = 0; m < N; ++m) fm += T.lam[sin_][m] * g[m];
@@ -443,7 +441,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                 }
             }
             // z lines: derivative and inflow correction of the z faces in one
-            // pass over the tile rows, r += sum_m (az Dz[m] - cz lam[m]) f_m,
+            // pass over the layers, r += sum_m (az Dz[m] - cz lam[m]) f_m,
             // then r += cz f+ (the interior trace folded into the coefficients)
             {
                 const int zin = v.sgn[2] > 0 ? 0 : 1;
@@ -455,14 +453,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                     const Real cm = az * Dz[m] - cz * T.lam[zin][m];
 #pragma unroll
                     for (int q = 0; q < NL; ++q) {
-                        r[q] = fma(cm, tile[wave][vl][m * NL + q], r[q]);
+                        r[q] = fma(cm, tS[tix<Real>(m * NL + q, vl)], r[q]);
                         keep(r[q]);
                     }
                     phase_fence();
                 }
 #pragma unroll
                 for (int q = 0; q < NL; ++q) {
-                    const Real fp = zflow ? tile[wave][vl][NS + q] : Real(0);
+                    const Real fp = zflow ? tZ[tix<Real>(q, vl)] : Real(0);
                     r[q] = fma(cz, fp, r[q]);
                 }
                 phase_fence();
@@ -472,15 +470,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
 #pragma unroll
                     for (int q = 0; q < NL; ++q) stb(outE, o + q * QB, -r[q]);
                 }
+                __syncthreads();  // every layer is done with the stage tile
                 continue;
             }
             // collision source and the Runge-Kutta combination, point by point
             const Real dt = (Real)A.sa.dt;
 #pragma unroll
             for (int q = 0; q < NL; ++q) {
-                const Real fq = trow[q];
+                const Real fq = tS[tix<Real>(l * NL + q, vl)];
                 Real L = -r[q];
-                if (collide) {
+                if (EQ_LDS && collide) {
                     const int s = l * NL + q;
                     const double *b = &s_eb[s * 8];
                     const double *V = &s_ev[s * 4];
@@ -495,6 +494,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                     E = fma(c1, t1, E);
                     E = fma(c2, t2, E);
                     L += (exp_r<Real>(E) - fq) * (Real)b[7];
+                } else if (collide) {
+                    // E = c0 - (c^T B c)/2, c = u - V, formed in FP64
+                    cdouble *rq = eqL + q * kEqW;
+                    const double c0 = v.u[0] - rq[EQ_V], c1 = v.u[1] - rq[EQ_V + 1], c2 = v.u[2] - rq[EQ_V + 2];
+                    const double d1 = c1 + c1, d2 = c2 + c2;
+                    double t0 = rq[EQ_B] * c0;
+                    t0 = fma(rq[EQ_B + 3], d1, t0);
+                    t0 = fma(rq[EQ_B + 4], d2, t0);
+                    double t1 = rq[EQ_B + 1] * c1;
+                    t1 = fma(rq[EQ_B + 5], d2, t1);
+                    double S = c0 * t0;
+                    S = fma(c1, t1, S);
+                    S = fma(c2 * rq[EQ_B + 2], c2, S);
+                    const double E = fma(-0.5, S, rq[EQ_C0]);
+                    L += (exp_r<Real>(E) - fq) * (Real)rq[EQ_INVTAU];
                 }
                 Real fo;
                 if (A.sa.scheme == 0) {
@@ -510,9 +524,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                 if (v.act) stb(outE, o + q * QB, fo);
                 if (q % 4 == 3) phase_fence();
             }
-        } else {
-#pragma unroll
-            for (int q = 0; q < NL; ++q) f[q] = trow[q];
         }
 
         // outflow traces of the produced value on the x and y faces, into
@@ -529,28 +540,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
 #pragma unroll
                     for (int a = 0; a < N; ++a) {
                         Real t = Real(0);
+                        if (FLUX) {
 #pragma unroll
-                        for (int m = 0; m < N; ++m)
-                            t += T.lam[side][m] * (d == 0 ? f[m + N * a] : f[a + N * m]);
+                            for (int m = 0; m < N; ++m)
+                                t += T.lam[side][m] * (d == 0 ? f[m + N * a] : f[a + N * m]);
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < N; ++m)
+                                t += T.lam[side][m] * tpub[tix<Real>(l * NL + (d == 0 ? m + N * a : a + N * m), vl)];
+                        }
                         tp[a * cnt] = t;
                     }
                 }
             }
         }
 
-        // tile of the produced value (the prime pass left the value there):
-        // z traces and the moment reduction
+        // produced value of every layer: z traces and the moment reduction
         if (A.do_moments || A.do_traces) {
             if (FLUX) {
-                wave_sync();
-                if (lane_ok) {
 #pragma unroll
-                    for (int q = 0; q < NL; ++q) tile[wave][vl][l * NL + q] = f[q];
-                }
-                wave_sync();
+                for (int q = 0; q < NL; ++q) tP[tix<Real>(l * NL + q, vl)] = f[q];
             }
+            __syncthreads();  // the produced tile is complete (and the stage tile no longer read)
             if (A.do_traces && v.act && v.sgn[2] != 0) {
-                // this lane writes the z-face points (i, j = l)
+                // this wave writes the z-face points (i, j = l)
                 const int side = v.sgn[2] > 0 ? 1 : 0;
                 const int face = 4 + side;
                 const int cnt = (int)T.cnt[face];
@@ -561,29 +574,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                     const int q = i + N * l;
                     Real t = Real(0);
 #pragma unroll
-                    for (int m = 0; m < N; ++m) t += T.lam[side][m] * tile[wave][vl][m * NL + q];
+                    for (int m = 0; m < N; ++m) t += T.lam[side][m] * tout[tix<Real>(m * NL + q, vl)];
                     tp[i * cnt] = t;
                 }
             }
-            if (A.do_moments && lane < NS) {
-                // Moments of this wave's velocities (lane = solution point).
-                // Along an x-row only w_x varies with the node; each row
-                // segment is summed as (sum w_x f, sum w_x u_x f, sum w_x u_x^2 f)
-                // and closed with the row's (y, z) weights: 3 FMA per node
-                // instead of one per moment.  Weights are wave-uniform and
-                // read through the scalar cache (never written by the kernel).
-                typedef const __attribute__((address_space(4))) double cdouble;
+            if (A.do_moments && vl < NS) {
+                // Moments of this wave's share of the chunk (lane = solution
+                // point).  Along an x-row only w_x varies with the node; each
+                // row segment is summed as (sum w_x f, sum w_x u_x f,
+                // sum w_x u_x^2 f) and closed with the row's (y, z) weights:
+                // 3 FMA per node instead of one per moment.  Weights are
+                // wave-uniform and read through the scalar cache (never
+                // written by the kernel).
                 cdouble *wx3 = (cdouble *)A.wx3;
                 cdouble *wrow = (cdouble *)A.wrow;
-                const int kb = kbase(ch);
+                const int j0 = l * VPM;
+                const int kb = ch * kChunk + j0;
                 const int nx = A.vg.nv[0];
-                const int jn = nu - kb < VPW ? nu - kb : VPW;
+                int jn = kChunk - j0 < VPM ? kChunk - j0 : VPM;
+                if (nu - kb < jn) jn = nu - kb;
                 int ix = kb % nx, row = kb / nx;
                 double M[NMOM], a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
                 for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
                 for (int j = 0; j < jn; ++j) {
-                    const double x = (double)tile[wave][j][lane];
+                    const double x = (double)tout[tix<Real>(vl, j0 + j)];
                     a0 = fma(wx3[3 * ix], x, a0);
                     a1 = fma(wx3[3 * ix + 1], x, a1);
                     a2 = fma(wx3[3 * ix + 2], x, a2);
@@ -611,23 +626,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(fr_waves
                     }
                 }
 #pragma unroll
-                for (int a = 0; a < NMOM; ++a) red[wave][lane][a] += M[a];
+                for (int a = 0; a < NMOM; ++a) Mrun[a] += M[a];
             }
+        } else if (FLUX) {
+            __syncthreads();  // every layer is done with the stage tile
         }
     }
 
     if (A.do_moments) {
+        __syncthreads();  // the tiles are free: they take the waves' partial sums
+        if (vl < NS) {
+#pragma unroll
+            for (int a = 0; a < NMOM; ++a) red[(l * NS + vl) * NMOM + a] = Mrun[a];
+        }
         __syncthreads();
-        for (int i = tid; i < NS * NMOM; i += kBlock) {
-            const int s = i / NMOM, a = i % NMOM;
-            A.sa.Q[(e * NS + s) * NMOM + a] = ((red[0][s][a] + red[1][s][a]) + red[2][s][a]) + red[3][s][a];
+        for (int i = tid; i < NS * NMOM; i += NT) {
+            double t = red[i];
+#pragma unroll
+            for (int w = 1; w < N; ++w) t += red[w * NS * NMOM + i];
+            A.sa.Q[(e * NS) * NMOM + i] = t;
         }
     }
 }
 
 template <typename Real, int P, int NMOM>
 int launch_p(fr_dvm *h, int mode, const FrArgs &A) {
-    dim3 grid((unsigned)(A.sa.ecount ? A.sa.ecount : h->ne)), block(kBlock);
+    dim3 grid((unsigned)(A.sa.ecount ? A.sa.ecount : h->ne)), block(kChunk * (P + 1));
     if (mode == MODE_PRIME)
         hipLaunchKernelGGL((k_fr_layer<Real, P, NMOM, MODE_PRIME>), grid, block, 0, h->stream, A);
     else if (mode == MODE_STAGE)
