@@ -14,9 +14,12 @@ U0 = 0.5 with a 1 % seeded perturbation):
     first, untimed, on states of this grid including the solver's own initial
     states) and warm afterwards;
   both timed over the same K steps from the same initial state.  ``value`` is
-  the mixed + learned throughput.  Equal error: the relative L2 difference of
-  the conserved moments between the two runs is compared with the FP64 run's
-  own time-discretisation error, estimated by a dt / 2 FP64 run.
+  the mixed + learned throughput.  Equal error (untimed runs over the
+  workload's horizon, 200 steps at 24^3): the relative L2 difference of the
+  conserved moments between the two forms is compared with the FP64
+  solution's own discretisation error, temporal from a dt / 2 FP64 run and
+  spatial by Richardson from an N / 2 FP64 run; the conservation drift of
+  both runs is reported too.
 ``--mode single`` times one configuration (flags choose precision, RK scheme,
 guess, model) and is what the profiler runs.
 
@@ -245,7 +248,10 @@ def main():
     ap.add_argument("--guess", type=int, default=None, help="single mode: 0 cold, 1 warm, 2 MLP, 3 MLP then warm")
     ap.add_argument("--model", type=int, default=None, help="0 BGK, 1 ES-BGK, 2 collisionless")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--no-error", action="store_true", help="compare mode: skip the dt/2 error estimate")
+    ap.add_argument("--no-error", action="store_true",
+                    help="compare mode: skip the error runs at the workload's horizon")
+    ap.add_argument("--horizon", type=int, default=None,
+                    help="compare mode: steps of the error runs (default: the workload's, 200 at 24^3)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="instead of the benchmark, copy this many GiB with the library's plain copy kernel "
@@ -314,25 +320,34 @@ def main():
     # compare mode: plain FP64 against mixed precision + learned Newton start
     p64 = dict(base, precision=0, rk=0, guess=0)
     pmx = dict(base, precision=1, rk=1, guess=3)
-    horizon = args.steps + args.warmup
     r64 = run_config(W, w, mesh, p64, args.steps, args.warmup, "fp64-plain", keep_moments=True)
-    err = None
-    if not args.no_error:
-        # discretisation error of the FP64 solution at the same horizon:
-        # temporal from a dt/2 run, spatial from the N/2 mesh at the same dt
-        # (Richardson with order p+1: e_N ~ |Q_N - I Q_N/2| / (2^(p+1) - 1))
-        rh = run_config(W, w, mesh, p64, args.steps, 0, "fp64-half-dt", keep_moments=True, dt_scale=0.5,
-                        nsteps_override=2 * horizon)
-        mesh_c = W.box_mesh(w["N"] // 2)
-        rc = run_config(W, w, mesh_c, p64, args.steps, 0, "fp64-coarse", keep_moments=True, dt_override=r64["dt"],
-                        nsteps_override=horizon)
-        e_t = rel_moments(r64["Q"], rh["Q"])
-        e_s = {k: v / (2 ** (w["p"] + 1) - 1)
-               for k, v in rel_moments(coarse_to_fine(rc["Q"], w["N"] // 2, w["p"]), r64["Q"]).items()}
-        err = {"temporal": e_t, "spatial": e_s, "total": {k: e_t[k] + e_s[k] for k in e_t}}
     weights, tinfo = train_guess(W, w, log)
     rmx = run_config(W, w, mesh, pmx, args.steps, args.warmup, "mixed-learned", weights=weights, keep_moments=True)
-    err_m = rel_moments(rmx["Q"], r64["Q"])
+    err = None
+    if args.no_error:
+        # moment difference after the timed runs only
+        horizon = args.steps + args.warmup
+        a64, amx = r64, rmx
+    else:
+        # the error comparison runs the workload's own horizon (untimed):
+        # FP64 and mixed + learned from the same initial state, and the
+        # discretisation error of the FP64 solution at that horizon:
+        # temporal from a dt/2 run, spatial from the N/2 mesh at the same dt
+        # (Richardson with order p+1: e_N ~ |Q_N - I Q_N/2| / (2^(p+1) - 1))
+        horizon = args.horizon if args.horizon is not None else int(w.get("steps", args.steps + args.warmup))
+        a64 = run_config(W, w, mesh, p64, 0, 0, "fp64-horizon", keep_moments=True, nsteps_override=horizon)
+        amx = run_config(W, w, mesh, pmx, 0, 0, "mixed-horizon", weights=weights, keep_moments=True,
+                         nsteps_override=horizon)
+        rh = run_config(W, w, mesh, p64, 0, 0, "fp64-half-dt", keep_moments=True, dt_scale=0.5,
+                        nsteps_override=2 * horizon)
+        mesh_c = W.box_mesh(w["N"] // 2)
+        rc = run_config(W, w, mesh_c, p64, 0, 0, "fp64-coarse", keep_moments=True, dt_override=a64["dt"],
+                        nsteps_override=horizon)
+        e_t = rel_moments(a64["Q"], rh["Q"])
+        e_s = {k: v / (2 ** (w["p"] + 1) - 1)
+               for k, v in rel_moments(coarse_to_fine(rc["Q"], w["N"] // 2, w["p"]), a64["Q"]).items()}
+        err = {"temporal": e_t, "spatial": e_s, "total": {k: e_t[k] + e_s[k] for k in e_t}}
+    err_m = rel_moments(amx["Q"], a64["Q"])
     # equal error: the mixed run differs from the FP64 run by less than a
     # tenth of the FP64 run's own discretisation error, field by field
     holds = None if err is None else all(err_m[k] <= 0.1 * err["total"][k] for k in err_m)
@@ -344,7 +359,7 @@ def main():
         ref = [abs(t0[0]), *[math.sqrt(2.0 * abs(t0[0] * t0[4]))] * 3, abs(t0[4])]
         return {k: abs(t1[i] - t0[i]) / max(ref[i], 1e-300)
                 for i, k in enumerate(("rho", "rhoUx", "rhoUy", "rhoUz", "E"))}
-    drift = {lab: drift_of(r) for lab, r in (("fp64", r64), ("mixed", rmx))}
+    drift = {lab: drift_of(r) for lab, r in (("fp64", a64), ("mixed", amx))}
     cfg.update(mixed="FP32 f, FP32 FR/RK arithmetic, FP64 moments + Newton; LSRK3-2N; learned then warm Newton start",
                plain="FP64 everything; SSP-RK3; cold Newton start")
     out = {"metric": "DOF-updates/s (N_e*N_s*N_u per RK stage), mixed+learned vs FP64 at equal error",
