@@ -75,10 +75,17 @@ def stage_bytes(p: int, es: int, rk: int, nsteps: int) -> float:
     return tot
 
 
+KERNEL_SOURCES = ("frdvm_fr.hip", "frdvm_dev.h", "frdvm_common.h")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources the fused stage kernel is compiled from."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2312_06567_amd", "csrc", "frdvm_fr.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_06567_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str, precision: int, rk: int):

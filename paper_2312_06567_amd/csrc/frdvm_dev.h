@@ -1,0 +1,32 @@
+// Device helpers shared by the HIP sources (included by .hip files only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace frdvm {
+
+// exp of an exponent held in FP64, rounded once to FP32.  E = (n + r) ln 2
+// with n integer and |r| <= 1/2, reduced in FP64; 2^r = e^t, t = r ln 2
+// (|t| <= 0.347), by its Taylor series to degree 8 in FP64 (error below
+// 3e-10 relative), scaled by 2^n and rounded to FP32: within half an FP32
+// ulp plus 3e-10, with no systematic sign.  (An FP32 exponent of a few units
+// would bias every equilibrium value of a point by ~1e-7; the hardware FP32
+// exp2, accurate to 1 ulp but not correctly rounded, still leaves a bias
+// that shows as a mass drift of the collision over many steps.)
+__device__ __forceinline__ float exp_to_f32(double E) {
+    const double e2 = E * 1.4426950408889634074;  // log2(e)
+    const double n = rint(e2);
+    const double t = (e2 - n) * 0.69314718055994530942;  // ln(2)
+    double p = 1.0 / 40320.0;  // Horner on 1/k!, k = 8 .. 0
+    p = fma(p, t, 1.0 / 5040.0);
+    p = fma(p, t, 1.0 / 720.0);
+    p = fma(p, t, 1.0 / 120.0);
+    p = fma(p, t, 1.0 / 24.0);
+    p = fma(p, t, 1.0 / 6.0);
+    p = fma(p, t, 0.5);
+    p = fma(p, t, 1.0);
+    p = fma(p, t, 1.0);
+    return (float)ldexp(p, (int)n);
+}
+
+}  // namespace frdvm

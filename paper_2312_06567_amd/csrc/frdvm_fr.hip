@@ -37,6 +37,7 @@
 #include <cstring>
 
 #include "frdvm_common.h"
+#include "frdvm_dev.h"
 
 namespace frdvm {
 
@@ -86,18 +87,13 @@ __device__ __forceinline__ const OpsR<float> &ops_of<float>(const FrArgs &A) { r
 template <>
 __device__ __forceinline__ const OpsR<double> &ops_of<double>(const FrArgs &A) { return A.od; }
 
-// exp of an exponent held in FP64, returned in the working precision.  For
-// FP32 the reduction to 2^n 2^r, |r| <= 1/2, is done in FP64 and only 2^r is
-// taken in FP32: the result carries the ~1 ulp error of the hardware exp2
-// and no error proportional to |E| (an FP32 exponent of a few units would
-// bias every equilibrium value of a point by ~1e-7 and spoil conservation).
+// exp of an exponent held in FP64, returned in the working precision (FP32:
+// evaluated in FP64 and rounded once, see exp_to_f32).
 template <typename Real>
 __device__ __forceinline__ Real exp_r(double E);
 template <>
 __device__ __forceinline__ float exp_r<float>(double E) {
-    const double e2 = E * 1.4426950408889634074;  // log2(e)
-    const double n = rint(e2);
-    return ldexpf(__builtin_amdgcn_exp2f((float)(e2 - n)), (int)n);
+    return exp_to_f32(E);
 }
 template <>
 __device__ __forceinline__ double exp_r<double>(double E) {

@@ -31,6 +31,7 @@
 #include <cstring>
 
 #include "frdvm_common.h"
+#include "frdvm_dev.h"
 
 namespace frdvm {
 
@@ -57,7 +58,7 @@ struct NewtonArgs {
     int max_iter;
     int guess;
     const float *dz_guess;  // [npts][5] learned correction (guess == MLP)
-    int use_fact;           // ES: factorised sums with per-wave LDS tables
+    int use_fact;           // ES: factorised sums with per-point LDS tables
 };
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
@@ -1052,11 +1053,12 @@ __global__ void k_collide(const VGrid vg, const double *__restrict__ eqs, const 
             double *So = (double *)Sv;
             So[idx] = accumulate ? So[idx] + S : S;
         } else {
-            const float c0 = (float)(u[0] - eq[EQ_V]), c1 = (float)(u[1] - eq[EQ_V + 1]), c2 = (float)(u[2] - eq[EQ_V + 2]);
-            const float q = (float)eq[EQ_B] * c0 * c0 + (float)eq[EQ_B + 1] * c1 * c1 + (float)eq[EQ_B + 2] * c2 * c2 +
-                            2.0f * ((float)eq[EQ_B + 3] * c0 * c1 + (float)eq[EQ_B + 4] * c0 * c2 +
-                                    (float)eq[EQ_B + 5] * c1 * c2);
-            const float g = __expf((float)eq[EQ_C0] - 0.5f * q);
+            // the exponent in FP64 and the exponential rounded once to FP32,
+            // as in the fused stage
+            const double c0 = u[0] - eq[EQ_V], c1 = u[1] - eq[EQ_V + 1], c2 = u[2] - eq[EQ_V + 2];
+            const double q = eq[EQ_B] * c0 * c0 + eq[EQ_B + 1] * c1 * c1 + eq[EQ_B + 2] * c2 * c2 +
+                             2.0 * (eq[EQ_B + 3] * c0 * c1 + eq[EQ_B + 4] * c0 * c2 + eq[EQ_B + 5] * c1 * c2);
+            const float g = exp_to_f32(eq[EQ_C0] - 0.5 * q);
             const float f = ((const float *)fv)[idx];
             const float S = (g - f) * (float)eq[EQ_INVTAU];
             float *So = (float *)Sv;

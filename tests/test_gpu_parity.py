@@ -1,7 +1,7 @@
 """GPU parity: every C-ABI call against the FP64 CPU oracle on the same
 seeded inputs (relative L2 <= 1e-12 in FP64 unless stated).
 
-Sizes span several velocity chunks of 256 with ragged tails, several
+Sizes span several velocity chunks of 64 with ragged tails, several
 elements and every supported order.
 """
 import numpy as np
@@ -112,6 +112,35 @@ def test_collide(F, orc, model, pr):
     assert rel(Qp.cpu().numpy().reshape(prim.shape), prim) < 1e-12
     stats = s.newton_stats()
     assert stats["n_fallback"] == 0 and stats["max_resid"] <= 1e-11
+
+
+def test_collide_fp32(F, orc):
+    """FP32 collision: the exponent is formed in FP64 and the exponential
+    rounded once to FP32, so S matches the FP64 oracle (given the same
+    FP32-rounded f) to FP32 rounding of its terms, and the mass and energy
+    moments of S vanish to the FP32 rounding level."""
+    mesh = W.box_mesh((2, 2, 2))
+    p = 2
+    grid = W.grid_spec(8, 6.0)
+    par = _params(model=1, pr=0.71, precision=1)
+    s = F.FrDvm(mesh, p, grid, par)
+    f = _noisy_maxwellian(mesh, p, grid, 5).astype(np.float32).astype(np.float64)
+    S = torch.zeros(s.shape, dtype=s.dtype, device="cuda")
+    s.collide(_gpu(s, f), S)
+    P = orc.Problem(mesh, p, grid, par)
+    Sr, prim, z, st, it = P.collide(f)
+    assert np.all(st == 0)
+    S32 = S.cpu().numpy().astype(np.float64)
+    tau_scale = np.abs(Sr).max() + np.abs(f).max() / 0.05
+    err = np.abs(S32 - Sr).max() / tau_scale
+    assert err < 3e-7, err
+    # per point, the mass and energy moments of S (psi >= 0, so the moments
+    # of |S| give the scale) vanish to the rounding of its FP32 values
+    # (2^-24 = 6e-8 of each term, mostly cancelling)
+    M, Ma = P.moments(S32), P.moments(np.abs(S32))
+    for a in (0, 4):
+        cons = (np.abs(M[..., a]) / Ma[..., a]).max()
+        assert cons < 1e-6, (a, cons)
 
 
 def test_maxwellian_is_steady(F):
