@@ -13,16 +13,27 @@ namespace frdvm {
 // would bias every equilibrium value of a point by ~1e-7; the hardware FP32
 // exp2, accurate to 1 ulp but not correctly rounded, still leaves a bias
 // that shows as a mass drift of the collision over many steps.)
+// a * b + c in FP64 as one three-operand instruction (all operands in VGPRs)
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 __device__ __forceinline__ float exp_to_f32(double E) {
     const double e2 = E * 1.4426950408889634074;  // log2(e)
     const double n = rint(e2);
     const double t = (e2 - n) * 0.69314718055994530942;  // ln(2)
-    double p = 1.0 / 40320.0;  // Horner on 1/k!, k = 8 .. 0
-    p = fma(p, t, 1.0 / 5040.0);
-    p = fma(p, t, 1.0 / 720.0);
-    p = fma(p, t, 1.0 / 120.0);
-    p = fma(p, t, 1.0 / 24.0);
-    p = fma(p, t, 1.0 / 6.0);
+    // Horner on 1/k!, k = 8 .. 0.  The three-operand FMA is spelled out:
+    // left to itself the compiler takes the accumulating two-operand form,
+    // which first copies each (loop-invariant) coefficient into the result
+    // register.
+    double p = 1.0 / 40320.0;
+    p = fma3(p, t, 1.0 / 5040.0);
+    p = fma3(p, t, 1.0 / 720.0);
+    p = fma3(p, t, 1.0 / 120.0);
+    p = fma3(p, t, 1.0 / 24.0);
+    p = fma3(p, t, 1.0 / 6.0);
     p = fma(p, t, 0.5);
     p = fma(p, t, 1.0);
     p = fma(p, t, 1.0);
