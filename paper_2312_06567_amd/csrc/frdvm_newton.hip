@@ -339,9 +339,9 @@ __device__ __forceinline__ double pair_block(const FactLayout &L, const double *
     const double c2a = tb[L.c2], c2b = tb[L.c2 + L.n2 - 1];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const int p = p0 + kLpp * b;
-        ii[b] = p % L.n0;
-        jj[b] = p / L.n0;
+        const unsigned p = (unsigned)(p0 + kLpp * b);  // non-negative: unsigned division is shorter
+        ii[b] = (int)(p % (unsigned)L.n0);
+        jj[b] = (int)(p / (unsigned)L.n0);
         const double kap = k02 * tb[L.c0 + ii[b]] + k12 * tb[L.c1 + jj[b]];
         gmax = fmax(gmax, fmax(fabs(kap * c2a), fabs(kap * c2b)));
         g[b] = tb[L.G0 + ii[b]] * tb[L.H0 + jj[b]];
