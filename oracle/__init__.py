@@ -76,6 +76,7 @@ def _declare(L):
     L.orc_rhs.argtypes = [P, _dp, _dp]
     L.orc_rk_step.argtypes = [P, _dp, C.c_double, C.c_int, C.c_int]
     L.orc_totals.argtypes = [P, _dp, _dp]
+    L.orc_kn_gll.argtypes = [P, _dp, _dp]
     L.orc_dt.argtypes = [P, C.c_double]
     L.orc_dt.restype = C.c_double
     L.orc_num_threads.restype = C.c_int
@@ -241,6 +242,15 @@ class Problem:
 
     def moments(self, f):
         return moments(_f64(f).reshape(self.shape), self.u, self.w)
+
+    def kn_gll(self, f):
+        """Density gradient-length local Knudsen number at every solution
+        point, [ne][ns] (Section "Results")."""
+        f = _f64(f).reshape(self.shape)
+        kn = np.zeros((self.ne, self.ns))
+        if lib().orc_kn_gll(C.byref(self._s), _d(f), _d(kn)) != 0:
+            raise RuntimeError("oracle kn_gll")
+        return kn
 
     def totals(self, f):
         f = _f64(f).reshape(self.shape)

@@ -892,6 +892,58 @@ double orc_dt(const orc_problem *P, double cfl) {
     return cfl * hmin / ((2 * P->p + 1) * umax);
 }
 
+/*
+ * Density gradient-length local Knudsen number (Section "Results", the
+ * continuum-breakdown indicator): Kn = lambda |grad rho| / rho with the local
+ * mean free path lambda = (mu(theta) / rho) sqrt(pi / (2 theta)), from the
+ * moments of f at every solution point.  grad rho is the gradient of the
+ * element's solution polynomial of rho at the point (no interface term):
+ * d rho / d x_c = (1/|J|) sum_d S[d][c] d rho / d xi_d, the xi derivatives
+ * along lines with D.  A point with rho <= 0 or theta <= 0 gets Kn = 0.
+ */
+int orc_kn_gll(const orc_problem *P, const double *f, double *kn) {
+    int n = P->p + 1, ns = n * n * n, nu = P->nu;
+    double xi[16], D[256], lL[16], lR[16], cM[16], cP[16];
+    if (orc_fr_ops(P->p, xi, D, lL, lR, cM, cP) != ORC_OK) return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < P->ne; ++e) {
+        ld Q[729][5];  /* ns <= 9^3 */
+        for (int s = 0; s < ns; ++s)
+            point_moments(nu, P->u, P->w, f + ((int64_t)e * ns + s) * nu, Q[s]);
+        for (int l = 0; l < n; ++l)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    int s = sidx(n, i, j, l);
+                    ld dr[3] = {0, 0, 0};
+                    for (int m = 0; m < n; ++m) {
+                        dr[0] += (ld)D[i * n + m] * Q[sidx(n, m, j, l)][0];
+                        dr[1] += (ld)D[j * n + m] * Q[sidx(n, i, m, l)][0];
+                        dr[2] += (ld)D[l * n + m] * Q[sidx(n, i, j, m)][0];
+                    }
+                    const double *Sm = P->S + ((int64_t)e * ns + s) * 9;
+                    ld dj = P->detJ[(int64_t)e * ns + s], g2 = 0;
+                    for (int c = 0; c < 3; ++c) {
+                        ld gc = 0;
+                        for (int d = 0; d < 3; ++d) gc += (ld)Sm[d * 3 + c] * dr[d];
+                        gc /= dj;
+                        g2 += gc * gc;
+                    }
+                    ld rho = Q[s][0];
+                    ld ux = Q[s][1] / rho, uy = Q[s][2] / rho, uz = Q[s][3] / rho;
+                    ld th = (2.0L / 3.0L) * (Q[s][4] / rho - 0.5L * (ux * ux + uy * uy + uz * uz));
+                    double out = 0.0;
+                    if (rho > 0 && th > 0) {
+                        ld mu = orc_viscosity((double)th, P->mu_ref, P->theta_ref, P->omega, P->visc_law,
+                                              P->theta_s);
+                        ld lam = mu / rho * sqrtl(3.14159265358979323846264338327950288L / (2.0L * th));
+                        out = (double)(lam * sqrtl(g2) / rho);
+                    }
+                    kn[(int64_t)e * ns + s] = out;
+                }
+    }
+    return ORC_OK;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();
