@@ -164,6 +164,15 @@ int fr_dvm_collide(fr_dvm_t h, const void *f, void *S, double *Qp, int accumulat
  * integrals (Gauss weights x |J|).  Synchronises when totals != NULL. */
 int fr_dvm_moments(fr_dvm_t h, const void *f, double *Q, double *totals);
 
+/* Gradient-length local Knudsen number at every solution point (Section
+ * "Results", the continuum-breakdown parameter): Kn = lambda |grad rho| / rho,
+ * lambda = mu(theta)/rho sqrt(pi / (2 theta)) with the handle's viscosity law,
+ * grad rho the derivative of the element's solution polynomial of the
+ * discrete density.  f: device [e][s][k] in the handle's precision; kn:
+ * device double [e][s], 0 where rho <= 0 or theta <= 0.  Asynchronous on the
+ * handle's stream; overwrites the handle's moment buffer. */
+int fr_dvm_kn_gll(fr_dvm_t h, const void *f, double *kn);
+
 /* Advance f (device, in place) by one / nsteps explicit steps of size dt of
  * df/dt = R(f) + S(f) with the scheme chosen in the parameters. */
 int fr_dvm_rk_step(fr_dvm_t h, void *f, double dt);

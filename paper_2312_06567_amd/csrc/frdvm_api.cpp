@@ -51,6 +51,14 @@ extern "C" int fr_dvm_moments(fr_dvm_t h, const void *f, double *Q, double *tota
     return FR_DVM_OK;
 }
 
+extern "C" int fr_dvm_kn_gll(fr_dvm_t h, const void *f, double *kn) {
+    int rc = ready(h);
+    if (rc) return rc;
+    if (!f || !kn) return h->fail(FR_DVM_EINVAL, "null f or kn");
+    if ((rc = prime(h, f, 0, 1))) return rc;
+    return launch_kn_gll(h, kn);
+}
+
 extern "C" int fr_dvm_residual(fr_dvm_t h, const void *f, void *R) {
     int rc = ready(h);
     if (rc) return rc;

@@ -182,5 +182,6 @@ int launch_collide(fr_dvm *h, const void *f, void *S, int accumulate);
 int launch_prim_out(fr_dvm *h, double *Qp);
 int launch_moments_out(fr_dvm *h, double *Q);
 int launch_totals(fr_dvm *h, double *host_tot);
+int launch_kn_gll(fr_dvm *h, double *kn);
 
 }  // namespace frdvm

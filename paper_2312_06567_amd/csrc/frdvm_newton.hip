@@ -1076,6 +1076,49 @@ __global__ void k_moments_out(int64_t npts, int nmom, const double *__restrict__
     o[4] = nmom == 5 ? q[4] : 0.5 * (q[4] + q[5] + q[6]);
 }
 
+// Gradient-length local Knudsen number (Section "Results"):
+// Kn = lambda |grad rho| / rho with the hard-sphere-type mean free path
+// lambda = mu(theta)/rho sqrt(pi/(2 theta)).  grad rho is the derivative of
+// the element's solution polynomial of rho (the FR interpolant, no interface
+// correction); on an axis-aligned box d/dx_d = (2/h_d) d/dxi_d.  One wave per
+// element (ns <= 64 points), the density of the element staged in LDS.
+// Points with rho <= 0 or theta <= 0 get 0.
+constexpr int kKnElems = 4;
+
+__global__ __launch_bounds__(64 * kKnElems) void k_kn_gll(NewtonArgs A, Ops1D ops, int n, int64_t ne,
+                                                          const double *__restrict__ gfac, double *__restrict__ kn) {
+    __shared__ double srho[kKnElems][64];
+    const int w = threadIdx.x >> 6, s = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * kKnElems + w;
+    const int ns = n * n * n;
+    const bool live = e < ne && s < ns;
+    const int64_t pt = e * ns + s;
+    if (live) srho[w][s] = A.Q[pt * A.nmom];
+    __syncthreads();
+    if (!live) return;
+    const int i = s % n, j = (s / n) % n, l = s / (n * n);
+    double d0 = 0, d1 = 0, d2 = 0;
+    for (int m = 0; m < n; ++m) {
+        d0 += ops.D[i * n + m] * srho[w][m + n * (j + n * l)];
+        d1 += ops.D[j * n + m] * srho[w][i + n * (m + n * l)];
+        d2 += ops.D[l * n + m] * srho[w][i + n * (j + n * m)];
+    }
+    d0 *= gfac[e * 3 + 0];
+    d1 *= gfac[e * 3 + 1];
+    d2 *= gfac[e * 3 + 2];
+    const double *q = A.Q + pt * A.nmom;
+    const double rho = q[0];
+    const double ux = q[1] / rho, uy = q[2] / rho, uz = q[3] / rho;
+    const double E = A.nmom == 5 ? q[4] : 0.5 * (q[4] + q[5] + q[6]);
+    const double th = (2.0 / 3.0) * (E / rho - 0.5 * (ux * ux + uy * uy + uz * uz));
+    double out = 0.0;
+    if (rho > 0.0 && th > 0.0) {
+        const double lam = viscosity(A, th) / rho * sqrt(kTwoPi / (4.0 * th));
+        out = lam * sqrt(d0 * d0 + d1 * d1 + d2 * d2) / rho;
+    }
+    kn[pt] = out;
+}
+
 // Domain totals: one workgroup, fixed-order strided sums and tree reduction.
 __global__ __launch_bounds__(1024) void k_totals(int64_t npts, int nmom, const double *__restrict__ Q,
                                                  const double *__restrict__ wJ, double *__restrict__ out) {
@@ -1303,6 +1346,13 @@ int launch_moments_out(fr_dvm *h, double *Q) {
     hipLaunchKernelGGL(k_moments_out, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, h->stream, npts, h->nmom,
                        h->d_Q, Q);
     return check(h, "moments output kernel");
+}
+
+int launch_kn_gll(fr_dvm *h, double *kn) {
+    NewtonArgs A = newton_args(h, FR_DVM_GUESS_COLD);
+    hipLaunchKernelGGL(k_kn_gll, dim3((unsigned)((h->ne + kKnElems - 1) / kKnElems)), dim3(64 * kKnElems), 0,
+                       h->stream, A, h->ops, h->n, h->ne, h->d_gfac, kn);
+    return check(h, "Knudsen number kernel");
 }
 
 int launch_totals(fr_dvm *h, double *host_tot) {

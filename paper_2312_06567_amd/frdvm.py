@@ -70,6 +70,7 @@ def lib():
         L.fr_dvm_residual.argtypes = [vp, vp, vp]
         L.fr_dvm_collide.argtypes = [vp, vp, vp, vp, C.c_int]
         L.fr_dvm_moments.argtypes = [vp, vp, vp, dp]
+        L.fr_dvm_kn_gll.argtypes = [vp, vp, vp]
         L.fr_dvm_rk_step.argtypes = [vp, vp, C.c_double]
         L.fr_dvm_rk_steps.argtypes = [vp, vp, C.c_double, C.c_int]
         L.fr_dvm_newton_stats.argtypes = [vp, i64p, i64p, i64p, i64p, dp, C.c_int]
@@ -302,6 +303,15 @@ class FrDvm:
         tp = tot.ctypes.data_as(C.POINTER(C.c_double)) if totals else None
         self._check(lib().fr_dvm_moments(self._h, _ptr(f), _ptr(Q), tp), "fr_dvm_moments")
         return tot
+
+    def kn_gll(self, f, kn):
+        """Gradient-length local Knudsen number per solution point into kn [e][s] (float64)."""
+        self._check_f(f, "f")
+        self._check_d(kn, self.ne * self.ns, "kn")
+        if kn is None:
+            raise FrDvmError("kn must be given")
+        self._check(lib().fr_dvm_kn_gll(self._h, _ptr(f), _ptr(kn)), "fr_dvm_kn_gll")
+        return kn
 
     def rk_step(self, f, dt):
         self._check_f(f, "f")

@@ -70,6 +70,24 @@ def test_moments_and_totals(F, orc, N, L, p, gn, um):
 
 
 @pytest.mark.parametrize("N,L,p,gn,um", CASES)
+@pytest.mark.parametrize("prm", [{"model": 0}, {"model": 1, "pr": 0.71}, {"model": 0, "visc_law": 1, "theta_s": 0.4}])
+def test_kn_gll(F, orc, N, L, p, gn, um, prm):
+    """Local Knudsen number per solution point; a vacuum point gives 0."""
+    mesh = W.box_mesh(N, length=L)
+    grid = W.grid_spec(gn, um)
+    par = _params(**prm)
+    s = F.FrDvm(mesh, p, grid, par)
+    f = _noisy_maxwellian(mesh, p, grid, 5)
+    f[1, 0] = 0.0
+    kn = torch.full((s.ne * s.ns,), -1.0, dtype=torch.float64, device="cuda")
+    s.kn_gll(_gpu(s, f), kn)
+    got = kn.cpu().numpy().reshape(s.ne, s.ns)
+    ref = orc.Problem(mesh, p, grid, par).kn_gll(f)
+    assert got[1, 0] == 0.0 and ref[1, 0] == 0.0
+    assert rel(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("N,L,p,gn,um", CASES)
 def test_residual(F, orc, N, L, p, gn, um):
     mesh = W.box_mesh(N, length=L)
     grid = W.grid_spec(gn, um)
