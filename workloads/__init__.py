@@ -78,6 +78,207 @@ def box_mesh(N, length=1.0, periodic=True) -> dict:
             "N": N, "length": L}
 
 
+def cylinder_mesh(n_theta=48, n_r=24, n_z=2, r0=0.5, r1=6.0, stretch=1.15, lz=0.25) -> dict:
+    """O-grid of 27-node (quadratic) hexes around a cylinder of radius r0 with
+    axis z: xi_0 radial (element widths growing by ``stretch`` from the wall
+    to r1), xi_1 azimuthal (mid-edge nodes on the arcs, so the faces are
+    curved), xi_2 spanwise over [0, lz] (periodic).  Element (i, j, k) has id
+    i + n_r (j + n_theta k).  Inner faces: diffuse wall (bc 2); outer faces:
+    farfield (bc 1)."""
+    g = stretch ** np.arange(n_r)
+    edges = r0 + (r1 - r0) * np.concatenate([[0.0], np.cumsum(g)]) / g.sum()
+    radii = np.empty(2 * n_r + 1)
+    radii[0::2] = edges
+    radii[1::2] = 0.5 * (edges[:-1] + edges[1:])
+    NR, NT, NZ = 2 * n_r + 1, 2 * n_theta, 2 * n_z + 1
+    th = 2 * np.pi * np.arange(NT) / NT
+    zz = lz * np.arange(NZ) / (NZ - 1)
+    R, T, Z = np.meshgrid(radii, th, zz, indexing="ij")
+    nodes = np.stack([R * np.cos(T), R * np.sin(T), Z], -1).transpose(2, 1, 0, 3).reshape(-1, 3)
+
+    def nid(a, b, c):
+        return a + NR * ((b % NT) + NT * c)
+
+    ne = n_r * n_theta * n_z
+    en = np.zeros((ne, 27), np.int32)
+    nbr = np.full((ne, 6), -1, np.int32)
+    nbf = np.zeros((ne, 6), np.int8)
+    bc = np.zeros((ne, 6), np.int8)
+    for k in range(n_z):
+        for j in range(n_theta):
+            for i in range(n_r):
+                e = i + n_r * (j + n_theta * k)
+                en[e] = [nid(2 * i + a, 2 * j + b, 2 * k + c) for c in range(3) for b in range(3) for a in range(3)]
+                if i > 0:
+                    nbr[e, 0] = e - 1
+                else:
+                    bc[e, 0] = 2
+                if i < n_r - 1:
+                    nbr[e, 1] = e + 1
+                else:
+                    bc[e, 1] = 1
+                nbr[e, 2] = i + n_r * ((j - 1) % n_theta + n_theta * k)
+                nbr[e, 3] = i + n_r * ((j + 1) % n_theta + n_theta * k)
+                nbr[e, 4] = i + n_r * (j + n_theta * ((k - 1) % n_z))
+                nbr[e, 5] = i + n_r * (j + n_theta * ((k + 1) % n_z))
+                for f in range(6):
+                    if nbr[e, f] >= 0:
+                        nbf[e, f] = FACE_OPPOSITE[f]
+    return {"n_elem": ne, "n_nodes": nodes.shape[0], "geom_order": 2,
+            "nodes": np.ascontiguousarray(nodes), "elem_nodes": en, "nbr_elem": nbr,
+            "nbr_face": nbf, "nbr_orient": np.zeros((ne, 6), np.int8), "bc": bc,
+            "r0": r0, "r1": r1, "lz": lz}
+
+
+def quadratic_map_mesh(N, eps=0.15, bc_all=1) -> dict:
+    """Non-periodic box [0,1]^3 of N^3 27-node hexes whose nodes are moved by
+    the global quadratic map x -> x + eps (x_1^2, x_2^2, x_0^2); every element
+    is then an exact quadratic image of a cube.  Every boundary face carries
+    bc ``bc_all``."""
+    if np.isscalar(N):
+        N = (int(N),) * 3
+    base = box_mesh(N, periodic=False)
+    nx, ny, nz = N
+    M = [2 * v + 1 for v in N]
+    gx = [np.linspace(0.0, 1.0, m) for m in M]
+    X = np.stack(np.meshgrid(gx[0], gx[1], gx[2], indexing="ij"), -1).transpose(2, 1, 0, 3).reshape(-1, 3)
+    X = X + eps * np.stack([X[:, 1] ** 2, X[:, 2] ** 2, X[:, 0] ** 2], -1)
+    ne = nx * ny * nz
+    en = np.zeros((ne, 27), np.int32)
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(nx):
+                e = ix + nx * (iy + ny * iz)
+                en[e] = [(2 * ix + a) + M[0] * ((2 * iy + b) + M[1] * (2 * iz + c))
+                         for c in range(3) for b in range(3) for a in range(3)]
+    bc = np.where(base["nbr_elem"] < 0, bc_all, 0).astype(np.int8)
+    return {**base, "n_nodes": X.shape[0], "geom_order": 2, "nodes": np.ascontiguousarray(X),
+            "elem_nodes": en, "bc": bc, "eps": eps}
+
+
+def _signed_perms():
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for flips in itertools.product((0, 1), repeat=3):
+            M = np.zeros((3, 3))
+            for d in range(3):
+                M[d, perm[d]] = -1.0 if flips[d] else 1.0
+            if np.linalg.det(M) > 0:
+                out.append((perm, flips))
+    return out
+
+
+def _orient_code(n, pairs):
+    """Orientation code (bit0 swap, bit1 reverse first, bit2 reverse second)
+    reproducing the face-point map pairs[(a, b)] = (pa, pb)."""
+    for o in range(8):
+        ok = True
+        for (a, b), (pa, pb) in pairs.items():
+            x, y = (b, a) if o & 1 else (a, b)
+            if o & 2:
+                x = n - 1 - x
+            if o & 4:
+                y = n - 1 - y
+            ok = ok and (x, y) == (pa, pb)
+        if ok:
+            return o
+    raise ValueError("no orientation code")
+
+
+def reorient_elements(mesh: dict, seed: int = 0):
+    """Give every element of a mesh built in one global frame (all faces
+    orientation 0, neighbour across face f on its face f^1, 8-node elements)
+    a random orientation-preserving local frame.  Returns (mesh, frames); the
+    frame of element e is (perm, flips): new axis d runs along old axis
+    perm[d], reversed if flips[d].  ``reindex_points`` maps per-element
+    arrays of tensor points between the frames."""
+    assert mesh["geom_order"] == 1
+    rng = np.random.default_rng(seed)
+    sp = _signed_perms()
+    ne = mesh["n_elem"]
+    frames = [sp[rng.integers(len(sp))] for _ in range(ne)]
+
+    def old_index(fr, I, n):
+        perm, flips = fr
+        J = [0, 0, 0]
+        for d in range(3):
+            J[perm[d]] = n - 1 - I[d] if flips[d] else I[d]
+        return J
+
+    def new_index(fr, J, n):
+        perm, flips = fr
+        return [n - 1 - J[perm[d]] if flips[d] else J[perm[d]] for d in range(3)]
+
+    en_old = mesh["elem_nodes"]
+    en = np.zeros_like(en_old)
+    for e in range(ne):
+        for c in range(2):
+            for b in range(2):
+                for a in range(2):
+                    J = old_index(frames[e], [a, b, c], 2)
+                    en[e, a + 2 * (b + 2 * c)] = en_old[e, J[0] + 2 * (J[1] + 2 * J[2])]
+    nbr = np.full((ne, 6), -1, np.int32)
+    nbf = np.zeros((ne, 6), np.int8)
+    nor = np.zeros((ne, 6), np.int8)
+    bc = np.zeros((ne, 6), np.int8)
+    n = 3  # face-point maps are independent of n; 3 points tell every code apart
+    for e in range(ne):
+        perm, flips = frames[e]
+        for f in range(6):
+            d, s = divmod(f, 2)
+            g = 2 * perm[d] + (s ^ flips[d])
+            nb = mesh["nbr_elem"][e, g]
+            if nb < 0:
+                bc[e, f] = mesh["bc"][e, g]
+                continue
+            t = [x for x in range(3) if x != d]
+            pairs = {}
+            nf_new = None
+            for bb in range(n):
+                for aa in range(n):
+                    I = [0, 0, 0]
+                    I[d] = s * (n - 1)
+                    I[t[0]], I[t[1]] = aa, bb
+                    J = old_index(frames[e], I, n)
+                    J[perm[d]] = n - 1 - J[perm[d]]
+                    K = new_index(frames[nb], J, n)
+                    pn, fn = frames[nb]
+                    dn = pn.index(perm[d])
+                    sn = (1 if J[perm[d]] == n - 1 else 0)
+                    sn_new = sn ^ fn[dn]
+                    nf_new = 2 * dn + sn_new
+                    tn = [x for x in range(3) if x != dn]
+                    pairs[(aa, bb)] = (K[tn[0]], K[tn[1]])
+            nbr[e, f] = nb
+            nbf[e, f] = nf_new
+            nor[e, f] = _orient_code(n, pairs)
+    out = {**mesh, "elem_nodes": en, "nbr_elem": nbr, "nbr_face": nbf, "nbr_orient": nor, "bc": bc}
+    return out, frames
+
+
+def reindex_points(a: np.ndarray, frames, p: int, to_new: bool = True) -> np.ndarray:
+    """Reorder axis 1 (the (p+1)^3 tensor points, x-fastest) of a per-element
+    array between the global frame and the frames of ``reorient_elements``."""
+    n = p + 1
+    out = np.empty_like(a)
+    for e, (perm, flips) in enumerate(frames):
+        for c in range(n):
+            for b in range(n):
+                for q in range(n):
+                    I = [q, b, c]
+                    J = [0, 0, 0]
+                    for d in range(3):
+                        J[perm[d]] = n - 1 - I[d] if flips[d] else I[d]
+                    sn = q + n * (b + n * c)
+                    so = J[0] + n * (J[1] + n * J[2])
+                    if to_new:
+                        out[e, sn] = a[e, so]
+                    else:
+                        out[e, so] = a[e, sn]
+    return out
+
+
 def gauss_points(p: int) -> np.ndarray:
     return np.polynomial.legendre.leggauss(p + 1)[0]
 
