@@ -31,7 +31,7 @@ int prime(fr_dvm *h, const void *f, int traces, int moments) {
     a.tr_out = h->d_tr[h->cur_tr];
     a.Q = h->d_Q;
     ProfScope ps(h, 2);
-    return launch_fr_axis(h, 0, a, traces, moments);
+    return launch_fr(h, 0, a, traces, moments);
 }
 
 int guess_mode(fr_dvm *h) {
@@ -69,7 +69,7 @@ extern "C" int fr_dvm_residual(fr_dvm_t h, const void *f, void *R) {
     a.f = f;
     a.fout = R;
     a.tr_in = h->d_tr[h->cur_tr];
-    return launch_fr_axis(h, 2, a, 0, 0);
+    return launch_fr(h, 2, a, 0, 0);
 }
 
 extern "C" int fr_dvm_collide(fr_dvm_t h, const void *f, void *S, double *Qp, int accumulate) {
@@ -160,7 +160,7 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
     // halves on its own stream (the neighbour traces it reads).  Per point
     // the work and its order are those of the single-stream path.
     // (decided after the first solve: a learned-then-warm start is warm from here on)
-    const bool split = h->prm.overlap && collide && h->ne >= 2 && newton_part_ok(h, guess);
+    const bool split = h->prm.overlap && h->axis_mode && collide && h->ne >= 2 && newton_part_ok(h, guess);
     if (split && (rc = ensure_aux(h))) return rc;
     const int64_t eh[3] = {0, h->ne / 2, h->ne};
     const int nst = 3 * nsteps;
@@ -172,7 +172,7 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
         if (!split) {
             if (k > 0 && collide && (rc = launch_newton(h, guess))) return rc;
             ProfScope ps(h, 0);
-            if ((rc = launch_fr_axis(h, 1, a, traces, moments))) return rc;
+            if ((rc = launch_fr(h, 1, a, traces, moments))) return rc;
         } else {
             for (int half = 0; half < 2; ++half) {
                 if (k > 0 && hipStreamWaitEvent(h->stream, h->ev_newton[half], 0) != hipSuccess)
@@ -181,7 +181,7 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
                 a.ecount = eh[half + 1] - eh[half];
                 {
                     ProfScope ps(h, 0);
-                    if ((rc = launch_fr_axis(h, 1, a, traces, moments))) return rc;
+                    if ((rc = launch_fr(h, 1, a, traces, moments))) return rc;
                 }
                 if (last) continue;
                 if (hipEventRecord(h->ev_stage[half], h->stream) != hipSuccess ||

@@ -79,6 +79,17 @@ struct fr_dvm {
 
     // device: geometry and tables
     double *d_gfac = nullptr;    // [ne][3]
+    // general (curved / re-oriented / bounded) meshes, axis_mode == false
+    double *d_S = nullptr;       // [ne][ns][3][3] S[d][c] = (|J| J^-1)_dc, rows a^d = |J| grad xi_d
+    double *d_ijac = nullptr;    // [ne][ns] 1/|J|
+    double *d_nf = nullptr;      // [ne][6][nfp][3] outward area-scaled normal at the flux points
+    float *d_Sf = nullptr, *d_ijacf = nullptr, *d_nff = nullptr;  // FP32 copies
+    int32_t *d_conn = nullptr;   // [ne][6][4] neighbour, its face, orientation code, bc tag
+    int32_t *d_wall = nullptr;   // [nwall] e*6+face of every diffuse-wall face
+    int64_t nwall = 0;
+    double *d_rw = nullptr;      // [ne*6][nfp] wall-Maxwellian density of the current stage
+    double *d_mw = nullptr;      // [nu] unit-density wall Maxwellian at theta_wall
+    double *d_finf = nullptr;    // [nu] farfield Maxwellian
     int32_t *d_nbr = nullptr;    // [ne][6]
     double *d_wq3J = nullptr;    // [ne*ns] Gauss weight x |J| per solution point
     double *d_wx3 = nullptr;     // [nv_x][3] moment weights along x: w, w u_x, w u_x^2
@@ -169,6 +180,14 @@ struct StageArgs {
     int64_t e0, ecount;      // element range [e0, e0 + ecount); ecount 0: all elements
 };
 int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);
+// ---- general meshes (frdvm_gen.hip): same modes and arguments ----
+int launch_fr_gen(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);
+// boundary tables of the current parameters (wall and farfield Maxwellians)
+int gen_boundary_tables(fr_dvm *h);
+inline int launch_fr(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments) {
+    return h->axis_mode ? launch_fr_axis(h, mode, a, do_traces, do_moments)
+                        : launch_fr_gen(h, mode, a, do_traces, do_moments);
+}
 
 // ---- launchers (frdvm_newton.hip) ----
 int launch_newton(fr_dvm *h, int guess);

@@ -1,0 +1,512 @@
+// FR residual + collision + Runge-Kutta stage on general hexahedral meshes
+// (gfx950): curved 27-node elements, faces met under any orientation,
+// farfield and diffuse isothermal wall boundaries.
+//
+// Paper, Section "Numerical method": per velocity node the transformed flux
+// F~_d = (a^d . u) f with the area-scaled contravariant vectors
+// a^d = |J| grad xi_d, its divergence along the element's tensor lines, and
+// at every flux point the upwind common flux F^I = u_n f- (u_n > 0) or
+// u_n f+ (otherwise), u_n = u . n with the area-scaled outward normal; the
+// jump F^I - u_n f- enters through the DG-recovering correction.  Exterior
+// states: the neighbour's trace, the freestream Maxwellian (farfield) or
+// rho_w M(0, theta_w) (diffuse wall at rest) with rho_w chosen so that no
+// mass crosses the wall.  The collision source (g(Q') - f)/tau and the RK
+// combination are those of the box kernel.
+//
+// Work decomposition: one wave per (element, 64 velocities), one lane per
+// velocity; the element's metrics and normals are read through the scalar
+// cache, its equilibrium records staged in LDS.  A lane keeps its velocity's
+// N^3 values and their residual in a private LDS column: the divergence is
+// scattered source point by source point (3N FMA each), the face terms
+// gathered along the lines through each flux point.  Every access to f, the
+// RK registers and the traces is a run of consecutive velocities.  Traces
+// are full (every velocity at every flux point, [e][face][point][k]); a lane
+// reads the neighbour trace only where its velocity enters the element.
+// The per-point moments are a separate reduction over the velocity axis.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "frdvm_common.h"
+#include "frdvm_dev.h"
+
+namespace frdvm {
+
+namespace {
+
+constexpr int GMODE_STAGE = 1, GMODE_RESID = 2;
+constexpr int kGBlock = 256;  // velocities per workgroup (traces, moments, wall sums)
+constexpr int kGWave = 64;    // velocities per workgroup of the stage kernel
+
+template <typename Real>
+struct GOps {
+    Real D[kMaxN * kMaxN];
+    Real lam[2][kMaxN];
+    Real corr[2][kMaxN];
+};
+
+struct GenArgs {
+    GOps<float> of;
+    GOps<double> od;
+    VGrid vg;
+    int nu, nvb, nvw;  // velocities; blocks of 256 and of 64 velocities per element
+    const double *wax;   // [3][64] 1-D trapezoid weights
+    const double *S;     // [ne][ns][3][3]
+    const double *ijac;  // [ne][ns]
+    const double *nf;    // [ne][6][nfp][3]
+    const float *Sf, *ijacf, *nff;  // the same in FP32
+    const int32_t *conn; // [ne][6][4]
+    const int32_t *wall; // [nwall]
+    double *rw;          // [ne*6][nfp]
+    const double *mw;    // [nu]
+    const double *finf;  // [nu]
+    StageArgs sa;
+    int do_traces;
+};
+
+template <typename Real>
+__device__ __forceinline__ const GOps<Real> &gops(const GenArgs &A);
+template <>
+__device__ __forceinline__ const GOps<float> &gops<float>(const GenArgs &A) { return A.of; }
+template <>
+__device__ __forceinline__ const GOps<double> &gops<double>(const GenArgs &A) { return A.od; }
+
+// Metric tables in the working precision, read through the scalar cache
+// (the indices are uniform over the workgroup).
+template <typename Real>
+using cptr = const __attribute__((address_space(4))) Real *;
+template <typename Real>
+struct Metrics {
+    cptr<Real> S, ijac, nf;
+};
+__device__ __forceinline__ Metrics<float> metrics(const GenArgs &A, float) {
+    return {(cptr<float>)A.Sf, (cptr<float>)A.ijacf, (cptr<float>)A.nff};
+}
+__device__ __forceinline__ Metrics<double> metrics(const GenArgs &A, double) {
+    return {(cptr<double>)A.S, (cptr<double>)A.ijac, (cptr<double>)A.nf};
+}
+
+template <typename Real>
+__device__ __forceinline__ Real gexp(double E);
+template <>
+__device__ __forceinline__ float gexp<float>(double E) { return exp_to_f32(E); }
+template <>
+__device__ __forceinline__ double gexp<double>(double E) { return exp(E); }
+
+// Uniform base + the lane's byte offset (a run of consecutive velocities).
+template <typename T>
+__device__ __forceinline__ T ldo(const T *base, uint32_t boff) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *base, uint32_t boff, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + boff) = v;
+}
+
+// Velocity node umin + i du (two roundings, as on the host).
+__device__ __forceinline__ double node_u(const VGrid &vg, int d, int i) {
+    return __dadd_rn(vg.umin[d], __dmul_rn((double)i, vg.du[d]));
+}
+
+__device__ __forceinline__ void split_k(const VGrid &vg, int k, int iv[3]) {
+    iv[0] = k % vg.nv[0];
+    iv[1] = (k / vg.nv[0]) % vg.nv[1];
+    iv[2] = k / (vg.nv[0] * vg.nv[1]);
+}
+
+template <int N>
+__device__ __forceinline__ constexpr int spt(int i, int j, int l) { return i + N * (j + N * l); }
+
+// m-th point of the line along axis d through face point (a, b); (a, b) run
+// along the two other axes in increasing order.
+template <int N>
+__device__ __forceinline__ constexpr int line_pt(int d, int a, int b, int m) {
+    return d == 0 ? spt<N>(m, a, b) : (d == 1 ? spt<N>(a, m, b) : spt<N>(a, b, m));
+}
+
+// Own face point (a, b) -> neighbour face point under orientation code o.
+template <int N>
+__device__ __forceinline__ int nbr_point(int o, int a, int b) {
+    int x = (o & 1) ? b : a, y = (o & 1) ? a : b;
+    if (o & 2) x = N - 1 - x;
+    if (o & 4) y = N - 1 - y;
+    return x + N * y;
+}
+
+// Traces of f at every flux point of the element, every velocity.
+template <typename Real, int P>
+__global__ __launch_bounds__(kGBlock) void k_gen_traces(const GenArgs A, const Real *__restrict__ f,
+                                                         Real *__restrict__ tr) {
+    constexpr int N = P + 1, NS = N * N * N, NFP = N * N;
+    const int64_t e = blockIdx.x / A.nvb;
+    const int k = (int)(blockIdx.x % A.nvb) * kGBlock + threadIdx.x;
+    if (k >= A.nu) return;
+    const int64_t nu = A.nu;
+    const GOps<Real> &op = gops<Real>(A);
+    const uint32_t ko = (uint32_t)k * (uint32_t)sizeof(Real);
+    const Real *fe = f + e * NS * nu;
+    Real v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = ldo(fe + s * nu, ko);
+    Real *te = tr + e * 6 * NFP * nu;
+#pragma unroll
+    for (int face = 0; face < 6; ++face) {
+        const int d = face / 2, side = face & 1;
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                Real t = Real(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) t += op.lam[side][m] * v[line_pt<N>(d, a, b, m)];
+                sto(te + (face * NFP + a + N * b) * nu, ko, t);
+            }
+    }
+}
+
+// Moments of one solution point over the velocity axis (FP64, fixed order:
+// lane-strided partial sums, wave butterfly, waves in order).  BGK: rho,
+// rho U, E; ES: rho, rho U and the raw second moments xx yy zz xy xz yz.
+template <typename Real, int NMOM>
+__global__ __launch_bounds__(kGBlock) void k_gen_moments(const GenArgs A, const Real *__restrict__ f,
+                                                          double *__restrict__ Q) {
+    __shared__ double red[kGBlock / 64][NMOM];
+    const int64_t pt = blockIdx.x;
+    const Real *fp = f + pt * A.nu;
+    double M[NMOM];
+#pragma unroll
+    for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
+    for (int k = threadIdx.x; k < A.nu; k += kGBlock) {
+        int iv[3];
+        split_k(A.vg, k, iv);
+        const double x = (double)fp[k] * (A.wax[iv[0]] * A.wax[64 + iv[1]] * A.wax[128 + iv[2]]);
+        const double ux = node_u(A.vg, 0, iv[0]), uy = node_u(A.vg, 1, iv[1]), uz = node_u(A.vg, 2, iv[2]);
+        M[0] += x;
+        M[1] += x * ux;
+        M[2] += x * uy;
+        M[3] += x * uz;
+        if constexpr (NMOM == 5) {
+            M[4] += 0.5 * x * (ux * ux + uy * uy + uz * uz);
+        } else {
+            M[4] += x * ux * ux;
+            M[5] += x * uy * uy;
+            M[6] += x * uz * uz;
+            M[7] += x * ux * uy;
+            M[8] += x * ux * uz;
+            M[9] += x * uy * uz;
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < NMOM; ++a) {
+        double v = M[a];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) red[w][a] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NMOM) {
+        double t = red[0][threadIdx.x];
+#pragma unroll
+        for (int q = 1; q < kGBlock / 64; ++q) t += red[q][threadIdx.x];
+        Q[pt * NMOM + threadIdx.x] = t;
+    }
+}
+
+// Wall density at each flux point of the diffuse-wall faces: the outflow
+// mass flux of the interior trace over the inflow flux of the unit wall
+// Maxwellian, rho_w = sum_{u_n>0} w u_n f- / sum_{u_n<0} w |u_n| M_w.
+template <typename Real, int P>
+__global__ __launch_bounds__(kGBlock) void k_gen_wall(const GenArgs A, const Real *__restrict__ tr) {
+    constexpr int N = P + 1, NFP = N * N;
+    __shared__ double red[kGBlock / 64][2];
+    const int64_t fid = A.wall[blockIdx.x / NFP];
+    const int fp = blockIdx.x % NFP;
+    const double *nv = A.nf + (fid * NFP + fp) * 3;
+    const double n0 = nv[0], n1 = nv[1], n2 = nv[2];
+    const Real *t = tr + (fid * NFP + fp) * (int64_t)A.nu;
+    double out = 0.0, in = 0.0;
+    for (int k = threadIdx.x; k < A.nu; k += kGBlock) {
+        int iv[3];
+        split_k(A.vg, k, iv);
+        const double w = A.wax[iv[0]] * A.wax[64 + iv[1]] * A.wax[128 + iv[2]];
+        const double un = node_u(A.vg, 0, iv[0]) * n0 + node_u(A.vg, 1, iv[1]) * n1 + node_u(A.vg, 2, iv[2]) * n2;
+        if (un > 0.0)
+            out += w * un * (double)t[k];
+        else
+            in -= w * un * A.mw[k];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        out += __shfl_xor(out, o);
+        in += __shfl_xor(in, o);
+    }
+    if (lane == 0) {
+        red[wv][0] = out;
+        red[wv][1] = in;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double so = red[0][0], si = red[0][1];
+#pragma unroll
+        for (int q = 1; q < kGBlock / 64; ++q) {
+            so += red[q][0];
+            si += red[q][1];
+        }
+        A.rw[fid * NFP + fp] = si > 0.0 ? so / si : 0.0;
+    }
+}
+
+// One wave per (element, 64 velocities).  Each lane keeps its velocity's N^3
+// stage values and residual accumulators in its own LDS column (lane-private:
+// no barrier between the phases), so the loops over source points and flux
+// points stay rolled and the registers hold only the current line.
+template <typename Real, int P, int MODE>
+__global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
+    constexpr int N = P + 1, NS = N * N * N, NFP = N * N;
+    constexpr bool STAGE = MODE == GMODE_STAGE;
+    __shared__ Real sf[NS][kGWave];
+    __shared__ Real sa[NS][kGWave];
+    __shared__ double sEb[STAGE ? NS * 8 : 1];
+    __shared__ double sEv[STAGE ? NS * 3 : 1];
+    const int64_t e = blockIdx.x / A.nvw;
+    const int lane = threadIdx.x;
+    const int k = (int)(blockIdx.x % A.nvw) * kGWave + lane;
+    const bool collide = STAGE && A.sa.collide;
+    if (collide) {
+        for (int s = lane; s < NS; s += kGWave) {
+            const double *q = A.sa.eq + (e * NS + s) * kEqW;
+            double *b = &sEb[s * 8];
+            b[0] = -0.5 * q[EQ_B];
+            b[1] = -0.5 * q[EQ_B + 1];
+            b[2] = -0.5 * q[EQ_B + 2];
+            b[3] = -q[EQ_B + 3];
+            b[4] = -q[EQ_B + 4];
+            b[5] = -q[EQ_B + 5];
+            b[6] = q[EQ_C0];
+            b[7] = q[EQ_INVTAU];
+            sEv[s * 3] = q[EQ_V];
+            sEv[s * 3 + 1] = q[EQ_V + 1];
+            sEv[s * 3 + 2] = q[EQ_V + 2];
+        }
+    }
+    __syncthreads();
+    if (k >= A.nu) return;
+
+    const GOps<Real> &op = gops<Real>(A);
+    const Metrics<Real> G = metrics(A, Real(0));
+    const cptr<Real> gS = G.S + e * NS * 9, gJ = G.ijac + e * NS, gN = G.nf + e * 6 * NFP * 3;
+    const int64_t nu = A.nu;
+    int iv[3];
+    split_k(A.vg, k, iv);
+    const double ud[3] = {node_u(A.vg, 0, iv[0]), node_u(A.vg, 1, iv[1]), node_u(A.vg, 2, iv[2])};
+    const Real u0 = (Real)ud[0], u1 = (Real)ud[1], u2 = (Real)ud[2];
+    const int64_t eoff = e * NS * nu;
+    const uint32_t ko = (uint32_t)k * (uint32_t)sizeof(Real), k8 = (uint32_t)k * 8u;
+    const Real *fe = reinterpret_cast<const Real *>(A.sa.f) + eoff;
+#pragma unroll 4
+    for (int s = 0; s < NS; ++s) {
+        sf[s][lane] = ldo(fe + s * nu, ko);
+        sa[s][lane] = Real(0);
+    }
+    // divergence of the transformed flux, scattered from each source point
+#pragma unroll 1
+    for (int m = 0; m < NS; ++m) {
+        const int i = m % N, j = (m / N) % N, l = m / NFP;
+        const cptr<Real> Sm = gS + m * 9;
+        const Real fm = sf[m][lane];
+        const Real F0 = (Sm[0] * u0 + Sm[1] * u1 + Sm[2] * u2) * fm;
+        const Real F1 = (Sm[3] * u0 + Sm[4] * u1 + Sm[5] * u2) * fm;
+        const Real F2 = (Sm[6] * u0 + Sm[7] * u1 + Sm[8] * u2) * fm;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            sa[spt<N>(r, j, l)][lane] += op.D[r * N + i] * F0;
+            sa[spt<N>(i, r, l)][lane] += op.D[r * N + j] * F1;
+            sa[spt<N>(i, j, r)][lane] += op.D[r * N + l] * F2;
+        }
+    }
+    // interface corrections
+    const Real *tin = reinterpret_cast<const Real *>(A.sa.tr_in);
+#pragma unroll 1
+    for (int face = 0; face < 6; ++face) {
+        const int d = face / 2, side = face & 1;
+        const int32_t *c = A.conn + (e * 6 + face) * 4;
+        const int32_t nb = c[0], nface = c[1], orient = c[2], bc = c[3];
+#pragma unroll 1
+        for (int q = 0; q < NFP; ++q) {
+            const int a = q % N, b = q / N;
+            int pts[N];
+#pragma unroll
+            for (int m = 0; m < N; ++m) pts[m] = line_pt<N>(d, a, b, m);
+            Real fm = Real(0);
+#pragma unroll
+            for (int m = 0; m < N; ++m) fm += op.lam[side][m] * sf[pts[m]][lane];
+            const cptr<Real> nv = gN + (face * NFP + q) * 3;
+            const Real un = nv[0] * u0 + nv[1] * u1 + nv[2] * u2;
+            if (un < Real(0)) {
+                Real fp;
+                if (nb >= 0)
+                    fp = ldo(tin + (((int64_t)nb * 6 + nface) * NFP + nbr_point<N>(orient, a, b)) * nu, ko);
+                else if (bc == 1)
+                    fp = (Real)ldo(A.finf, k8);
+                else
+                    fp = (Real)(A.rw[(e * 6 + face) * NFP + q] * ldo(A.mw, k8));
+                const Real jump = un * (fp - fm);
+#pragma unroll
+                for (int m = 0; m < N; ++m) sa[pts[m]][lane] += op.corr[side][m] * jump;
+            }
+        }
+    }
+    if (MODE == GMODE_RESID) {
+        Real *R = reinterpret_cast<Real *>(A.sa.fout) + eoff;
+#pragma unroll 4
+        for (int s = 0; s < NS; ++s) sto(R + s * nu, ko, -sa[s][lane] * gJ[s]);
+        return;
+    }
+    // collision source and the Runge-Kutta combination
+    const Real dt = (Real)A.sa.dt;
+    const bool useX = A.sa.scheme == 0 ? A.sa.alpha != 0.0 : A.sa.lsA != 0.0;
+    const Real *XE = (A.sa.scheme == 0 ? reinterpret_cast<const Real *>(A.sa.fn) : reinterpret_cast<const Real *>(A.sa.dF)) + eoff;
+    Real *outE = reinterpret_cast<Real *>(A.sa.fout) + eoff;
+    Real *dFE = reinterpret_cast<Real *>(A.sa.dF) + eoff;
+#pragma unroll 1
+    for (int s = 0; s < NS; ++s) {
+        const Real fq = sf[s][lane];
+        Real L = -sa[s][lane] * gJ[s];
+        if (collide) {
+            const double *bq = &sEb[s * 8];
+            const double c0 = ud[0] - sEv[s * 3], c1 = ud[1] - sEv[s * 3 + 1], c2 = ud[2] - sEv[s * 3 + 2];
+            double t0 = bq[0] * c0;
+            t0 = fma(bq[3], c1, t0);
+            t0 = fma(bq[4], c2, t0);
+            double t1 = bq[1] * c1;
+            t1 = fma(bq[5], c2, t1);
+            const double t2 = bq[2] * c2;
+            double E = fma(c0, t0, bq[6]);
+            E = fma(c1, t1, E);
+            E = fma(c2, t2, E);
+            L += (gexp<Real>(E) - fq) * (Real)bq[7];
+        }
+        Real fo;
+        if (A.sa.scheme == 0) {
+            fo = (Real)A.sa.beta * (fq + dt * L);
+            if (useX) fo += (Real)A.sa.alpha * ldo(XE + s * nu, ko);
+        } else {
+            Real dd = dt * L;
+            if (useX) dd += (Real)A.sa.lsA * ldo(XE + s * nu, ko);
+            if (A.sa.keep_dF) sto(dFE + s * nu, ko, dd);
+            fo = fq + (Real)A.sa.lsB * dd;
+        }
+        sto(outE + s * nu, ko, fo);
+        sf[s][lane] = fo;
+    }
+    if (A.do_traces) {
+        Real *te = reinterpret_cast<Real *>(A.sa.tr_out) + e * 6 * NFP * nu;
+#pragma unroll 1
+        for (int face = 0; face < 6; ++face) {
+            const int d = face / 2, side = face & 1;
+#pragma unroll 1
+            for (int q = 0; q < NFP; ++q) {
+                const int a = q % N, b = q / N;
+                Real t = Real(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) t += op.lam[side][m] * sf[line_pt<N>(d, a, b, m)][lane];
+                sto(te + (face * NFP + q) * nu, ko, t);
+            }
+        }
+    }
+}
+
+int gcheck(fr_dvm *h, const char *what) {
+    hipError_t st = hipGetLastError();
+    if (st != hipSuccess) return h->fail(FR_DVM_EHIP, std::string(what) + ": " + hipGetErrorString(st));
+    return FR_DVM_OK;
+}
+
+template <typename Real, int P>
+int gen_run(fr_dvm *h, int mode, const GenArgs &A, int do_moments) {
+    const unsigned blocks = (unsigned)(h->ne * A.nvb);
+    const int64_t npts = h->ne * h->ns;
+    auto moments = [&](const void *src) {
+        if (h->nmom == 5)
+            hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A,
+                               reinterpret_cast<const Real *>(src), A.sa.Q);
+        else
+            hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A,
+                               reinterpret_cast<const Real *>(src), A.sa.Q);
+        return gcheck(h, "moment kernel");
+    };
+    int rc;
+    if (mode == 0) {
+        if (A.do_traces) {
+            hipLaunchKernelGGL((k_gen_traces<Real, P>), dim3(blocks), dim3(kGBlock), 0, h->stream, A,
+                               reinterpret_cast<const Real *>(A.sa.f), reinterpret_cast<Real *>(A.sa.tr_out));
+            if ((rc = gcheck(h, "trace kernel"))) return rc;
+        }
+        return do_moments ? moments(A.sa.f) : FR_DVM_OK;
+    }
+    if (h->nwall) {
+        hipLaunchKernelGGL((k_gen_wall<Real, P>), dim3((unsigned)(h->nwall * h->nfp)), dim3(kGBlock), 0, h->stream,
+                           A, reinterpret_cast<const Real *>(A.sa.tr_in));
+        if ((rc = gcheck(h, "wall kernel"))) return rc;
+    }
+    const unsigned wblocks = (unsigned)(h->ne * A.nvw);
+    if (mode == GMODE_RESID)
+        hipLaunchKernelGGL((k_gen_stage<Real, P, GMODE_RESID>), dim3(wblocks), dim3(kGWave), 0, h->stream, A);
+    else
+        hipLaunchKernelGGL((k_gen_stage<Real, P, GMODE_STAGE>), dim3(wblocks), dim3(kGWave), 0, h->stream, A);
+    if ((rc = gcheck(h, "general stage kernel"))) return rc;
+    return (mode == GMODE_STAGE && do_moments) ? moments(A.sa.fout) : FR_DVM_OK;
+}
+
+template <typename Real>
+int gen_p(fr_dvm *h, int mode, const GenArgs &A, int do_moments) {
+    switch (h->p) {
+        case 1: return gen_run<Real, 1>(h, mode, A, do_moments);
+        case 2: return gen_run<Real, 2>(h, mode, A, do_moments);
+        case 3: return gen_run<Real, 3>(h, mode, A, do_moments);
+    }
+    return h->fail(FR_DVM_EUNSUPPORTED, "order");
+}
+
+}  // namespace
+
+int launch_fr_gen(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_moments) {
+    if (sa.e0 != 0 || sa.ecount != 0) return h->fail(FR_DVM_EINVAL, "element ranges need an axis-aligned box mesh");
+    GenArgs A;
+    std::memset(&A, 0, sizeof(A));
+    for (int i = 0; i < kMaxN * kMaxN; ++i) {
+        A.od.D[i] = h->ops.D[i];
+        A.of.D[i] = (float)h->ops.D[i];
+    }
+    for (int s = 0; s < 2; ++s)
+        for (int m = 0; m < kMaxN; ++m) {
+            A.od.lam[s][m] = h->ops.lam[s][m];
+            A.of.lam[s][m] = (float)h->ops.lam[s][m];
+            A.od.corr[s][m] = h->ops.corr[s][m];
+            A.of.corr[s][m] = (float)h->ops.corr[s][m];
+        }
+    A.vg = h->vg;
+    A.nu = h->vg.nu;
+    A.nvb = (A.nu + kGBlock - 1) / kGBlock;
+    A.nvw = (A.nu + kGWave - 1) / kGWave;
+    A.wax = h->d_wax;
+    A.S = h->d_S;
+    A.ijac = h->d_ijac;
+    A.nf = h->d_nf;
+    A.Sf = h->d_Sf;
+    A.ijacf = h->d_ijacf;
+    A.nff = h->d_nff;
+    A.conn = h->d_conn;
+    A.wall = h->d_wall;
+    A.rw = h->d_rw;
+    A.mw = h->d_mw;
+    A.finf = h->d_finf;
+    A.sa = sa;
+    A.do_traces = do_traces;
+    return h->prm.precision == FR_DVM_FP64 ? gen_p<double>(h, mode, A, do_moments)
+                                           : gen_p<float>(h, mode, A, do_moments);
+}
+
+}  // namespace frdvm

@@ -1080,13 +1080,15 @@ __global__ void k_moments_out(int64_t npts, int nmom, const double *__restrict__
 // Kn = lambda |grad rho| / rho with the hard-sphere-type mean free path
 // lambda = mu(theta)/rho sqrt(pi/(2 theta)).  grad rho is the derivative of
 // the element's solution polynomial of rho (the FR interpolant, no interface
-// correction); on an axis-aligned box d/dx_d = (2/h_d) d/dxi_d.  One wave per
+// correction); on an axis-aligned box d/dx_d = (2/h_d) d/dxi_d, on a general
+// element grad = (1/|J|) sum_d a^d d/dxi_d.  One wave per
 // element (ns <= 64 points), the density of the element staged in LDS.
 // Points with rho <= 0 or theta <= 0 get 0.
 constexpr int kKnElems = 4;
 
 __global__ __launch_bounds__(64 * kKnElems) void k_kn_gll(NewtonArgs A, Ops1D ops, int n, int64_t ne,
-                                                          const double *__restrict__ gfac, double *__restrict__ kn) {
+                                                          const double *__restrict__ gfac, const double *__restrict__ S,
+                                                          const double *__restrict__ ijac, double *__restrict__ kn) {
     __shared__ double srho[kKnElems][64];
     const int w = threadIdx.x >> 6, s = threadIdx.x & 63;
     const int64_t e = (int64_t)blockIdx.x * kKnElems + w;
@@ -1103,9 +1105,19 @@ __global__ __launch_bounds__(64 * kKnElems) void k_kn_gll(NewtonArgs A, Ops1D op
         d1 += ops.D[j * n + m] * srho[w][i + n * (m + n * l)];
         d2 += ops.D[l * n + m] * srho[w][i + n * (j + n * m)];
     }
-    d0 *= gfac[e * 3 + 0];
-    d1 *= gfac[e * 3 + 1];
-    d2 *= gfac[e * 3 + 2];
+    if (S) {  // general element: grad = (1/|J|) sum_d a^d d/dxi_d
+        const double *a = S + pt * 9;
+        const double g0 = ijac[pt] * (a[0] * d0 + a[3] * d1 + a[6] * d2);
+        const double g1 = ijac[pt] * (a[1] * d0 + a[4] * d1 + a[7] * d2);
+        const double g2 = ijac[pt] * (a[2] * d0 + a[5] * d1 + a[8] * d2);
+        d0 = g0;
+        d1 = g1;
+        d2 = g2;
+    } else {
+        d0 *= gfac[e * 3 + 0];
+        d1 *= gfac[e * 3 + 1];
+        d2 *= gfac[e * 3 + 2];
+    }
     const double *q = A.Q + pt * A.nmom;
     const double rho = q[0];
     const double ux = q[1] / rho, uy = q[2] / rho, uz = q[3] / rho;
@@ -1351,7 +1363,8 @@ int launch_moments_out(fr_dvm *h, double *Q) {
 int launch_kn_gll(fr_dvm *h, double *kn) {
     NewtonArgs A = newton_args(h, FR_DVM_GUESS_COLD);
     hipLaunchKernelGGL(k_kn_gll, dim3((unsigned)((h->ne + kKnElems - 1) / kKnElems)), dim3(64 * kKnElems), 0,
-                       h->stream, A, h->ops, h->n, h->ne, h->d_gfac, kn);
+                       h->stream, A, h->ops, h->n, h->ne, h->axis_mode ? h->d_gfac : nullptr,
+                       h->axis_mode ? nullptr : h->d_S, h->d_ijac, kn);
     return check(h, "Knudsen number kernel");
 }
 

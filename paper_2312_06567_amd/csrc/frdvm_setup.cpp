@@ -119,6 +119,235 @@ bool element_box(const fr_dvm_mesh *m, int e, double lo[3], double hh[3]) {
     return hh[0] > 0 && hh[1] > 0 && hh[2] > 0;
 }
 
+constexpr int kNotAxis = 1000;
+
+// Straight axis-aligned boxes whose every face meets the opposite face of a
+// neighbour under orientation 0 with the same face size (periodic boxes):
+// constant metrics per element and the compact outflow-half traces.  Returns
+// kNotAxis (nothing set) for any other mesh.
+int setup_axis(fr_dvm *h, const fr_dvm_mesh *mesh, std::vector<double> &wq3J) {
+    if (mesh->geom_order != 1) return kNotAxis;
+    std::vector<double> hsz(3 * h->ne);
+    for (int64_t e = 0; e < h->ne; ++e) {
+        double lo[3], hh[3];
+        if (!element_box(mesh, (int)e, lo, hh)) return kNotAxis;
+        for (int d = 0; d < 3; ++d) hsz[3 * e + d] = hh[d];
+    }
+    for (int64_t e = 0; e < h->ne; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int32_t nb = mesh->nbr_elem[e * 6 + f];
+            if (nb < 0 || mesh->nbr_face[e * 6 + f] != (f ^ 1) || mesh->nbr_orient[e * 6 + f] != 0) return kNotAxis;
+            for (int t = 0; t < 3; ++t)
+                if (t != f / 2 && std::fabs(hsz[3 * e + t] - hsz[3 * (int64_t)nb + t]) > 1e-12 * hsz[3 * e + t])
+                    return kNotAxis;
+        }
+    h->axis_mode = true;
+    h->h_gfac.resize(3 * h->ne);
+    h->h_detJ.resize(h->ne * h->ns);
+    double hmin = 1e300;
+    for (int64_t e = 0; e < h->ne; ++e) {
+        const double *hh = &hsz[3 * e];
+        const double detJ = hh[0] * hh[1] * hh[2] / 8.0;
+        for (int d = 0; d < 3; ++d) {
+            h->h_gfac[3 * e + d] = 2.0 / hh[d];
+            hmin = std::min(hmin, hh[d]);
+        }
+        int s = 0;
+        for (int l = 0; l < h->n; ++l)
+            for (int j = 0; j < h->n; ++j)
+                for (int i = 0; i < h->n; ++i, ++s) {
+                    h->h_detJ[e * h->ns + s] = detJ;
+                    wq3J[e * h->ns + s] = h->ops.wq[i] * h->ops.wq[j] * h->ops.wq[l] * detJ;
+                }
+    }
+    h->hmin = hmin;
+    // trace layout: per face only the velocities that leave through it
+    const VGrid &vg = h->vg;
+    TraceLayout &tl = h->tl;
+    int64_t off = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int d = f / 2;
+        const int64_t per = vg.nu / vg.nv[d];
+        tl.cnt[f] = (f & 1) ? (int64_t)(vg.nv[d] - vg.pos_start[d]) * per : (int64_t)vg.neg_end[d] * per;
+        tl.face_off[f] = off;
+        off += tl.cnt[f] * h->nfp;
+    }
+    tl.elem = off;
+    int rc;
+    if ((rc = dev_alloc(h, &h->d_gfac, 3 * h->ne))) return rc;
+    return upload(h, h->d_gfac, h->h_gfac.data(), 3 * h->ne * sizeof(double));
+}
+
+// Lagrange basis of the equispaced nodes -1, 0, 1 (q = 2) or -1, 1 (q = 1)
+// at x, and its derivative.
+void shape_1d(int q, double x, double N[3], double dN[3]) {
+    if (q == 1) {
+        N[0] = 0.5 * (1.0 - x); N[1] = 0.5 * (1.0 + x);
+        dN[0] = -0.5; dN[1] = 0.5;
+    } else {
+        N[0] = 0.5 * x * (x - 1.0); N[1] = 1.0 - x * x; N[2] = 0.5 * x * (x + 1.0);
+        dN[0] = x - 0.5; dN[1] = -2.0 * x; dN[2] = x + 0.5;
+    }
+}
+
+// Area-scaled contravariant vectors a^d = |J| grad xi_d (rows of the
+// cofactor matrix of dx/dxi) and |J| at reference point r of an element
+// with node coordinates X [(q+1)^3][3], x-fastest.
+// Also the mapped position x(r) (pos, may be null).
+void element_metrics(int q, const double *X, const double r[3], double a[3][3], double &detJ, double *pos = nullptr) {
+    const int m = q + 1;
+    double N[3][3], dN[3][3];
+    for (int d = 0; d < 3; ++d) shape_1d(q, r[d], N[d], dN[d]);
+    double t[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // t[d] = dx/dxi_d
+    double x[3] = {0, 0, 0};
+    for (int k = 0; k < m; ++k)
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) {
+                const double *P = X + 3 * (i + m * (j + m * k));
+                const double g = N[0][i] * N[1][j] * N[2][k];
+                const double g0 = dN[0][i] * N[1][j] * N[2][k];
+                const double g1 = N[0][i] * dN[1][j] * N[2][k];
+                const double g2 = N[0][i] * N[1][j] * dN[2][k];
+                for (int c = 0; c < 3; ++c) {
+                    x[c] += g * P[c];
+                    t[0][c] += g0 * P[c];
+                    t[1][c] += g1 * P[c];
+                    t[2][c] += g2 * P[c];
+                }
+            }
+    if (pos)
+        for (int c = 0; c < 3; ++c) pos[c] = x[c];
+    for (int d = 0; d < 3; ++d) {
+        const double *u = t[(d + 1) % 3], *v = t[(d + 2) % 3];
+        a[d][0] = u[1] * v[2] - u[2] * v[1];
+        a[d][1] = u[2] * v[0] - u[0] * v[2];
+        a[d][2] = u[0] * v[1] - u[1] * v[0];
+    }
+    detJ = t[0][0] * a[0][0] + t[0][1] * a[0][1] + t[0][2] * a[0][2];
+}
+
+// Own face point (a, b) -> the neighbour's face point under orientation
+// code o (bit0 swaps the indices, bit1 reverses the first, bit2 the second).
+void face_point_map(int n, int o, int a, int b, int &pa, int &pb) {
+    pa = (o & 1) ? b : a;
+    pb = (o & 1) ? a : b;
+    if (o & 2) pa = n - 1 - pa;
+    if (o & 4) pb = n - 1 - pb;
+}
+
+// Any hexahedral mesh (8- or 27-node, faces met under any orientation,
+// farfield / wall boundaries): pointwise metrics at solution and flux points
+// and full traces (every velocity at every flux point).
+int setup_general(fr_dvm *h, const fr_dvm_mesh *mesh, std::vector<double> &wq3J) {
+    const int q = mesh->geom_order, m = q + 1, ng = m * m * m, n = h->n, ns = h->ns, nfp = h->nfp;
+    const int64_t ne = h->ne;
+    h->axis_mode = false;
+    std::vector<double> S((size_t)ne * ns * 9), ijac((size_t)ne * ns), nf((size_t)ne * 6 * nfp * 3);
+    std::vector<double> xf((size_t)ne * 6 * nfp * 3);  // flux-point positions (face matching)
+    h->h_detJ.resize(ne * ns);
+    double hmin = 1e300;
+    double X[27 * 3];
+    for (int64_t e = 0; e < ne; ++e) {
+        for (int g = 0; g < ng; ++g)
+            for (int c = 0; c < 3; ++c) X[3 * g + c] = mesh->nodes[3 * (int64_t)mesh->elem_nodes[e * ng + g] + c];
+        for (int l = 0, s = 0; l < n; ++l)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i, ++s) {
+                    const double r[3] = {h->ops.xi[i], h->ops.xi[j], h->ops.xi[l]};
+                    double a[3][3], J;
+                    element_metrics(q, X, r, a, J);
+                    if (!(J > 0)) return h->fail(FR_DVM_EINVAL, "non-positive Jacobian in element " + std::to_string(e));
+                    const int64_t pt = e * ns + s;
+                    for (int d = 0; d < 3; ++d) {
+                        for (int c = 0; c < 3; ++c) S[pt * 9 + 3 * d + c] = a[d][c];
+                        hmin = std::min(hmin, 2.0 * J / std::sqrt(a[d][0] * a[d][0] + a[d][1] * a[d][1] + a[d][2] * a[d][2]));
+                    }
+                    h->h_detJ[pt] = J;
+                    ijac[pt] = 1.0 / J;
+                    wq3J[pt] = h->ops.wq[i] * h->ops.wq[j] * h->ops.wq[l] * J;
+                }
+        for (int f = 0; f < 6; ++f) {
+            const int d = f / 2, side = f & 1;
+            const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+            for (int b = 0; b < n; ++b)
+                for (int a = 0; a < n; ++a) {
+                    double r[3];
+                    r[d] = side ? 1.0 : -1.0;
+                    r[t0] = h->ops.xi[a];
+                    r[t1] = h->ops.xi[b];
+                    double av[3][3], J;
+                    element_metrics(q, X, r, av, J, &xf[((e * 6 + f) * nfp + a + n * b) * 3]);
+                    for (int c = 0; c < 3; ++c)
+                        nf[((e * 6 + f) * nfp + a + n * b) * 3 + c] = side ? av[d][c] : -av[d][c];
+                }
+        }
+    }
+    h->hmin = hmin;
+    // conforming faces: at matched flux points the two outward normals
+    // cancel and the two positions differ by one vector for the whole face
+    // (zero, or the period of a periodic pair)
+    std::vector<int32_t> conn((size_t)ne * 24), wall;
+    for (int64_t e = 0; e < ne; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int32_t nb = mesh->nbr_elem[e * 6 + f];
+            int32_t *c = &conn[(e * 6 + f) * 4];
+            c[0] = nb;
+            c[1] = nb >= 0 ? mesh->nbr_face[e * 6 + f] : 0;
+            c[2] = nb >= 0 ? mesh->nbr_orient[e * 6 + f] : 0;
+            c[3] = nb >= 0 ? 0 : mesh->bc[e * 6 + f];
+            if (nb < 0) {
+                if (c[3] == 2) wall.push_back((int32_t)(e * 6 + f));
+                continue;
+            }
+            const double *x00 = &xf[((e * 6 + f) * nfp) * 3];
+            double shift[3] = {0, 0, 0}, ext = 0;
+            for (int t = 1; t < nfp; ++t)
+                for (int c = 0; c < 3; ++c) ext = std::max(ext, std::fabs(x00[3 * t + c] - x00[c]));
+            for (int b = 0; b < n; ++b)
+                for (int a = 0; a < n; ++a) {
+                    int pa, pb;
+                    face_point_map(n, c[2], a, b, pa, pb);
+                    const int64_t own = (e * 6 + f) * nfp + a + n * b;
+                    const int64_t oth = ((int64_t)nb * 6 + c[1]) * nfp + pa + n * pb;
+                    const double *u = &nf[own * 3], *v = &nf[oth * 3];
+                    const double mag = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                    const double gap = std::fabs(u[0] + v[0]) + std::fabs(u[1] + v[1]) + std::fabs(u[2] + v[2]);
+                    double dev = 0;
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const double dx = xf[oth * 3 + cc] - xf[own * 3 + cc];
+                        if (a == 0 && b == 0) shift[cc] = dx;
+                        dev = std::max(dev, std::fabs(dx - shift[cc]));
+                    }
+                    if (!(gap <= 1e-9 * mag) || !(dev <= 1e-9 * ext))
+                        return h->fail(FR_DVM_EINVAL, "non-conforming face " + std::to_string(f) + " of element " + std::to_string(e));
+                }
+        }
+    h->nwall = (int64_t)wall.size();
+    h->tl.elem = (int64_t)6 * nfp * h->vg.nu;
+    int rc;
+    if ((rc = dev_alloc(h, &h->d_S, S.size())) || (rc = upload(h, h->d_S, S.data(), S.size() * sizeof(double))))
+        return rc;
+    if ((rc = dev_alloc(h, &h->d_ijac, ijac.size())) || (rc = upload(h, h->d_ijac, ijac.data(), ijac.size() * sizeof(double))))
+        return rc;
+    if ((rc = dev_alloc(h, &h->d_nf, nf.size())) || (rc = upload(h, h->d_nf, nf.data(), nf.size() * sizeof(double))))
+        return rc;
+    {
+        std::vector<float> Sf(S.begin(), S.end()), jf(ijac.begin(), ijac.end()), nff(nf.begin(), nf.end());
+        if ((rc = dev_alloc(h, &h->d_Sf, Sf.size())) || (rc = upload(h, h->d_Sf, Sf.data(), Sf.size() * sizeof(float))) ||
+            (rc = dev_alloc(h, &h->d_ijacf, jf.size())) || (rc = upload(h, h->d_ijacf, jf.data(), jf.size() * sizeof(float))) ||
+            (rc = dev_alloc(h, &h->d_nff, nff.size())) || (rc = upload(h, h->d_nff, nff.data(), nff.size() * sizeof(float))))
+            return rc;
+    }
+    if ((rc = dev_alloc(h, &h->d_conn, conn.size())) || (rc = upload(h, h->d_conn, conn.data(), conn.size() * sizeof(int32_t))))
+        return rc;
+    if (!wall.empty() && ((rc = dev_alloc(h, &h->d_wall, wall.size())) ||
+                          (rc = upload(h, h->d_wall, wall.data(), wall.size() * sizeof(int32_t)))))
+        return rc;
+    if ((rc = dev_alloc(h, &h->d_rw, (size_t)ne * 6 * nfp))) return rc;
+    if ((rc = dev_alloc(h, &h->d_mw, (size_t)h->vg.nu))) return rc;
+    return dev_alloc(h, &h->d_finf, (size_t)h->vg.nu);
+}
+
 }  // namespace
 
 extern "C" void fr_dvm_default_params(fr_dvm_params *p) {
@@ -182,73 +411,32 @@ extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vg
     }
     vg.nu = (int)nu;
 
-    // mesh: this build handles straight axis-aligned boxes with interior /
-    // periodic faces (matching opposite faces, orientation 0)
-    if (mesh->geom_order != 1) return bail(h->fail(FR_DVM_EUNSUPPORTED, "curved (27-node) elements are not handled by this build"));
-    h->axis_mode = true;
-    h->h_gfac.resize(3 * h->ne);
-    h->h_detJ.resize(h->ne * h->ns);
-    std::vector<double> wq3J(h->ne * h->ns);
-    std::vector<double> hsz(3 * h->ne);
-    double hmin = 1e300;
-    for (int64_t e = 0; e < h->ne; ++e) {
-        double lo[3], hh[3];
-        for (int a = 0; a < 8; ++a) {
-            int32_t id = mesh->elem_nodes[e * 8 + a];
-            if (id < 0 || id >= mesh->n_nodes) return bail(h->fail(FR_DVM_EINVAL, "element node id out of range"));
-        }
-        if (!element_box(mesh, (int)e, lo, hh))
-            return bail(h->fail(FR_DVM_EUNSUPPORTED, "element " + std::to_string(e) + " is not an axis-aligned box"));
-        double detJ = hh[0] * hh[1] * hh[2] / 8.0;
-        for (int d = 0; d < 3; ++d) {
-            h->h_gfac[3 * e + d] = 2.0 / hh[d];
-            hsz[3 * e + d] = hh[d];
-            hmin = std::min(hmin, hh[d]);
-        }
-        int s = 0;
-        for (int l = 0; l < h->n; ++l)
-            for (int j = 0; j < h->n; ++j)
-                for (int i = 0; i < h->n; ++i, ++s) {
-                    h->h_detJ[e * h->ns + s] = detJ;
-                    wq3J[e * h->ns + s] = h->ops.wq[i] * h->ops.wq[j] * h->ops.wq[l] * detJ;
-                }
-    }
-    h->hmin = hmin;
+    // mesh: connectivity and tags
+    if (mesh->geom_order != 1 && mesh->geom_order != 2) return bail(h->fail(FR_DVM_EINVAL, "geom_order must be 1 or 2"));
+    const int ngeo = mesh->geom_order == 2 ? 27 : 8;
+    for (int64_t i = 0; i < h->ne * ngeo; ++i)
+        if (mesh->elem_nodes[i] < 0 || mesh->elem_nodes[i] >= mesh->n_nodes)
+            return bail(h->fail(FR_DVM_EINVAL, "element node id out of range"));
     for (int64_t e = 0; e < h->ne; ++e)
         for (int f = 0; f < 6; ++f) {
-            int32_t nb = mesh->nbr_elem[e * 6 + f];
-            int d = f / 2;
+            const int32_t nb = mesh->nbr_elem[e * 6 + f];
             if (nb < 0) {
-                if (mesh->bc[e * 6 + f] != 0)
-                    return bail(h->fail(FR_DVM_EUNSUPPORTED, "boundary conditions need the curved-mesh path"));
-                return bail(h->fail(FR_DVM_EINVAL, "face without neighbour and without a boundary tag"));
+                if (mesh->bc[e * 6 + f] != 1 && mesh->bc[e * 6 + f] != 2)
+                    return bail(h->fail(FR_DVM_EINVAL, "face without neighbour and without a boundary tag"));
+                continue;
             }
             if (nb >= h->ne) return bail(h->fail(FR_DVM_EINVAL, "neighbour id out of range"));
-            if (mesh->nbr_face[e * 6 + f] != (f ^ 1) || mesh->nbr_orient[e * 6 + f] != 0)
-                return bail(h->fail(FR_DVM_EUNSUPPORTED, "axis-aligned path needs opposite-face neighbours with orientation 0"));
-            if (mesh->nbr_elem[(int64_t)nb * 6 + (f ^ 1)] != e)
+            const int nf = mesh->nbr_face[e * 6 + f], no = mesh->nbr_orient[e * 6 + f];
+            if (nf < 0 || nf > 5 || no < 0 || no > 7) return bail(h->fail(FR_DVM_EINVAL, "neighbour face or orientation code out of range"));
+            if (mesh->nbr_elem[(int64_t)nb * 6 + nf] != e || mesh->nbr_face[(int64_t)nb * 6 + nf] != f)
                 return bail(h->fail(FR_DVM_EINVAL, "neighbour relation is not symmetric"));
-            for (int t = 0; t < 3; ++t)
-                if (t != d && std::fabs(hsz[3 * e + t] - hsz[3 * (int64_t)nb + t]) > 1e-12 * hsz[3 * e + t])
-                    return bail(h->fail(FR_DVM_EINVAL, "non-conforming face"));
         }
-
-    // trace layout
-    TraceLayout &tl = h->tl;
-    int64_t off = 0;
-    for (int f = 0; f < 6; ++f) {
-        int d = f / 2;
-        int64_t per = nu / vg.nv[d];
-        tl.cnt[f] = (f & 1) ? (int64_t)(vg.nv[d] - vg.pos_start[d]) * per : (int64_t)vg.neg_end[d] * per;
-        tl.face_off[f] = off;
-        off += tl.cnt[f] * h->nfp;
-    }
-    tl.elem = off;
+    std::vector<double> wq3J(h->ne * h->ns);
+    int rc = setup_axis(h, mesh, wq3J);
+    if (rc == kNotAxis) rc = setup_general(h, mesh, wq3J);
+    if (rc) return bail(rc);
 
     // device tables
-    int rc;
-    if ((rc = dev_alloc(h, &h->d_gfac, 3 * h->ne))) return bail(rc);
-    if ((rc = upload(h, h->d_gfac, h->h_gfac.data(), 3 * h->ne * sizeof(double)))) return bail(rc);
     if ((rc = dev_alloc(h, &h->d_nbr, 6 * h->ne))) return bail(rc);
     if ((rc = upload(h, h->d_nbr, mesh->nbr_elem, 6 * h->ne * sizeof(int32_t)))) return bail(rc);
     if ((rc = dev_alloc(h, &h->d_wq3J, h->ne * h->ns))) return bail(rc);
@@ -331,6 +519,7 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
         if ((rc = dev_alloc(h, &h->d_wrow, wrow.size()))) return rc;
         if ((rc = upload(h, h->d_wrow, wrow.data(), wrow.size() * sizeof(double)))) return rc;
     }
+    if (!h->axis_mode && (rc = gen_boundary_tables(h))) return rc;
     // verification switch: FRDVM_ES_DIRECT=1 makes the ES Newton use the
     // direct per-node sums instead of the factorised ones
     const char *ev = std::getenv("FRDVM_ES_DIRECT");
@@ -338,6 +527,34 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     h->have_params = true;
     return FR_DVM_OK;
 }
+
+namespace frdvm {
+
+// Wall Maxwellian of unit density at rest at theta_wall and the farfield
+// Maxwellian (rho, U, theta) at every velocity node, in FP64 (boundary
+// exteriors of the general-mesh path).
+int gen_boundary_tables(fr_dvm *h) {
+    const VGrid &vg = h->vg;
+    std::vector<double> mw(vg.nu), fi(vg.nu);
+    const double kPi = 3.14159265358979323846;
+    const double tw = h->prm.theta_wall, *F = h->prm.farfield;
+    for (int64_t k = 0; k < vg.nu; ++k) {
+        const int i = (int)(k % vg.nv[0]), j = (int)((k / vg.nv[0]) % vg.nv[1]);
+        const int l = (int)(k / ((int64_t)vg.nv[0] * vg.nv[1]));
+        const double u[3] = {vg.umin[0] + i * vg.du[0], vg.umin[1] + j * vg.du[1], vg.umin[2] + l * vg.du[2]};
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        mw[k] = tw > 0 ? std::pow(2.0 * kPi * tw, -1.5) * std::exp(-uu / (2.0 * tw)) : 0.0;
+        const double c0 = u[0] - F[1], c1 = u[1] - F[2], c2 = u[2] - F[3];
+        fi[k] = (F[0] > 0 && F[4] > 0)
+                    ? F[0] * std::pow(2.0 * kPi * F[4], -1.5) * std::exp(-(c0 * c0 + c1 * c1 + c2 * c2) / (2.0 * F[4]))
+                    : 0.0;
+    }
+    int rc = upload(h, h->d_mw, mw.data(), mw.size() * sizeof(double));
+    if (!rc) rc = upload(h, h->d_finf, fi.data(), fi.size() * sizeof(double));
+    return rc;
+}
+
+}  // namespace frdvm
 
 extern "C" int fr_dvm_set_stream(fr_dvm_t h, void *stream) {
     if (!h) return FR_DVM_EINVAL;
@@ -389,7 +606,8 @@ extern "C" void fr_dvm_destroy(fr_dvm_t h) {
     void *ptrs[] = {h->d_gfac, h->d_nbr, h->d_wq3J, h->d_wx3, h->d_wrow, h->d_wax, h->d_reg, h->d_tr[0], h->d_tr[1],
                     h->d_Q, h->d_eq, h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
                     h->d_mlp_x, h->d_mlp_work, h->d_mlp_dz, h->d_pt_iters, h->d_pt_evals, h->d_pt_status,
-                    h->d_pt_resid};
+                    h->d_pt_resid, h->d_S, h->d_ijac, h->d_nf, h->d_conn, h->d_wall, h->d_rw, h->d_mw,
+                    h->d_finf, h->d_Sf, h->d_ijacf, h->d_nff};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (auto &r : h->prof_recs) {
