@@ -65,13 +65,30 @@ def stage_values_per_dof(p: int, rk: int, stage: int, last: bool) -> float:
     return v
 
 
-def stage_bytes(p: int, es: int, rk: int, nsteps: int) -> float:
+def gen_stage_values_per_dof(p: int, rk: int, stage: int, last: bool) -> float:
+    """The same for a stage on a general hexahedral mesh (stage kernel plus
+    the moment pass over its result): read f, write the result; read the
+    neighbour traces where the velocity enters (half of the 6/(p+1) full
+    traces per DOF) and, unless last, write the result's full traces
+    (6/(p+1)) and read the result once more for its moments; the second RK
+    register as for the box kernel."""
+    full = 6.0 / (p + 1)
+    v = 2.0 + 0.5 * full + (0.0 if last else full + 1.0)
+    if stage > 0:
+        v += 1.0
+    if rk == 1 and stage < 2:
+        v += 1.0
+    return v
+
+
+def stage_bytes(p: int, es: int, rk: int, nsteps: int, general: bool = False) -> float:
     """Algorithmic bytes per DOF summed over the stage launches of one
     rk_steps call of nsteps steps."""
+    per = gen_stage_values_per_dof if general else stage_values_per_dof
     tot = 0.0
     for k in range(nsteps):
         for st in range(3):
-            tot += stage_values_per_dof(p, rk, st, k == nsteps - 1 and st == 2) * es
+            tot += per(p, rk, st, k == nsteps - 1 and st == 2) * es
     return tot
 
 
@@ -166,15 +183,17 @@ def run_config(W, w, mesh, params, steps, warmup, label, weights=None, keep_mome
     return out
 
 
-def roofline(r, p, workload):
+def roofline(r, p, workload, general=False):
     """The fused stage kernel against HBM bandwidth: algorithmic bytes of all
     its launches in the timed call over their summed HIP-event durations (on
-    the library's stream)."""
+    the library's stream).  General meshes: the stage kernel with its wall
+    and moment passes."""
     es = 8 if r["precision"] == 0 else 4
     ms, n = r["prof"]["stage"]
-    tot_bytes = stage_bytes(p, es, r["rk"], r["steps"]) * r["dof"]
+    tot_bytes = stage_bytes(p, es, r["rk"], r["steps"], general) * r["dof"]
     ach = tot_bytes / (ms / 1e3) / 1e9
-    out = {"kernel": "k_fr_layer (fused FR stage)", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+    name = "k_gen_stage + k_gen_wall + k_gen_moments (general hexes)" if general else "k_fr_layer (fused FR stage)"
+    out = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
            "algorithmic_bytes_per_launch": tot_bytes / max(n, 1), "avg_launch_ms": ms / max(n, 1)}
     t = measured_traffic(workload, r["precision"], r["rk"])
@@ -292,7 +311,7 @@ def main():
         return
 
     w = W.workload(args.workload)
-    mesh = W.box_mesh(w["N"])
+    mesh = W.workload_mesh(w)
     base = W.physics_params(w)
     if args.model is not None:
         base["model"] = args.model
@@ -318,7 +337,7 @@ def main():
                "dtype": "f64" if par["precision"] == 0 else "f32 (FP64 moments and Newton)",
                "data": "synthetic (seeded initial Maxwellian of the workload's macroscopic field)", "config": cfg,
                "kernels_ms_per_step": {k: v[0] / r["steps"] for k, v in r["prof"].items()},
-               "newton": r["newton"], "roofline": roofline(r, w["p"], w["name"])}
+               "newton": r["newton"], "roofline": roofline(r, w["p"], w["name"], w.get("mesh") == "cylinder")}
         if not args.no_cpu:
             out["cpu_baseline"] = cpu_baseline(w, par, args.cpu_seconds)
         print(json.dumps(out), flush=True)

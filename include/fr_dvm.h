@@ -126,8 +126,14 @@ void fr_dvm_default_params(fr_dvm_params *p);
 /* Create a handle for a mesh, FR order p (solution points (p+1)^3 per
  * element) and velocity grid.  Builds the FR operators, metrics,
  * connectivity and velocity tables on the device of the current HIP device.
- * Returns FR_DVM_EINVAL for an inconsistent mesh (non-positive Jacobian,
- * unmatched neighbours), FR_DVM_EUNSUPPORTED for p outside 1..3. */
+ * Periodic boxes of axis-aligned hexahedra (every face on the opposite face
+ * of its neighbour, orientation 0) take the fused box path; any other mesh
+ * (27-node curved elements, any orientation codes, farfield / wall faces)
+ * the general path with pointwise metrics and full traces.  A face pair must
+ * conform: at matched flux points opposite normals, positions differing by
+ * one vector (zero, or a period).  Returns FR_DVM_EINVAL for an inconsistent
+ * mesh (non-positive Jacobian, non-conforming or asymmetric neighbours, a
+ * boundary face without tag 1 or 2), FR_DVM_EUNSUPPORTED for p outside 1..3. */
 int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out);
 
 /* Set physics / precision / solver parameters; allocates the work buffers

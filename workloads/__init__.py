@@ -481,14 +481,36 @@ def workload(name: str) -> dict:
         "box24_p3_v20_es": dict(N=24, p=3, grid=grid_spec(20, 8.0), model=1, prandtl=0.71,
                                 kn=2e-4, ic="tgv", U0=0.5, pert=0.01, seed=5, steps=200,
                                 rk=1, precision=1),
+        # O-grid around the cylinder of diameter 1: 24 radial (growth 1.15) x 48 azimuthal
+        # x 2 spanwise quadratic hexes, p=2, 24^3 grid on [-14,14]^3, ES-BGK Pr=2/3,
+        # Kn=0.01, uniform Mach-8 inflow at theta=1 (1% seeded density noise),
+        # diffuse wall at theta_w=2, farfield outside
+        "cyl48x24x2_p2_v24_es": dict(mesh="cylinder", p=2, grid=grid_spec(24, 14.0), model=1,
+                                     prandtl=2.0 / 3.0, kn=0.01, ic="uniform", mach=8.0, noise=0.01,
+                                     theta_wall=2.0, seed=31, steps=2000, rk=1, precision=1),
     }
     w = dict(W[name])
     w["name"] = name
     w["mu_ref"] = mu_ref_from_knudsen(w["kn"])
+    if w.get("ic") == "uniform":
+        w["farfield"] = [1.0, w["mach"] * math.sqrt(5.0 / 3.0), 0.0, 0.0, 1.0]
     return w
 
 
+def workload_mesh(w: dict) -> dict:
+    if w.get("mesh") == "cylinder":
+        return cylinder_mesh()
+    return box_mesh(w["N"])
+
+
 def initial_prim(mesh: dict, p: int, w: dict) -> np.ndarray:
+    if w["ic"] == "uniform":
+        # the farfield state everywhere, density with seeded uniform noise
+        ns = (p + 1) ** 3
+        rng = np.random.default_rng(w["seed"])
+        prim = np.tile(np.asarray(w["farfield"], dtype=float), (mesh["n_elem"], ns, 1))
+        prim[..., 0] *= 1.0 + w["noise"] * rng.uniform(-1.0, 1.0, size=(mesh["n_elem"], ns))
+        return prim
     xs = box_solution_points(mesh, p)
     if w["ic"] == "modes":
         return prim_random_modes(xs, seed=w["seed"])
@@ -498,6 +520,10 @@ def initial_prim(mesh: dict, p: int, w: dict) -> np.ndarray:
 
 
 def physics_params(w: dict) -> dict:
-    return {"model": w["model"], "prandtl": w["prandtl"], "mu_ref": w["mu_ref"],
-            "theta_ref": 1.0, "omega": OMEGA_POWER_LAW, "visc_law": 0, "theta_s": 0.0,
-            "newton_tol": 1e-13, "newton_max_iter": 50}
+    par = {"model": w["model"], "prandtl": w["prandtl"], "mu_ref": w["mu_ref"],
+           "theta_ref": 1.0, "omega": OMEGA_POWER_LAW, "visc_law": 0, "theta_s": 0.0,
+           "newton_tol": 1e-13, "newton_max_iter": 50}
+    if "farfield" in w:
+        par["farfield"] = list(w["farfield"])
+        par["theta_wall"] = w["theta_wall"]
+    return par
