@@ -20,7 +20,8 @@
  *    in u (Mieussens form); for ES-BGK the quadratic's shape is fixed by the
  *    continuous ES temperature tensor and only its scale is solved for;
  *  - Newton in the frame shifted by U and scaled by sqrt(theta), backtracking
- *    on the residual 2-norm, stop at max-norm <= tol, then one extra step.
+ *    on the residual 2-norm (step halved per rejected trial, at most 40
+ *    rejected trials per solve), stop at max-norm <= tol, then one extra step.
  */
 #include <math.h>
 #include <stdint.h>
@@ -691,7 +692,7 @@ static int point_equilibrium(const orc_problem *P, const double *f, double *g, d
     ld zc[5] = {-1.5L * logl(twopi) + 0.5L * logl(det3(A)), 0, 0, 0, 1};
     ld z[5], r[5], J[5][5];
     for (int a = 0; a < 5; ++a) z[a] = zc[a];
-    int conv = 0, it = 0;
+    int conv = 0, it = 0, rej = 0; /* rej: rejected line-search trials over the whole solve */
     newton_system(nu, c, wt, qf, z, r, J);
     for (it = 0; it < P->newton_max_iter; ++it) {
         ld rn = norm2(r);
@@ -706,15 +707,18 @@ static int point_equilibrium(const orc_problem *P, const double *f, double *g, d
             ++it;
             break;
         }
+        /* backtracking: halve the step after each rejected trial; at most
+         * 40 rejected trials in the whole solve */
         ld alpha = 1, zt[5], rt[5], Jt[5][5];
         int acc = 0;
-        for (int h = 0; h < 40; ++h) {
+        while (rej < 40) {
             for (int a = 0; a < 5; ++a) zt[a] = z[a] + alpha * dz[a];
             if (zt[4] > 0) {
                 newton_system(nu, c, wt, qf, zt, rt, Jt);
                 if (norm2(rt) < (1.0L - 1e-4L * alpha) * rn) { acc = 1; break; }
             }
             alpha *= 0.5L;
+            ++rej;
         }
         if (!acc) break;
         for (int a = 0; a < 5; ++a) {

@@ -164,6 +164,28 @@ __global__ __launch_bounds__(kGBlock) void k_gen_traces(const GenArgs A, const R
     }
 }
 
+template <int NMOM>
+__device__ __forceinline__ void moment_add(const GenArgs &A, int k, double fv, double M[NMOM]) {
+    int iv[3];
+    split_k(A.vg, k, iv);
+    const double x = fv * (A.wax[iv[0]] * A.wax[64 + iv[1]] * A.wax[128 + iv[2]]);
+    const double ux = node_u(A.vg, 0, iv[0]), uy = node_u(A.vg, 1, iv[1]), uz = node_u(A.vg, 2, iv[2]);
+    M[0] += x;
+    M[1] += x * ux;
+    M[2] += x * uy;
+    M[3] += x * uz;
+    if constexpr (NMOM == 5) {
+        M[4] += 0.5 * x * (ux * ux + uy * uy + uz * uz);
+    } else {
+        M[4] += x * ux * ux;
+        M[5] += x * uy * uy;
+        M[6] += x * uz * uz;
+        M[7] += x * ux * uy;
+        M[8] += x * ux * uz;
+        M[9] += x * uy * uz;
+    }
+}
+
 // Moments of one solution point over the velocity axis (FP64, fixed order:
 // lane-strided partial sums, wave butterfly, waves in order).  BGK: rho,
 // rho U, E; ES: rho, rho U and the raw second moments xx yy zz xy xz yz.
@@ -176,26 +198,16 @@ __global__ __launch_bounds__(kGBlock) void k_gen_moments(const GenArgs A, const 
     double M[NMOM];
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
-    for (int k = threadIdx.x; k < A.nu; k += kGBlock) {
-        int iv[3];
-        split_k(A.vg, k, iv);
-        const double x = (double)fp[k] * (A.wax[iv[0]] * A.wax[64 + iv[1]] * A.wax[128 + iv[2]]);
-        const double ux = node_u(A.vg, 0, iv[0]), uy = node_u(A.vg, 1, iv[1]), uz = node_u(A.vg, 2, iv[2]);
-        M[0] += x;
-        M[1] += x * ux;
-        M[2] += x * uy;
-        M[3] += x * uz;
-        if constexpr (NMOM == 5) {
-            M[4] += 0.5 * x * (ux * ux + uy * uy + uz * uz);
-        } else {
-            M[4] += x * ux * ux;
-            M[5] += x * uy * uy;
-            M[6] += x * uz * uz;
-            M[7] += x * ux * uy;
-            M[8] += x * ux * uz;
-            M[9] += x * uy * uz;
-        }
+    // four values per lane requested at once, then accumulated in order
+    int k0 = threadIdx.x;
+    for (; k0 + 3 * kGBlock < A.nu; k0 += 4 * kGBlock) {
+        Real v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = fp[k0 + r * kGBlock];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) moment_add<NMOM>(A, k0 + r * kGBlock, (double)v[r], M);
     }
+    for (int k = k0; k < A.nu; k += kGBlock) moment_add<NMOM>(A, k, (double)fp[k], M);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) {
@@ -305,10 +317,17 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     const int64_t eoff = e * NS * nu;
     const uint32_t ko = (uint32_t)k * (uint32_t)sizeof(Real), k8 = (uint32_t)k * 8u;
     const Real *fe = reinterpret_cast<const Real *>(A.sa.f) + eoff;
-#pragma unroll 4
-    for (int s = 0; s < NS; ++s) {
-        sf[s][lane] = ldo(fe + s * nu, ko);
-        sa[s][lane] = Real(0);
+    // layer by layer: the layer's loads in flight together
+#pragma unroll 1
+    for (int s0 = 0; s0 < NS; s0 += NFP) {
+        Real v[NFP];
+#pragma unroll
+        for (int r = 0; r < NFP; ++r) v[r] = ldo(fe + (s0 + r) * nu, ko);
+#pragma unroll
+        for (int r = 0; r < NFP; ++r) {
+            sf[s0 + r][lane] = v[r];
+            sa[s0 + r][lane] = Real(0);
+        }
     }
     // divergence of the transformed flux, scattered from each source point
 #pragma unroll 1
@@ -333,26 +352,36 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
         const int d = face / 2, side = face & 1;
         const int32_t *c = A.conn + (e * 6 + face) * 4;
         const int32_t nb = c[0], nface = c[1], orient = c[2], bc = c[3];
-#pragma unroll 1
+        // the face's exterior values first (all its loads in flight at once)
+        Real un[NFP], ext[NFP];
+        const cptr<Real> nv = gN + face * NFP * 3;
+#pragma unroll
+        for (int q = 0; q < NFP; ++q) un[q] = nv[3 * q] * u0 + nv[3 * q + 1] * u1 + nv[3 * q + 2] * u2;
+        if (nb >= 0) {
+            const Real *tn = tin + ((int64_t)nb * 6 + nface) * NFP * nu;
+#pragma unroll
+            for (int q = 0; q < NFP; ++q)
+                ext[q] = un[q] < Real(0) ? ldo(tn + nbr_point<N>(orient, q % N, q / N) * nu, ko) : Real(0);
+        } else if (bc == 1) {
+            const Real fi = (Real)ldo(A.finf, k8);
+#pragma unroll
+            for (int q = 0; q < NFP; ++q) ext[q] = fi;
+        } else {
+            const double mw = ldo(A.mw, k8);
+#pragma unroll
+            for (int q = 0; q < NFP; ++q) ext[q] = (Real)(A.rw[(e * 6 + face) * NFP + q] * mw);
+        }
+#pragma unroll
         for (int q = 0; q < NFP; ++q) {
-            const int a = q % N, b = q / N;
-            int pts[N];
+            if (un[q] < Real(0)) {
+                const int a = q % N, b = q / N;
+                int pts[N];
 #pragma unroll
-            for (int m = 0; m < N; ++m) pts[m] = line_pt<N>(d, a, b, m);
-            Real fm = Real(0);
+                for (int m = 0; m < N; ++m) pts[m] = line_pt<N>(d, a, b, m);
+                Real fm = Real(0);
 #pragma unroll
-            for (int m = 0; m < N; ++m) fm += op.lam[side][m] * sf[pts[m]][lane];
-            const cptr<Real> nv = gN + (face * NFP + q) * 3;
-            const Real un = nv[0] * u0 + nv[1] * u1 + nv[2] * u2;
-            if (un < Real(0)) {
-                Real fp;
-                if (nb >= 0)
-                    fp = ldo(tin + (((int64_t)nb * 6 + nface) * NFP + nbr_point<N>(orient, a, b)) * nu, ko);
-                else if (bc == 1)
-                    fp = (Real)ldo(A.finf, k8);
-                else
-                    fp = (Real)(A.rw[(e * 6 + face) * NFP + q] * ldo(A.mw, k8));
-                const Real jump = un * (fp - fm);
+                for (int m = 0; m < N; ++m) fm += op.lam[side][m] * sf[pts[m]][lane];
+                const Real jump = un[q] * (ext[q] - fm);
 #pragma unroll
                 for (int m = 0; m < N; ++m) sa[pts[m]][lane] += op.corr[side][m] * jump;
             }
@@ -371,35 +400,43 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     Real *outE = reinterpret_cast<Real *>(A.sa.fout) + eoff;
     Real *dFE = reinterpret_cast<Real *>(A.sa.dF) + eoff;
 #pragma unroll 1
-    for (int s = 0; s < NS; ++s) {
-        const Real fq = sf[s][lane];
-        Real L = -sa[s][lane] * gJ[s];
-        if (collide) {
-            const double *bq = &sEb[s * 8];
-            const double c0 = ud[0] - sEv[s * 3], c1 = ud[1] - sEv[s * 3 + 1], c2 = ud[2] - sEv[s * 3 + 2];
-            double t0 = bq[0] * c0;
-            t0 = fma(bq[3], c1, t0);
-            t0 = fma(bq[4], c2, t0);
-            double t1 = bq[1] * c1;
-            t1 = fma(bq[5], c2, t1);
-            const double t2 = bq[2] * c2;
-            double E = fma(c0, t0, bq[6]);
-            E = fma(c1, t1, E);
-            E = fma(c2, t2, E);
-            L += (gexp<Real>(E) - fq) * (Real)bq[7];
+    for (int s0 = 0; s0 < NS; s0 += NFP) {
+        // the layer's second-register values requested together
+        Real xv[NFP];
+#pragma unroll
+        for (int r = 0; r < NFP; ++r) xv[r] = useX ? ldo(XE + (s0 + r) * nu, ko) : Real(0);
+#pragma unroll
+        for (int r = 0; r < NFP; ++r) {
+            const int s = s0 + r;
+            const Real fq = sf[s][lane];
+            Real L = -sa[s][lane] * gJ[s];
+            if (collide) {
+                const double *bq = &sEb[s * 8];
+                const double c0 = ud[0] - sEv[s * 3], c1 = ud[1] - sEv[s * 3 + 1], c2 = ud[2] - sEv[s * 3 + 2];
+                double t0 = bq[0] * c0;
+                t0 = fma(bq[3], c1, t0);
+                t0 = fma(bq[4], c2, t0);
+                double t1 = bq[1] * c1;
+                t1 = fma(bq[5], c2, t1);
+                const double t2 = bq[2] * c2;
+                double E = fma(c0, t0, bq[6]);
+                E = fma(c1, t1, E);
+                E = fma(c2, t2, E);
+                L += (gexp<Real>(E) - fq) * (Real)bq[7];
+            }
+            Real fo;
+            if (A.sa.scheme == 0) {
+                fo = (Real)A.sa.beta * (fq + dt * L);
+                if (useX) fo += (Real)A.sa.alpha * xv[r];
+            } else {
+                Real dd = dt * L;
+                if (useX) dd += (Real)A.sa.lsA * xv[r];
+                if (A.sa.keep_dF) sto(dFE + s * nu, ko, dd);
+                fo = fq + (Real)A.sa.lsB * dd;
+            }
+            sto(outE + s * nu, ko, fo);
+            sf[s][lane] = fo;
         }
-        Real fo;
-        if (A.sa.scheme == 0) {
-            fo = (Real)A.sa.beta * (fq + dt * L);
-            if (useX) fo += (Real)A.sa.alpha * ldo(XE + s * nu, ko);
-        } else {
-            Real dd = dt * L;
-            if (useX) dd += (Real)A.sa.lsA * ldo(XE + s * nu, ko);
-            if (A.sa.keep_dF) sto(dFE + s * nu, ko, dd);
-            fo = fq + (Real)A.sa.lsB * dd;
-        }
-        sto(outE + s * nu, ko, fo);
-        sf[s][lane] = fo;
     }
     if (A.do_traces) {
         Real *te = reinterpret_cast<Real *>(A.sa.tr_out) + e * 6 * NFP * nu;

@@ -62,6 +62,10 @@ struct NewtonArgs {
 };
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+// Line search: the step is halved after each rejected trial point (z4 <= 0 or
+// too little decrease of |r|_2); a solve may reject at most this many trial
+// points in total, then it stops (fallback unless at the rounding floor).
+constexpr int kRejectBudget = 40;
 
 // Velocity node umin + i du, rounded as two separate operations (no FMA
 // contraction) so that every kernel sees the node values the host sees.
@@ -679,7 +683,7 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const 
             for (int a = 0; a < 5; ++a) { z[a] = zc[a]; r[a] = rc[a]; }
         }
     }
-    int conv = 0, it;
+    int conv = 0, it, rej = 0;  // rej: rejected line-search trials over the whole solve
     for (it = 0; it < A.max_iter; ++it) {
         const double rn = norm2_5(r), ri = normi_5(r);
         double rhs[5] = {-r[0], -r[1], -r[2], -r[3], -r[4]}, dz[5], rdum[5];
@@ -699,7 +703,7 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const 
         double alpha = 1.0, zt[5], rt[5];
         Sums st;
         bool acc = false;
-        for (int hh = 0; hh < 40; ++hh) {
+        while (rej < kRejectBudget) {
 #pragma unroll
             for (int a = 0; a < 5; ++a) zt[a] = z[a] + alpha * dz[a];
             if (zt[4] > 0.0) {
@@ -709,6 +713,7 @@ __device__ int newton_solve(const NewtonArgs &A, SumsFn sums, int64_t pt, const 
                 if (norm2_5(rt) < (1.0 - 1e-4 * alpha) * rn) { acc = true; break; }
             }
             alpha *= 0.5;
+            ++rej;
         }
         if (!acc) {
             // stagnation at the rounding floor of the FP64 sums
@@ -802,8 +807,8 @@ __device__ int newton_solve_es(const NewtonArgs &A, SumsFn sums, int64_t pt, con
                     ++hh;
 #pragma unroll
                     for (int a = 0; a < 5; ++a) ze[a] = z[a] + alpha * dz[a];
-                } while (hh < 40 && !(ze[4] > 0.0));
-                if (hh < 40) continue;
+                } while (hh < kRejectBudget && !(ze[4] > 0.0));
+                if (hh < kRejectBudget) continue;
                 // stagnation at the rounding floor of the FP64 sums
                 if (ri <= 100.0 * A.tol) { res = ri; conv = 1; ++it; }
                 break;
@@ -833,16 +838,16 @@ __device__ int newton_solve_es(const NewtonArgs &A, SumsFn sums, int64_t pt, con
         if (!ok) break;
         chord = rn <= kChord;
         alpha = 1.0;
-        hh = 0;
+        // hh counts the rejected trials of the whole solve (not reset here)
 #pragma unroll
         for (int a = 0; a < 5; ++a) ze[a] = z[a] + alpha * dz[a];
-        while (hh < 40 && !(ze[4] > 0.0)) {
+        while (hh < kRejectBudget && !(ze[4] > 0.0)) {
             alpha *= 0.5;
             ++hh;
 #pragma unroll
             for (int a = 0; a < 5; ++a) ze[a] = z[a] + alpha * dz[a];
         }
-        if (hh == 40) {
+        if (hh >= kRejectBudget) {
             if (ri <= 100.0 * A.tol) { res = ri; conv = 1; ++it; }
             break;
         }
