@@ -58,7 +58,7 @@ class _Problem(C.Structure):
                 ("model", C.c_int32), ("Pr", C.c_double), ("mu_ref", C.c_double),
                 ("theta_ref", C.c_double), ("omega", C.c_double),
                 ("visc_law", C.c_int32), ("theta_s", C.c_double),
-                ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32)]
+                ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32), ("nv", C.c_int32 * 3)]
 
 
 def _declare(L):
@@ -199,6 +199,8 @@ class Problem:
         s.theta_s = float(params.get("theta_s", 0.0))
         s.newton_tol = float(params.get("newton_tol", 1e-13))
         s.newton_max_iter = int(params.get("newton_max_iter", 50))
+        for d in range(3):
+            s.nv[d] = int(grid["n"][d])
         self._s = s
 
     @property

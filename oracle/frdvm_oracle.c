@@ -278,7 +278,8 @@ typedef struct {
     const int32_t *nbr_elem; /* [ne][6], -1 on a boundary */
     const int8_t *nbr_face;  /* [ne][6] */
     const int8_t *nbr_orient;/* [ne][6] */
-    const int8_t *bc;        /* [ne][6]: 0 interior/periodic, 1 farfield, 2 diffuse wall */
+    const int8_t *bc;        /* [ne][6]: 0 interior/periodic, 1 farfield, 2 diffuse wall,
+                                3 specular (symmetry) wall */
     const double *f_inf;     /* [nu] farfield exterior state (bc 1) */
     double theta_w;          /* wall temperature (bc 2) */
     int32_t model;           /* 0 BGK, 1 ES-BGK, 2 collisionless (S = 0) */
@@ -287,6 +288,7 @@ typedef struct {
     double theta_s;
     double newton_tol;
     int32_t newton_max_iter;
+    int32_t nv[3];           /* velocity nodes per axis, k = i + nv0 (j + nv1 l) */
 } orc_problem;
 
 /* Neighbour face point for own face point (a,b) under orientation code o:
@@ -309,7 +311,8 @@ static void orient_map(int n, int o, int a, int b, int *pa, int *pb) {
  *     F^I = u_n f- if u_n > 0 else u_n f+,  jump = F^I - u_n f-
  *     corr(line) += c_side[m] * jump
  *   R_s = -(div_s + corr_s) / |J|_s
- * Exterior states: neighbour trace; farfield f_inf; diffuse wall rho_w M_w.
+ * Exterior states: neighbour trace; farfield f_inf; diffuse wall rho_w M_w;
+ * specular wall: the interior trace at the mirrored velocity.
  */
 int orc_residual(const orc_problem *P, const double *f, double *R) {
     int n = P->p + 1, ns = n * n * n, nfp = n * n, nu = P->nu;
@@ -393,6 +396,32 @@ int orc_residual(const orc_problem *P, const double *f, double *R) {
                             const double *uk = P->u + 3 * k;
                             ld uu = (ld)uk[0] * uk[0] + (ld)uk[1] * uk[1] + (ld)uk[2] * uk[2];
                             fp[k] = (double)(rw * c0 * expl(-uu / (2 * tw)));
+                        }
+                    } else if (P->bc[e * 6 + face] == 3) {
+                        /* specular wall: the exterior state at u is the
+                         * interior trace at the mirror image of u in the wall
+                         * plane; the plane must be normal to a coordinate
+                         * axis and the grid symmetric in that axis, so the
+                         * image is a node */
+                        double nn = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+                        int ax = -1;
+                        for (int c = 0; c < 3; ++c)
+                            if (fabs(fabs(nv[c]) - nn) <= 1e-12 * nn) ax = c;
+                        int str[3] = {1, P->nv[0], P->nv[0] * P->nv[1]};
+                        int ok = ax >= 0;
+                        if (ok) {
+                            double lo = P->u[ax], hi = P->u[3 * (int64_t)(P->nv[ax] - 1) * str[ax] + ax];
+                            ok = fabs(lo + hi) <= 1e-12 * (fabs(lo) > 1.0 ? fabs(lo) : 1.0);
+                        }
+                        if (!ok) {
+                            bad++;
+                            for (int k = 0; k < nu; ++k) fp[k] = fm[k];
+                        } else {
+                            for (int k = 0; k < nu; ++k) {
+                                int idx = (k / str[ax]) % P->nv[ax];
+                                int km = k + (P->nv[ax] - 1 - 2 * idx) * str[ax];
+                                fp[k] = fm[km];
+                            }
                         }
                     } else {
                         bad++;

@@ -135,3 +135,69 @@ def test_cylinder_mesh_geometry(orc):
     exact = math.pi * (m["r1"] ** 2 - m["r0"] ** 2) * m["lz"]
     assert (P.geo["detJ"] > 0).all()
     assert abs(V - exact) < 1e-4 * exact
+
+
+def _specular_half_and_mirror(p, grid):
+    """Half box [0,1] x [0,0.8] x [0,0.6] with specular walls at x = 0 and
+    x = 1 (periodic in y, z), and the periodic box of twice the length in x
+    that holds the mirrored state."""
+    half = W.box_mesh((2, 2, 2), length=(1.0, 0.8, 0.6))
+    nb = half["nbr_elem"].copy()
+    bc = half["bc"].copy()
+    for e in range(half["n_elem"]):
+        ix = e % 2
+        if ix == 0:
+            nb[e, 0], bc[e, 0] = -1, 3
+        if ix == 1:
+            nb[e, 1], bc[e, 1] = -1, 3
+    half = dict(half, nbr_elem=nb, bc=bc)
+    full = W.box_mesh((4, 2, 2), length=(2.0, 0.8, 0.6))
+    return half, full
+
+
+def _mirror_state(fh, p, grid):
+    """f on the doubled box: elements ix = 0, 1 hold fh, ix = 2, 3 the image
+    under x -> 2 - x, u_x -> -u_x."""
+    n = p + 1
+    nx = grid["n"][0]
+    ne_h, ns, nu = fh.shape
+    ff = np.zeros((2 * ne_h, ns, nu))
+    fr = fh.reshape(ne_h, n, n, n, -1, nx)  # [e][l][j][i][k_yz][k_x]
+    mir = fr[:, :, :, ::-1, :, ::-1].reshape(ne_h, ns, nu)
+    for e in range(ne_h):
+        ix, rest = e % 2, e // 2
+        ff[0 + 4 * rest + ix] = fh[e]
+        ff[3 - ix + 4 * rest] = mir[e]
+    return ff
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_specular_wall_is_a_mirror_plane(orc, p):
+    """Specular walls at x = 0 and x = 1 give the residual of the periodic
+    box of twice the length holding the mirrored state, restricted to the
+    original half."""
+    grid = W.grid_spec((6, 3, 4), 4.0)
+    half, full = _specular_half_and_mirror(p, grid)
+    Ph = orc.Problem(half, p, grid, FREE)
+    fh = _noisy(Ph, grid, 9)
+    Pf = orc.Problem(full, p, grid, FREE)
+    Rf = Pf.residual(_mirror_state(fh, p, grid))
+    Rh = Ph.residual(fh)
+    keep = [e for e in range(full["n_elem"]) if e % 4 < 2]
+    assert np.abs(Rh - Rf[keep]).max() < 1e-12 * np.abs(Rh).max()
+
+
+def test_specular_box_conserves_mass_and_energy(orc):
+    mesh = _walls(W.box_mesh((2, 2, 2), periodic=False, length=(1.0, 1.2, 0.8)), 3)
+    grid = W.grid_spec(6, 5.0)
+    P = orc.Problem(mesh, 2, grid, FREE)
+    R = P.residual(_noisy(P, grid, 10))
+    tot, scale = P.totals(R), P.totals(np.abs(R))
+    assert abs(tot[0]) < 1e-13 * scale[0] and abs(tot[4]) < 1e-13 * scale[4]
+
+
+def test_specular_wall_needs_an_axis_plane(orc):
+    mesh = W.quadratic_map_mesh(2, eps=0.15, bc_all=3)
+    P = orc.Problem(mesh, 2, W.grid_spec(4, 3.0), FREE)
+    with pytest.raises(ValueError):
+        P.residual(np.ones(P.shape))
