@@ -268,7 +268,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="box24_p3_v20_es")
-    ap.add_argument("--mode", choices=("compare", "single"), default="compare")
+    ap.add_argument("--mode", choices=("compare", "single", "kn"), default="compare")
     ap.add_argument("--precision", type=int, default=None, help="single mode: 0 FP64, 1 FP32")
     ap.add_argument("--rk", type=int, default=None, help="single mode: 0 SSP-RK3, 1 low-storage")
     ap.add_argument("--guess", type=int, default=None, help="single mode: 0 cold, 1 warm, 2 MLP, 3 MLP then warm")
@@ -319,6 +319,10 @@ def main():
            "nu": int(w["grid"]["n"][0] * w["grid"]["n"][1] * w["grid"]["n"][2]),
            "model": ["BGK", "ES-BGK", "free"][base["model"]], "prandtl": base["prandtl"], "kn": w["kn"],
            "parallelism": "single GPU"}
+
+    if args.mode == "kn":
+        print(json.dumps(kn_bench(W, w, mesh, base, args, cfg)), flush=True)
+        return
 
     if args.mode == "single":
         par = dict(base)
@@ -406,6 +410,43 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, p64, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def kn_bench(W, w, mesh, base, args, cfg):
+    """Local Knudsen number of the whole field: the moment pass over f plus
+    the per-element gradient kernel, timed with HIP events over `steps`
+    calls.  Algorithmic bytes: read f once, write and read the moments, write
+    Kn."""
+    import torch
+
+    from paper_2312_06567_amd.frdvm import FrDvm
+    par = dict(base, precision=w["precision"] if args.precision is None else args.precision)
+    s = FrDvm(mesh, w["p"], w["grid"], par)
+    ne, ns, nu = s.shape
+    f = W.maxwellian(W.initial_prim(mesh, w["p"], w), w["grid"], dtype=s.dtype, device="cuda").reshape(ne, ns, nu)
+    kn = torch.empty(ne * ns, dtype=torch.float64, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        s.kn_gll(f, kn)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        s.kn_gll(f, kn)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    es = 8 if par["precision"] == 0 else 4
+    nbytes = ne * ns * (nu * es + (10 if par["model"] == 1 else 5) * 8 * 2 + 8)
+    ach = nbytes / (ms / 1e3) / 1e9
+    kmax = float(kn.max().item())
+    cfg = dict(cfg, precision=["FP64", "FP32"][par["precision"]])
+    return {"metric": "local Knudsen number field evaluations/s", "value": 1e3 / ms, "unit": "fields/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_call": ms, "higher_is_better": True,
+            "dtype": "f64" if par["precision"] == 0 else "f32 (FP64 moments and gradient)", "data": "synthetic",
+            "config": cfg, "kn_max": kmax,
+            "roofline": {"kernel": "moment pass + k_kn_gll", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_call": nbytes}}
 
 
 def cpu_baseline(w: dict, params: dict, budget_s: float) -> dict:

@@ -87,7 +87,10 @@ typedef struct {
                                             bit2 the second; (a,b) run along the two other
                                             reference axes in increasing order */
     const int8_t *bc;                    /* [n_elem][6] 0 interior/periodic, 1 farfield,
-                                            2 diffuse isothermal wall */
+                                            2 diffuse isothermal wall, 3 specular
+                                            (symmetry) wall: a plane normal to a
+                                            coordinate axis, velocity grid symmetric
+                                            in that axis */
 } fr_dvm_mesh;
 
 /* Uniform Cartesian velocity grid, closed (end points are nodes), trapezoid
@@ -133,7 +136,8 @@ void fr_dvm_default_params(fr_dvm_params *p);
  * conform: at matched flux points opposite normals, positions differing by
  * one vector (zero, or a period).  Returns FR_DVM_EINVAL for an inconsistent
  * mesh (non-positive Jacobian, non-conforming or asymmetric neighbours, a
- * boundary face without tag 1 or 2), FR_DVM_EUNSUPPORTED for p outside 1..3. */
+ * boundary face without tag 1, 2 or 3, a specular face that is not a
+ * coordinate plane), FR_DVM_EUNSUPPORTED for p outside 1..3. */
 int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out);
 
 /* Set physics / precision / solver parameters; allocates the work buffers

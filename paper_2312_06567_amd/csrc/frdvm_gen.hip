@@ -8,9 +8,10 @@
 // at every flux point the upwind common flux F^I = u_n f- (u_n > 0) or
 // u_n f+ (otherwise), u_n = u . n with the area-scaled outward normal; the
 // jump F^I - u_n f- enters through the DG-recovering correction.  Exterior
-// states: the neighbour's trace, the freestream Maxwellian (farfield) or
+// states: the neighbour's trace, the freestream Maxwellian (farfield),
 // rho_w M(0, theta_w) (diffuse wall at rest) with rho_w chosen so that no
-// mass crosses the wall.  The collision source (g(Q') - f)/tau and the RK
+// mass crosses the wall, or the element's own trace at the mirrored velocity
+// (specular symmetry wall).  The collision source (g(Q') - f)/tau and the RK
 // combination are those of the box kernel.
 //
 // Work decomposition: one wave per (element, 64 velocities), one lane per
@@ -366,6 +367,16 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
             const Real fi = (Real)ldo(A.finf, k8);
 #pragma unroll
             for (int q = 0; q < NFP; ++q) ext[q] = fi;
+        } else if (bc == 3) {
+            // specular: the own trace at the velocity mirrored in the face's
+            // axis (orient holds the axis)
+            const int str = orient == 0 ? 1 : (orient == 1 ? A.vg.nv[0] : A.vg.nv[0] * A.vg.nv[1]);
+            const int ia = orient == 0 ? iv[0] : (orient == 1 ? iv[1] : iv[2]);
+            const int km = k + (A.vg.nv[orient] - 1 - 2 * ia) * str;
+            const uint32_t kmo = (uint32_t)km * (uint32_t)sizeof(Real);
+            const Real *to = tin + (e * 6 + face) * NFP * nu;
+#pragma unroll
+            for (int q = 0; q < NFP; ++q) ext[q] = un[q] < Real(0) ? ldo(to + q * nu, kmo) : Real(0);
         } else {
             const double mw = ldo(A.mw, k8);
 #pragma unroll

@@ -297,6 +297,32 @@ int setup_general(fr_dvm *h, const fr_dvm_mesh *mesh, std::vector<double> &wq3J)
             c[3] = nb >= 0 ? 0 : mesh->bc[e * 6 + f];
             if (nb < 0) {
                 if (c[3] == 2) wall.push_back((int32_t)(e * 6 + f));
+                if (c[3] == 3) {
+                    // specular: the face must be a plane normal to a coordinate
+                    // axis (its mirror image of a node is then a node of a
+                    // grid symmetric in that axis); the axis goes in c[2]
+                    int ax = -1;
+                    for (int t = 0; t < nfp; ++t) {
+                        const double *u = &nf[((e * 6 + f) * nfp + t) * 3];
+                        const double mag = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                        int at = -1;
+                        for (int cc = 0; cc < 3; ++cc)
+                            if (std::fabs(std::fabs(u[cc]) - mag) <= 1e-12 * mag) at = cc;
+                        if (at < 0 || (ax >= 0 && at != ax)) { ax = -2; break; }
+                        ax = at;
+                    }
+                    const VGrid &vg = h->vg;
+                    bool sym = ax >= 0;
+                    if (sym) {
+                        const double lo = vg.umin[ax], hi = vg.umin[ax] + (vg.nv[ax] - 1) * vg.du[ax];
+                        sym = std::fabs(lo + hi) <= 1e-12 * std::max(1.0, std::fabs(lo));
+                    }
+                    if (!sym)
+                        return h->fail(FR_DVM_EINVAL, "specular face " + std::to_string(f) + " of element " +
+                                                          std::to_string(e) +
+                                                          " is not a coordinate plane on a velocity grid symmetric in its axis");
+                    c[2] = ax;
+                }
                 continue;
             }
             const double *x00 = &xf[((e * 6 + f) * nfp) * 3];
@@ -421,7 +447,7 @@ extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vg
         for (int f = 0; f < 6; ++f) {
             const int32_t nb = mesh->nbr_elem[e * 6 + f];
             if (nb < 0) {
-                if (mesh->bc[e * 6 + f] != 1 && mesh->bc[e * 6 + f] != 2)
+                if (mesh->bc[e * 6 + f] < 1 || mesh->bc[e * 6 + f] > 3)
                     return bail(h->fail(FR_DVM_EINVAL, "face without neighbour and without a boundary tag"));
                 continue;
             }

@@ -145,6 +145,38 @@ def test_general_rk_steps_mixed(F, orc):
         assert rel(Qg[..., a], Qr[..., a]) < 1e-6, a
 
 
+@pytest.mark.parametrize("p,prec", [(1, 0), (2, 0), (2, 1)])
+def test_specular_wall(F, orc, p, prec):
+    """Half box with specular walls at x = 0 and x = 1 (the oracle's mirror
+    pin holds for it): residual against the oracle, FP64 to 1e-12, FP32 to
+    1e-6."""
+    from test_oracle_bc import _specular_half_and_mirror
+    grid = W.grid_spec((7, 6, 8), 4.0)  # 336 velocities
+    half, _ = _specular_half_and_mirror(p, grid)
+    par = _params()
+    P = _oracle(orc, half, p, grid, par)
+    f = _state(P, grid, 9)
+    s = F.FrDvm(half, p, grid, dict(par, precision=prec))
+    R = torch.zeros(s.shape, dtype=s.dtype, device="cuda")
+    s.residual(_gpu(s, f), R)
+    ref = P.residual(f if prec == 0 else f.astype(np.float32).astype(np.float64))
+    assert rel(R.double().cpu().numpy(), ref) < (1e-12 if prec == 0 else 1e-6)
+
+
+def test_specular_box_rk_conserves_mass_and_energy(F):
+    mesh = W.box_mesh((2, 2, 2), periodic=False, length=(1.0, 1.2, 0.8))
+    mesh = dict(mesh, bc=np.where(mesh["nbr_elem"] < 0, 3, 0).astype(np.int8))
+    grid = W.grid_spec(8, 6.0)
+    s = F.FrDvm(mesh, 2, grid, _params(model=1, prandtl=2.0 / 3.0, mu_ref=0.02))
+    prim = np.tile([1.0, 0.4, -0.2, 0.1, 1.1], (s.ne, s.ns, 1))
+    prim[..., 0] += 0.1 * np.random.default_rng(3).uniform(-1, 1, size=(s.ne, s.ns))
+    f = _gpu(s, W.maxwellian(prim, grid).numpy())
+    t0 = s.moments(f, totals=True)
+    s.rk_steps(f, s.dt(0.2), 3)
+    t1 = s.moments(f, totals=True)
+    assert abs(t1[0] - t0[0]) < 1e-13 * t0[0] and abs(t1[4] - t0[4]) < 1e-13 * t0[4]
+
+
 def test_wall_box_conserves_mass_and_keeps_wall_maxwellian(F):
     mesh = W.quadratic_map_mesh(2, eps=0.1, bc_all=2)
     grid = W.grid_spec(8, 6.0)
@@ -176,6 +208,11 @@ def test_general_create_rejects_bad_meshes(F):
     with pytest.raises(F.FrDvmError):
         F.FrDvm(untagged, 1, W.grid_spec(3, 2.0))
     assert nb >= 0 and nf >= 0
+    with pytest.raises(F.FrDvmError):  # specular faces must be coordinate planes
+        F.FrDvm(W.quadratic_map_mesh(2, eps=0.15, bc_all=3), 2, W.grid_spec(4, 3.0))
+    with pytest.raises(F.FrDvmError):  # ... on a grid symmetric in their axis
+        sym = dict(open_box, bc=np.where(open_box["nbr_elem"] < 0, 3, 0).astype(np.int8))
+        F.FrDvm(sym, 1, W.grid_spec(4, 3.0, umin=-2.0))
 
 
 # ---------------------------------------------------------------------------
