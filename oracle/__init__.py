@@ -58,12 +58,16 @@ class _Problem(C.Structure):
                 ("model", C.c_int32), ("Pr", C.c_double), ("mu_ref", C.c_double),
                 ("theta_ref", C.c_double), ("omega", C.c_double),
                 ("visc_law", C.c_int32), ("theta_s", C.c_double),
-                ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32), ("nv", C.c_int32 * 3)]
+                ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32), ("nv", C.c_int32 * 3),
+                ("nodes", C.c_int32)]
 
 
 def _declare(L):
     L.orc_gauss_legendre.argtypes = [C.c_int, _dp, _dp]
     L.orc_fr_ops.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_fr_ops_set.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_gauss_lobatto.argtypes = [C.c_int, _dp, _dp]
+    L.orc_geometry_set.argtypes = [C.c_int, C.c_int, _dp, _ip, C.c_int, C.c_int, _dp, _dp, _dp, _dp]
     L.orc_geometry.argtypes = [C.c_int, C.c_int, _dp, _ip, C.c_int, _dp, _dp, _dp, _dp]
     L.orc_vgrid.argtypes = [_ip, _dp, _dp, _dp, _dp]
     L.orc_moments.argtypes = [C.c_int64, C.c_int, _dp, _dp, _dp, _dp]
@@ -100,12 +104,19 @@ def gauss_legendre(n: int):
     return xi, w
 
 
-def fr_ops(p: int) -> dict:
+def gauss_lobatto(n: int):
+    xi, w = np.zeros(n), np.zeros(n)
+    assert lib().orc_gauss_lobatto(n, _d(xi), _d(w)) == 0
+    return xi, w
+
+
+def fr_ops(p: int, nodes: int = 0) -> dict:
+    """1-D FR operators on Gauss-Legendre (nodes 0) or Gauss-Lobatto (1) points."""
     n = p + 1
     o = {k: np.zeros(n) for k in ("xi", "lamL", "lamR", "cM", "cP")}
     o["D"] = np.zeros((n, n))
-    assert lib().orc_fr_ops(p, _d(o["xi"]), _d(o["D"]), _d(o["lamL"]), _d(o["lamR"]),
-                            _d(o["cM"]), _d(o["cP"])) == 0
+    assert lib().orc_fr_ops_set(p, nodes, _d(o["xi"]), _d(o["D"]), _d(o["lamL"]), _d(o["lamR"]),
+                                _d(o["cM"]), _d(o["cP"])) == 0
     return o
 
 
@@ -118,16 +129,16 @@ def vgrid(n, umin, umax):
     return u, w
 
 
-def geometry(mesh: dict, p: int) -> dict:
+def geometry(mesh: dict, p: int, nodes: int = 0) -> dict:
     ne = int(mesh["n_elem"])
     n = p + 1
     ns = n ** 3
-    nodes = _f64(mesh["nodes"])
+    X = _f64(mesh["nodes"])
     en = np.ascontiguousarray(mesh["elem_nodes"], dtype=np.int32)
     g = {"xs": np.zeros((ne, ns, 3)), "detJ": np.zeros((ne, ns)),
          "S": np.zeros((ne, ns, 3, 3)), "nf": np.zeros((ne, 6, n * n, 3))}
-    rc = lib().orc_geometry(ne, int(mesh["geom_order"]), _d(nodes), en.ctypes.data_as(_ip), p,
-                            _d(g["xs"]), _d(g["detJ"]), _d(g["S"]), _d(g["nf"]))
+    rc = lib().orc_geometry_set(ne, int(mesh["geom_order"]), _d(X), en.ctypes.data_as(_ip), p, int(nodes),
+                                _d(g["xs"]), _d(g["detJ"]), _d(g["S"]), _d(g["nf"]))
     if rc != 0:
         raise ValueError("oracle geometry: non-positive Jacobian")
     return g
@@ -172,7 +183,8 @@ class Problem:
         self.ne = int(mesh["n_elem"])
         self.u, self.w = vgrid(grid["n"], grid["umin"], grid["umax"])
         self.nu = self.u.shape[0]
-        self.geo = geometry(mesh, p)
+        self.nodes = int(params.get("nodes", 0))
+        self.geo = geometry(mesh, p, self.nodes)
         self.nbr_elem = np.ascontiguousarray(mesh["nbr_elem"], dtype=np.int32)
         self.nbr_face = np.ascontiguousarray(mesh["nbr_face"], dtype=np.int8)
         self.nbr_orient = np.ascontiguousarray(mesh["nbr_orient"], dtype=np.int8)
@@ -201,6 +213,7 @@ class Problem:
         s.newton_max_iter = int(params.get("newton_max_iter", 50))
         for d in range(3):
             s.nv[d] = int(grid["n"][d])
+        s.nodes = self.nodes
         self._s = s
 
     @property

@@ -78,6 +78,37 @@ int orc_gauss_legendre(int n, double *xi, double *wq) {
     return ORC_OK;
 }
 
+/* n >= 2 Gauss-Lobatto-Legendre nodes (ascending: -1, the roots of
+ * P'_{n-1}, +1) and weights 2 / (n (n-1) P_{n-1}(x)^2) on [-1,1]. */
+int orc_gauss_lobatto(int n, double *xi, double *wq) {
+    if (n < 2 || n > 32) return ORC_EINVAL;
+    int p = n - 1;
+    for (int i = 0; i < n; ++i) {
+        ld x = -cosl(3.14159265358979323846264338327950288L * i / p);
+        if (i > 0 && i < p) {
+            /* Newton on P_p'(x), with P_p'' from the Legendre equation */
+            for (int it = 0; it < 100; ++it) {
+                ld P, dP;
+                legendre(p, x, &P, &dP);
+                ld d2P = (2.0L * x * dP - p * (p + 1.0L) * P) / (1.0L - x * x);
+                ld dx = dP / d2P;
+                x -= dx;
+                if (fabsl(dx) < 1e-19L) break;
+            }
+        }
+        ld P, dP;
+        legendre(p, x, &P, &dP);
+        xi[i] = (double)x;
+        if (wq) wq[i] = (double)(2.0L / (p * (p + 1.0L) * P * P));
+    }
+    return ORC_OK;
+}
+
+/* Solution points of one axis: set 0 Gauss-Legendre, set 1 Gauss-Lobatto. */
+static int solution_points(int set, int n, double *xi, double *wq) {
+    return set == 1 ? orc_gauss_lobatto(n, xi, wq) : orc_gauss_legendre(n, xi, wq);
+}
+
 /* Lagrange basis l_j(x) on nodes z[0..n-1]. */
 static ld lagr(int n, const ld *z, int j, ld x) {
     ld v = 1.0L;
@@ -100,7 +131,8 @@ static ld lagr_d(int n, const ld *z, int j, ld x) {
 }
 
 /*
- * One-dimensional FR operators for degree p on Gauss-Legendre points
+ * One-dimensional FR operators for degree p on Gauss-Legendre (set 0) or
+ * Gauss-Lobatto (set 1) points
  * (Section "Numerical method", the corrected flux and its correction
  * functions h_i chosen to recover nodal DG).
  *   xi[n]       solution points, n = p+1
@@ -110,13 +142,13 @@ static ld lagr_d(int n, const ld *z, int j, ld x) {
  * with the DG correction functions (right/left Radau polynomials)
  *   gL(x) = (-1)^n/2 (P_n - P_{n-1}),  gR(x) = 1/2 (P_n + P_{n-1}).
  */
-int orc_fr_ops(int p, double *xi, double *D, double *lamL, double *lamR,
-               double *cM, double *cP) {
+int orc_fr_ops_set(int p, int set, double *xi, double *D, double *lamL, double *lamR,
+                   double *cM, double *cP) {
     int n = p + 1;
-    if (p < 0 || p > 8) return ORC_EINVAL;
+    if (p < 0 || p > 8 || (set == 1 && p < 1)) return ORC_EINVAL;
     double xd[16];
     ld z[16];
-    orc_gauss_legendre(n, xd, NULL);
+    solution_points(set, n, xd, NULL);
     for (int i = 0; i < n; ++i) { z[i] = xd[i]; xi[i] = xd[i]; }
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j)
@@ -136,6 +168,10 @@ int orc_fr_ops(int p, double *xi, double *D, double *lamL, double *lamR,
         cP[i] = (double)dgR;
     }
     return ORC_OK;
+}
+
+int orc_fr_ops(int p, double *xi, double *D, double *lamL, double *lamR, double *cM, double *cP) {
+    return orc_fr_ops_set(p, 0, xi, D, lamL, lamR, cM, cP);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -216,12 +252,12 @@ static void contravariant(ld dxdr[3][3], ld S[3][3], ld *detJ) {
  * Face f = 2*d + side (side 0 at xi_d = -1, side 1 at +1); face point
  * index a + n*b with (a,b) along the two other axes in increasing order.
  */
-int orc_geometry(int ne, int q, const double *nodes, const int32_t *elem_nodes,
-                 int p, double *xs, double *detJ, double *S, double *nf) {
-    if (q < 1 || q > 2 || p < 0) return ORC_EINVAL;
+int orc_geometry_set(int ne, int q, const double *nodes, const int32_t *elem_nodes,
+                     int p, int set, double *xs, double *detJ, double *S, double *nf) {
+    if (q < 1 || q > 2 || p < 0 || (set == 1 && p < 1)) return ORC_EINVAL;
     int n = p + 1, ns = n * n * n, m = q + 1, ng = m * m * m;
     double xi[16];
-    orc_gauss_legendre(n, xi, NULL);
+    solution_points(set, n, xi, NULL);
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : bad)
     for (int e = 0; e < ne; ++e) {
@@ -264,6 +300,11 @@ int orc_geometry(int ne, int q, const double *nodes, const int32_t *elem_nodes,
     return bad ? ORC_EINVAL : ORC_OK;
 }
 
+int orc_geometry(int ne, int q, const double *nodes, const int32_t *elem_nodes, int p, double *xs,
+                 double *detJ, double *S, double *nf) {
+    return orc_geometry_set(ne, q, nodes, elem_nodes, p, 0, xs, detJ, S, nf);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Problem description shared by the residual, collision and RK routines     */
 /* ------------------------------------------------------------------------ */
@@ -289,6 +330,7 @@ typedef struct {
     double newton_tol;
     int32_t newton_max_iter;
     int32_t nv[3];           /* velocity nodes per axis, k = i + nv0 (j + nv1 l) */
+    int32_t nodes;           /* solution points: 0 Gauss-Legendre, 1 Gauss-Lobatto */
 } orc_problem;
 
 /* Neighbour face point for own face point (a,b) under orientation code o:
@@ -317,7 +359,7 @@ static void orient_map(int n, int o, int a, int b, int *pa, int *pb) {
 int orc_residual(const orc_problem *P, const double *f, double *R) {
     int n = P->p + 1, ns = n * n * n, nfp = n * n, nu = P->nu;
     double xi[16], D[256], lam[2][16], cv[2][16];
-    orc_fr_ops(P->p, xi, D, lam[0], lam[1], cv[0], cv[1]);
+    if (orc_fr_ops_set(P->p, P->nodes, xi, D, lam[0], lam[1], cv[0], cv[1]) != ORC_OK) return ORC_EINVAL;
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
     for (int e = 0; e < P->ne; ++e) {
@@ -887,7 +929,7 @@ int orc_rk_step(const orc_problem *P, double *f, double dt, int scheme, int nste
 int orc_totals(const orc_problem *P, const double *f, double *tot) {
     int n = P->p + 1, ns = n * n * n;
     double xi[16], wq[16];
-    orc_gauss_legendre(n, xi, wq);
+    solution_points(P->nodes, n, xi, wq);
     int64_t npts = (int64_t)P->ne * ns;
     double *Q = (double *)malloc(sizeof(double) * 5 * npts);
     if (!Q) return ORC_ENOMEM;
@@ -937,7 +979,7 @@ double orc_dt(const orc_problem *P, double cfl) {
 int orc_kn_gll(const orc_problem *P, const double *f, double *kn) {
     int n = P->p + 1, ns = n * n * n, nu = P->nu;
     double xi[16], D[256], lL[16], lR[16], cM[16], cP[16];
-    if (orc_fr_ops(P->p, xi, D, lL, lR, cM, cP) != ORC_OK) return ORC_EINVAL;
+    if (orc_fr_ops_set(P->p, P->nodes, xi, D, lL, lR, cM, cP) != ORC_OK) return ORC_EINVAL;
 #pragma omp parallel for schedule(static)
     for (int e = 0; e < P->ne; ++e) {
         ld Q[729][5];  /* ns <= 9^3 */
