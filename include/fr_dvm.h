@@ -140,6 +140,18 @@ void fr_dvm_default_params(fr_dvm_params *p);
  * coordinate plane), FR_DVM_EUNSUPPORTED for p outside 1..3. */
 int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out);
 
+/* fr_dvm_create with a choice of solution points per axis (Section
+ * "Numerical method": the paper places Gauss-Lobatto points on tensor-product
+ * elements): nodes FR_DVM_NODES_GAUSS (Gauss-Legendre, what fr_dvm_create
+ * uses) or FR_DVM_NODES_LOBATTO (Gauss-Lobatto, order >= 1; points on the
+ * element faces).  The correction functions recover nodal DG with the exact
+ * mass matrix in both cases; moments' domain totals use the same rule's
+ * weights.  FR_DVM_EINVAL for another value. */
+#define FR_DVM_NODES_GAUSS 0
+#define FR_DVM_NODES_LOBATTO 1
+int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes, const fr_dvm_vgrid *grid,
+                        fr_dvm_t *out);
+
 /* Set physics / precision / solver parameters; allocates the work buffers
  * of the chosen precision.  Must be called before any compute call. */
 int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p);

@@ -65,6 +65,7 @@ struct fr_dvm {
 
     // discretisation
     int p = 0, n = 0, ns = 0, nfp = 0;
+    int nodes = 0;  // solution points: 0 Gauss-Legendre, 1 Gauss-Lobatto
     int64_t ne = 0;
     frdvm::VGrid vg{};
     std::vector<double> wax[3];  // 1-D trapezoid weights per axis

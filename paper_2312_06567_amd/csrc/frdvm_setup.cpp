@@ -32,32 +32,68 @@ void legendre_eval(int n, double x, double &P, double &dP) {
     dP = n * (x * pc - pm) / (x * x - 1.0);  // valid inside (-1,1)
 }
 
-// Gauss-Legendre rule and the FR operators in barycentric form.
-// D: l_m'(xi_i) from barycentric weights; traces l_m(+-1); the correction
-// derivative at xi_i for a unit jump on a face is the DG lifting l_i(face)/w_i
-// (Huynh's g_DG correction reproduces nodal DG exactly).
-void build_ops(int p, Ops1D &o) {
-    int n = p + 1;
-    std::memset(&o, 0, sizeof(o));
+// n-point Gauss-Legendre rule (ascending) by Newton on P_n.
+void gauss_legendre_rule(int n, double *x, double *w) {
     for (int i = 0; i < n; ++i) {
-        double x = std::cos(M_PI * (4.0 * (n - i) - 1.0) / (4.0 * n + 2.0));
-        if (n == 1) x = 0.0;
+        double t = std::cos(M_PI * (4.0 * (n - i) - 1.0) / (4.0 * n + 2.0));
+        if (n == 1) t = 0.0;
         for (int it = 0; it < 60 && n > 1; ++it) {
             double P, dP;
-            legendre_eval(n, x, P, dP);
-            double dx = P / dP;
-            x -= dx;
+            legendre_eval(n, t, P, dP);
+            const double dx = P / dP;
+            t -= dx;
             if (std::fabs(dx) < 1e-17) break;
         }
-        double P, dP;
-        if (n > 1) {
-            legendre_eval(n, x, P, dP);
-        } else {
-            dP = 1.0;
-        }
-        o.xi[i] = x;
-        o.wq[i] = 2.0 / ((1.0 - x * x) * dP * dP);
+        double P, dP = 1.0;
+        if (n > 1) legendre_eval(n, t, P, dP);
+        x[i] = t;
+        w[i] = 2.0 / ((1.0 - t * t) * dP * dP);
     }
+}
+
+// n-point Gauss-Lobatto rule (ascending): the end points and the extrema of
+// P_{n-1}, weights 2 / (n (n-1) P_{n-1}^2).  The interior nodes are the
+// roots of P'_{n-1}; Newton uses P'' from Legendre's equation.
+void gauss_lobatto_rule(int n, double *x, double *w) {
+    const int p = n - 1;
+    for (int i = 0; i < n; ++i) {
+        double t = -std::cos(M_PI * i / p);
+        if (i > 0 && i < p) {
+            for (int it = 0; it < 60; ++it) {
+                double P, dP;
+                legendre_eval(p, t, P, dP);
+                const double d2P = (2.0 * t * dP - p * (p + 1.0) * P) / (1.0 - t * t);
+                const double dx = dP / d2P;
+                t -= dx;
+                if (std::fabs(dx) < 1e-17) break;
+            }
+        }
+        // P_p at the node by the three-term recurrence (the end points too)
+        double pm = 1.0, pc = t;
+        for (int k = 2; k <= p; ++k) {
+            const double pn = ((2.0 * k - 1.0) * t * pc - (k - 1.0) * pm) / k;
+            pm = pc;
+            pc = pn;
+        }
+        x[i] = t;
+        w[i] = 2.0 / (p * (p + 1.0) * pc * pc);
+    }
+}
+
+// FR operators in barycentric form on Gauss-Legendre (nodes 0) or
+// Gauss-Lobatto (nodes 1) points.  D: l_m'(xi_i) from barycentric weights;
+// traces l_m(+-1); the correction derivative at xi_i for a unit jump on a
+// face is the DG lifting M^-1 l(face) with the exact mass matrix
+// M_ij = int l_i l_j (Huynh's g_DG correction reproduces nodal DG); on
+// Gauss points M = diag(w), elsewhere it is assembled with an (n+1)-point
+// Gauss rule and solved.
+void build_ops(int p, int nodes, Ops1D &o) {
+    const int n = p + 1;
+    std::memset(&o, 0, sizeof(o));
+    if (nodes == 1)
+        gauss_lobatto_rule(n, o.xi, o.wq);
+    else
+        gauss_legendre_rule(n, o.xi, o.wq);
     double lamb[kMaxN];
     for (int j = 0; j < n; ++j) {
         double pr = 1.0;
@@ -69,18 +105,54 @@ void build_ops(int p, Ops1D &o) {
         double diag = 0.0;
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
-            double v = (lamb[j] / lamb[i]) / (o.xi[i] - o.xi[j]);
+            const double v = (lamb[j] / lamb[i]) / (o.xi[i] - o.xi[j]);
             o.D[i * n + j] = v;
             diag -= v;
         }
         o.D[i * n + i] = diag;
     }
-    for (int side = 0; side < 2; ++side) {
-        double x = side ? 1.0 : -1.0, den = 0.0;
+    // l_m(x) in barycentric form (exactly the unit vector at a node)
+    auto basis = [&](double x, double *l) {
+        for (int m = 0; m < n; ++m)
+            if (x == o.xi[m]) {
+                for (int r = 0; r < n; ++r) l[r] = r == m ? 1.0 : 0.0;
+                return;
+            }
+        double den = 0.0;
         for (int m = 0; m < n; ++m) den += lamb[m] / (x - o.xi[m]);
-        for (int m = 0; m < n; ++m) o.lam[side][m] = (lamb[m] / (x - o.xi[m])) / den;
-        for (int i = 0; i < n; ++i) o.corr[side][i] = o.lam[side][i] / o.wq[i];
+        for (int m = 0; m < n; ++m) l[m] = (lamb[m] / (x - o.xi[m])) / den;
+    };
+    for (int side = 0; side < 2; ++side) basis(side ? 1.0 : -1.0, o.lam[side]);
+    if (nodes != 1) {
+        for (int side = 0; side < 2; ++side)
+            for (int i = 0; i < n; ++i) o.corr[side][i] = o.lam[side][i] / o.wq[i];
+        return;
     }
+    double xg[kMaxN + 1], wg[kMaxN + 1], M[kMaxN][kMaxN + 2] = {};
+    gauss_legendre_rule(n + 1, xg, wg);
+    for (int g = 0; g < n + 1; ++g) {
+        double l[kMaxN];
+        basis(xg[g], l);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) M[i][j] += wg[g] * l[i] * l[j];
+    }
+    // solve M [c-, c+] = [l(-1), l(+1)] (symmetric positive definite, n <= 4)
+    for (int i = 0; i < n; ++i) {
+        M[i][n] = o.lam[0][i];
+        M[i][n + 1] = o.lam[1][i];
+    }
+    for (int c = 0; c < n; ++c) {
+        for (int r = c + 1; r < n; ++r) {
+            const double fct = M[r][c] / M[c][c];
+            for (int k = c; k < n + 2; ++k) M[r][k] -= fct * M[c][k];
+        }
+    }
+    for (int side = 0; side < 2; ++side)
+        for (int i = n - 1; i >= 0; --i) {
+            double v = M[i][n + side];
+            for (int k = i + 1; k < n; ++k) v -= M[i][k] * o.corr[side][k];
+            o.corr[side][i] = v / M[i][i];
+        }
 }
 
 template <typename T>
@@ -395,7 +467,8 @@ extern "C" void fr_dvm_default_params(fr_dvm_params *p) {
     p->overlap = 0;
 }
 
-extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out) {
+extern "C" int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes, const fr_dvm_vgrid *grid,
+                                   fr_dvm_t *out) {
     if (!out) return FR_DVM_EINVAL;
     *out = nullptr;
     if (!mesh || !grid || !mesh->nodes || !mesh->elem_nodes || !mesh->nbr_elem || !mesh->nbr_face ||
@@ -411,7 +484,9 @@ extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vg
     h->ns = h->n * h->n * h->n;
     h->nfp = h->n * h->n;
     h->ne = mesh->n_elem;
-    build_ops(order, h->ops);
+    if (nodes != 0 && nodes != 1) return bail(h->fail(FR_DVM_EINVAL, "solution point set must be 0 or 1"));
+    h->nodes = nodes;
+    build_ops(order, nodes, h->ops);
 
     // velocity grid
     VGrid &vg = h->vg;
@@ -479,6 +554,10 @@ extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vg
     hipMemset(h->d_maxres, 0, sizeof(double));
     *out = h;
     return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out) {
+    return fr_dvm_create_nodes(mesh, order, 0, grid, out);
 }
 
 extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {

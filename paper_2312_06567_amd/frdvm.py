@@ -61,6 +61,7 @@ def lib():
         vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
         L.fr_dvm_default_params.argtypes = [C.POINTER(_Params)]
         L.fr_dvm_create.argtypes = [C.POINTER(_Mesh), C.c_int, C.POINTER(_VGrid), C.POINTER(vp)]
+        L.fr_dvm_create_nodes.argtypes = [C.POINTER(_Mesh), C.c_int, C.c_int, C.POINTER(_VGrid), C.POINTER(vp)]
         L.fr_dvm_set_params.argtypes = [vp, C.POINTER(_Params)]
         L.fr_dvm_set_stream.argtypes = [vp, vp]
         L.fr_dvm_sizes.argtypes = [vp, i64p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -162,7 +163,8 @@ def _ptr(t):
 class FrDvm:
     """One handle of the library: a mesh, an FR order and a velocity grid."""
 
-    def __init__(self, mesh: dict, order: int, grid: dict, params: dict | None = None):
+    def __init__(self, mesh: dict, order: int, grid: dict, params: dict | None = None, nodes: int = 0):
+        """nodes: solution points per axis, 0 Gauss-Legendre, 1 Gauss-Lobatto."""
         L = lib()
         self._keep = {
             "nodes": np.ascontiguousarray(mesh["nodes"], np.float64),
@@ -186,7 +188,7 @@ class FrDvm:
             g.umin[d] = float(grid["umin"][d])
             g.umax[d] = float(grid["umax"][d])
         h = C.c_void_p()
-        rc = L.fr_dvm_create(C.byref(m), int(order), C.byref(g), C.byref(h))
+        rc = L.fr_dvm_create_nodes(C.byref(m), int(order), int(nodes), C.byref(g), C.byref(h))
         self._h = h
         if rc != 0:
             msg = self.last_error() if h.value else "invalid argument"
@@ -196,6 +198,7 @@ class FrDvm:
         L.fr_dvm_sizes(h, C.byref(ne), C.byref(ns), C.byref(nf), C.byref(nu), None)
         self.ne, self.ns, self.nf, self.nu = ne.value, ns.value, nf.value, nu.value
         self.order = int(order)
+        self.nodes = int(nodes)
         self.precision = FP64
         if params is not None:
             self.set_params(**params)
