@@ -279,6 +279,8 @@ template <typename Real, int P, int MODE>
 __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     constexpr int N = P + 1, NS = N * N * N, NFP = N * N;
     constexpr bool STAGE = MODE == GMODE_STAGE;
+    constexpr int CHF = NS <= 27 ? NS : 2 * NFP;  // values requested together
+    constexpr bool EARLY_X = STAGE && NS <= 27;
     __shared__ Real sf[NS][kGWave];
     __shared__ Real sa[NS][kGWave];
     __shared__ double sEb[STAGE ? NS * 8 : 1];
@@ -318,17 +320,26 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     const int64_t eoff = e * NS * nu;
     const uint32_t ko = (uint32_t)k * (uint32_t)sizeof(Real), k8 = (uint32_t)k * 8u;
     const Real *fe = reinterpret_cast<const Real *>(A.sa.f) + eoff;
-    // layer by layer: the layer's loads in flight together
+    // all of f (two layers at a time at p = 3) requested together
 #pragma unroll 1
-    for (int s0 = 0; s0 < NS; s0 += NFP) {
-        Real v[NFP];
+    for (int s0 = 0; s0 < NS; s0 += CHF) {
+        Real v[CHF];
 #pragma unroll
-        for (int r = 0; r < NFP; ++r) v[r] = ldo(fe + (s0 + r) * nu, ko);
+        for (int r = 0; r < CHF; ++r) v[r] = ldo(fe + (s0 + r) * nu, ko);
 #pragma unroll
-        for (int r = 0; r < NFP; ++r) {
+        for (int r = 0; r < CHF; ++r) {
             sf[s0 + r][lane] = v[r];
             sa[s0 + r][lane] = Real(0);
         }
+    }
+    // the second RK register of the stage, requested now (p <= 2) so that
+    // the FR work covers its latency
+    const bool useX = STAGE && (A.sa.scheme == 0 ? A.sa.alpha != 0.0 : A.sa.lsA != 0.0);
+    const Real *XE = (A.sa.scheme == 0 ? reinterpret_cast<const Real *>(A.sa.fn) : reinterpret_cast<const Real *>(A.sa.dF)) + eoff;
+    Real xe[EARLY_X ? NS : 1];
+    if constexpr (EARLY_X) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) xe[s] = useX ? ldo(XE + s * nu, ko) : Real(0);
     }
     // divergence of the transformed flux, scattered from each source point
 #pragma unroll 1
@@ -346,57 +357,64 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
             sa[spt<N>(i, j, r)][lane] += op.D[r * N + l] * F2;
         }
     }
-    // interface corrections
+    // interface corrections, axis by axis: the exterior values of both faces
+    // of an axis requested together, then the jumps
     const Real *tin = reinterpret_cast<const Real *>(A.sa.tr_in);
 #pragma unroll 1
-    for (int face = 0; face < 6; ++face) {
-        const int d = face / 2, side = face & 1;
-        const int32_t *c = A.conn + (e * 6 + face) * 4;
-        const int32_t nb = c[0], nface = c[1], orient = c[2], bc = c[3];
-        // the face's exterior values first (all its loads in flight at once)
-        Real un[NFP], ext[NFP];
-        const cptr<Real> nv = gN + face * NFP * 3;
+    for (int d = 0; d < 3; ++d) {
+        Real un[2][NFP], ext[2][NFP];
 #pragma unroll
-        for (int q = 0; q < NFP; ++q) un[q] = nv[3 * q] * u0 + nv[3 * q + 1] * u1 + nv[3 * q + 2] * u2;
-        if (nb >= 0) {
-            const Real *tn = tin + ((int64_t)nb * 6 + nface) * NFP * nu;
+        for (int side = 0; side < 2; ++side) {
+            const int face = 2 * d + side;
+            const int32_t *c = A.conn + (e * 6 + face) * 4;
+            const int32_t nb = c[0], nface = c[1], orient = c[2], bc = c[3];
+            const cptr<Real> nv = gN + face * NFP * 3;
 #pragma unroll
             for (int q = 0; q < NFP; ++q)
-                ext[q] = un[q] < Real(0) ? ldo(tn + nbr_point<N>(orient, q % N, q / N) * nu, ko) : Real(0);
-        } else if (bc == 1) {
-            const Real fi = (Real)ldo(A.finf, k8);
+                un[side][q] = nv[3 * q] * u0 + nv[3 * q + 1] * u1 + nv[3 * q + 2] * u2;
+            if (nb >= 0) {
+                const Real *tn = tin + ((int64_t)nb * 6 + nface) * NFP * nu;
 #pragma unroll
-            for (int q = 0; q < NFP; ++q) ext[q] = fi;
-        } else if (bc == 3) {
-            // specular: the own trace at the velocity mirrored in the face's
-            // axis (orient holds the axis)
-            const int str = orient == 0 ? 1 : (orient == 1 ? A.vg.nv[0] : A.vg.nv[0] * A.vg.nv[1]);
-            const int ia = orient == 0 ? iv[0] : (orient == 1 ? iv[1] : iv[2]);
-            const int km = k + (A.vg.nv[orient] - 1 - 2 * ia) * str;
-            const uint32_t kmo = (uint32_t)km * (uint32_t)sizeof(Real);
-            const Real *to = tin + (e * 6 + face) * NFP * nu;
+                for (int q = 0; q < NFP; ++q)
+                    ext[side][q] =
+                        un[side][q] < Real(0) ? ldo(tn + nbr_point<N>(orient, q % N, q / N) * nu, ko) : Real(0);
+            } else if (bc == 1) {
+                const Real fi = (Real)ldo(A.finf, k8);
 #pragma unroll
-            for (int q = 0; q < NFP; ++q) ext[q] = un[q] < Real(0) ? ldo(to + q * nu, kmo) : Real(0);
-        } else {
-            const double mw = ldo(A.mw, k8);
+                for (int q = 0; q < NFP; ++q) ext[side][q] = fi;
+            } else if (bc == 3) {
+                // specular: the own trace at the velocity mirrored in the
+                // face's axis (orient holds the axis)
+                const int str = orient == 0 ? 1 : (orient == 1 ? A.vg.nv[0] : A.vg.nv[0] * A.vg.nv[1]);
+                const int ia = orient == 0 ? iv[0] : (orient == 1 ? iv[1] : iv[2]);
+                const int km = k + (A.vg.nv[orient] - 1 - 2 * ia) * str;
+                const uint32_t kmo = (uint32_t)km * (uint32_t)sizeof(Real);
+                const Real *to = tin + (e * 6 + face) * NFP * nu;
 #pragma unroll
-            for (int q = 0; q < NFP; ++q) ext[q] = (Real)(A.rw[(e * 6 + face) * NFP + q] * mw);
-        }
+                for (int q = 0; q < NFP; ++q) ext[side][q] = un[side][q] < Real(0) ? ldo(to + q * nu, kmo) : Real(0);
+            } else {
+                const double mw = ldo(A.mw, k8);
 #pragma unroll
-        for (int q = 0; q < NFP; ++q) {
-            if (un[q] < Real(0)) {
-                const int a = q % N, b = q / N;
-                int pts[N];
-#pragma unroll
-                for (int m = 0; m < N; ++m) pts[m] = line_pt<N>(d, a, b, m);
-                Real fm = Real(0);
-#pragma unroll
-                for (int m = 0; m < N; ++m) fm += op.lam[side][m] * sf[pts[m]][lane];
-                const Real jump = un[q] * (ext[q] - fm);
-#pragma unroll
-                for (int m = 0; m < N; ++m) sa[pts[m]][lane] += op.corr[side][m] * jump;
+                for (int q = 0; q < NFP; ++q) ext[side][q] = (Real)(A.rw[(e * 6 + face) * NFP + q] * mw);
             }
         }
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int q = 0; q < NFP; ++q) {
+                if (un[side][q] < Real(0)) {
+                    const int a = q % N, b = q / N;
+                    int pts[N];
+#pragma unroll
+                    for (int m = 0; m < N; ++m) pts[m] = line_pt<N>(d, a, b, m);
+                    Real fm = Real(0);
+#pragma unroll
+                    for (int m = 0; m < N; ++m) fm += op.lam[side][m] * sf[pts[m]][lane];
+                    const Real jump = un[side][q] * (ext[side][q] - fm);
+#pragma unroll
+                    for (int m = 0; m < N; ++m) sa[pts[m]][lane] += op.corr[side][m] * jump;
+                }
+            }
     }
     if (MODE == GMODE_RESID) {
         Real *R = reinterpret_cast<Real *>(A.sa.fout) + eoff;
@@ -406,16 +424,15 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     }
     // collision source and the Runge-Kutta combination
     const Real dt = (Real)A.sa.dt;
-    const bool useX = A.sa.scheme == 0 ? A.sa.alpha != 0.0 : A.sa.lsA != 0.0;
-    const Real *XE = (A.sa.scheme == 0 ? reinterpret_cast<const Real *>(A.sa.fn) : reinterpret_cast<const Real *>(A.sa.dF)) + eoff;
     Real *outE = reinterpret_cast<Real *>(A.sa.fout) + eoff;
     Real *dFE = reinterpret_cast<Real *>(A.sa.dF) + eoff;
-#pragma unroll 1
+#pragma unroll
     for (int s0 = 0; s0 < NS; s0 += NFP) {
-        // the layer's second-register values requested together
+        // (p = 3) the layer's second-register values requested together
         Real xv[NFP];
 #pragma unroll
-        for (int r = 0; r < NFP; ++r) xv[r] = useX ? ldo(XE + (s0 + r) * nu, ko) : Real(0);
+        for (int r = 0; r < NFP; ++r)
+            xv[r] = EARLY_X ? xe[EARLY_X ? s0 + r : 0] : (useX ? ldo(XE + (s0 + r) * nu, ko) : Real(0));
 #pragma unroll
         for (int r = 0; r < NFP; ++r) {
             const int s = s0 + r;
