@@ -293,3 +293,37 @@ def test_cylinder_fullsize_mixed_step(cyl, F):
     assert (Q[..., 0] > 0).all().item()
     st = m.newton_stats()
     assert st["n_fallback"] == 0
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_general_single_element_all_farfield_one_velocity(F, orc, p):
+    """Edge case: one curved element whose six faces are all farfield, a
+    velocity grid of one node (one lane of one wave active)."""
+    mesh = W.quadratic_map_mesh(1, eps=0.1, bc_all=1)
+    grid = {"n": (1, 1, 1), "umin": (0.7, -0.4, 0.3), "umax": (0.7, -0.4, 0.3)}
+    par = _params(farfield=[1.2, 0.1, 0.0, 0.0, 1.0])
+    P = _oracle(orc, mesh, p, grid, par)
+    f = np.random.default_rng(p).uniform(0.5, 1.5, size=P.shape)
+    s = F.FrDvm(mesh, p, grid, par)
+    R = torch.zeros(s.shape, dtype=s.dtype, device="cuda")
+    s.residual(_gpu(s, f), R)
+    assert rel(R.cpu().numpy(), P.residual(f)) < 1e-12
+
+
+def test_general_wide_velocity_grid_ragged(F, orc):
+    """A velocity count far from a multiple of 64 (17 x 19 x 13 = 4199) on
+    the small O-grid with walls: residual and two FP64 ES steps."""
+    mesh = _small_cylinder()
+    grid = W.grid_spec((17, 19, 13), 6.0)
+    par = _params(model=1, prandtl=2.0 / 3.0, mu_ref=0.02)
+    P = _oracle(orc, mesh, 1, grid, par)
+    f0 = _state(P, grid, 12, amp=0.1)
+    s = F.FrDvm(mesh, 1, grid, par)
+    f = _gpu(s, f0)
+    R = torch.zeros_like(f)
+    s.residual(f, R)
+    assert rel(R.cpu().numpy(), P.residual(f0)) < 1e-12
+    dt = P.dt(0.2)
+    ref = P.rk_step(f0, dt, scheme=0, nsteps=1)
+    s.rk_steps(f, dt, 1)
+    assert rel(f.cpu().numpy(), ref) < 1e-12
