@@ -141,8 +141,8 @@ void fr_dvm_default_params(fr_dvm_params *p);
 int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out);
 
 /* fr_dvm_create with a choice of solution points per axis (Section
- * "Numerical method": the paper places Gauss-Lobatto points on tensor-product
- * elements): nodes FR_DVM_NODES_GAUSS (Gauss-Legendre, what fr_dvm_create
+ * "Implementation & problem setup": the paper places Gauss-Lobatto points on
+ * tensor-product elements): nodes FR_DVM_NODES_GAUSS (Gauss-Legendre, what fr_dvm_create
  * uses) or FR_DVM_NODES_LOBATTO (Gauss-Lobatto, order >= 1; points on the
  * element faces).  The correction functions recover nodal DG with the exact
  * mass matrix in both cases; moments' domain totals use the same rule's

@@ -8,7 +8,7 @@
 // at every flux point the upwind common flux F^I = u_n f- (u_n > 0) or
 // u_n f+ (otherwise), u_n = u . n with the area-scaled outward normal; the
 // jump F^I - u_n f- enters through the DG-recovering correction.  Exterior
-// states: the neighbour's trace, the freestream Maxwellian (farfield),
+// states (Section "Implementation & problem setup"): the neighbour's trace, the freestream Maxwellian (farfield),
 // rho_w M(0, theta_w) (diffuse wall at rest) with rho_w chosen so that no
 // mass crosses the wall, or the element's own trace at the mirrored velocity
 // (specular symmetry wall).  The collision source (g(Q') - f)/tau and the RK

@@ -327,3 +327,31 @@ def test_general_wide_velocity_grid_ragged(F, orc):
     ref = P.rk_step(f0, dt, scheme=0, nsteps=1)
     s.rk_steps(f, dt, 1)
     assert rel(f.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_half_cylinder_paper_units(F, orc, model):
+    """The paper's boundary set and units on curved elements: half O-grid
+    with a specular symmetry plane on the cut, diffuse wall at the
+    freestream temperature, farfield Maxwellian, Sutherland viscosity with
+    mu_ref = 1/Re and P = 1/(gamma M^2) (Mach 2, Re 500): residual and one
+    FP64 step against the oracle."""
+    mesh = W.cylinder_mesh(n_theta=6, n_r=3, n_z=1, r1=2.0, half=True)
+    grid = W.grid_spec((11, 12, 9), 2.5)
+    par = dict(_params(model=model, prandtl=2.0 / 3.0 if model else 1.0), **W.paper_freestream(2.0, 500.0, 10.0))
+    P = _oracle(orc, mesh, 2, grid, par)
+    th = par["theta_ref"]
+    prim = np.zeros(P.shape[:2] + (5,))
+    prim[..., 0] = 1.0 + 0.05 * np.random.default_rng(6).uniform(-1, 1, size=P.shape[:2])
+    prim[..., 1:4] = par["farfield"][1:4]
+    prim[..., 4] = th
+    f0 = W.maxwellian(prim, grid).numpy()
+    s = F.FrDvm(mesh, 2, grid, par)
+    f = _gpu(s, f0)
+    R = torch.zeros_like(f)
+    s.residual(f, R)
+    assert rel(R.cpu().numpy(), P.residual(f0)) < 1e-12
+    dt = P.dt(0.2)
+    ref = P.rk_step(f0, dt, scheme=0, nsteps=1)
+    s.rk_steps(f, dt, 1)
+    assert rel(f.cpu().numpy(), ref) < 1e-12

@@ -1,9 +1,10 @@
 """Pins of the oracle on general hexahedral meshes: curved (27-node)
 elements, element frames that differ across a face, and the two boundary
-conditions of the paper's external flows (Section "Numerical method": the
-farfield exterior is the freestream Maxwellian; the wall is diffuse and
-isothermal, its exterior a wall Maxwellian whose density makes the net mass
-flux through the wall vanish)."""
+conditions of the paper's external flows plus its symmetry plane (Section
+"Implementation & problem setup": the farfield exterior is the freestream
+Maxwellian; the wall is diffuse and isothermal, its exterior a wall
+Maxwellian whose density makes the net mass flux through the wall vanish;
+the symmetry plane reflects specularly)."""
 import math
 
 import numpy as np

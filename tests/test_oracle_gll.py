@@ -1,5 +1,6 @@
 """Pins of the oracle with Gauss-Lobatto solution points (the point set the
-paper uses on tensor-product elements, Section "Numerical method").  The
+paper uses on tensor-product elements, Section "Implementation & problem
+setup").  The
 correction functions are still the DG-recovering ones, so the scheme is
 nodal DG with the exact mass matrix on these points."""
 import numpy as np

@@ -78,20 +78,21 @@ def box_mesh(N, length=1.0, periodic=True) -> dict:
             "N": N, "length": L}
 
 
-def cylinder_mesh(n_theta=48, n_r=24, n_z=2, r0=0.5, r1=6.0, stretch=1.15, lz=0.25) -> dict:
+def cylinder_mesh(n_theta=48, n_r=24, n_z=2, r0=0.5, r1=6.0, stretch=1.15, lz=0.25, half=False) -> dict:
     """O-grid of 27-node (quadratic) hexes around a cylinder of radius r0 with
     axis z: xi_0 radial (element widths growing by ``stretch`` from the wall
     to r1), xi_1 azimuthal (mid-edge nodes on the arcs, so the faces are
     curved), xi_2 spanwise over [0, lz] (periodic).  Element (i, j, k) has id
     i + n_r (j + n_theta k).  Inner faces: diffuse wall (bc 2); outer faces:
-    farfield (bc 1)."""
+    farfield (bc 1).  ``half``: only the upper half (0 <= angle <= pi) with
+    specular symmetry walls (bc 3) on the cut y = 0."""
     g = stretch ** np.arange(n_r)
     edges = r0 + (r1 - r0) * np.concatenate([[0.0], np.cumsum(g)]) / g.sum()
     radii = np.empty(2 * n_r + 1)
     radii[0::2] = edges
     radii[1::2] = 0.5 * (edges[:-1] + edges[1:])
-    NR, NT, NZ = 2 * n_r + 1, 2 * n_theta, 2 * n_z + 1
-    th = 2 * np.pi * np.arange(NT) / NT
+    NR, NT, NZ = 2 * n_r + 1, 2 * n_theta + (1 if half else 0), 2 * n_z + 1
+    th = (np.pi * np.arange(NT) / (NT - 1)) if half else (2 * np.pi * np.arange(NT) / NT)
     zz = lz * np.arange(NZ) / (NZ - 1)
     R, T, Z = np.meshgrid(radii, th, zz, indexing="ij")
     nodes = np.stack([R * np.cos(T), R * np.sin(T), Z], -1).transpose(2, 1, 0, 3).reshape(-1, 3)
@@ -117,8 +118,14 @@ def cylinder_mesh(n_theta=48, n_r=24, n_z=2, r0=0.5, r1=6.0, stretch=1.15, lz=0.
                     nbr[e, 1] = e + 1
                 else:
                     bc[e, 1] = 1
-                nbr[e, 2] = i + n_r * ((j - 1) % n_theta + n_theta * k)
-                nbr[e, 3] = i + n_r * ((j + 1) % n_theta + n_theta * k)
+                if half and j == 0:
+                    bc[e, 2] = 3
+                else:
+                    nbr[e, 2] = i + n_r * ((j - 1) % n_theta + n_theta * k)
+                if half and j == n_theta - 1:
+                    bc[e, 3] = 3
+                else:
+                    nbr[e, 3] = i + n_r * ((j + 1) % n_theta + n_theta * k)
                 nbr[e, 4] = i + n_r * (j + n_theta * ((k - 1) % n_z))
                 nbr[e, 5] = i + n_r * (j + n_theta * ((k + 1) % n_z))
                 for f in range(6):
@@ -495,6 +502,18 @@ def workload(name: str) -> dict:
     if w.get("ic") == "uniform":
         w["farfield"] = [1.0, w["mach"] * math.sqrt(5.0 / 3.0), 0.0, 0.0, 1.0]
     return w
+
+
+def paper_freestream(mach: float, reynolds: float, alpha_deg: float = 0.0, t_inf_kelvin: float = 203.0,
+                     gamma: float = 5.0 / 3.0) -> dict:
+    """Physics parameters in the paper's freestream units (unit density and
+    speed, P = 1/(gamma M^2), mu_ref = 1/Re at theta_ref = P, Sutherland
+    temperature 110.4 K scaled by the freestream temperature, wall at the
+    freestream temperature, farfield = the freestream Maxwellian)."""
+    th = 1.0 / (gamma * mach * mach)
+    a = math.radians(alpha_deg)
+    return {"mu_ref": 1.0 / reynolds, "theta_ref": th, "visc_law": 1, "theta_s": th * 110.4 / t_inf_kelvin,
+            "farfield": [1.0, math.cos(a), math.sin(a), 0.0, th], "theta_wall": th}
 
 
 def workload_mesh(w: dict) -> dict:
