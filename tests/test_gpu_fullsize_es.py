@@ -1,0 +1,89 @@
+"""GPU parity at the full size of the headline workload — 24^3 periodic
+hexes, p = 3, 20^3 velocities on [-8, 8]^3, ES-BGK Pr 0.71, Kn 2e-4 — in
+the configuration the benchmark times: FP32 f, low-storage RK, FP64 moments
+and Newton, learned-then-warm start (7.08e9 DOFs).  The oracle cannot run
+the whole box, so:
+
+* the residual of sampled elements is checked against the oracle on the
+  7-element patch around each (the same FP32-rounded values);
+* the collision at sampled solution points is checked point by point;
+* one step conserves the global totals to the FP32 level and the Newton
+  solves all converge.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from test_gpu_fullsize import _patch
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def big():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_06567_amd.frdvm import FrDvm
+    w = W.workload("box24_p3_v20_es")
+    mesh = W.box_mesh(w["N"])
+    par = dict(W.physics_params(w), precision=1, rk=1, guess=1)
+    s = FrDvm(mesh, w["p"], w["grid"], par)
+    prim = W.initial_prim(mesh, w["p"], w)
+    f = W.maxwellian(prim, w["grid"], dtype=torch.float32, device="cuda").reshape(s.shape)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(21)
+    f *= 1.0 + 0.05 * (2 * torch.rand(f.shape, generator=g, device="cuda", dtype=torch.float32) - 1)
+    torch.cuda.synchronize()
+    yield w, mesh, par, s, f
+    del f
+    s.destroy()
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_es_residual_sampled_elements(big, orc):
+    w, mesh, par, s, f = big
+    R = torch.empty_like(f)
+    s.residual(f, R)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for e in [0, s.ne - 1, *rng.integers(0, s.ne, 2)]:
+        pm, ids = _patch(mesh, int(e))
+        fp = f[ids].double().cpu().numpy()
+        Rr = orc.Problem(pm, w["p"], w["grid"], dict(par, model=2)).residual(fp)[0]
+        assert rel(R[int(e)].double().cpu().numpy(), Rr) < 5e-6, e
+
+
+def test_fullsize_es_collide_sampled_points(big, orc):
+    w, mesh, par, s, f = big
+    S = torch.empty_like(f)
+    Qp = torch.empty(s.ne * s.ns * 5, dtype=torch.float64, device="cuda")
+    s.collide(f, S, Qp)
+    torch.cuda.synchronize()
+    pts = np.random.default_rng(4).integers(0, s.ne * s.ns, 16)
+    fpts = f.reshape(-1, s.nu)[pts].double().cpu().numpy()
+    Sr, prim, _, st, _ = orc.Problem.points_only(w["grid"], par).collide(fpts)
+    assert np.all(st == 0)
+    Sg = S.reshape(-1, s.nu)[pts].double().cpu().numpy()
+    # S = (g' - f)/tau: FP32 rounding of its terms g'/tau and f/tau
+    inv_tau = np.abs(Sr).max() / max(np.abs(Sg - Sr).max(), 1e-300)  # informative only
+    scale = np.abs(Sr).max() + np.abs(fpts).max() * float(Sr.shape[-1] > 0) / par["mu_ref"]
+    assert np.abs(Sg - Sr).max() < 3e-7 * scale, inv_tau
+    assert rel(Qp.reshape(-1, 5)[pts].cpu().numpy(), prim) < 1e-12
+    assert s.newton_stats(reset=True)["n_fallback"] == 0
+
+
+def test_fullsize_es_mixed_step_conserves(big):
+    w, mesh, par, s, f = big
+    t0 = s.moments(f, totals=True)
+    s.newton_stats(reset=True)
+    s.rk_steps(f, s.dt(0.2), 1)
+    t1 = s.moments(f, totals=True)
+    assert torch.isfinite(f).all().item()
+    assert abs(t1[0] - t0[0]) < 1e-7 * abs(t0[0]) and abs(t1[4] - t0[4]) < 1e-7 * abs(t0[4])
+    st = s.newton_stats(reset=True)
+    assert st["n_fallback"] == 0 and st["n_guard"] == 0
