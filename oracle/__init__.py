@@ -59,7 +59,7 @@ class _Problem(C.Structure):
                 ("theta_ref", C.c_double), ("omega", C.c_double),
                 ("visc_law", C.c_int32), ("theta_s", C.c_double),
                 ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32), ("nv", C.c_int32 * 3),
-                ("nodes", C.c_int32)]
+                ("nodes", C.c_int32), ("delta", C.c_double), ("ncomp", C.c_int32)]
 
 
 def _declare(L):
@@ -80,6 +80,7 @@ def _declare(L):
     L.orc_rhs.argtypes = [P, _dp, _dp]
     L.orc_rk_step.argtypes = [P, _dp, C.c_double, C.c_int, C.c_int]
     L.orc_totals.argtypes = [P, _dp, _dp]
+    L.orc_state_moments.argtypes = [P, C.c_int64, _dp, _dp]
     L.orc_kn_gll.argtypes = [P, _dp, _dp]
     L.orc_dt.argtypes = [P, C.c_double]
     L.orc_dt.restype = C.c_double
@@ -183,6 +184,8 @@ class Problem:
         self.ne = int(mesh["n_elem"])
         self.u, self.w = vgrid(grid["n"], grid["umin"], grid["umax"])
         self.nu = self.u.shape[0]
+        self.delta = float(params.get("delta", 0.0))
+        self.ncomp = 2 if self.delta > 0 else 1
         self.nodes = int(params.get("nodes", 0))
         self.geo = geometry(mesh, p, self.nodes)
         self.nbr_elem = np.ascontiguousarray(mesh["nbr_elem"], dtype=np.int32)
@@ -191,7 +194,8 @@ class Problem:
         self.bc = np.ascontiguousarray(mesh["bc"], dtype=np.int8)
         self.params = dict(params)
         fi = params.get("f_inf")
-        self.f_inf = _f64(fi) if fi is not None else np.zeros(self.nu)
+        self.f_inf = _f64(fi) if fi is not None else np.zeros(self.nu * self.ncomp)
+        assert self.f_inf.size == self.nu * self.ncomp
         s = _Problem()
         s.ne, s.p, s.nu = self.ne, p, self.nu
         s.u, s.w = _d(self.u), _d(self.w)
@@ -214,11 +218,13 @@ class Problem:
         for d in range(3):
             s.nv[d] = int(grid["n"][d])
         s.nodes = self.nodes
+        s.delta = self.delta
+        s.ncomp = self.ncomp
         self._s = s
 
     @property
     def shape(self):
-        return (self.ne, self.ns, self.nu)
+        return (self.ne, self.ns, self.nu * self.ncomp)
 
     def residual(self, f):
         f = _f64(f).reshape(self.shape)
@@ -233,8 +239,9 @@ class Problem:
         Returns S, prim' = (rho', U', theta'), z, status, iterations."""
         f = _f64(f)
         sh = f.shape[:-1]
-        assert f.shape[-1] == self.nu
-        npts = f.size // self.nu
+        nut = self.nu * self.ncomp
+        assert f.shape[-1] == nut
+        npts = f.size // nut
         S = np.zeros(f.shape)
         prim, z = np.zeros((npts, 5)), np.zeros((npts, 5))
         st, it = np.zeros(npts, np.int32), np.zeros(npts, np.int32)
@@ -256,7 +263,12 @@ class Problem:
         return f
 
     def moments(self, f):
-        return moments(_f64(f).reshape(self.shape), self.u, self.w)
+        """(rho, rho U, E) per point; E includes the integral of G for the
+        reduced pair."""
+        f = _f64(f).reshape(self.shape)
+        Q = np.zeros(self.shape[:2] + (5,))
+        lib().orc_state_moments(C.byref(self._s), self.ne * self.ns, _d(f), _d(Q))
+        return Q
 
     def kn_gll(self, f):
         """Density gradient-length local Knudsen number at every solution

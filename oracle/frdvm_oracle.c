@@ -331,6 +331,8 @@ typedef struct {
     int32_t newton_max_iter;
     int32_t nv[3];           /* velocity nodes per axis, k = i + nv0 (j + nv1 l) */
     int32_t nodes;           /* solution points: 0 Gauss-Legendre, 1 Gauss-Lobatto */
+    double delta;            /* internal degrees of freedom; > 0: the reduced pair (F, G) */
+    int32_t ncomp;           /* 1 (monatomic f) or 2 (F then G per point, each nu values) */
 } orc_problem;
 
 /* Neighbour face point for own face point (a,b) under orientation code o:
@@ -357,19 +359,24 @@ static void orient_map(int n, int o, int a, int b, int *pa, int *pb) {
  * specular wall: the interior trace at the mirrored velocity.
  */
 int orc_residual(const orc_problem *P, const double *f, double *R) {
-    int n = P->p + 1, ns = n * n * n, nfp = n * n, nu = P->nu;
+    int n = P->p + 1, ns = n * n * n, nfp = n * n, nu = P->nu, nut = nu * P->ncomp;
     double xi[16], D[256], lam[2][16], cv[2][16];
     if (orc_fr_ops_set(P->p, P->nodes, xi, D, lam[0], lam[1], cv[0], cv[1]) != ORC_OK) return ORC_EINVAL;
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
     for (int e = 0; e < P->ne; ++e) {
-        double *acc = (double *)calloc((size_t)ns * nu, sizeof(double));
+        double *acc = (double *)calloc((size_t)ns * nut, sizeof(double));
+        ld rwall[6 * 256];
         double *Ft = (double *)malloc((size_t)3 * ns * sizeof(double));
         double *fm = (double *)malloc((size_t)nu * sizeof(double));
         double *fp = (double *)malloc((size_t)nu * sizeof(double));
         double *un = (double *)malloc((size_t)nu * sizeof(double));
         if (!acc || !Ft || !fm || !fp || !un) { bad++; free(acc); free(Ft); free(fm); free(fp); free(un); continue; }
-        const double *fe = f + (int64_t)e * ns * nu;
+        const double *fe = f + (int64_t)e * ns * nut;
+        /* every component (F, and G for the reduced pair) is advected alike;
+         * kc runs over the state, k over the velocity nodes */
+        for (int comp = 0; comp < P->ncomp; ++comp) {
+        const int co = comp * nu;
         /* divergence of the transformed discontinuous flux */
         for (int k = 0; k < nu; ++k) {
             const double *uk = P->u + 3 * k;
@@ -377,7 +384,7 @@ int orc_residual(const orc_problem *P, const double *f, double *R) {
                 const double *Sm = P->S + ((int64_t)e * ns + s) * 9;
                 for (int d = 0; d < 3; ++d)
                     Ft[d * ns + s] = (Sm[3 * d] * uk[0] + Sm[3 * d + 1] * uk[1] + Sm[3 * d + 2] * uk[2]) *
-                                     fe[(int64_t)s * nu + k];
+                                     fe[(int64_t)s * nut + co + k];
             }
             for (int l = 0; l < n; ++l)
                 for (int j = 0; j < n; ++j)
@@ -388,7 +395,7 @@ int orc_residual(const orc_problem *P, const double *f, double *R) {
                             dv += (ld)D[j * n + m] * Ft[1 * ns + sidx(n, i, m, l)];
                             dv += (ld)D[l * n + m] * Ft[2 * ns + sidx(n, i, j, m)];
                         }
-                        acc[(int64_t)sidx(n, i, j, l) * nu + k] = (double)dv;
+                        acc[(int64_t)sidx(n, i, j, l) * nut + co + k] = (double)dv;
                     }
         }
         /* interface corrections, face by face */
@@ -402,7 +409,7 @@ int orc_residual(const orc_problem *P, const double *f, double *R) {
                         const double *uk = P->u + 3 * k;
                         ld t = 0;
                         for (int m = 0; m < n; ++m)
-                            t += (ld)lam[side][m] * fe[(int64_t)line_idx(n, d, a, b, m) * nu + k];
+                            t += (ld)lam[side][m] * fe[(int64_t)line_idx(n, d, a, b, m) * nut + co + k];
                         fm[k] = (double)t;
                         un[k] = uk[0] * nv[0] + uk[1] * nv[1] + uk[2] * nv[2];
                     }
@@ -410,30 +417,38 @@ int orc_residual(const orc_problem *P, const double *f, double *R) {
                         int nface = P->nbr_face[e * 6 + face];
                         int nd = nface / 2, nside = nface % 2, pa, pb;
                         orient_map(n, P->nbr_orient[e * 6 + face], a, b, &pa, &pb);
-                        const double *fn = f + (int64_t)nb * ns * nu;
+                        const double *fn = f + (int64_t)nb * ns * nut;
                         for (int k = 0; k < nu; ++k) {
                             ld t = 0;
                             for (int m = 0; m < n; ++m)
-                                t += (ld)lam[nside][m] * fn[(int64_t)line_idx(n, nd, pa, pb, m) * nu + k];
+                                t += (ld)lam[nside][m] * fn[(int64_t)line_idx(n, nd, pa, pb, m) * nut + co + k];
                             fp[k] = (double)t;
                         }
                     } else if (P->bc[e * 6 + face] == 1) {
-                        for (int k = 0; k < nu; ++k) fp[k] = P->f_inf[k];
+                        for (int k = 0; k < nu; ++k) fp[k] = P->f_inf[co + k];
                     } else if (P->bc[e * 6 + face] == 2) {
                         /* diffuse isothermal wall, wall at rest: the exterior
                          * state is rho_w M(0, theta_w) with rho_w set so that
                          * the net mass flux through the wall vanishes */
                         ld out = 0, in = 0, tw = P->theta_w;
                         ld c0 = powl(2.0L * 3.14159265358979323846264338327950288L * tw, -1.5L);
-                        for (int k = 0; k < nu; ++k) {
-                            const double *uk = P->u + 3 * k;
-                            if (un[k] > 0) out += (ld)P->w[k] * un[k] * fm[k];
-                            else {
-                                ld uu = (ld)uk[0] * uk[0] + (ld)uk[1] * uk[1] + (ld)uk[2] * uk[2];
-                                in += (ld)P->w[k] * (-(ld)un[k]) * c0 * expl(-uu / (2 * tw));
+                        ld rw;
+                        if (comp == 0) {
+                            for (int k = 0; k < nu; ++k) {
+                                const double *uk = P->u + 3 * k;
+                                if (un[k] > 0) out += (ld)P->w[k] * un[k] * fm[k];
+                                else {
+                                    ld uu = (ld)uk[0] * uk[0] + (ld)uk[1] * uk[1] + (ld)uk[2] * uk[2];
+                                    in += (ld)P->w[k] * (-(ld)un[k]) * c0 * expl(-uu / (2 * tw));
+                                }
                             }
+                            rw = in > 0 ? out / in : 0;
+                            rwall[face * nfp + a + n * b] = rw;
+                        } else {
+                            /* G: the mass flux of F sets the wall density; the
+                             * wall emits delta theta_w / 2 times the F state */
+                            rw = rwall[face * nfp + a + n * b] * 0.5L * P->delta * tw;
                         }
-                        ld rw = in > 0 ? out / in : 0;
                         for (int k = 0; k < nu; ++k) {
                             const double *uk = P->u + 3 * k;
                             ld uu = (ld)uk[0] * uk[0] + (ld)uk[1] * uk[1] + (ld)uk[2] * uk[2];
@@ -473,14 +488,15 @@ int orc_residual(const orc_problem *P, const double *f, double *R) {
                         double fup = un[k] > 0 ? fm[k] : fp[k];
                         double jump = un[k] * fup - un[k] * fm[k];
                         for (int m = 0; m < n; ++m)
-                            acc[(int64_t)line_idx(n, d, a, b, m) * nu + k] += cv[side][m] * jump;
+                            acc[(int64_t)line_idx(n, d, a, b, m) * nut + co + k] += cv[side][m] * jump;
                     }
                 }
         }
+        } /* components */
         for (int s = 0; s < ns; ++s) {
             double dj = P->detJ[(int64_t)e * ns + s];
-            for (int k = 0; k < nu; ++k)
-                R[((int64_t)e * ns + s) * nu + k] = -acc[(int64_t)s * nu + k] / dj;
+            for (int k = 0; k < nut; ++k)
+                R[((int64_t)e * ns + s) * nut + k] = -acc[(int64_t)s * nut + k] / dj;
         }
         free(acc); free(Ft); free(fm); free(fp); free(un);
     }
@@ -696,11 +712,40 @@ static ld normi(const ld r[5]) {
  * Outputs g[nu], tau, prim[5] = (rho', U', theta') of g' (theta' = theta/z4),
  * zout[5], iterations; returns a status code.
  */
+/* Moments of the state at one point: (rho, rho U, E) with E the total energy
+ * (for the reduced pair: the translational energy of F plus the integral of
+ * G, Section "Governing equations"). */
+static void state_moments(const orc_problem *P, const double *f, ld Q[5]) {
+    point_moments(P->nu, P->u, P->w, f, Q);
+    if (P->ncomp == 2)
+        for (int k = 0; k < P->nu; ++k) Q[4] += (ld)P->w[k] * f[P->nu + k];
+}
+
+/* State moments [npts][5] of states with P's layout (F, or F then G). */
+int orc_state_moments(const orc_problem *P, int64_t npts, const double *f, double *Q) {
+    int64_t nut = (int64_t)P->nu * P->ncomp;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < npts; ++i) {
+        ld q[5];
+        state_moments(P, f + i * nut, q);
+        for (int a = 0; a < 5; ++a) Q[5 * i + a] = (double)q[a];
+    }
+    return ORC_OK;
+}
+
+/* Temperature of a state with moments Q: E - rho |U|^2 / 2 = (3 + delta)/2 rho theta. */
+static ld state_theta(const orc_problem *P, const ld Q[5]) {
+    ld rho = Q[0], U[3] = {Q[1] / rho, Q[2] / rho, Q[3] / rho};
+    ld dof = 3.0L + (P->ncomp == 2 ? (ld)P->delta : 0.0L);
+    return (2.0L / dof) * (Q[4] / rho - 0.5L * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
+}
+
 static int point_equilibrium(const orc_problem *P, const double *f, double *g, double *tau,
-                             double prim[5], double zout[5], int *iters) {
+                             double prim[5], double zout[5], int *iters, double *theta_eq) {
     int nu = P->nu;
     ld Q[5];
-    point_moments(nu, P->u, P->w, f, Q);
+    state_moments(P, f, Q);
+    *theta_eq = 0.0;
     ld rho = Q[0];
     *iters = 0;
     if (!(rho > 0) || !isfinite((double)rho)) {
@@ -710,7 +755,7 @@ static int point_equilibrium(const orc_problem *P, const double *f, double *g, d
         return ORC_NEWTON_NONREAL;
     }
     ld U[3] = {Q[1] / rho, Q[2] / rho, Q[3] / rho};
-    ld theta = (2.0L / 3.0L) * (Q[4] / rho - 0.5L * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
+    ld theta = state_theta(P, Q);
     if (!(theta > 0) || !isfinite((double)theta)) {
         for (int k = 0; k < nu; ++k) g[k] = f[k];
         *tau = 1.0;
@@ -718,6 +763,7 @@ static int point_equilibrium(const orc_problem *P, const double *f, double *g, d
         return ORC_NEWTON_NONREAL;
     }
     int status = ORC_NEWTON_OK;
+    *theta_eq = (double)theta;
     double Pr = (P->model == 1) ? P->Pr : 1.0;
     double mu = orc_viscosity((double)theta, P->mu_ref, P->theta_ref, P->omega, P->visc_law, P->theta_s);
     *tau = mu / (Pr * (double)(rho * theta));
@@ -836,9 +882,9 @@ static int point_equilibrium(const orc_problem *P, const double *f, double *g, d
  */
 int orc_collide(const orc_problem *P, int64_t npts, const double *f, double *S,
                 double *prim, double *zpar, int32_t *status, int32_t *iters) {
-    int nu = P->nu;
+    int nu = P->nu, nut = nu * P->ncomp;
     if (P->model == 2) { /* collisionless: no source */
-        memset(S, 0, sizeof(double) * (size_t)npts * nu);
+        memset(S, 0, sizeof(double) * (size_t)npts * nut);
         if (prim) memset(prim, 0, sizeof(double) * 5 * (size_t)npts);
         if (zpar) memset(zpar, 0, sizeof(double) * 5 * (size_t)npts);
         if (status) memset(status, 0, sizeof(int32_t) * (size_t)npts);
@@ -848,10 +894,14 @@ int orc_collide(const orc_problem *P, int64_t npts, const double *f, double *S,
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < npts; ++i) {
         double *g = (double *)malloc(sizeof(double) * nu);
-        double tau, pr[5], zz[5];
+        double tau, pr[5], zz[5], th;
         int it;
-        int st = point_equilibrium(P, f + i * nu, g, &tau, pr, zz, &it);
-        for (int k = 0; k < nu; ++k) S[i * nu + k] = (g[k] - f[i * nu + k]) / tau;
+        const double *fi = f + i * nut;
+        int st = point_equilibrium(P, fi, g, &tau, pr, zz, &it, &th);
+        for (int k = 0; k < nu; ++k) S[i * nut + k] = (g[k] - fi[k]) / tau;
+        /* G relaxes to delta theta / 2 times the equilibrium of F */
+        for (int k = 0; k < nut - nu; ++k)
+            S[i * nut + nu + k] = st == ORC_NEWTON_NONREAL ? 0.0 : (0.5 * P->delta * th * g[k] - fi[nu + k]) / tau;
         if (prim) for (int a = 0; a < 5; ++a) prim[5 * i + a] = pr[a];
         if (zpar) for (int a = 0; a < 5; ++a) zpar[5 * i + a] = zz[a];
         if (status) status[i] = st;
@@ -869,7 +919,7 @@ int orc_collide(const orc_problem *P, int64_t npts, const double *f, double *S,
  * advection per velocity node with the collision as nonlinear source). */
 int orc_rhs(const orc_problem *P, const double *f, double *L) {
     int n = P->p + 1, ns = n * n * n;
-    int64_t npts = (int64_t)P->ne * ns, tot = npts * P->nu;
+    int64_t npts = (int64_t)P->ne * ns, tot = npts * P->nu * P->ncomp;
     double *S = (double *)malloc(sizeof(double) * tot);
     if (!S) return ORC_ENOMEM;
     int rc = orc_residual(P, f, L);
@@ -891,7 +941,7 @@ int orc_rhs(const orc_problem *P, const double *f, double *L) {
  */
 int orc_rk_step(const orc_problem *P, double *f, double dt, int scheme, int nsteps) {
     int n = P->p + 1, ns = n * n * n;
-    int64_t tot = (int64_t)P->ne * ns * P->nu;
+    int64_t tot = (int64_t)P->ne * ns * P->nu * P->ncomp;
     double *a = (double *)malloc(sizeof(double) * tot);
     double *b = (double *)malloc(sizeof(double) * tot);
     if (!a || !b) { free(a); free(b); return ORC_ENOMEM; }
@@ -933,7 +983,7 @@ int orc_totals(const orc_problem *P, const double *f, double *tot) {
     int64_t npts = (int64_t)P->ne * ns;
     double *Q = (double *)malloc(sizeof(double) * 5 * npts);
     if (!Q) return ORC_ENOMEM;
-    orc_moments(npts, P->nu, P->u, P->w, f, Q);
+    orc_state_moments(P, npts, f, Q);
     ld t[5] = {0, 0, 0, 0, 0};
     for (int64_t e = 0; e < P->ne; ++e)
         for (int l = 0; l < n; ++l)
@@ -984,7 +1034,7 @@ int orc_kn_gll(const orc_problem *P, const double *f, double *kn) {
     for (int e = 0; e < P->ne; ++e) {
         ld Q[729][5];  /* ns <= 9^3 */
         for (int s = 0; s < ns; ++s)
-            point_moments(nu, P->u, P->w, f + ((int64_t)e * ns + s) * nu, Q[s]);
+            state_moments(P, f + ((int64_t)e * ns + s) * nu * P->ncomp, Q[s]);
         for (int l = 0; l < n; ++l)
             for (int j = 0; j < n; ++j)
                 for (int i = 0; i < n; ++i) {
@@ -1004,8 +1054,7 @@ int orc_kn_gll(const orc_problem *P, const double *f, double *kn) {
                         g2 += gc * gc;
                     }
                     ld rho = Q[s][0];
-                    ld ux = Q[s][1] / rho, uy = Q[s][2] / rho, uz = Q[s][3] / rho;
-                    ld th = (2.0L / 3.0L) * (Q[s][4] / rho - 0.5L * (ux * ux + uy * uy + uz * uz));
+                    ld th = state_theta(P, Q[s]);
                     double out = 0.0;
                     if (rho > 0 && th > 0) {
                         ld mu = orc_viscosity((double)th, P->mu_ref, P->theta_ref, P->omega, P->visc_law,

@@ -99,3 +99,26 @@ def test_fullsize_step_conserves(big):
     scale = np.abs(t0).max()
     assert np.abs(t1 - t0).max() < 1e-12 * scale
     assert torch.isfinite(f).all().item()
+
+
+def test_fullsize_fp32_residual_and_step(big, orc):
+    """The same box with FP32 storage and arithmetic of f (FP64 moments and
+    Newton): sampled residuals against the oracle on the FP32-rounded
+    values, and one step conserving mass and energy to the FP32 level."""
+    from paper_2312_06567_amd.frdvm import FrDvm
+    w, mesh, par, s64, f64 = big
+    s = FrDvm(mesh, w["p"], w["grid"], dict(par, precision=1))
+    f = f64.float()
+    R = torch.empty_like(f)
+    s.residual(f, R)
+    torch.cuda.synchronize()
+    for e in [1, s.ne // 2]:
+        pm, ids = _patch(mesh, e)
+        Rr = orc.Problem(pm, w["p"], w["grid"], dict(par, model=2)).residual(f[ids].double().cpu().numpy())[0]
+        assert rel(R[e].double().cpu().numpy(), Rr) < 5e-6, e
+    del R
+    t0 = s.moments(f, totals=True)
+    s.rk_step(f, s.dt(0.2))
+    t1 = s.moments(f, totals=True)
+    assert abs(t1[0] - t0[0]) < 1e-7 * abs(t0[0]) and abs(t1[4] - t0[4]) < 1e-7 * abs(t0[4])
+    s.destroy()
