@@ -152,6 +152,21 @@ int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, 
 int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes, const fr_dvm_vgrid *grid,
                         fr_dvm_t *out);
 
+/* fr_dvm_create_nodes for a gas with delta >= 0 internal degrees of freedom
+ * (Section "Governing equations", the reduced distribution pair).  delta > 0:
+ * the state is the pair (F, G), every state buffer (f, R, S, the RK
+ * register) holds per solution point F then G, nu values each
+ * ([e][s][2][k]); F and G are advected alike and relax with the same tau to
+ * g and delta theta / 2 g; theta follows from E - rho |U|^2 / 2 =
+ * (3 + delta)/2 rho theta with E the translational energy of F plus the
+ * integral of G; moments report that total E.  Walls emit delta theta_w / 2
+ * times their F state as G, the farfield G is delta theta_inf / 2 times the
+ * farfield F.  The pair runs on the general path; the learned Newton start
+ * is replaced by the cold start.  delta = 0 is fr_dvm_create_nodes.
+ * FR_DVM_EINVAL for delta < 0 or not finite. */
+int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, double delta,
+                      const fr_dvm_vgrid *grid, fr_dvm_t *out);
+
 /* Set physics / precision / solver parameters; allocates the work buffers
  * of the chosen precision.  Must be called before any compute call. */
 int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p);

@@ -79,7 +79,7 @@ extern "C" int fr_dvm_collide(fr_dvm_t h, const void *f, void *S, double *Qp, in
     if (h->prm.model == FR_DVM_FREE) {
         if (!accumulate) {
             size_t es = h->prm.precision == FR_DVM_FP64 ? sizeof(double) : sizeof(float);
-            if (hipMemsetAsync(S, 0, es * h->ne * h->ns * h->vg.nu, h->stream) != hipSuccess)
+            if (hipMemsetAsync(S, 0, es * h->ne * h->ns * h->vg.nu * h->ncomp, h->stream) != hipSuccess)
                 return h->fail(FR_DVM_EHIP, "memset");
         }
         if (Qp && hipMemsetAsync(Qp, 0, sizeof(double) * 5 * h->ne * h->ns, h->stream) != hipSuccess)

@@ -66,6 +66,8 @@ struct fr_dvm {
     // discretisation
     int p = 0, n = 0, ns = 0, nfp = 0;
     int nodes = 0;  // solution points: 0 Gauss-Legendre, 1 Gauss-Lobatto
+    double delta = 0;  // internal degrees of freedom of the gas
+    int ncomp = 1;     // 1: f; 2: the reduced pair (F, G), per point F then G (nu values each)
     int64_t ne = 0;
     frdvm::VGrid vg{};
     std::vector<double> wax[3];  // 1-D trapezoid weights per axis
@@ -90,7 +92,8 @@ struct fr_dvm {
     int64_t nwall = 0;
     double *d_rw = nullptr;      // [ne*6][nfp] wall-Maxwellian density of the current stage
     double *d_mw = nullptr;      // [nu] unit-density wall Maxwellian at theta_wall
-    double *d_finf = nullptr;    // [nu] farfield Maxwellian
+    double *d_finf = nullptr;    // [ncomp * nu] farfield Maxwellian (and its G)
+    double *d_gfp = nullptr;     // [ne*ns] delta theta / 2 of each point (the pair's G equilibrium factor)
     int32_t *d_nbr = nullptr;    // [ne][6]
     double *d_wq3J = nullptr;    // [ne*ns] Gauss weight x |J| per solution point
     double *d_wx3 = nullptr;     // [nv_x][3] moment weights along x: w, w u_x, w u_x^2

@@ -50,7 +50,10 @@ struct GenArgs {
     GOps<float> of;
     GOps<double> od;
     VGrid vg;
-    int nu, nvb, nvw;  // velocities; blocks of 256 and of 64 velocities per element
+    int nu, nut, ncomp;  // velocities; state values per point (ncomp components of nu)
+    int nvb, nvw;        // blocks of 256 and of 64 state values per element
+    double gwall;        // the pair's G wall factor delta theta_w / 2
+    const double *gfp;   // [npts] the pair's G equilibrium factor delta theta / 2
     const double *wax;   // [3][64] 1-D trapezoid weights
     const double *S;     // [ne][ns][3][3]
     const double *ijac;  // [ne][ns]
@@ -141,8 +144,8 @@ __global__ __launch_bounds__(kGBlock) void k_gen_traces(const GenArgs A, const R
     constexpr int N = P + 1, NS = N * N * N, NFP = N * N;
     const int64_t e = blockIdx.x / A.nvb;
     const int k = (int)(blockIdx.x % A.nvb) * kGBlock + threadIdx.x;
-    if (k >= A.nu) return;
-    const int64_t nu = A.nu;
+    if (k >= A.nut) return;
+    const int64_t nu = A.nut;  // stride of a solution point
     const GOps<Real> &op = gops<Real>(A);
     const uint32_t ko = (uint32_t)k * (uint32_t)sizeof(Real);
     const Real *fe = f + e * NS * nu;
@@ -165,17 +168,26 @@ __global__ __launch_bounds__(kGBlock) void k_gen_traces(const GenArgs A, const R
     }
 }
 
+// k runs over the state of a point: F (k < nu), then the pair's G, which
+// adds only its integral (last slot of the record).
 template <int NMOM>
 __device__ __forceinline__ void moment_add(const GenArgs &A, int k, double fv, double M[NMOM]) {
     int iv[3];
-    split_k(A.vg, k, iv);
+    const bool g = k >= A.nu;
+    split_k(A.vg, g ? k - A.nu : k, iv);
     const double x = fv * (A.wax[iv[0]] * A.wax[64 + iv[1]] * A.wax[128 + iv[2]]);
+    if constexpr (NMOM == 6 || NMOM == 11) {
+        if (g) {
+            M[NMOM - 1] += x;
+            return;
+        }
+    }
     const double ux = node_u(A.vg, 0, iv[0]), uy = node_u(A.vg, 1, iv[1]), uz = node_u(A.vg, 2, iv[2]);
     M[0] += x;
     M[1] += x * ux;
     M[2] += x * uy;
     M[3] += x * uz;
-    if constexpr (NMOM == 5) {
+    if constexpr (NMOM == 5 || NMOM == 6) {
         M[4] += 0.5 * x * (ux * ux + uy * uy + uz * uz);
     } else {
         M[4] += x * ux * ux;
@@ -195,20 +207,20 @@ __global__ __launch_bounds__(kGBlock) void k_gen_moments(const GenArgs A, const 
                                                           double *__restrict__ Q) {
     __shared__ double red[kGBlock / 64][NMOM];
     const int64_t pt = blockIdx.x;
-    const Real *fp = f + pt * A.nu;
+    const Real *fp = f + pt * A.nut;
     double M[NMOM];
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
     // four values per lane requested at once, then accumulated in order
     int k0 = threadIdx.x;
-    for (; k0 + 3 * kGBlock < A.nu; k0 += 4 * kGBlock) {
+    for (; k0 + 3 * kGBlock < A.nut; k0 += 4 * kGBlock) {
         Real v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = fp[k0 + r * kGBlock];
 #pragma unroll
         for (int r = 0; r < 4; ++r) moment_add<NMOM>(A, k0 + r * kGBlock, (double)v[r], M);
     }
-    for (int k = k0; k < A.nu; k += kGBlock) moment_add<NMOM>(A, k, (double)fp[k], M);
+    for (int k = k0; k < A.nut; k += kGBlock) moment_add<NMOM>(A, k, (double)fp[k], M);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) {
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(kGBlock) void k_gen_wall(const GenArgs A, const Rea
     const int fp = blockIdx.x % NFP;
     const double *nv = A.nf + (fid * NFP + fp) * 3;
     const double n0 = nv[0], n1 = nv[1], n2 = nv[2];
-    const Real *t = tr + (fid * NFP + fp) * (int64_t)A.nu;
+    const Real *t = tr + (fid * NFP + fp) * (int64_t)A.nut;  // F part of the trace
     double out = 0.0, in = 0.0;
     for (int k = threadIdx.x; k < A.nu; k += kGBlock) {
         int iv[3];
@@ -285,6 +297,7 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     __shared__ Real sa[NS][kGWave];
     __shared__ double sEb[STAGE ? NS * 8 : 1];
     __shared__ double sEv[STAGE ? NS * 3 : 1];
+    __shared__ double sLg[STAGE ? NS : 1];  // log of the pair's G factor per point
     const int64_t e = blockIdx.x / A.nvw;
     const int lane = threadIdx.x;
     const int k = (int)(blockIdx.x % A.nvw) * kGWave + lane;
@@ -304,21 +317,24 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
             sEv[s * 3] = q[EQ_V];
             sEv[s * 3 + 1] = q[EQ_V + 1];
             sEv[s * 3 + 2] = q[EQ_V + 2];
+            const double gf = A.ncomp == 2 ? A.gfp[e * NS + s] : 1.0;
+            sLg[s] = gf > 0.0 ? log(gf) : -1000.0;
         }
     }
     __syncthreads();
-    if (k >= A.nu) return;
+    if (k >= A.nut) return;
 
     const GOps<Real> &op = gops<Real>(A);
     const Metrics<Real> G = metrics(A, Real(0));
     const cptr<Real> gS = G.S + e * NS * 9, gJ = G.ijac + e * NS, gN = G.nf + e * 6 * NFP * 3;
-    const int64_t nu = A.nu;
+    const int64_t nu = A.nut;  // stride of a solution point
+    const int comp = k >= A.nu, kv = k - comp * A.nu;  // component, velocity node
     int iv[3];
-    split_k(A.vg, k, iv);
+    split_k(A.vg, kv, iv);
     const double ud[3] = {node_u(A.vg, 0, iv[0]), node_u(A.vg, 1, iv[1]), node_u(A.vg, 2, iv[2])};
     const Real u0 = (Real)ud[0], u1 = (Real)ud[1], u2 = (Real)ud[2];
     const int64_t eoff = e * NS * nu;
-    const uint32_t ko = (uint32_t)k * (uint32_t)sizeof(Real), k8 = (uint32_t)k * 8u;
+    const uint32_t ko = (uint32_t)k * (uint32_t)sizeof(Real), k8 = (uint32_t)k * 8u, kv8 = (uint32_t)kv * 8u;
     const Real *fe = reinterpret_cast<const Real *>(A.sa.f) + eoff;
     // all of f (two layers at a time at p = 3) requested together
 #pragma unroll 1
@@ -387,13 +403,13 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
                 // face's axis (orient holds the axis)
                 const int str = orient == 0 ? 1 : (orient == 1 ? A.vg.nv[0] : A.vg.nv[0] * A.vg.nv[1]);
                 const int ia = orient == 0 ? iv[0] : (orient == 1 ? iv[1] : iv[2]);
-                const int km = k + (A.vg.nv[orient] - 1 - 2 * ia) * str;
+                const int km = k + (A.vg.nv[orient] - 1 - 2 * ia) * str;  // same component
                 const uint32_t kmo = (uint32_t)km * (uint32_t)sizeof(Real);
                 const Real *to = tin + (e * 6 + face) * NFP * nu;
 #pragma unroll
                 for (int q = 0; q < NFP; ++q) ext[side][q] = un[side][q] < Real(0) ? ldo(to + q * nu, kmo) : Real(0);
             } else {
-                const double mw = ldo(A.mw, k8);
+                const double mw = ldo(A.mw, kv8) * (comp ? A.gwall : 1.0);
 #pragma unroll
                 for (int q = 0; q < NFP; ++q) ext[side][q] = (Real)(A.rw[(e * 6 + face) * NFP + q] * mw);
             }
@@ -447,7 +463,7 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
                 double t1 = bq[1] * c1;
                 t1 = fma(bq[5], c2, t1);
                 const double t2 = bq[2] * c2;
-                double E = fma(c0, t0, bq[6]);
+                double E = fma(c0, t0, comp ? bq[6] + sLg[s] : bq[6]);
                 E = fma(c1, t1, E);
                 E = fma(c2, t2, E);
                 L += (gexp<Real>(E) - fq) * (Real)bq[7];
@@ -494,12 +510,13 @@ int gen_run(fr_dvm *h, int mode, const GenArgs &A, int do_moments) {
     const unsigned blocks = (unsigned)(h->ne * A.nvb);
     const int64_t npts = h->ne * h->ns;
     auto moments = [&](const void *src) {
-        if (h->nmom == 5)
-            hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A,
-                               reinterpret_cast<const Real *>(src), A.sa.Q);
-        else
-            hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A,
-                               reinterpret_cast<const Real *>(src), A.sa.Q);
+        const Real *fs = reinterpret_cast<const Real *>(src);
+        switch (h->nmom) {
+            case 5: hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A, fs, A.sa.Q); break;
+            case 6: hipLaunchKernelGGL((k_gen_moments<Real, 6>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A, fs, A.sa.Q); break;
+            case 10: hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A, fs, A.sa.Q); break;
+            default: hipLaunchKernelGGL((k_gen_moments<Real, 11>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A, fs, A.sa.Q);
+        }
         return gcheck(h, "moment kernel");
     };
     int rc;
@@ -554,8 +571,12 @@ int launch_fr_gen(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int d
         }
     A.vg = h->vg;
     A.nu = h->vg.nu;
-    A.nvb = (A.nu + kGBlock - 1) / kGBlock;
-    A.nvw = (A.nu + kGWave - 1) / kGWave;
+    A.ncomp = h->ncomp;
+    A.nut = A.nu * A.ncomp;
+    A.nvb = (A.nut + kGBlock - 1) / kGBlock;
+    A.nvw = (A.nut + kGWave - 1) / kGWave;
+    A.gwall = 0.5 * h->delta * h->prm.theta_wall;
+    A.gfp = h->d_gfp;
     A.wax = h->d_wax;
     A.S = h->d_S;
     A.ijac = h->d_ijac;

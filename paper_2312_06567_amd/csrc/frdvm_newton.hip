@@ -59,7 +59,21 @@ struct NewtonArgs {
     int guess;
     const float *dz_guess;  // [npts][5] learned correction (guess == MLP)
     int use_fact;           // ES: factorised sums with per-point LDS tables
+    double delta;           // internal degrees of freedom (the reduced pair)
+    double *gfp;            // [npts] delta theta / 2 per point (pair only, else null)
 };
+
+// Total energy of a moment record: E (BGK), half the trace of the raw second
+// moments (ES), plus the integral of G in the last slot for the reduced pair
+// (records of 6 / 11 values).
+__device__ __forceinline__ double record_energy(const double *q, int nmom) {
+    switch (nmom) {
+        case 5: return q[4];
+        case 6: return q[4] + q[5];
+        case 10: return 0.5 * (q[4] + q[5] + q[6]);
+        default: return 0.5 * (q[4] + q[5] + q[6]) + q[10];
+    }
+}
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 // Line search: the step is halved after each rejected trial point (z4 <= 0 or
@@ -870,13 +884,16 @@ __global__ __launch_bounds__(256) void k_newton_bgk(const NewtonArgs A) {
     const double rho = Q[0];
     const double irho = 1.0 / rho;
     double U[3] = {Q[1] * irho, Q[2] * irho, Q[3] * irho};
-    const double E = A.nmom == 5 ? Q[4] : 0.5 * (Q[4] + Q[5] + Q[6]);
-    const double th = (2.0 / 3.0) * (E * irho - 0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
+    // E - rho |U|^2 / 2 = (3 + delta)/2 rho theta
+    const double E = record_energy(Q, A.nmom);
+    const double th = (2.0 / (3.0 + A.delta)) * (E * irho - 0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
     if (!(rho > 0.0) || !(th > 0.0) || !isfinite(rho) || !isfinite(th)) {
         write_nonreal(A, pt);
+        if (A.gfp) A.gfp[pt] = 0.0;
         record_stats(A, pt, 0, 0, FR_DVM_NEWTON_NONREAL, -1.0);
         return;
     }
+    if (A.gfp) A.gfp[pt] = 0.5 * A.delta * th;
     const double inv_tau = rho * th / viscosity(A, th);
     const double ist = 1.0 / sqrt(th);
     const double zc[5] = {-1.5 * log(kTwoPi), 0.0, 0.0, 0.0, 1.0};
@@ -920,14 +937,17 @@ __global__ __launch_bounds__(kEsBlock) __attribute__((amdgpu_waves_per_eu(FRDVM_
     // raw second moments -> pressure tensor Pi = M2 - rho U U^T
     const double Pi[6] = {Q[4] - rho * U[0] * U[0], Q[5] - rho * U[1] * U[1], Q[6] - rho * U[2] * U[2],
                           Q[7] - rho * U[0] * U[1], Q[8] - rho * U[0] * U[2], Q[9] - rho * U[1] * U[2]};
-    const double th = (Pi[0] + Pi[1] + Pi[2]) / (3.0 * rho);
+    // (3 + delta) rho theta = tr Pi + 2 (integral of G)
+    const double th = (Pi[0] + Pi[1] + Pi[2] + (A.nmom == 11 ? 2.0 * Q[10] : 0.0)) / ((3.0 + A.delta) * rho);
     if (!(rho > 0.0) || !(th > 0.0) || !isfinite(rho) || !isfinite(th)) {
         if (lane == 0) {
             write_nonreal(A, pt);
+            if (A.gfp) A.gfp[pt] = 0.0;
             record_stats(A, pt, 0, 0, FR_DVM_NEWTON_NONREAL, -1.0);
         }
         return;
     }
+    if (A.gfp && lane == 0) A.gfp[pt] = 0.5 * A.delta * th;
     const double Pr = A.Pr;
     const double inv_tau = Pr * rho * th / viscosity(A, th);
     const double ist = 1.0 / sqrt(th);
@@ -1038,21 +1058,27 @@ __global__ void k_mlp_features(int64_t npts, int nmom, const double *__restrict_
 }
 
 __global__ void k_collide(const VGrid vg, const double *__restrict__ eqs, const void *fv, void *Sv, int accumulate,
-                          int fp64) {
+                          int fp64, int ncomp, const double *__restrict__ gfp) {
     const int64_t pt = blockIdx.x;
     const double *eqp = eqs + pt * kEqW;
     double eq[kEqW];
 #pragma unroll
     for (int a = 0; a < kEqW; ++a) eq[a] = eqp[a];
-    for (int k = threadIdx.x; k < vg.nu; k += blockDim.x) {
+    // the pair's G relaxes to delta theta / 2 times the equilibrium of F:
+    // its exponent is shifted by the logarithm of that factor
+    const double lg = ncomp == 2 ? (gfp[pt] > 0.0 ? log(gfp[pt]) : -1000.0) : 0.0;
+    const int nut = vg.nu * ncomp;
+    for (int kk = threadIdx.x; kk < nut; kk += blockDim.x) {
+        const int comp = kk >= vg.nu, k = kk - comp * vg.nu;
         const int i = k % vg.nv[0], j = (k / vg.nv[0]) % vg.nv[1], l = k / (vg.nv[0] * vg.nv[1]);
         const double u[3] = {gridu(vg, 0, i), gridu(vg, 1, j), gridu(vg, 2, l)};
-        const int64_t idx = pt * vg.nu + k;
+        const int64_t idx = pt * nut + kk;
+        const double c0g = eq[EQ_C0] + (comp ? lg : 0.0);
         if (fp64) {
             const double c0 = u[0] - eq[EQ_V], c1 = u[1] - eq[EQ_V + 1], c2 = u[2] - eq[EQ_V + 2];
             const double q = eq[EQ_B] * c0 * c0 + eq[EQ_B + 1] * c1 * c1 + eq[EQ_B + 2] * c2 * c2 +
                              2.0 * (eq[EQ_B + 3] * c0 * c1 + eq[EQ_B + 4] * c0 * c2 + eq[EQ_B + 5] * c1 * c2);
-            const double g = exp(eq[EQ_C0] - 0.5 * q);
+            const double g = exp(c0g - 0.5 * q);
             const double f = ((const double *)fv)[idx];
             const double S = (g - f) * eq[EQ_INVTAU];
             double *So = (double *)Sv;
@@ -1063,7 +1089,7 @@ __global__ void k_collide(const VGrid vg, const double *__restrict__ eqs, const 
             const double c0 = u[0] - eq[EQ_V], c1 = u[1] - eq[EQ_V + 1], c2 = u[2] - eq[EQ_V + 2];
             const double q = eq[EQ_B] * c0 * c0 + eq[EQ_B + 1] * c1 * c1 + eq[EQ_B + 2] * c2 * c2 +
                              2.0 * (eq[EQ_B + 3] * c0 * c1 + eq[EQ_B + 4] * c0 * c2 + eq[EQ_B + 5] * c1 * c2);
-            const float g = exp_to_f32(eq[EQ_C0] - 0.5 * q);
+            const float g = exp_to_f32(c0g - 0.5 * q);
             const float f = ((const float *)fv)[idx];
             const float S = (g - f) * (float)eq[EQ_INVTAU];
             float *So = (float *)Sv;
@@ -1078,7 +1104,7 @@ __global__ void k_moments_out(int64_t npts, int nmom, const double *__restrict__
     const double *q = Q + pt * nmom;
     double *o = out + pt * 5;
     o[0] = q[0]; o[1] = q[1]; o[2] = q[2]; o[3] = q[3];
-    o[4] = nmom == 5 ? q[4] : 0.5 * (q[4] + q[5] + q[6]);
+    o[4] = record_energy(q, nmom);
 }
 
 // Gradient-length local Knudsen number (Section "Results"):
@@ -1126,8 +1152,8 @@ __global__ __launch_bounds__(64 * kKnElems) void k_kn_gll(NewtonArgs A, Ops1D op
     const double *q = A.Q + pt * A.nmom;
     const double rho = q[0];
     const double ux = q[1] / rho, uy = q[2] / rho, uz = q[3] / rho;
-    const double E = A.nmom == 5 ? q[4] : 0.5 * (q[4] + q[5] + q[6]);
-    const double th = (2.0 / 3.0) * (E / rho - 0.5 * (ux * ux + uy * uy + uz * uz));
+    const double E = record_energy(q, A.nmom);
+    const double th = (2.0 / (3.0 + A.delta)) * (E / rho - 0.5 * (ux * ux + uy * uy + uz * uz));
     double out = 0.0;
     if (rho > 0.0 && th > 0.0) {
         const double lam = viscosity(A, th) / rho * sqrt(kTwoPi / (4.0 * th));
@@ -1145,7 +1171,7 @@ __global__ __launch_bounds__(1024) void k_totals(int64_t npts, int nmom, const d
         const double *q = Q + pt * nmom;
         const double w = wJ[pt];
         a[0] += w * q[0]; a[1] += w * q[1]; a[2] += w * q[2]; a[3] += w * q[3];
-        a[4] += w * (nmom == 5 ? q[4] : 0.5 * (q[4] + q[5] + q[6]));
+        a[4] += w * record_energy(q, nmom);
     }
 #pragma unroll
     for (int c = 0; c < 5; ++c) red[c][threadIdx.x] = a[c];
@@ -1187,7 +1213,10 @@ NewtonArgs newton_args(fr_dvm *h, int guess) {
     A.tol = h->prm.newton_tol;
     A.max_iter = h->prm.newton_max_iter;
     A.guess = (guess == FR_DVM_GUESS_WARM && !h->zvalid) ? FR_DVM_GUESS_COLD : guess;
-    if (A.guess == FR_DVM_GUESS_MLP && !h->d_mlp) A.guess = FR_DVM_GUESS_COLD;
+    // the learned start is trained on monatomic states: cold start for the pair
+    if (A.guess == FR_DVM_GUESS_MLP && (!h->d_mlp || h->ncomp == 2)) A.guess = FR_DVM_GUESS_COLD;
+    A.delta = h->ncomp == 2 ? h->delta : 0.0;
+    A.gfp = h->d_gfp;
     return A;
 }
 
@@ -1253,6 +1282,7 @@ int newton_run(fr_dvm *h, NewtonArgs A, int64_t p0, int64_t np, hipStream_t s) {
     A.z += p0 * 5;
     A.prim += p0 * 5;
     if (A.dz_guess) A.dz_guess += p0 * 5;
+    if (A.gfp) A.gfp += p0;
     A.pt_iters = h->d_pt_iters + p0;
     A.pt_evals = h->d_pt_evals + p0;
     A.pt_status = h->d_pt_status + p0;
@@ -1334,6 +1364,8 @@ int launch_newton_points(fr_dvm *h, const double *Q, int64_t n, int guess, doubl
         A.pt_evals = evals;
         A.pt_status = status;
         A.pt_resid = resid;
+        A.delta = 0.0;  // monatomic moment vectors
+        A.gfp = nullptr;
         if (!(A.mu_ref > 0)) A.mu_ref = 1.0;  // tau is not an output here
         hipLaunchKernelGGL(k_newton_bgk, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, A);
         rc = check(h, "newton kernel");
@@ -1347,7 +1379,7 @@ int launch_newton_points(fr_dvm *h, const double *Q, int64_t n, int guess, doubl
 
 int launch_collide(fr_dvm *h, const void *f, void *S, int accumulate) {
     hipLaunchKernelGGL(k_collide, dim3((unsigned)(h->ne * h->ns)), dim3(256), 0, h->stream, h->vg, h->d_eq, f, S,
-                       accumulate, h->prm.precision == FR_DVM_FP64 ? 1 : 0);
+                       accumulate, h->prm.precision == FR_DVM_FP64 ? 1 : 0, h->ncomp, h->d_gfp);
     return check(h, "collide kernel");
 }
 

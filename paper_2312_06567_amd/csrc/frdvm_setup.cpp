@@ -421,7 +421,7 @@ int setup_general(fr_dvm *h, const fr_dvm_mesh *mesh, std::vector<double> &wq3J)
                 }
         }
     h->nwall = (int64_t)wall.size();
-    h->tl.elem = (int64_t)6 * nfp * h->vg.nu;
+    h->tl.elem = (int64_t)6 * nfp * h->vg.nu * h->ncomp;
     int rc;
     if ((rc = dev_alloc(h, &h->d_S, S.size())) || (rc = upload(h, h->d_S, S.data(), S.size() * sizeof(double))))
         return rc;
@@ -443,7 +443,8 @@ int setup_general(fr_dvm *h, const fr_dvm_mesh *mesh, std::vector<double> &wq3J)
         return rc;
     if ((rc = dev_alloc(h, &h->d_rw, (size_t)ne * 6 * nfp))) return rc;
     if ((rc = dev_alloc(h, &h->d_mw, (size_t)h->vg.nu))) return rc;
-    return dev_alloc(h, &h->d_finf, (size_t)h->vg.nu);
+    if (h->ncomp == 2 && (rc = dev_alloc(h, &h->d_gfp, (size_t)ne * ns))) return rc;
+    return dev_alloc(h, &h->d_finf, (size_t)h->vg.nu * h->ncomp);
 }
 
 }  // namespace
@@ -467,8 +468,8 @@ extern "C" void fr_dvm_default_params(fr_dvm_params *p) {
     p->overlap = 0;
 }
 
-extern "C" int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes, const fr_dvm_vgrid *grid,
-                                   fr_dvm_t *out) {
+extern "C" int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, double delta,
+                                 const fr_dvm_vgrid *grid, fr_dvm_t *out) {
     if (!out) return FR_DVM_EINVAL;
     *out = nullptr;
     if (!mesh || !grid || !mesh->nodes || !mesh->elem_nodes || !mesh->nbr_elem || !mesh->nbr_face ||
@@ -486,6 +487,9 @@ extern "C" int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes
     h->ne = mesh->n_elem;
     if (nodes != 0 && nodes != 1) return bail(h->fail(FR_DVM_EINVAL, "solution point set must be 0 or 1"));
     h->nodes = nodes;
+    if (!(delta >= 0.0) || !std::isfinite(delta)) return bail(h->fail(FR_DVM_EINVAL, "delta must be finite and >= 0"));
+    h->delta = delta;
+    h->ncomp = delta > 0.0 ? 2 : 1;
     build_ops(order, nodes, h->ops);
 
     // velocity grid
@@ -533,7 +537,8 @@ extern "C" int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes
                 return bail(h->fail(FR_DVM_EINVAL, "neighbour relation is not symmetric"));
         }
     std::vector<double> wq3J(h->ne * h->ns);
-    int rc = setup_axis(h, mesh, wq3J);
+    // the reduced pair runs on the general path
+    int rc = h->ncomp == 1 ? setup_axis(h, mesh, wq3J) : kNotAxis;
     if (rc == kNotAxis) rc = setup_general(h, mesh, wq3J);
     if (rc) return bail(rc);
 
@@ -556,8 +561,13 @@ extern "C" int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes
     return FR_DVM_OK;
 }
 
+extern "C" int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes, const fr_dvm_vgrid *grid,
+                                   fr_dvm_t *out) {
+    return fr_dvm_create_gas(mesh, order, nodes, 0.0, grid, out);
+}
+
 extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out) {
-    return fr_dvm_create_nodes(mesh, order, 0, grid, out);
+    return fr_dvm_create_gas(mesh, order, 0, 0.0, grid, out);
 }
 
 extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
@@ -571,13 +581,15 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     if (p->guess < 0 || p->guess > 3) return h->fail(FR_DVM_EINVAL, "unknown guess mode");
     if (p->overlap != 0 && p->overlap != 1) return h->fail(FR_DVM_EINVAL, "overlap must be 0 or 1");
     bool realloc_all = !h->have_params || p->precision != h->prm.precision;
-    int nmom = (p->model == FR_DVM_ESBGK) ? 10 : 5;
+    // moment record: rho, rho U, then E (BGK) or the raw second moments (ES),
+    // plus the integral of G for the reduced pair
+    int nmom = ((p->model == FR_DVM_ESBGK) ? 10 : 5) + (h->ncomp == 2 ? 1 : 0);
     bool realloc_mom = !h->have_params || nmom != h->nmom;
     h->prm = *p;
     h->nmom = nmom;
     size_t es = p->precision == FR_DVM_FP64 ? sizeof(double) : sizeof(float);
     int64_t npts = h->ne * h->ns;
-    int64_t nu = h->vg.nu;
+    int64_t nu = h->vg.nu * h->ncomp;  // state values per point
     int rc;
     if (realloc_all) {
         if (h->d_reg) { hipFree(h->d_reg); h->owned_bytes -= npts * nu * es; h->d_reg = nullptr; }
@@ -640,7 +652,7 @@ namespace frdvm {
 // exteriors of the general-mesh path).
 int gen_boundary_tables(fr_dvm *h) {
     const VGrid &vg = h->vg;
-    std::vector<double> mw(vg.nu), fi(vg.nu);
+    std::vector<double> mw(vg.nu), fi((size_t)vg.nu * h->ncomp);
     const double kPi = 3.14159265358979323846;
     const double tw = h->prm.theta_wall, *F = h->prm.farfield;
     for (int64_t k = 0; k < vg.nu; ++k) {
@@ -654,6 +666,8 @@ int gen_boundary_tables(fr_dvm *h) {
                     ? F[0] * std::pow(2.0 * kPi * F[4], -1.5) * std::exp(-(c0 * c0 + c1 * c1 + c2 * c2) / (2.0 * F[4]))
                     : 0.0;
     }
+    // the pair's farfield G: delta theta_inf / 2 times the farfield F
+    for (int64_t k = 0; k < (int64_t)vg.nu * (h->ncomp - 1); ++k) fi[vg.nu + k] = 0.5 * h->delta * F[4] * fi[k];
     int rc = upload(h, h->d_mw, mw.data(), mw.size() * sizeof(double));
     if (!rc) rc = upload(h, h->d_finf, fi.data(), fi.size() * sizeof(double));
     return rc;
@@ -712,7 +726,7 @@ extern "C" void fr_dvm_destroy(fr_dvm_t h) {
                     h->d_Q, h->d_eq, h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
                     h->d_mlp_x, h->d_mlp_work, h->d_mlp_dz, h->d_pt_iters, h->d_pt_evals, h->d_pt_status,
                     h->d_pt_resid, h->d_S, h->d_ijac, h->d_nf, h->d_conn, h->d_wall, h->d_rw, h->d_mw,
-                    h->d_finf, h->d_Sf, h->d_ijacf, h->d_nff};
+                    h->d_finf, h->d_Sf, h->d_ijacf, h->d_nff, h->d_gfp};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (auto &r : h->prof_recs) {

@@ -62,6 +62,8 @@ def lib():
         L.fr_dvm_default_params.argtypes = [C.POINTER(_Params)]
         L.fr_dvm_create.argtypes = [C.POINTER(_Mesh), C.c_int, C.POINTER(_VGrid), C.POINTER(vp)]
         L.fr_dvm_create_nodes.argtypes = [C.POINTER(_Mesh), C.c_int, C.c_int, C.POINTER(_VGrid), C.POINTER(vp)]
+        L.fr_dvm_create_gas.argtypes = [C.POINTER(_Mesh), C.c_int, C.c_int, C.c_double, C.POINTER(_VGrid),
+                                        C.POINTER(vp)]
         L.fr_dvm_set_params.argtypes = [vp, C.POINTER(_Params)]
         L.fr_dvm_set_stream.argtypes = [vp, vp]
         L.fr_dvm_sizes.argtypes = [vp, i64p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -163,8 +165,10 @@ def _ptr(t):
 class FrDvm:
     """One handle of the library: a mesh, an FR order and a velocity grid."""
 
-    def __init__(self, mesh: dict, order: int, grid: dict, params: dict | None = None, nodes: int = 0):
-        """nodes: solution points per axis, 0 Gauss-Legendre, 1 Gauss-Lobatto."""
+    def __init__(self, mesh: dict, order: int, grid: dict, params: dict | None = None, nodes: int = 0,
+                 delta: float = 0.0):
+        """nodes: solution points per axis, 0 Gauss-Legendre, 1 Gauss-Lobatto;
+        delta > 0: a gas with delta internal degrees of freedom, state (F, G)."""
         L = lib()
         self._keep = {
             "nodes": np.ascontiguousarray(mesh["nodes"], np.float64),
@@ -188,7 +192,7 @@ class FrDvm:
             g.umin[d] = float(grid["umin"][d])
             g.umax[d] = float(grid["umax"][d])
         h = C.c_void_p()
-        rc = L.fr_dvm_create_nodes(C.byref(m), int(order), int(nodes), C.byref(g), C.byref(h))
+        rc = L.fr_dvm_create_gas(C.byref(m), int(order), int(nodes), float(delta), C.byref(g), C.byref(h))
         self._h = h
         if rc != 0:
             msg = self.last_error() if h.value else "invalid argument"
@@ -199,6 +203,7 @@ class FrDvm:
         self.ne, self.ns, self.nf, self.nu = ne.value, ns.value, nf.value, nu.value
         self.order = int(order)
         self.nodes = int(nodes)
+        self.ncomp = 2 if delta > 0 else 1
         self.precision = FP64
         if params is not None:
             self.set_params(**params)
@@ -226,7 +231,7 @@ class FrDvm:
 
     @property
     def shape(self):
-        return (self.ne, self.ns, self.nu)
+        return (self.ne, self.ns, self.ncomp * self.nu)
 
     @property
     def dtype(self):
@@ -237,7 +242,7 @@ class FrDvm:
         import torch
         if t is None:
             raise FrDvmError(f"{name} is None")
-        if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous() or t.numel() != self.ne * self.ns * self.nu:
+        if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous() or t.numel() != self.ne * self.ns * self.ncomp * self.nu:
             raise FrDvmError(f"{name} must be a contiguous {self.dtype} CUDA tensor with {self.shape} elements")
 
     def _check_d(self, t, n, name):
