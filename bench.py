@@ -129,15 +129,23 @@ def run_config(W, w, mesh, params, steps, warmup, label, weights=None, keep_mome
     import torch
 
     from paper_2312_06567_amd.frdvm import FrDvm
-    s = FrDvm(mesh, w["p"], w["grid"], params)
+    delta = float(w.get("delta", 0.0))
+    s = FrDvm(mesh, w["p"], w["grid"], params, delta=delta)
     if weights is not None:
         s.mlp_set_weights(weights)
-    ne, ns, nu = s.shape
+    ne, ns, nu = s.shape  # nu: state values per point (both components of a pair)
     dof = ne * ns * nu
     dt = (s.dt(0.2) if dt_override is None else dt_override) * dt_scale
     prim = W.initial_prim(mesh, w["p"], w)
     log(f"{label}: generating f0 ({dof:.3e} DOFs, {s.dtype})")
-    f = W.maxwellian(prim, w["grid"], dtype=s.dtype, device="cuda").reshape(ne, ns, nu)
+    if delta > 0:
+        # the pair in equilibrium: G = delta theta / 2 F
+        Fm = W.maxwellian(prim, w["grid"], dtype=s.dtype, device="cuda").reshape(ne, ns, nu // 2)
+        th = torch.as_tensor(prim[..., 4], dtype=s.dtype, device="cuda").reshape(ne, ns, 1)
+        f = torch.cat([Fm, 0.5 * delta * th * Fm], -1).contiguous()
+        del Fm
+    else:
+        f = W.maxwellian(prim, w["grid"], dtype=s.dtype, device="cuda").reshape(ne, ns, nu)
     torch.cuda.synchronize()
     tot0 = None
     if keep_moments:
@@ -273,6 +281,8 @@ def main():
     ap.add_argument("--rk", type=int, default=None, help="single mode: 0 SSP-RK3, 1 low-storage")
     ap.add_argument("--guess", type=int, default=None, help="single mode: 0 cold, 1 warm, 2 MLP, 3 MLP then warm")
     ap.add_argument("--model", type=int, default=None, help="0 BGK, 1 ES-BGK, 2 collisionless")
+    ap.add_argument("--delta", type=float, default=None,
+                    help="single mode: internal degrees of freedom (> 0: the reduced pair F, G)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-error", action="store_true",
                     help="compare mode: skip the error runs at the workload's horizon")
@@ -311,6 +321,8 @@ def main():
         return
 
     w = W.workload(args.workload)
+    if args.delta is not None:
+        w["delta"] = args.delta
     mesh = W.workload_mesh(w)
     base = W.physics_params(w)
     if args.model is not None:
@@ -333,6 +345,8 @@ def main():
         if par["guess"] in (2, 3):
             weights, _ = train_guess(W, w, log)
         r = run_config(W, w, mesh, par, args.steps, args.warmup, "single", weights=weights)
+        if w.get("delta", 0.0) > 0:
+            cfg.update(delta=w["delta"], state="reduced pair (F, G): 2 values per velocity node")
         cfg.update(precision=["FP64", "FP32"][par["precision"]], rk=["SSP-RK3", "LSRK3-2N"][par["rk"]],
                    guess=["cold", "warm", "learned", "learned+warm"][par["guess"]])
         out = {"metric": "DOF-updates/s (N_e*N_s*N_u per RK stage)", "value": r["value"], "unit": "DOF-updates/s",
