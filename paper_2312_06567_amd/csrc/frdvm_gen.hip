@@ -17,9 +17,8 @@
 // Work decomposition: one wave per (element, 64 velocities), one lane per
 // velocity; the element's metrics and normals are read through the scalar
 // cache, its equilibrium records staged in LDS.  A lane keeps its velocity's
-// N^3 values and their residual in a private LDS column: the divergence is
-// scattered source point by source point (3N FMA each), the face terms
-// gathered along the lines through each flux point.  Every access to f, the
+// N^3 values and their residual in a private LDS column; the derivative and
+// the face terms are formed line by line, direction by direction.  Every access to f, the
 // RK registers and the traces is a run of consecutive velocities.  Traces
 // are full (every velocity at every flux point, [e][face][point][k]); a lane
 // reads the neighbour trace only where its velocity enters the element.
@@ -343,10 +342,7 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
 #pragma unroll
         for (int r = 0; r < CHF; ++r) v[r] = ldo(fe + (s0 + r) * nu, ko);
 #pragma unroll
-        for (int r = 0; r < CHF; ++r) {
-            sf[s0 + r][lane] = v[r];
-            sa[s0 + r][lane] = Real(0);
-        }
+        for (int r = 0; r < CHF; ++r) sf[s0 + r][lane] = v[r];
     }
     // the second RK register of the stage, requested now (p <= 2) so that
     // the FR work covers its latency
@@ -357,27 +353,16 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) xe[s] = useX ? ldo(XE + s * nu, ko) : Real(0);
     }
-    // divergence of the transformed flux, scattered from each source point
-#pragma unroll 1
-    for (int m = 0; m < NS; ++m) {
-        const int i = m % N, j = (m / N) % N, l = m / NFP;
-        const cptr<Real> Sm = gS + m * 9;
-        const Real fm = sf[m][lane];
-        const Real F0 = (Sm[0] * u0 + Sm[1] * u1 + Sm[2] * u2) * fm;
-        const Real F1 = (Sm[3] * u0 + Sm[4] * u1 + Sm[5] * u2) * fm;
-        const Real F2 = (Sm[6] * u0 + Sm[7] * u1 + Sm[8] * u2) * fm;
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            sa[spt<N>(r, j, l)][lane] += op.D[r * N + i] * F0;
-            sa[spt<N>(i, r, l)][lane] += op.D[r * N + j] * F1;
-            sa[spt<N>(i, j, r)][lane] += op.D[r * N + l] * F2;
-        }
-    }
-    // interface corrections, axis by axis: the exterior values of both faces
-    // of an axis requested together, then the jumps
+    // Divergence and interface corrections, direction by direction: along
+    // each line of direction d the transformed flux F_d = (a^d . u) f, its
+    // derivative, and the corrections of the line's two flux points on the
+    // faces 2d and 2d+1 are formed in registers; each point's accumulator
+    // is then written once per direction (the first direction initialises
+    // it), so no accumulator waits on another update of itself.
     const Real *tin = reinterpret_cast<const Real *>(A.sa.tr_in);
 #pragma unroll 1
     for (int d = 0; d < 3; ++d) {
+        // the exterior values of both faces of the axis, requested together
         Real un[2][NFP], ext[2][NFP];
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
@@ -415,22 +400,39 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
             }
         }
 #pragma unroll
-        for (int side = 0; side < 2; ++side)
+        for (int q = 0; q < NFP; ++q) {
+            const int a = q % N, b = q / N;
+            int pts[N];
+            Real fl[N], Fd[N];
 #pragma unroll
-            for (int q = 0; q < NFP; ++q) {
+            for (int m = 0; m < N; ++m) {
+                pts[m] = line_pt<N>(d, a, b, m);
+                fl[m] = sf[pts[m]][lane];
+                const cptr<Real> Sm = gS + pts[m] * 9 + 3 * d;
+                Fd[m] = (Sm[0] * u0 + Sm[1] * u1 + Sm[2] * u2) * fl[m];
+            }
+            Real acc[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                Real t = Real(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) t += op.D[r * N + m] * Fd[m];
+                acc[r] = t;
+            }
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
                 if (un[side][q] < Real(0)) {
-                    const int a = q % N, b = q / N;
-                    int pts[N];
-#pragma unroll
-                    for (int m = 0; m < N; ++m) pts[m] = line_pt<N>(d, a, b, m);
                     Real fm = Real(0);
 #pragma unroll
-                    for (int m = 0; m < N; ++m) fm += op.lam[side][m] * sf[pts[m]][lane];
+                    for (int m = 0; m < N; ++m) fm += op.lam[side][m] * fl[m];
                     const Real jump = un[side][q] * (ext[side][q] - fm);
 #pragma unroll
-                    for (int m = 0; m < N; ++m) sa[pts[m]][lane] += op.corr[side][m] * jump;
+                    for (int r = 0; r < N; ++r) acc[r] += op.corr[side][r] * jump;
                 }
             }
+#pragma unroll
+            for (int r = 0; r < N; ++r) sa[pts[r]][lane] = d == 0 ? acc[r] : sa[pts[r]][lane] + acc[r];
+        }
     }
     if (MODE == GMODE_RESID) {
         Real *R = reinterpret_cast<Real *>(A.sa.fout) + eoff;
