@@ -111,10 +111,17 @@ __device__ __forceinline__ double node_u(const VGrid &vg, int d, int i) {
     return __dadd_rn(vg.umin[d], __dmul_rn((double)i, vg.du[d]));
 }
 
+// Velocity node k = i + n0 (j + n1 l) -> (i, j, l).  The quotients are taken
+// in FP32 from (k + 1/2) times the reciprocal, exact for k < 2^22 (a grid
+// has at most 64^3 nodes), instead of integer divisions.
 __device__ __forceinline__ void split_k(const VGrid &vg, int k, int iv[3]) {
-    iv[0] = k % vg.nv[0];
-    iv[1] = (k / vg.nv[0]) % vg.nv[1];
-    iv[2] = k / (vg.nv[0] * vg.nv[1]);
+    const int n0 = vg.nv[0], n01 = vg.nv[0] * vg.nv[1];
+    const int q2 = (int)(((float)k + 0.5f) * (1.0f / (float)n01));
+    const int r = k - q2 * n01;
+    const int q1 = (int)(((float)r + 0.5f) * (1.0f / (float)n0));
+    iv[0] = r - q1 * n0;
+    iv[1] = q1;
+    iv[2] = q2;
 }
 
 template <int N>
@@ -211,13 +218,14 @@ __global__ __launch_bounds__(kGBlock) void k_gen_moments(const GenArgs A, const 
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
     // four values per lane requested at once, then accumulated in order
+    constexpr int kIn = 4;
     int k0 = threadIdx.x;
-    for (; k0 + 3 * kGBlock < A.nut; k0 += 4 * kGBlock) {
-        Real v[4];
+    for (; k0 + (kIn - 1) * kGBlock < A.nut; k0 += kIn * kGBlock) {
+        Real v[kIn];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = fp[k0 + r * kGBlock];
+        for (int r = 0; r < kIn; ++r) v[r] = fp[k0 + r * kGBlock];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) moment_add<NMOM>(A, k0 + r * kGBlock, (double)v[r], M);
+        for (int r = 0; r < kIn; ++r) moment_add<NMOM>(A, k0 + r * kGBlock, (double)v[r], M);
     }
     for (int k = k0; k < A.nut; k += kGBlock) moment_add<NMOM>(A, k, (double)fp[k], M);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
