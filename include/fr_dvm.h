@@ -174,7 +174,9 @@ int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p);
 /* Run subsequent calls on this hipStream_t (passed as void*). */
 int fr_dvm_set_stream(fr_dvm_t h, void *stream);
 
-/* Sizes and the bytes of device memory the handle owns. */
+/* Sizes and the bytes of device memory the handle owns.  nu counts velocity
+ * nodes; a state of the reduced pair (fr_dvm_create_gas, delta > 0) holds
+ * 2 nu values per solution point. */
 int fr_dvm_sizes(fr_dvm_t h, int64_t *n_elem, int32_t *ns, int32_t *nf, int32_t *nu,
                  size_t *workspace_bytes);
 
