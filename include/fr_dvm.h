@@ -119,7 +119,8 @@ typedef struct {
                              on a second library-owned stream, half of the elements
                              at a time, while the current stage still streams the
                              other half; 0 = one stream, stage and Newton in turn.
-                             Results are identical. */
+                             Results are identical.  Box path only: ignored on
+                             general meshes and for the reduced pair. */
 } fr_dvm_params;
 
 /* Fill p with defaults: BGK, Pr 1, mu_ref 1e-3, theta_ref 1, omega 0.81,
