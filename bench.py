@@ -105,7 +105,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: int, rk: int):
+def measured_traffic(workload: str, precision: int, rk: int, delta: float = 0.0):
     """HBM bytes per stage launch from the committed rocprofv3 counter runs
     (FETCH_SIZE and WRITE_SIZE, calibrated on a copy kernel), or None when
     no run matches this configuration or the kernel source has changed since."""
@@ -116,7 +116,8 @@ def measured_traffic(workload: str, precision: int, rk: int):
         recs = json.load(fh)
     src = kernel_source_hash()
     for r in recs:
-        if r["workload"] == workload and r["precision"] == precision and r["rk"] == rk and r["source"] == src:
+        if (r["workload"] == workload and r["precision"] == precision and r["rk"] == rk
+                and r.get("delta", 0.0) == delta and r["source"] == src):
             return r
     return None
 
@@ -171,7 +172,7 @@ def run_config(W, w, mesh, params, steps, warmup, label, weights=None, keep_mome
     log(f"{label}: {n_timed} steps in {elapsed:.3f} s")
     out = {"label": label, "dof": dof, "steps": n_timed, "elapsed": elapsed, "dt": dt,
            "value": dof * 3 * n_timed / elapsed, "ms_per_step": elapsed / n_timed * 1e3, "prof": prof,
-           "stats": stats, "precision": params.get("precision", 0), "rk": params.get("rk", 0)}
+           "stats": stats, "precision": params.get("precision", 0), "rk": params.get("rk", 0), "delta": delta}
     hist = stats["hist"]
     nsol = max(int(hist.sum()), 1)
     out["newton"] = {"mean_iters": float((hist * np.arange(64)).sum() / nsol),
@@ -204,7 +205,7 @@ def roofline(r, p, workload, general=False):
     out = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
            "algorithmic_bytes_per_launch": tot_bytes / max(n, 1), "avg_launch_ms": ms / max(n, 1)}
-    t = measured_traffic(workload, r["precision"], r["rk"])
+    t = measured_traffic(workload, r["precision"], r["rk"], r.get("delta", 0.0))
     if t is not None:
         out["traffic"] = t["bytes_per_launch"]
         out["traffic_source"] = t["profile"]
