@@ -120,7 +120,7 @@ typedef struct {
                              at a time, while the current stage still streams the
                              other half; 0 = one stream, stage and Newton in turn.
                              Results are identical.  Box path only: ignored on
-                             general meshes and for the reduced pair. */
+                             general meshes. */
 } fr_dvm_params;
 
 /* Fill p with defaults: BGK, Pr 1, mu_ref 1e-3, theta_ref 1, omega 0.81,
@@ -162,8 +162,10 @@ int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes, const fr_
  * (3 + delta)/2 rho theta with E the translational energy of F plus the
  * integral of G; moments report that total E.  Walls emit delta theta_w / 2
  * times their F state as G, the farfield G is delta theta_inf / 2 times the
- * farfield F.  The pair runs on the general path; the learned Newton start
- * is replaced by the cold start.  delta = 0 is fr_dvm_create_nodes.
+ * farfield F.  Periodic axis-aligned boxes keep the fused box path (F's
+ * chunks, then G's, per element), other meshes the general path; the
+ * learned Newton start is replaced by the cold start.  delta = 0 is
+ * fr_dvm_create_nodes.
  * FR_DVM_EINVAL for delta < 0 or not finite. */
 int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, double delta,
                       const fr_dvm_vgrid *grid, fr_dvm_t *out);

@@ -32,6 +32,12 @@
 // neighbour's block of the next stage's trace buffer, so each element reads
 // its exterior states from its own block.  Two trace buffers alternate
 // between stages.
+//
+// Reduced pair (F, G) (Section "Governing equations", moment records of 6 or
+// 11 values): the chunk loop runs over F's velocities, then G's; each
+// component has its own half of the element's trace block.  G relaxes to
+// delta theta / 2 times F's equilibrium (its exponent shifted by the log of
+// that factor) and adds only its integral to the moments.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -78,6 +84,8 @@ struct FrArgs {
     const double *wrow;     // [nv_y nv_z][6] moment weights of a (y, z) row
     StageArgs sa;
     int do_traces, do_moments;
+    int64_t elem_comp;   // trace entries of one component in an element block
+    const double *gfp;   // [npts] the pair's G factor delta theta / 2 (records of 6 / 11)
 };
 
 template <typename Real>
@@ -238,6 +246,10 @@ k_fr_layer(const FrArgs A) {
     constexpr int VPM = (kChunk + N - 1) / N;       // chunk velocities per wave in the moment pass
     constexpr bool FLUX = MODE != MODE_PRIME;
     constexpr bool STAGE = MODE == MODE_STAGE;
+    // moment records of 6 / 11 values: the reduced pair (F, G), per point F
+    // then G (nu values each); G is advected like F, relaxes to delta theta /
+    // 2 times F's equilibrium and adds only its integral to the moments
+    constexpr int NCOMP = (NMOM == 6 || NMOM == 11) ? 2 : 1;
     // the chunk's stage value (all layers, for the z lines) and z-face inflow
     // traces; the produced value (for the z traces and the moments).  The
     // prime pass uses the two value tiles alternately, chunk by chunk.  The
@@ -264,9 +276,9 @@ k_fr_layer(const FrArgs A) {
     const int vl = tid & (kChunk - 1);                       // velocity of the chunk (lane)
     const int l = __builtin_amdgcn_readfirstlane(tid >> 6);  // z-layer of the wave
     const int nu = A.nu;
-    const int64_t ebase = e * (int64_t)NS * nu;
-    const uint32_t lrow = (uint32_t)(l * NL) * (uint32_t)nu;     // offset of the layer inside the element
-    const uint32_t QB = (uint32_t)nu * (uint32_t)sizeof(Real);  // bytes between solution points
+    const int64_t ebase = e * (int64_t)NS * nu * NCOMP;
+    const uint32_t lrow = (uint32_t)(l * NL) * (uint32_t)(nu * NCOMP);  // offset of the layer inside the element
+    const uint32_t QB = (uint32_t)(nu * NCOMP) * (uint32_t)sizeof(Real);  // bytes between solution points
 
     const bool collide = STAGE && A.sa.collide;
     // equilibrium records of this wave's layer: c0, V, B, 1/tau per point,
@@ -289,7 +301,12 @@ k_fr_layer(const FrArgs A) {
             s_ev[s * 4] = q[EQ_V];
             s_ev[s * 4 + 1] = q[EQ_V + 1];
             s_ev[s * 4 + 2] = q[EQ_V + 2];
-            s_ev[s * 4 + 3] = 0.0;
+            if constexpr (NCOMP == 2) {
+                const double gf = A.gfp[e * NS + s];
+                s_ev[s * 4 + 3] = gf > 0.0 ? log(gf) : -1000.0;  // the G exponent shift
+            } else {
+                s_ev[s * 4 + 3] = 0.0;
+            }
         }
     }
 
@@ -332,6 +349,7 @@ k_fr_layer(const FrArgs A) {
                                                             : reinterpret_cast<const Real *>(A.sa.dF) + ebase)
                                         : nullptr;
     const int nchunk = (nu + kChunk - 1) / kChunk;
+    const int ntot = NCOMP * nchunk;  // chunks of all components, F first
 
     // The stage value and the inflow traces of chunk c+1 are requested while
     // chunk c is computed.  Of the z-face traces (N^2 points per velocity,
@@ -356,12 +374,14 @@ k_fr_layer(const FrArgs A) {
         }
     }
 
-    for (int ch = 0; ch < nchunk; ++ch) {
+    for (int cc = 0; cc < ntot; ++cc) {
+        const int comp = NCOMP == 2 && cc >= nchunk ? 1 : 0;
+        const int ch = cc - comp * nchunk;
         const Vel v = velocity(A, ch * kChunk + vl, true);
-        const uint32_t o = (lrow + (uint32_t)v.k) * (uint32_t)sizeof(Real);
+        const uint32_t o = (lrow + (uint32_t)(comp * nu + v.k)) * (uint32_t)sizeof(Real);
         // tile taking the stage value of the chunk, and tile read by the z
         // traces and the moment pass (the same, alternating, for the prime pass)
-        Real *const tpub = FLUX ? tS : ((ch & 1) ? tP : tS);
+        Real *const tpub = FLUX ? tS : ((cc & 1) ? tP : tS);
         Real *const tout = FLUX ? tP : tpub;
         // Publish the stage value (the prime pass: into the tile its z traces
         // and moments read) and this wave's z-face traces; every later use of
@@ -374,9 +394,13 @@ k_fr_layer(const FrArgs A) {
             for (int a = 0; a < N; ++a) tZ[tix<Real>(N * l + a, vl)] = TZ[a];
         }
         TraceOff nx{0u, 0u}, ny{0u, 0u};
+        // the next chunk (possibly the first of the next component)
+        const int compn = NCOMP == 2 && cc + 1 >= nchunk ? 1 : 0;
+        const Real *__restrict__ trEn = trE + (NCOMP == 2 ? compn * A.elem_comp : 0);
         {
-            const Vel vn = velocity(A, (ch + 1) * kChunk + vl, true);
-            const uint32_t on = (lrow + (uint32_t)vn.k) * (uint32_t)sizeof(Real);
+            const int chn = cc + 1 - compn * nchunk;
+            const Vel vn = velocity(A, chn * kChunk + vl, NCOMP == 1 || cc + 1 < ntot);
+            const uint32_t on = (lrow + (uint32_t)(compn * nu + vn.k)) * (uint32_t)sizeof(Real);
 #pragma unroll
             for (int q = 0; q < NL; ++q) fc[q] = ldb(fE, on + q * QB);
             if (FLUX) {
@@ -384,7 +408,7 @@ k_fr_layer(const FrArgs A) {
                 ny = trace_in<Real>(A, T, vn, 1, N * l);
                 const TraceOff nz = trace_in<Real>(A, T, vn, 2, N * l);
 #pragma unroll
-                for (int a = 0; a < N; ++a) TZ[a] = ldb(trE, nz.off + a * nz.stride);
+                for (int a = 0; a < N; ++a) TZ[a] = ldb(trEn, nz.off + a * nz.stride);
             }
         }
         // the second RK register of this chunk, requested before the x/y/z
@@ -422,7 +446,7 @@ k_fr_layer(const FrArgs A) {
                     for (int m = 0; m < N; ++m) fm += T.lam[sin_][m] * g[m];
                     Real &tin = d == 0 ? TX[a] : TY[a];
                     const Real jmp = flow ? un * (tin - fm) : Real(0);
-                    tin = ldb(trE, sn.off + a * sn.stride);
+                    tin = ldb(trEn, sn.off + a * sn.stride);
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
                         Real t = Real(0);
@@ -486,7 +510,11 @@ k_fr_layer(const FrArgs A) {
                     double t1 = b[1] * c1;
                     t1 = fma(b[5], c2, t1);
                     const double t2 = b[2] * c2;
-                    double E = fma(c0, t0, b[6]);
+                    double E;
+                    if constexpr (NCOMP == 2)
+                        E = fma(c0, t0, comp ? b[6] + V[3] : b[6]);
+                    else
+                        E = fma(c0, t0, b[6]);
                     E = fma(c1, t1, E);
                     E = fma(c2, t2, E);
                     L += (exp_r<Real>(E) - fq) * (Real)b[7];
@@ -503,7 +531,14 @@ k_fr_layer(const FrArgs A) {
                     double S = c0 * t0;
                     S = fma(c1, t1, S);
                     S = fma(c2 * rq[EQ_B + 2], c2, S);
-                    const double E = fma(-0.5, S, rq[EQ_C0]);
+                    double lc = rq[EQ_C0];
+                    if constexpr (NCOMP == 2) {
+                        if (comp) {
+                            const double gq = A.gfp[e * NS + l * NL + q];
+                            lc += gq > 0.0 ? log(gq) : -1000.0;
+                        }
+                    }
+                    const double E = fma(-0.5, S, lc);
                     L += (exp_r<Real>(E) - fq) * (Real)rq[EQ_INVTAU];
                 }
                 Real fo;
@@ -531,7 +566,8 @@ k_fr_layer(const FrArgs A) {
                     const int side = v.sgn[d] > 0 ? 1 : 0;
                     const int face = 2 * d + side;
                     const int cnt = (int)T.cnt[face];
-                    Real *tp = trout + T.nb[face] + T.fo[face] + compact_index(A.vg, d, side, v.iv) +
+                    Real *tp = trout + T.nb[face] + (NCOMP == 2 ? comp * A.elem_comp : 0) + T.fo[face] +
+                               compact_index(A.vg, d, side, v.iv) +
                                (int64_t)(N * l) * cnt;
 #pragma unroll
                     for (int a = 0; a < N; ++a) {
@@ -563,7 +599,8 @@ k_fr_layer(const FrArgs A) {
                 const int side = v.sgn[2] > 0 ? 1 : 0;
                 const int face = 4 + side;
                 const int cnt = (int)T.cnt[face];
-                Real *tp = trout + T.nb[face] + T.fo[face] + compact_index(A.vg, 2, side, v.iv) +
+                Real *tp = trout + T.nb[face] + (NCOMP == 2 ? comp * A.elem_comp : 0) + T.fo[face] +
+                           compact_index(A.vg, 2, side, v.iv) +
                            (int64_t)(N * l) * cnt;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
@@ -600,11 +637,21 @@ k_fr_layer(const FrArgs A) {
                     a2 = fma(wx3[3 * ix + 2], x, a2);
                     if (++ix == nx || j == jn - 1) {
                         cdouble *wr = wrow + 6 * row;
+                        if (NCOMP == 2 && comp) {
+                            // G: only its integral
+                            M[NMOM - 1] = fma(wr[0], a0, M[NMOM - 1]);
+                            a0 = a1 = a2 = 0.0;
+                            if (ix == nx) {
+                                ix = 0;
+                                ++row;
+                            }
+                            continue;
+                        }
                         M[0] = fma(wr[0], a0, M[0]);
                         M[1] = fma(wr[0], a1, M[1]);
                         M[2] = fma(wr[1], a0, M[2]);
                         M[3] = fma(wr[2], a0, M[3]);
-                        if constexpr (NMOM == 5) {
+                        if constexpr (NMOM == 5 || NMOM == 6) {
                             M[4] = fma(0.5, fma(wr[0], a2, (wr[3] + wr[4]) * a0), M[4]);
                         } else {
                             M[4] = fma(wr[0], a2, M[4]);
@@ -714,10 +761,15 @@ int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int 
     A.sa = sa;
     A.do_traces = do_traces;
     A.do_moments = do_moments;
+    A.elem_comp = h->tl.elem / h->ncomp;
+    A.gfp = h->d_gfp;
     const bool fp64 = h->prm.precision == FR_DVM_FP64;
-    if (h->nmom == 5)
-        return fp64 ? launch_np<double, 5>(h, mode, A) : launch_np<float, 5>(h, mode, A);
-    return fp64 ? launch_np<double, 10>(h, mode, A) : launch_np<float, 10>(h, mode, A);
+    switch (h->nmom) {
+        case 5: return fp64 ? launch_np<double, 5>(h, mode, A) : launch_np<float, 5>(h, mode, A);
+        case 6: return fp64 ? launch_np<double, 6>(h, mode, A) : launch_np<float, 6>(h, mode, A);
+        case 10: return fp64 ? launch_np<double, 10>(h, mode, A) : launch_np<float, 10>(h, mode, A);
+    }
+    return fp64 ? launch_np<double, 11>(h, mode, A) : launch_np<float, 11>(h, mode, A);
 }
 
 }  // namespace frdvm

@@ -244,8 +244,9 @@ int setup_axis(fr_dvm *h, const fr_dvm_mesh *mesh, std::vector<double> &wq3J) {
         tl.face_off[f] = off;
         off += tl.cnt[f] * h->nfp;
     }
-    tl.elem = off;
+    tl.elem = off * h->ncomp;  // one such layout per component of the state
     int rc;
+    if (h->ncomp == 2 && (rc = dev_alloc(h, &h->d_gfp, (size_t)h->ne * h->ns))) return rc;
     if ((rc = dev_alloc(h, &h->d_gfac, 3 * h->ne))) return rc;
     return upload(h, h->d_gfac, h->h_gfac.data(), 3 * h->ne * sizeof(double));
 }
@@ -537,8 +538,7 @@ extern "C" int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, 
                 return bail(h->fail(FR_DVM_EINVAL, "neighbour relation is not symmetric"));
         }
     std::vector<double> wq3J(h->ne * h->ns);
-    // the reduced pair runs on the general path
-    int rc = h->ncomp == 1 ? setup_axis(h, mesh, wq3J) : kNotAxis;
+    int rc = setup_axis(h, mesh, wq3J);
     if (rc == kNotAxis) rc = setup_general(h, mesh, wq3J);
     if (rc) return bail(rc);
 

@@ -64,7 +64,8 @@ def _mesh(name):
     return W.cylinder_mesh(n_theta=6, n_r=2, n_z=1, r1=2.0, half=True)
 
 
-@pytest.mark.parametrize("name,p", [("box", 1), ("box", 3), ("cylinder", 2), ("half", 2)])
+# periodic boxes run on the fused box path, the O-grids on the general path
+@pytest.mark.parametrize("name,p", [("box", 1), ("box", 2), ("box", 3), ("cylinder", 2), ("half", 2)])
 def test_pair_residual(F, orc, name, p):
     grid = GRID if name != "half" else W.grid_spec((7, 6, 5), 5.0)
     P, s = _make(orc, F, _mesh(name), p, grid, _params())
@@ -99,12 +100,14 @@ def test_pair_collide_moments_kn(F, orc, model):
     assert rel(kn.cpu().numpy().reshape(s.ne, s.ns), P.kn_gll(f)) < 1e-12
 
 
-@pytest.mark.parametrize("name,rk", [("box", 0), ("box", 1), ("cylinder", 0)])
-def test_pair_rk_steps_es(F, orc, name, rk):
+# (5, 5, 6) nodes: 150 velocities, an odd number of 64-wide chunks per component
+@pytest.mark.parametrize("name,rk,p,nv", [("box", 0, 2, 8), ("box", 1, 2, 8), ("box", 1, 3, (5, 5, 6)),
+                                          ("box", 0, 1, (5, 5, 6)), ("cylinder", 0, 2, 8)])
+def test_pair_rk_steps_es(F, orc, name, rk, p, nv):
     mesh = _mesh(name)
-    grid = W.grid_spec(8, 6.0)
+    grid = W.grid_spec(nv, 6.0)
     par = _params(model=1, prandtl=0.71, mu_ref=0.02, rk=rk)
-    P, s = _make(orc, F, mesh, 2, grid, par)
+    P, s = _make(orc, F, mesh, p, grid, par)
     f0 = _pair_of(P, grid, 5, amp=0.1)
     dt = P.dt(0.2)
     ref = P.rk_step(f0, dt, scheme=rk, nsteps=2)
@@ -128,6 +131,26 @@ def test_pair_mixed_precision_bounds(F, orc):
     Qg, Qr = P.moments(got), P.moments(ref)
     for a in range(5):
         assert rel(Qg[..., a], Qr[..., a]) < 1e-6, a
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pair_overlapped_newton_is_identical(F, orc, precision):
+    # the Newton solve of the next stage on the second stream, half of the
+    # elements at a time, gives the same bits as the one-stream order
+    mesh = W.box_mesh((4, 2, 2), length=(1.0, 0.5, 0.5))
+    grid = W.grid_spec((5, 5, 6), 6.0)
+    out = []
+    for ov in (0, 1):
+        par = _params(model=1, prandtl=0.71, mu_ref=0.02, rk=1, precision=precision, guess=0, overlap=ov)
+        P, s = _make(orc, F, mesh, 2, grid, par)
+        f0 = _pair_of(P, grid, 9, amp=0.1)
+        f = _gpu(s, f0)
+        dt = P.dt(0.2)
+        s.rk_steps(f, dt, 3)
+        out.append(f.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+    if precision == 0:
+        assert rel(out[1], P.rk_step(f0, dt, scheme=1, nsteps=3)) < 1e-12
 
 
 def test_pair_periodic_step_conserves_total_energy(F):
