@@ -110,7 +110,7 @@ __device__ __forceinline__ double exp_r<double>(double E) {
 
 // Element-relative access: `base` is uniform (one element's slab), `boff`
 // the lane's byte offset inside it (a slab stays below 4 GiB: at most
-// 64 solution points x 64^3 velocities x 8 bytes).
+// 64 solution points x 2 components x 64^3 velocities x 8 bytes).
 template <typename T>
 __device__ __forceinline__ T ldb(const T *base, uint32_t boff) {
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + boff);
