@@ -296,7 +296,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU sharding is not implemented",
+        print(json.dumps({"error": "the benchmark runs on exactly one GPU; multi-GPU sharding is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
