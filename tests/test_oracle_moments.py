@@ -96,3 +96,60 @@ def test_knudsen_to_reference_viscosity():
     for kn in (0.05, 1e-3, 2e-4):
         mu = W.mu_ref_from_knudsen(kn)
         assert mu * np.sqrt(np.pi / 2) == pytest.approx(kn, rel=1e-15)
+
+
+def _uniform_moments(rho, U, theta):
+    U = np.asarray(U, float)
+    return np.array([rho, *(rho * U), 0.5 * rho * U @ U + 1.5 * rho * theta])
+
+
+@pytest.mark.parametrize("p,nodes", [(1, 0), (3, 0), (2, 1)])
+def test_totals_of_uniform_maxwellian_are_volume_times_moments(orc, p, nodes):
+    """Domain totals of a uniform sampled Maxwellian on a box of side lengths
+    (0.7, 1.3, 0.9): V (rho, rho U, E) with V = 0.819 and the closed-form
+    moments (fine velocity grid: trapezoid aliasing below 1e-20)."""
+    mesh = W.box_mesh((1, 2, 1), length=(0.7, 1.3, 0.9))
+    grid = W.grid_spec(31, 9.0)
+    P = orc.Problem(mesh, p, grid, {"model": 2, "mu_ref": 1.0, "nodes": nodes})
+    rho, U, th = 1.3, (0.3, -0.2, 0.1), 0.9
+    prim = np.tile([rho, *U, th], (P.ne, P.ns, 1))
+    f = W.maxwellian(prim, grid).numpy()
+    V = 0.7 * 1.3 * 0.9
+    ref = V * _uniform_moments(rho, U, th)
+    assert np.allclose(P.totals(f), ref, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_totals_of_linear_density_on_curved_mesh(orc, p):
+    """rho(X) = 1 + a . X on the image of the unit cube under the quadratic
+    map X = x + eps (y^2, z^2, x^2), with U and theta uniform: the mass total
+    is the integral of rho over the image, computed here by a 12-point Gauss
+    rule on the unit cube with the map's Jacobian 1 + 8 eps^3 x y z, and the
+    other totals follow from the uniform U and theta."""
+    eps = 0.2
+    N = (2, 1, 2)
+    mesh = W.quadratic_map_mesh(N, eps=eps)
+    grid = W.grid_spec(31, 10.0)
+    P = orc.Problem(mesh, p, grid, {"model": 2, "mu_ref": 1.0})
+    a = np.array([0.3, -0.2, 0.25])
+    U, th = np.array([0.2, 0.1, -0.3]), 1.1
+    n = p + 1
+    xi = np.polynomial.legendre.leggauss(n)[0]
+    rho = np.zeros((P.ne, P.ns))
+    for e in range(P.ne):
+        idx = np.array((e % N[0], (e // N[0]) % N[1], e // (N[0] * N[1])))
+        for s in range(P.ns):
+            r = np.array([xi[s % n], xi[(s // n) % n], xi[s // (n * n)]])
+            x = (idx + 0.5 * (r + 1.0)) / np.array(N)
+            X = x + eps * np.array([x[1] ** 2, x[2] ** 2, x[0] ** 2])
+            rho[e, s] = 1.0 + a @ X
+    prim = np.concatenate([rho[..., None], np.broadcast_to(U, rho.shape + (3,)), np.full(rho.shape + (1,), th)], -1)
+    f = W.maxwellian(prim, grid).numpy()
+    g, wg = np.polynomial.legendre.leggauss(12)
+    g, wg = 0.5 * (g + 1.0), 0.5 * wg
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    wt = wg[:, None, None] * wg[None, :, None] * wg[None, None, :]
+    X = np.stack([x + eps * y ** 2, y + eps * z ** 2, z + eps * x ** 2])
+    mass = float(np.sum(wt * (1.0 + np.tensordot(a, X, 1)) * (1.0 + 8.0 * eps ** 3 * x * y * z)))
+    ref = mass * _uniform_moments(1.0, U, th)
+    assert np.allclose(P.totals(f), ref, rtol=1e-13, atol=1e-14)
