@@ -47,6 +47,8 @@ extern "C" {
 #define FR_DVM_ENOMEM (-2)      /* device allocation failed */
 #define FR_DVM_EHIP (-3)        /* HIP runtime error */
 #define FR_DVM_EUNSUPPORTED (-4) /* valid input this build does not handle */
+#define FR_DVM_ESCRATCH (-5)     /* request larger than the fixed scratch of a
+                                    no-allocation entry point */
 
 /* collision models (Section "Governing equations") */
 #define FR_DVM_BGK 0

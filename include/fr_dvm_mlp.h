@@ -47,6 +47,20 @@ size_t fr_mlp_workspace_floats(int H, int64_t B);
 /* Prediction dz[B][5] (denormalised) for features X[B][FR_MLP_INPUTS]. */
 int fr_mlp_forward(int H, const float *w, const float *X, int64_t B, float *dz, float *work, void *stream);
 
+/* fr_mlp_forward without allocation or workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The intermediate activations live in a
+ * fixed library scratch of FR_MLP_NOALLOC_FLOATS floats (16 MiB) per GPU,
+ * held from the first call on that GPU until the process ends; a batch needs
+ * B * (2 H + 5) floats of it (H = 64: B <= 31,536).  Larger requests return
+ * FR_DVM_ESCRATCH before anything is launched.  No hipMalloc, hipFree or
+ * allocating library routine is called.  Every call on one GPU shares its
+ * scratch: calls that overlap on one GPU (other streams, other threads) race
+ * and must be ordered by the caller.  Results equal fr_mlp_forward's bit for
+ * bit (same kernels, same order). */
+#define FR_MLP_NOALLOC_FLOATS ((size_t)1 << 22)
+int fr_mlp_forward_noalloc(int H, const float *w, const float *X, int64_t B, float *dz, void *stream);
+
 /* Mean-squared-error loss L = 1/(2B) sum |y - T|^2 on normalised targets T,
  * its gradient grad[param_count] (zero on the output affine) and L itself
  * (device float[1]). */

@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/fr_dvm_mlp.h"
 #include "frdvm_common.h"
@@ -180,6 +181,32 @@ void forward(hipStream_t s, int H, const float *w, const float *X, int64_t B, co
     hipLaunchKernelGGL(k_bias_act, dim3(blocks(B * 5)), dim3(256), 0, s, B, 5, wk.Y, w + L.b[3], (float *)nullptr, 0);
 }
 
+// Scratch of fr_mlp_forward_noalloc: two [B][H] activation buffers used in
+// turn (each layer's GEMM writes one from the other, bias and SiLU in place)
+// and the [B][5] output.  In host code `scratch` names a host-side stand-in;
+// kernels receive the device address from hipGetSymbolAddress, kept per GPU.
+static __device__ __align__(256) float scratch[FR_MLP_NOALLOC_FLOATS];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+float *scratch_dev[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch, looked up once per GPU with
+// that GPU current.
+int scratch_ptr(float **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return FR_DVM_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return FR_DVM_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FR_DVM_EHIP;
+        scratch_dev[dev] = static_cast<float *>(ptr);
+    }
+    *out = scratch_dev[dev];
+    return FR_DVM_OK;
+}
+
 int hip_ok(const char *what) {
     (void)what;
     return hipGetLastError() == hipSuccess ? FR_DVM_OK : FR_DVM_EHIP;
@@ -205,6 +232,30 @@ extern "C" int fr_mlp_forward(int H, const float *w, const float *X, int64_t B, 
     Layout L = layout(H);
     hipLaunchKernelGGL(k_affine, dim3(blocks(B * 5)), dim3(256), 0, s, B, wk.Y, w + L.scale, w + L.offset, dz);
     return hip_ok("mlp forward");
+}
+
+extern "C" int fr_mlp_forward_noalloc(int H, const float *w, const float *X, int64_t B, float *dz, void *stream) {
+    if (H < 1 || H > 1024 || B < 0 || !w || (B > 0 && (!X || !dz))) return FR_DVM_EINVAL;
+    if (B == 0) return FR_DVM_OK;
+    if ((size_t)B > FR_MLP_NOALLOC_FLOATS / (size_t)(2 * H + 5)) return FR_DVM_ESCRATCH;
+    float *base = nullptr;
+    int rc = scratch_ptr(&base);
+    if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Layout L = layout(H);
+    float *act[2] = {base, base + (size_t)B * H};
+    float *Y = base + (size_t)2 * B * H;
+    const float *a = X;
+    for (int l = 0; l < 3; ++l) {
+        float *z = act[l & 1];
+        gemm(s, (int)B, H, L.in[l], a, L.in[l], 0, w + L.W[l], L.in[l], 1, z, H);
+        hipLaunchKernelGGL(k_bias_act, dim3(blocks(B * H)), dim3(256), 0, s, B, H, z, w + L.b[l], z, 1);
+        a = z;
+    }
+    gemm(s, (int)B, 5, H, a, H, 0, w + L.W[3], H, 1, Y, 5);
+    hipLaunchKernelGGL(k_bias_act, dim3(blocks(B * 5)), dim3(256), 0, s, B, 5, Y, w + L.b[3], (float *)nullptr, 0);
+    hipLaunchKernelGGL(k_affine, dim3(blocks(B * 5)), dim3(256), 0, s, B, Y, w + L.scale, w + L.offset, dz);
+    return hip_ok("mlp forward (no allocation)");
 }
 
 extern "C" int fr_mlp_grad(int H, const float *w, const float *X, const float *T, int64_t B, float *grad, float *loss,

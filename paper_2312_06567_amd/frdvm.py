@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libfrdvm.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "fr_dvm.h")
 
 BGK, ESBGK, FREE = 0, 1, 2
+E_SCRATCH = -5  # FR_DVM_ESCRATCH of fr_dvm.h
+MLP_NOALLOC_FLOATS = 1 << 22  # FR_MLP_NOALLOC_FLOATS of fr_dvm_mlp.h
 FP64, FP32 = 0, 1
 GUESS_COLD, GUESS_WARM, GUESS_MLP, GUESS_MLP_WARM = 0, 1, 2, 3
 MLP_INPUTS = 13  # FR_MLP_INPUTS of fr_dvm_mlp.h
@@ -84,6 +86,7 @@ def lib():
         L.fr_mlp_workspace_floats.argtypes = [C.c_int, C.c_int64]
         L.fr_mlp_workspace_floats.restype = C.c_size_t
         L.fr_mlp_forward.argtypes = [C.c_int, vp, vp, C.c_int64, vp, vp, vp]
+        L.fr_mlp_forward_noalloc.argtypes = [C.c_int, vp, vp, C.c_int64, vp, vp]
         L.fr_mlp_grad.argtypes = [C.c_int, vp, vp, vp, C.c_int64, vp, vp, vp, vp]
         L.fr_mlp_adam.argtypes = [C.c_int, vp, vp, vp, vp, C.c_int, C.c_float, vp]
         L.fr_dvm_hbm_copy.argtypes = [vp, vp, C.c_size_t, vp]
@@ -137,6 +140,17 @@ class Mlp:
         rc = lib().fr_mlp_forward(self.H, _ptr(w), _ptr(X), B, _ptr(out), _ptr(work), None)
         if rc != 0:
             raise FrDvmError(f"fr_mlp_forward failed ({rc})")
+        return out
+
+    def forward_noalloc(self, w, X, out, stream=None):
+        """Forward pass on the library's fixed per-GPU scratch (no allocation,
+        no workspace); ``out`` [B, 5] float32 must be given."""
+        if X.dim() != 2 or X.shape[1] != MLP_INPUTS:
+            raise FrDvmError(f"features must be [B, {MLP_INPUTS}]")
+        s = getattr(stream, "cuda_stream", stream) or 0
+        rc = lib().fr_mlp_forward_noalloc(self.H, _ptr(w), _ptr(X), X.shape[0], _ptr(out), C.c_void_p(int(s)))
+        if rc != 0:
+            raise FrDvmError(f"fr_mlp_forward_noalloc failed ({rc})")
         return out
 
     def grad(self, w, X, T, grad=None, loss=None, work=None):
