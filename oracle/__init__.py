@@ -59,7 +59,8 @@ class _Problem(C.Structure):
                 ("theta_ref", C.c_double), ("omega", C.c_double),
                 ("visc_law", C.c_int32), ("theta_s", C.c_double),
                 ("newton_tol", C.c_double), ("newton_max_iter", C.c_int32), ("nv", C.c_int32 * 3),
-                ("nodes", C.c_int32), ("delta", C.c_double), ("ncomp", C.c_int32)]
+                ("nodes", C.c_int32), ("delta", C.c_double), ("ncomp", C.c_int32),
+                ("positivity", C.c_int32)]
 
 
 def _declare(L):
@@ -79,6 +80,7 @@ def _declare(L):
     L.orc_collide.argtypes = [P, C.c_int64, _dp, _dp, _dp, _dp, _ip, _ip]
     L.orc_rhs.argtypes = [P, _dp, _dp]
     L.orc_rk_step.argtypes = [P, _dp, C.c_double, C.c_int, C.c_int]
+    L.orc_positivity.argtypes = [P, _dp]
     L.orc_totals.argtypes = [P, _dp, _dp]
     L.orc_state_moments.argtypes = [P, C.c_int64, _dp, _dp]
     L.orc_kn_gll.argtypes = [P, _dp, _dp]
@@ -220,6 +222,7 @@ class Problem:
         s.nodes = self.nodes
         s.delta = self.delta
         s.ncomp = self.ncomp
+        s.positivity = int(params.get("positivity", 0))
         self._s = s
 
     @property
@@ -260,6 +263,15 @@ class Problem:
         rc = lib().orc_rk_step(C.byref(self._s), _d(f), float(dt), int(scheme), int(nsteps))
         if rc != 0:
             raise RuntimeError(f"oracle rk_step rc={rc}")
+        return f
+
+    def positivity(self, f):
+        """The positivity limiter applied to a copy of f (every element, every
+        state value): nonnegative at solution and flux points, element means
+        kept."""
+        f = _f64(f).reshape(self.shape).copy()
+        if lib().orc_positivity(C.byref(self._s), _d(f)) != 0:
+            raise RuntimeError("oracle positivity")
         return f
 
     def moments(self, f):

@@ -333,6 +333,7 @@ typedef struct {
     int32_t nodes;           /* solution points: 0 Gauss-Legendre, 1 Gauss-Lobatto */
     double delta;            /* internal degrees of freedom; > 0: the reduced pair (F, G) */
     int32_t ncomp;           /* 1 (monatomic f) or 2 (F then G per point, each nu values) */
+    int32_t positivity;      /* 1: limit every RK stage value to f >= 0 (orc_positivity) */
 } orc_problem;
 
 /* Neighbour face point for own face point (a,b) under orientation code o:
@@ -939,6 +940,62 @@ int orc_rhs(const orc_problem *P, const double *f, double *L) {
  *   A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15):
  *   dF = A_k dF + dt L(f); f = f + B_k dF.
  */
+/*
+ * Positivity limiter (Section "Numerical method": the scheme is the cited
+ * positivity-preserving and conservative FR method; the limiter is the
+ * scaling of Zhang and Shu).  For every element and every state value (each
+ * velocity node of each component) separately:
+ *   mean = sum_s W_s f_s / sum_s W_s,  W_s = (Gauss weight x |J|) at point s,
+ *          the element integral of the value's polynomial over its volume;
+ *   m    = the smallest value of the polynomial at the element's solution
+ *          points and at its flux points (the face traces);
+ *   if m < 0:  theta = mean / (mean - m) (0 if mean <= 0),
+ *              f_s <- mean + theta (f_s - mean) at every solution point.
+ * The mean, hence the element integral of every moment, is unchanged, and
+ * the limited polynomial is nonnegative at all those points.
+ */
+int orc_positivity(const orc_problem *P, double *f) {
+    const int n = P->p + 1, ns = n * n * n, nfp = n * n;
+    const int nut = P->nu * P->ncomp;
+    double xi[16], wq[16], xd[16], D[16 * 16], lam[2][16], cM[16], cP[16];
+    solution_points(P->nodes, n, xi, wq);
+    if (orc_fr_ops_set(P->p, P->nodes, xd, D, lam[0], lam[1], cM, cP)) return ORC_EINVAL;
+#pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < P->ne; ++e) {
+        double Wt[729];  /* ns <= 9^3 */
+        ld wsum = 0;
+        for (int l = 0; l < n; ++l)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    const int s = sidx(n, i, j, l);
+                    Wt[s] = wq[i] * wq[j] * wq[l] * P->detJ[e * ns + s];
+                    wsum += Wt[s];
+                }
+        for (int k = 0; k < nut; ++k) {
+            double *fe = f + (int64_t)e * ns * nut + k;  /* stride nut between points */
+            ld acc = 0;
+            double m = fe[0];
+            for (int s = 0; s < ns; ++s) {
+                acc += (ld)Wt[s] * fe[(int64_t)s * nut];
+                if (fe[(int64_t)s * nut] < m) m = fe[(int64_t)s * nut];
+            }
+            for (int d = 0; d < 3; ++d)
+                for (int side = 0; side < 2; ++side)
+                    for (int q = 0; q < nfp; ++q) {
+                        ld t = 0;
+                        for (int mm = 0; mm < n; ++mm)
+                            t += (ld)lam[side][mm] * fe[(int64_t)line_idx(n, d, q % n, q / n, mm) * nut];
+                        if ((double)t < m) m = (double)t;
+                    }
+            if (!(m < 0.0)) continue;
+            const double mean = (double)(acc / wsum);
+            const double th = mean > 0.0 ? mean / (mean - m) : 0.0;
+            for (int s = 0; s < ns; ++s) fe[(int64_t)s * nut] = mean + th * (fe[(int64_t)s * nut] - mean);
+        }
+    }
+    return ORC_OK;
+}
+
 int orc_rk_step(const orc_problem *P, double *f, double dt, int scheme, int nsteps) {
     int n = P->p + 1, ns = n * n * n;
     int64_t tot = (int64_t)P->ne * ns * P->nu * P->ncomp;
@@ -951,12 +1008,15 @@ int orc_rk_step(const orc_problem *P, double *f, double dt, int scheme, int nste
             rc |= orc_rhs(P, f, b);
 #pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < tot; ++i) a[i] = f[i] + dt * b[i];
+            if (P->positivity) rc |= orc_positivity(P, a);
             rc |= orc_rhs(P, a, b);
 #pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < tot; ++i) a[i] = 0.75 * f[i] + 0.25 * (a[i] + dt * b[i]);
+            if (P->positivity) rc |= orc_positivity(P, a);
             rc |= orc_rhs(P, a, b);
 #pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < tot; ++i) f[i] = f[i] / 3.0 + 2.0 / 3.0 * (a[i] + dt * b[i]);
+            if (P->positivity) rc |= orc_positivity(P, f);
         } else {
             const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
             const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
@@ -967,6 +1027,7 @@ int orc_rk_step(const orc_problem *P, double *f, double dt, int scheme, int nste
                     a[i] = (st == 0 ? 0.0 : A[st] * a[i]) + dt * b[i];
                     f[i] += B[st] * a[i];
                 }
+                if (P->positivity) rc |= orc_positivity(P, f);
             }
         }
     }
