@@ -123,10 +123,21 @@ typedef struct {
                              other half; 0 = one stream, stage and Newton in turn.
                              Results are identical.  Box path only: ignored on
                              general meshes. */
+    int32_t positivity;   /* 1: positivity limiter on every RK stage value (the
+                             cited positivity-preserving FR scheme of Section
+                             "Numerical method"): per element and state value,
+                             the polynomial is scaled about its element mean
+                             (Gauss weights x |J|) so that it is nonnegative at
+                             the solution and flux points; element integrals,
+                             hence all moments, are kept.  Runs in the
+                             general-mesh stage kernel: a periodic box handle
+                             moves to that path for good at the first
+                             fr_dvm_set_params with positivity 1.  0: off. */
 } fr_dvm_params;
 
 /* Fill p with defaults: BGK, Pr 1, mu_ref 1e-3, theta_ref 1, omega 0.81,
- * FP64, tol 1e-13, 50 iterations, cold guess, SSP-RK3, overlap 0. */
+ * FP64, tol 1e-13, 50 iterations, cold guess, SSP-RK3, overlap 0,
+ * positivity 0. */
 void fr_dvm_default_params(fr_dvm_params *p);
 
 /* Create a handle for a mesh, FR order p (solution points (p+1)^3 per
@@ -229,6 +240,14 @@ int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps);
  * pointer may be NULL.  reset != 0 clears the counters afterwards. */
 int fr_dvm_newton_stats(fr_dvm_t h, int64_t *iters_hist, int64_t *n_fallback,
                         int64_t *n_guard, int64_t *n_evals, double *max_resid, int reset);
+
+/* Per-point outcome of the handle's most recent conservative-equilibrium
+ * solve (the last Newton launch of rk_step(s), or collide): status
+ * (FR_DVM_NEWTON_*), linear solves and final scaled residual of every
+ * solution point, into caller-owned DEVICE arrays int32 status[e][s], int32
+ * iters[e][s], double resid[e][s] (any may be NULL).  Asynchronous on the
+ * handle's stream.  FR_DVM_EINVAL before the first solve. */
+int fr_dvm_newton_points(fr_dvm_t h, int32_t *status, int32_t *iters, double *resid);
 
 /* Weights of the learned Newton initial guess: an MLP 7 -> H -> H -> H -> 5
  * with SiLU activations (FP32, layout documented in fr_dvm_mlp.h).  n is the

@@ -100,6 +100,7 @@ StageArgs stage_args(fr_dvm *h, void *f, double dt, int st, int collide) {
     StageArgs a = blank();
     a.dt = dt;
     a.collide = collide;
+    a.positivity = h->prm.positivity;
     a.eq = h->d_eq;
     a.tr_in = h->d_tr[h->cur_tr];
     a.tr_out = h->d_tr[h->cur_tr ^ 1];
@@ -218,6 +219,21 @@ extern "C" int fr_dvm_newton_stats(fr_dvm_t h, int64_t *iters_hist, int64_t *n_f
         hipMemset(h->d_stats, 0, sizeof(buf));
         hipMemset(h->d_maxres, 0, sizeof(double));
     }
+    return FR_DVM_OK;
+}
+
+extern "C" int fr_dvm_newton_points(fr_dvm_t h, int32_t *status, int32_t *iters, double *resid) {
+    int rc = ready(h);
+    if (rc) return rc;
+    if (!h->newton_done) return h->fail(FR_DVM_EINVAL, "no conservative-equilibrium solve has run yet");
+    const size_t n = (size_t)h->ne * h->ns;
+    if ((status && hipMemcpyAsync(status, h->d_pt_status, n * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream) !=
+                       hipSuccess) ||
+        (iters && hipMemcpyAsync(iters, h->d_pt_iters, n * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream) !=
+                      hipSuccess) ||
+        (resid && hipMemcpyAsync(resid, h->d_pt_resid, n * sizeof(double), hipMemcpyDeviceToDevice, h->stream) !=
+                      hipSuccess))
+        return h->fail(FR_DVM_EHIP, "per-point Newton outcome copy");
     return FR_DVM_OK;
 }
 

@@ -76,6 +76,15 @@ struct fr_dvm {
     frdvm::TraceLayout tl{};
     double hmin = 0;
 
+    // copy of the caller's mesh of a box handle, kept so that enabling the
+    // positivity limiter can move the handle to the general-mesh path
+    struct MeshCopy {
+        int32_t n_elem = 0, n_nodes = 0, geom_order = 0;
+        std::vector<double> nodes;
+        std::vector<int32_t> elem_nodes, nbr_elem;
+        std::vector<int8_t> nbr_face, nbr_orient, bc;
+    } mesh_copy;
+
     // host geometry (for totals / dt)
     std::vector<double> h_gfac;  // [ne][3]  2/h_d for axis boxes
     std::vector<double> h_detJ;  // [ne][ns]
@@ -115,6 +124,7 @@ struct fr_dvm {
     double *d_z = nullptr;       // [ne*ns][5] Newton solution (warm start)
     double *d_prim = nullptr;    // [ne*ns][5] primitive state of g(Q')
     int zvalid = 0;
+    bool newton_done = false;    // a solve has filled the per-point outcome arrays
     int32_t *d_pt_iters = nullptr;   // [ne*ns] per-point Newton outcome of the last solve
     int32_t *d_pt_evals = nullptr;
     int32_t *d_pt_status = nullptr;
@@ -181,6 +191,7 @@ struct StageArgs {
     int scheme;              // 0 SSP, 1 LSRK
     int keep_dF;             // LSRK: store dF (not after the last stage of a step, where it is dead)
     int collide;             // include the collision source
+    int positivity;          // limit the stage result to f >= 0 (general-mesh kernel)
     int64_t e0, ecount;      // element range [e0, e0 + ecount); ecount 0: all elements
 };
 int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);

@@ -54,6 +54,7 @@ struct GenArgs {
     double gwall;        // the pair's G wall factor delta theta_w / 2
     const double *gfp;   // [npts] the pair's G equilibrium factor delta theta / 2
     const double *wax;   // [3][64] 1-D trapezoid weights
+    const double *wJ;    // [ne][ns] Gauss weight x |J| (positivity limiter)
     const double *S;     // [ne][ns][3][3]
     const double *ijac;  // [ne][ns]
     const double *nf;    // [ne][6][nfp][3]
@@ -452,6 +453,12 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     const Real dt = (Real)A.sa.dt;
     Real *outE = reinterpret_cast<Real *>(A.sa.fout) + eoff;
     Real *dFE = reinterpret_cast<Real *>(A.sa.dF) + eoff;
+    // positivity limiter: the result is held in the lane's column until its
+    // element mean and smallest value are known
+    const bool limit = A.sa.positivity != 0;
+    const cptr<double> gW = (cptr<double>)A.wJ + e * NS;
+    double lim_int = 0.0, lim_w = 0.0;
+    Real lim_min = Real(0);
 #pragma unroll
     for (int s0 = 0; s0 < NS; s0 += NFP) {
         // (p = 3) the layer's second-register values requested together
@@ -488,9 +495,40 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
                 if (A.sa.keep_dF) sto(dFE + s * nu, ko, dd);
                 fo = fq + (Real)A.sa.lsB * dd;
             }
-            sto(outE + s * nu, ko, fo);
             sf[s][lane] = fo;
+            if (limit) {
+                lim_int = fma(gW[s], (double)fo, lim_int);
+                lim_w += gW[s];
+                lim_min = s == 0 ? fo : (fo < lim_min ? fo : lim_min);
+            } else {
+                sto(outE + s * nu, ko, fo);
+            }
         }
+    }
+    if (limit) {
+        // the smallest value of the element polynomial at its solution and
+        // flux points; if negative, scale about the element mean (weights
+        // Gauss x |J|) so that it becomes zero there: the element integral of
+        // the value, hence every moment, is kept
+#pragma unroll 1
+        for (int face = 0; face < 6; ++face) {
+            const int d = face / 2, side = face & 1;
+#pragma unroll 1
+            for (int q = 0; q < NFP; ++q) {
+                Real t = Real(0);
+#pragma unroll
+                for (int m = 0; m < N; ++m) t += op.lam[side][m] * sf[line_pt<N>(d, q % N, q / N, m)][lane];
+                lim_min = t < lim_min ? t : lim_min;
+            }
+        }
+        if (lim_min < Real(0)) {
+            const double mean = lim_int / lim_w;
+            const double th = mean > 0.0 ? mean / (mean - (double)lim_min) : 0.0;
+#pragma unroll 1
+            for (int s = 0; s < NS; ++s) sf[s][lane] = (Real)fma(th, (double)sf[s][lane] - mean, mean);
+        }
+#pragma unroll 4
+        for (int s = 0; s < NS; ++s) sto(outE + s * nu, ko, sf[s][lane]);
     }
     if (A.do_traces) {
         Real *te = reinterpret_cast<Real *>(A.sa.tr_out) + e * 6 * NFP * nu;
@@ -588,6 +626,7 @@ int launch_fr_gen(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int d
     A.gwall = 0.5 * h->delta * h->prm.theta_wall;
     A.gfp = h->d_gfp;
     A.wax = h->d_wax;
+    A.wJ = h->d_wq3J;
     A.S = h->d_S;
     A.ijac = h->d_ijac;
     A.nf = h->d_nf;

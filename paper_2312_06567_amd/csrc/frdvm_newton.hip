@@ -1299,7 +1299,9 @@ int newton_run(fr_dvm *h, NewtonArgs A, int64_t p0, int64_t np, hipStream_t s) {
     if (nb > 1024) nb = 1024;
     hipLaunchKernelGGL(k_stats_reduce, dim3((unsigned)nb), dim3(256), 0, s, A.npts, A.pt_iters, A.pt_evals,
                        A.pt_status, A.pt_resid, A.stats, A.maxres);
-    return check(h, "newton kernel");
+    const int rc = check(h, "newton kernel");
+    if (!rc) h->newton_done = true;
+    return rc;
 }
 
 }  // namespace

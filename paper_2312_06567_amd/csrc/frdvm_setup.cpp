@@ -541,6 +541,19 @@ extern "C" int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, 
     int rc = setup_axis(h, mesh, wq3J);
     if (rc == kNotAxis) rc = setup_general(h, mesh, wq3J);
     if (rc) return bail(rc);
+    if (h->axis_mode) {
+        // kept for a later move to the general-mesh path (positivity limiter)
+        fr_dvm::MeshCopy &mc = h->mesh_copy;
+        mc.n_elem = mesh->n_elem;
+        mc.n_nodes = mesh->n_nodes;
+        mc.geom_order = mesh->geom_order;
+        mc.nodes.assign(mesh->nodes, mesh->nodes + 3 * (size_t)mesh->n_nodes);
+        mc.elem_nodes.assign(mesh->elem_nodes, mesh->elem_nodes + (size_t)ngeo * mesh->n_elem);
+        mc.nbr_elem.assign(mesh->nbr_elem, mesh->nbr_elem + 6 * (size_t)mesh->n_elem);
+        mc.nbr_face.assign(mesh->nbr_face, mesh->nbr_face + 6 * (size_t)mesh->n_elem);
+        mc.nbr_orient.assign(mesh->nbr_orient, mesh->nbr_orient + 6 * (size_t)mesh->n_elem);
+        mc.bc.assign(mesh->bc, mesh->bc + 6 * (size_t)mesh->n_elem);
+    }
 
     // device tables
     if ((rc = dev_alloc(h, &h->d_nbr, 6 * h->ne))) return bail(rc);
@@ -570,6 +583,39 @@ extern "C" int fr_dvm_create(const fr_dvm_mesh *mesh, int order, const fr_dvm_vg
     return fr_dvm_create_gas(mesh, order, 0, 0.0, grid, out);
 }
 
+namespace {
+
+// A box handle moves to the general-mesh path (the positivity limiter runs
+// in the general stage kernel): pointwise metrics, full traces, its own
+// boundary tables.  The box path's trace buffers are released here (their
+// size depends on the path) and reallocated by the caller.
+int move_to_general(fr_dvm *h) {
+    const size_t es = h->prm.precision == FR_DVM_FP64 ? sizeof(double) : sizeof(float);
+    for (int b = 0; b < 2; ++b)
+        if (h->d_tr[b]) {
+            hipFree(h->d_tr[b]);
+            h->d_tr[b] = nullptr;
+            if (h->have_params) h->owned_bytes -= h->ne * h->tl.elem * es;
+        }
+    const fr_dvm::MeshCopy &mc = h->mesh_copy;
+    fr_dvm_mesh m;
+    m.n_elem = mc.n_elem;
+    m.n_nodes = mc.n_nodes;
+    m.geom_order = mc.geom_order;
+    m.nodes = mc.nodes.data();
+    m.elem_nodes = mc.elem_nodes.data();
+    m.nbr_elem = mc.nbr_elem.data();
+    m.nbr_face = mc.nbr_face.data();
+    m.nbr_orient = mc.nbr_orient.data();
+    m.bc = mc.bc.data();
+    std::vector<double> wq3J(h->ne * h->ns);
+    int rc = setup_general(h, &m, wq3J);
+    if (!rc) rc = upload(h, h->d_wq3J, wq3J.data(), wq3J.size() * sizeof(double));
+    return rc;
+}
+
+}  // namespace
+
 extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     if (!h || !p) return FR_DVM_EINVAL;
     if (p->model < 0 || p->model > 2) return h->fail(FR_DVM_EINVAL, "unknown model");
@@ -580,11 +626,19 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     if (p->rk != FR_DVM_SSPRK3 && p->rk != FR_DVM_LSRK3_2N) return h->fail(FR_DVM_EINVAL, "unknown RK scheme");
     if (p->guess < 0 || p->guess > 3) return h->fail(FR_DVM_EINVAL, "unknown guess mode");
     if (p->overlap != 0 && p->overlap != 1) return h->fail(FR_DVM_EINVAL, "overlap must be 0 or 1");
+    if (p->positivity != 0 && p->positivity != 1) return h->fail(FR_DVM_EINVAL, "positivity must be 0 or 1");
     bool realloc_all = !h->have_params || p->precision != h->prm.precision;
+    if (p->positivity && h->axis_mode) {
+        int rc0 = move_to_general(h);
+        if (rc0) return rc0;
+        realloc_all = true;
+    }
     // moment record: rho, rho U, then E (BGK) or the raw second moments (ES),
     // plus the integral of G for the reduced pair
     int nmom = ((p->model == FR_DVM_ESBGK) ? 10 : 5) + (h->ncomp == 2 ? 1 : 0);
     bool realloc_mom = !h->have_params || nmom != h->nmom;
+    // element size of the buffers allocated under the previous parameters
+    const size_t es_old = h->have_params && h->prm.precision == FR_DVM_FP32 ? sizeof(float) : sizeof(double);
     h->prm = *p;
     h->nmom = nmom;
     size_t es = p->precision == FR_DVM_FP64 ? sizeof(double) : sizeof(float);
@@ -592,9 +646,9 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     int64_t nu = h->vg.nu * h->ncomp;  // state values per point
     int rc;
     if (realloc_all) {
-        if (h->d_reg) { hipFree(h->d_reg); h->owned_bytes -= npts * nu * es; h->d_reg = nullptr; }
+        if (h->d_reg) { hipFree(h->d_reg); h->owned_bytes -= npts * nu * es_old; h->d_reg = nullptr; }
         for (int b = 0; b < 2; ++b)
-            if (h->d_tr[b]) { hipFree(h->d_tr[b]); h->d_tr[b] = nullptr; h->owned_bytes -= h->ne * h->tl.elem * es; }
+            if (h->d_tr[b]) { hipFree(h->d_tr[b]); h->d_tr[b] = nullptr; h->owned_bytes -= h->ne * h->tl.elem * es_old; }
         if (hipMalloc(&h->d_reg, npts * nu * es) != hipSuccess) { h->d_reg = nullptr; return h->fail(FR_DVM_ENOMEM, "register allocation failed"); }
         h->owned_bytes += npts * nu * es;
         for (int b = 0; b < 2; ++b) {

@@ -46,7 +46,8 @@ class _Params(C.Structure):
                 ("theta_ref", C.c_double), ("omega", C.c_double), ("visc_law", C.c_int32),
                 ("theta_s", C.c_double), ("precision", C.c_int32), ("newton_tol", C.c_double),
                 ("newton_max_iter", C.c_int32), ("guess", C.c_int32), ("rk", C.c_int32),
-                ("farfield", C.c_double * 5), ("theta_wall", C.c_double), ("overlap", C.c_int32)]
+                ("farfield", C.c_double * 5), ("theta_wall", C.c_double), ("overlap", C.c_int32),
+                ("positivity", C.c_int32)]
 
 
 _lib = None
@@ -79,6 +80,7 @@ def lib():
         L.fr_dvm_rk_step.argtypes = [vp, vp, C.c_double]
         L.fr_dvm_rk_steps.argtypes = [vp, vp, C.c_double, C.c_int]
         L.fr_dvm_newton_stats.argtypes = [vp, i64p, i64p, i64p, i64p, dp, C.c_int]
+        L.fr_dvm_newton_points.argtypes = [vp, vp, vp, vp]
         L.fr_dvm_mlp_set_weights.argtypes = [vp, C.POINTER(C.c_float), C.c_size_t]
         L.fr_dvm_equilibrium.argtypes = [vp, vp, C.c_int64, C.c_int, vp, vp, vp, vp, vp]
         L.fr_mlp_param_count.argtypes = [C.c_int]
@@ -353,6 +355,17 @@ class FrDvm:
                     "fr_dvm_newton_stats")
         return {"hist": hist, "n_fallback": nf.value, "n_guard": ng.value, "n_evals": ne.value,
                 "max_resid": mr.value}
+
+    def newton_points(self):
+        """Per-point outcome of the most recent Newton solve: status, linear
+        solves and final scaled residual, device tensors [n_elem, ns]."""
+        import torch
+        n = self.ne * self.ns
+        st = torch.empty(n, dtype=torch.int32, device="cuda")
+        it = torch.empty(n, dtype=torch.int32, device="cuda")
+        res = torch.empty(n, dtype=torch.float64, device="cuda")
+        self._check(lib().fr_dvm_newton_points(self._h, _ptr(st), _ptr(it), _ptr(res)), "fr_dvm_newton_points")
+        return st.view(self.ne, self.ns), it.view(self.ne, self.ns), res.view(self.ne, self.ns)
 
     def equilibrium(self, Q, guess=GUESS_COLD):
         """FP64 Newton for the conservative equilibria of moment vectors Q[n][5]

@@ -494,7 +494,7 @@ def workload(name: str) -> dict:
         # diffuse wall at theta_w=2, farfield outside
         "cyl48x24x2_p2_v24_es": dict(mesh="cylinder", p=2, grid=grid_spec(24, 14.0), model=1,
                                      prandtl=2.0 / 3.0, kn=0.01, ic="uniform", mach=8.0, noise=0.01,
-                                     theta_wall=2.0, seed=31, steps=2000, rk=1, precision=1),
+                                     theta_wall=2.0, seed=31, steps=2000, rk=1, precision=1, positivity=1),
     }
     w = dict(W[name])
     w["name"] = name
@@ -545,4 +545,7 @@ def physics_params(w: dict) -> dict:
     if "farfield" in w:
         par["farfield"] = list(w["farfield"])
         par["theta_wall"] = w["theta_wall"]
+    # the positivity-preserving scheme: on where a wall meets an impulsive
+    # start (the smooth periodic boxes keep f positive without it)
+    par["positivity"] = int(w.get("positivity", 0))
     return par
