@@ -8,18 +8,22 @@ being one of the N_e * N_s * N_u values advanced by one RK stage.
 Default (``--mode compare``, workload box24_p3_v20_es: 24^3 periodic hexes,
 p = 3, 20^3 velocities on [-8, 8]^3, ES-BGK Pr 0.71, Kn 2e-4, Taylor-Green
 U0 = 0.5 with a 1 % seeded perturbation):
-  * plain FP64: FP64 storage and arithmetic, SSP-RK3, cold-start Newton;
-  * mixed + learned: FP32 storage and FR/RK arithmetic with FP64 moments and
-    Newton, low-storage RK, Newton started from the learned guess (MLP trained
-    first, untimed, on states of this grid including the solver's own initial
-    states) and warm afterwards;
-  both timed over the same K steps from the same initial state.  ``value`` is
-  the mixed + learned throughput.  Equal error (untimed runs over the
-  workload's horizon, 200 steps at 24^3): the relative L2 difference of the
-  conserved moments between the two forms is compared with the FP64
-  solution's own discretisation error, temporal from a dt / 2 FP64 run and
-  spatial by Richardson from an N / 2 FP64 run; the conservation drift of
-  both runs is reported too.
+  * plain FP64: FP64 storage and arithmetic, SSP-RK3, warm-start Newton;
+  * mixed + learned: the mixed storage form (see ``MIXED``), low-storage RK,
+    FP64 moments and Newton, Newton started from the learned guess where no
+    previous solution exists (MLP trained first, untimed, on states of this
+    grid including the solver's own initial states) and warm afterwards;
+  both timed over the same K steps from the same initial state after the
+  same warm-up, so both timed runs use the warm start and the speed-up is
+  that of the storage form.  The learned start acts where no previous
+  solution exists: the first solve of a run, reported separately (cold vs
+  learned start on the initial state).  ``value`` is the mixed throughput,
+  reported under the equal-error metric only when equal error holds.  Equal
+  error (untimed runs over the workload's horizon, 200 steps at 24^3): the
+  relative L2 difference of the conserved moments between the two forms is
+  compared with the FP64 solution's own discretisation error, temporal from
+  a dt / 2 FP64 run and spatial by Richardson from an N / 2 FP64 run; the
+  conservation drift of both runs is reported too.
 ``--mode single`` times one configuration (flags choose precision, RK scheme,
 guess, model) and is what the profiler runs.
 
@@ -42,30 +46,44 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# The mixed storage form of the compare mode (precision code of fr_dvm_params):
+# FR_DVM_FP32_DEV, f held in FP32 as its deviation from the local conservative
+# equilibrium between stages, all stage arithmetic in FP64.
+MIXED = 2
+MIXED_LABEL = ("FP32 storage of f as the deviation from the local equilibrium (FP32 f at call boundaries), "
+               "FP32 RK register, FP64 stage arithmetic, traces, moments and Newton")
+MIXED_DTYPE = "f32 storage (deviation from equilibrium), f64 arithmetic"
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_values_per_dof(p: int, rk: int, stage: int, last: bool) -> float:
-    """Algorithmic HBM traffic of one fused stage launch, in values per DOF:
-    read the stage value f and write the result; read the neighbours' outflow
-    traces (3/(p+1) values per DOF) and, unless it is the last stage of the
-    call, write the result's own outflow traces (3/(p+1)); SSP-RK3 reads f^n
-    in stages 2 and 3; the low-storage scheme reads dF in stages 2 and 3 and
-    writes it in stages 1 and 2 (after stage 3 it is dead).  (Moments and
-    equilibrium records are per solution point, not per DOF: below 0.1 % at
-    20^3 velocities.)"""
+def value_sizes(precision: int):
+    """Bytes of a state value and of a trace value: FP64 (0) 8 / 8, FP32 (1)
+    4 / 4, FP32 deviation storage (2) 4 / 8 (its traces are FP64)."""
+    return (8 if precision == 0 else 4), (4 if precision == 1 else 8)
+
+
+def stage_values_per_dof(p: int, rk: int, stage: int, last: bool):
+    """Algorithmic HBM traffic of one fused stage launch per DOF, as (state
+    values, trace values): read the stage value f and write the result; read
+    the neighbours' outflow traces (3/(p+1) values per DOF) and, unless it is
+    the last stage of the call, write the result's own outflow traces
+    (3/(p+1)); SSP-RK3 reads f^n in stages 2 and 3; the low-storage scheme
+    reads dF in stages 2 and 3 and writes it in stages 1 and 2 (after stage 3
+    it is dead).  (Moments and equilibrium records are per solution point,
+    not per DOF: below 0.1 % at 20^3 velocities.)"""
     tr = 3.0 / (p + 1)
-    v = 2.0 + tr + (0.0 if last else tr)
+    v = 2.0
     if stage > 0:
         v += 1.0
     if rk == 1 and stage < 2:
         v += 1.0
-    return v
+    return v, tr + (0.0 if last else tr)
 
 
-def gen_stage_values_per_dof(p: int, rk: int, stage: int, last: bool) -> float:
+def gen_stage_values_per_dof(p: int, rk: int, stage: int, last: bool):
     """The same for a stage on a general hexahedral mesh (stage kernel plus
     the moment pass over its result): read f, write the result; read the
     neighbour traces where the velocity enters (half of the 6/(p+1) full
@@ -73,22 +91,24 @@ def gen_stage_values_per_dof(p: int, rk: int, stage: int, last: bool) -> float:
     (6/(p+1)) and read the result once more for its moments; the second RK
     register as for the box kernel."""
     full = 6.0 / (p + 1)
-    v = 2.0 + 0.5 * full + (0.0 if last else full + 1.0)
+    v = 2.0 + (0.0 if last else 1.0)
     if stage > 0:
         v += 1.0
     if rk == 1 and stage < 2:
         v += 1.0
-    return v
+    return v, 0.5 * full + (0.0 if last else full)
 
 
-def stage_bytes(p: int, es: int, rk: int, nsteps: int, general: bool = False) -> float:
+def stage_bytes(p: int, precision: int, rk: int, nsteps: int, general: bool = False) -> float:
     """Algorithmic bytes per DOF summed over the stage launches of one
     rk_steps call of nsteps steps."""
     per = gen_stage_values_per_dof if general else stage_values_per_dof
+    es, te = value_sizes(precision)
     tot = 0.0
     for k in range(nsteps):
         for st in range(3):
-            tot += per(p, rk, st, k == nsteps - 1 and st == 2) * es
+            sv, tv = per(p, rk, st, k == nsteps - 1 and st == 2)
+            tot += sv * es + tv * te
     return tot
 
 
@@ -123,7 +143,7 @@ def measured_traffic(workload: str, precision: int, rk: int, delta: float = 0.0)
 
 
 def run_config(W, w, mesh, params, steps, warmup, label, weights=None, keep_moments=False, dt_scale=1.0,
-               nsteps_override=None, dt_override=None):
+               nsteps_override=None, dt_override=None, keep_f=False):
     """Build a handle, generate f0 on the GPU, warm up, time `steps` steps.
     Returns a dict with timing, kernel times and (optionally) final moments."""
     import numpy as np
@@ -135,7 +155,7 @@ def run_config(W, w, mesh, params, steps, warmup, label, weights=None, keep_mome
     if weights is not None:
         s.mlp_set_weights(weights)
     ne, ns, nu = s.shape  # nu: state values per point (both components of a pair)
-    dof = ne * ns * nu
+    dof = ne * ns * s.nu  # N_e N_s N_u: velocity nodes, once for the pair (F, G)
     dt = (s.dt(0.2) if dt_override is None else dt_override) * dt_scale
     prim = W.initial_prim(mesh, w["p"], w)
     log(f"{label}: generating f0 ({dof:.3e} DOFs, {s.dtype})")
@@ -163,15 +183,26 @@ def run_config(W, w, mesh, params, steps, warmup, label, weights=None, keep_mome
     s.profile_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.rk_steps(f, dt, n_timed)
+    if n_timed <= 500:
+        s.rk_steps(f, dt, n_timed)
+    else:
+        # long horizons in calls of 100 steps, each reported
+        done = 0
+        while done < n_timed:
+            k = min(100, n_timed - done)
+            s.rk_steps(f, dt, k)
+            torch.cuda.synchronize()
+            done += k
+            log(f"{label}: {done}/{n_timed} steps")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = s.profile_read(reset=True)
     s.profile(False)
     stats = s.newton_stats(reset=True)
     log(f"{label}: {n_timed} steps in {elapsed:.3f} s")
-    out = {"label": label, "dof": dof, "steps": n_timed, "elapsed": elapsed, "dt": dt,
-           "value": dof * 3 * n_timed / elapsed, "ms_per_step": elapsed / n_timed * 1e3, "prof": prof,
+    out = {"label": label, "dof": dof, "ncomp": s.ncomp, "steps": n_timed, "elapsed": elapsed, "dt": dt,
+           "value": dof * 3 * n_timed / elapsed, "state_values_per_s": dof * s.ncomp * 3 * n_timed / elapsed,
+           "ms_per_step": elapsed / n_timed * 1e3, "prof": prof,
            "stats": stats, "precision": params.get("precision", 0), "rk": params.get("rk", 0), "delta": delta}
     hist = stats["hist"]
     nsol = max(int(hist.sum()), 1)
@@ -186,6 +217,9 @@ def run_config(W, w, mesh, params, steps, warmup, label, weights=None, keep_mome
         out["totals"] = [float(x) for x in tot]
         out["totals0"] = [float(x) for x in tot0]
     out["totals_finite"] = bool(torch.isfinite(f).all().item())
+    if keep_f:
+        out["f"] = f
+        out["f_min"] = float(f.min().item())
     del f
     s.destroy()
     torch.cuda.empty_cache()
@@ -197,19 +231,41 @@ def roofline(r, p, workload, general=False):
     its launches in the timed call over their summed HIP-event durations (on
     the library's stream).  General meshes: the stage kernel with its wall
     and moment passes."""
-    es = 8 if r["precision"] == 0 else 4
     ms, n = r["prof"]["stage"]
-    tot_bytes = stage_bytes(p, es, r["rk"], r["steps"], general) * r["dof"]
+    tot_bytes = stage_bytes(p, r["precision"], r["rk"], r["steps"], general) * r["dof"] * r.get("ncomp", 1)
     ach = tot_bytes / (ms / 1e3) / 1e9
     name = "k_gen_stage + k_gen_wall + k_gen_moments (general hexes)" if general else "k_fr_layer (fused FR stage)"
+    avg_ms = ms / max(n, 1)
     out = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-           "algorithmic_bytes_per_launch": tot_bytes / max(n, 1), "avg_launch_ms": ms / max(n, 1)}
+           "algorithmic_bytes_per_launch": tot_bytes / max(n, 1), "avg_launch_ms": avg_ms}
+    # the same launches priced with the unfused per-DOF traffic of the FR x
+    # DVM stage (read f twice, the RK register, traces at both ends): p = 3
+    # SSP FP64 56 B, FP32 28 B, low-storage FP32 32 B per DOF and stage
+    if not general:
+        ub = unfused_bytes_per_dof(p, r["precision"], r["rk"]) * r["dof"] * r.get("ncomp", 1)
+        out["unfused_bytes_per_dof"] = unfused_bytes_per_dof(p, r["precision"], r["rk"])
+        out["frac_unfused_bytes"] = ub / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS
     t = measured_traffic(workload, r["precision"], r["rk"], r.get("delta", 0.0))
     if t is not None:
         out["traffic"] = t["bytes_per_launch"]
         out["traffic_source"] = t["profile"]
+        # bandwidth the launches actually drew: counted bytes over the live time
+        out["counted_GBps"] = t["bytes_per_launch"] / (avg_ms / 1e3) / 1e9
+        out["frac_counted"] = out["counted_GBps"] / HBM_PEAK_GBS
     return out
+
+
+def unfused_bytes_per_dof(p: int, precision: int, rk: int) -> float:
+    """Per-DOF traffic of one RK stage when its parts are separate passes
+    (moments read f, the residual reads f and writes traces of r = 6/(p+1)
+    face values and reads them back, the update reads the RK register and
+    writes f): 4 state values plus 2 r trace values for SSP-RK3, one more
+    state value for the low-storage register's second access.  p = 3: FP64
+    SSP 56 B, FP32 SSP 28 B, FP32 low-storage 32 B."""
+    es, te = value_sizes(precision)
+    r = 6.0 / (p + 1)
+    return es * (4.0 + (1.0 if rk == 1 else 0.0)) + te * 2.0 * r
 
 
 def coarse_to_fine(Qc, Nc, p):
@@ -271,13 +327,61 @@ def train_guess(W, w, log_fn):
     return wts, info
 
 
+def first_solve(W, w, mesh, params, weights):
+    """The learned start where it acts: the first conservative-equilibrium
+    solve of a run (no previous solution at any point), on the workload's
+    initial state, from the cold start and from the learned start.  Newton
+    linear solves and grid passes per point, fallbacks, the largest final
+    residual and the Newton kernel time (HIP events)."""
+    import numpy as np
+    import torch
+
+    from paper_2312_06567_amd.frdvm import FrDvm
+    out = {}
+    for label, guess in (("cold", 0), ("learned", 2)):
+        s = FrDvm(mesh, w["p"], w["grid"], dict(params, guess=guess))
+        if guess == 2:
+            s.mlp_set_weights(weights)
+        ne, ns, nu = s.shape
+        f = W.maxwellian(W.initial_prim(mesh, w["p"], w), w["grid"], dtype=s.dtype, device="cuda").reshape(ne, ns, nu)
+        S = torch.empty_like(f)
+        s.collide(f, S)  # compiles / warms the kernels
+        s.newton_stats(reset=True)
+        s.profile(True)
+        s.profile_read(reset=True)
+        s.collide(f, S)
+        prof = s.profile_read(reset=True)
+        st = s.newton_stats(reset=True)
+        hist = st["hist"]
+        nsol = max(int(hist.sum()), 1)
+        out[label] = {"mean_solves": float((hist * np.arange(64)).sum() / nsol),
+                      "mean_passes": float(st["n_evals"] / nsol), "fallback": int(st["n_fallback"]),
+                      "max_resid": float(st["max_resid"]), "newton_ms": prof["newton"][0],
+                      "mlp_ms": prof["other"][0]}
+        del f, S
+        s.destroy()
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="box24_p3_v20_es")
-    ap.add_argument("--mode", choices=("compare", "single", "kn"), default="compare")
+    ap.add_argument("--mode", choices=("compare", "single", "kn", "horizon"), default="compare")
     ap.add_argument("--precision", type=int, default=None, help="single mode: 0 FP64, 1 FP32")
     ap.add_argument("--rk", type=int, default=None, help="single mode: 0 SSP-RK3, 1 low-storage")
     ap.add_argument("--guess", type=int, default=None, help="single mode: 0 cold, 1 warm, 2 MLP, 3 MLP then warm")
@@ -337,6 +441,10 @@ def main():
         print(json.dumps(kn_bench(W, w, mesh, base, args, cfg)), flush=True)
         return
 
+    if args.mode == "horizon":
+        print(json.dumps(horizon_compare(W, w, mesh, base, args, cfg)), flush=True)
+        return
+
     if args.mode == "single":
         par = dict(base)
         par["precision"] = w["precision"] if args.precision is None else args.precision
@@ -362,9 +470,11 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    # compare mode: plain FP64 against mixed precision + learned Newton start
-    p64 = dict(base, precision=0, rk=0, guess=0)
-    pmx = dict(base, precision=1, rk=1, guess=3)
+    # compare mode: plain FP64 against the mixed form + learned Newton start;
+    # both timed with the warm start (the learned start acts at the first
+    # solve only, reported by first_solve)
+    p64 = dict(base, precision=0, rk=0, guess=1)
+    pmx = dict(base, precision=MIXED, rk=1, guess=3)
     r64 = run_config(W, w, mesh, p64, args.steps, args.warmup, "fp64-plain", keep_moments=True)
     weights, tinfo = train_guess(W, w, log)
     rmx = run_config(W, w, mesh, pmx, args.steps, args.warmup, "mixed-learned", weights=weights, keep_moments=True)
@@ -405,12 +515,16 @@ def main():
         return {k: abs(t1[i] - t0[i]) / max(ref[i], 1e-300)
                 for i, k in enumerate(("rho", "rhoUx", "rhoUy", "rhoUz", "E"))}
     drift = {lab: drift_of(r) for lab, r in (("fp64", a64), ("mixed", amx))}
-    cfg.update(mixed="FP32 f, FP32 FR/RK arithmetic, FP64 moments + Newton; LSRK3-2N; learned then warm Newton start",
-               plain="FP64 everything; SSP-RK3; cold Newton start")
-    out = {"metric": "DOF-updates/s (N_e*N_s*N_u per RK stage), mixed+learned vs FP64 at equal error",
+    first = first_solve(W, w, mesh, dict(base, precision=MIXED, rk=1), weights)
+    cfg.update(mixed=MIXED_LABEL + "; LSRK3-2N; learned then warm Newton start",
+               plain="FP64 everything; SSP-RK3; warm Newton start")
+    metric = "DOF-updates/s (N_e*N_s*N_u per RK stage), mixed+learned vs FP64 at equal error"
+    if holds is not True:
+        metric = "DOF-updates/s (N_e*N_s*N_u per RK stage), mixed precision; equal error NOT reached"
+    out = {"metric": metric, "equal_error_holds": holds,
            "value": rmx["value"], "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": rmx["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32 (FP64 moments and Newton)",
+           "dtype": MIXED_DTYPE,
            "data": "synthetic (seeded initial Maxwellian of the workload's macroscopic field)", "config": cfg,
            "fp64_plain": {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
                           "kernels_ms_per_step": {k: v[0] / r64["steps"] for k, v in r64["prof"].items()},
@@ -421,10 +535,45 @@ def main():
                            "horizon_steps": horizon, "conservation_drift": drift},
            "kernels_ms_per_step": {k: v[0] / rmx["steps"] for k, v in rmx["prof"].items()},
            "newton": rmx["newton"], "learned_guess": {k: tinfo[k] for k in ("n_converged", "train_seconds")},
+           "learned_start_first_solve": first,
            "roofline": roofline(rmx, w["p"], w["name"])}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, p64, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def horizon_compare(W, w, mesh, base, args, cfg):
+    """The mixed form against FP64 after the workload's horizon (2000 steps
+    on the Mach-8 O-grid) from the same initial state: relative L2
+    differences of rho, rho U, E and f, the domain totals of both runs and
+    their Newton outcomes; both runs timed (HIP-event kernel times)."""
+    import numpy as np
+    import torch
+    H = args.horizon if args.horizon is not None else int(w.get("steps", 100))
+    r64 = run_config(W, w, mesh, dict(base, precision=0, rk=0, guess=1), 0, 0, "fp64-horizon", keep_moments=True,
+                     nsteps_override=H, keep_f=True)
+    # the deviation storage runs on box meshes; elsewhere the mixed form is FP32
+    mprec = MIXED if w.get("mesh") != "cylinder" else 1
+    rmx = run_config(W, w, mesh, dict(base, precision=mprec, rk=1, guess=1), 0, 0, "mixed-horizon",
+                     keep_moments=True, nsteps_override=H, keep_f=True)
+    f64, fmx = r64.pop("f"), rmx.pop("f")
+    num = 0.0
+    den = 0.0
+    for a, b in zip(fmx.reshape(-1, fmx.shape[-1]).split(4096), f64.reshape(-1, f64.shape[-1]).split(4096)):
+        num += float((a.double() - b).pow(2).sum().item())
+        den += float(b.pow(2).sum().item())
+    del f64, fmx
+    torch.cuda.empty_cache()
+    err = bench_rel = rel_moments(rmx["Q"], r64["Q"])
+    err["f"] = math.sqrt(num / den)
+    cfg = dict(cfg, mixed=(MIXED_LABEL if mprec == MIXED else "FP32 f, FP32 FR/RK arithmetic, FP64 moments + Newton")
+               + "; LSRK3-2N; warm Newton start",
+               plain="FP64 everything; SSP-RK3; warm Newton start", positivity=base.get("positivity", 0))
+    return {"metric": "mixed vs FP64 relative L2 difference at the horizon", "horizon_steps": H,
+            "mixed_vs_fp64_rel_l2": bench_rel, "config": cfg,
+            "fp64": {k: r64[k] for k in ("value", "ms_per_step", "newton", "totals0", "totals", "f_min")},
+            "mixed": {k: rmx[k] for k in ("value", "ms_per_step", "newton", "totals0", "totals", "f_min")},
+            "speedup_vs_fp64": rmx["value"] / r64["value"]}
 
 
 def kn_bench(W, w, mesh, base, args, cfg):
@@ -488,7 +637,26 @@ def cpu_baseline(w: dict, params: dict, budget_s: float) -> dict:
     if el < budget_s / 8:
         nsample = max(2, min(8, int(nsample * (budget_s / max(el, 1e-3)) ** (1 / 3))))
         el, dof = one(nsample)
+    # the same oracle on one thread (a child process: OpenMP reads the
+    # thread count at start-up), on the 2^3-element sample
+    one_thread = None
+    import subprocess
+    code = ("import sys, time, json; sys.path.insert(0, %r); import workloads as W, oracle; "
+            "w = W.workload(%r); p = json.loads(%r); mesh = W.box_mesh(2); "
+            "P = oracle.Problem(mesh, w['p'], w['grid'], p); "
+            "f0 = W.maxwellian(W.initial_prim(mesh, w['p'], w), w['grid']).numpy(); "
+            "t0 = time.perf_counter(); P.rk_step(f0, P.dt(0.2), scheme=0, nsteps=1); "
+            "print(json.dumps([time.perf_counter() - t0, P.ne * P.ns * P.nu]))") % (ROOT, w["name"], json.dumps(par))
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, OMP_NUM_THREADS="1"),
+                           capture_output=True, text=True, timeout=600)
+        el1, dof1 = json.loads(r.stdout.strip().splitlines()[-1])
+        one_thread = {"value": dof1 * 3 / el1, "seconds": el1,
+                      "sample": f"one SSP-RK3 step on the 2^3-element box ({dof1:.3e} DOFs)"}
+    except Exception as exc:  # reported, not fatal
+        one_thread = {"error": str(exc)[:200]}
     return {"value": dof * 3 / el, "unit": "DOF-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "one_thread": one_thread,
             "sample": f"one SSP-RK3 step on a {nsample}^3-element periodic box, p={w['p']}, "
                       f"{w['grid']['n'][0]}^3 velocities ({dof:.3e} DOFs), FP64, {el:.1f} s"}
 
