@@ -456,12 +456,13 @@ def main():
         r = run_config(W, w, mesh, par, args.steps, args.warmup, "single", weights=weights)
         if w.get("delta", 0.0) > 0:
             cfg.update(delta=w["delta"], state="reduced pair (F, G): 2 values per velocity node")
-        cfg.update(precision=["FP64", "FP32"][par["precision"]], rk=["SSP-RK3", "LSRK3-2N"][par["rk"]],
+        cfg.update(precision=["FP64", "FP32", "FP32 deviation storage"][par["precision"]],
+                   rk=["SSP-RK3", "LSRK3-2N"][par["rk"]],
                    guess=["cold", "warm", "learned", "learned+warm"][par["guess"]])
         out = {"metric": "DOF-updates/s (N_e*N_s*N_u per RK stage)", "value": r["value"], "unit": "DOF-updates/s",
                "n_gpus": 1, "steps": r["steps"], "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-               "dtype": "f64" if par["precision"] == 0 else "f32 (FP64 moments and Newton)",
+               "dtype": ["f64", "f32 (FP64 moments and Newton)", MIXED_DTYPE][par["precision"]],
                "data": "synthetic (seeded initial Maxwellian of the workload's macroscopic field)", "config": cfg,
                "kernels_ms_per_step": {k: v[0] / r["steps"] for k, v in r["prof"].items()},
                "newton": r["newton"], "roofline": roofline(r, w["p"], w["name"], w.get("mesh") == "cylinder")}
@@ -478,11 +479,15 @@ def main():
     r64 = run_config(W, w, mesh, p64, args.steps, args.warmup, "fp64-plain", keep_moments=True)
     weights, tinfo = train_guess(W, w, log)
     rmx = run_config(W, w, mesh, pmx, args.steps, args.warmup, "mixed-learned", weights=weights, keep_moments=True)
+    # the plain FP32 form (FP32 state, stochastic rounding, FP32 stage
+    # arithmetic) timed beside them
+    p32 = dict(base, precision=1, rk=1, guess=3)
+    r32 = run_config(W, w, mesh, p32, args.steps, args.warmup, "fp32-learned", weights=weights, keep_moments=True)
     err = None
     if args.no_error:
         # moment difference after the timed runs only
         horizon = args.steps + args.warmup
-        a64, amx = r64, rmx
+        a64, amx, a32 = r64, rmx, r32
     else:
         # the error comparison runs the workload's own horizon (untimed):
         # FP64 and mixed + learned from the same initial state, and the
@@ -492,6 +497,8 @@ def main():
         horizon = args.horizon if args.horizon is not None else int(w.get("steps", args.steps + args.warmup))
         a64 = run_config(W, w, mesh, p64, 0, 0, "fp64-horizon", keep_moments=True, nsteps_override=horizon)
         amx = run_config(W, w, mesh, pmx, 0, 0, "mixed-horizon", weights=weights, keep_moments=True,
+                         nsteps_override=horizon)
+        a32 = run_config(W, w, mesh, p32, 0, 0, "fp32-horizon", weights=weights, keep_moments=True,
                          nsteps_override=horizon)
         rh = run_config(W, w, mesh, p64, 0, 0, "fp64-half-dt", keep_moments=True, dt_scale=0.5,
                         nsteps_override=2 * horizon)
@@ -514,7 +521,8 @@ def main():
         ref = [abs(t0[0]), *[math.sqrt(2.0 * abs(t0[0] * t0[4]))] * 3, abs(t0[4])]
         return {k: abs(t1[i] - t0[i]) / max(ref[i], 1e-300)
                 for i, k in enumerate(("rho", "rhoUx", "rhoUy", "rhoUz", "E"))}
-    drift = {lab: drift_of(r) for lab, r in (("fp64", a64), ("mixed", amx))}
+    drift = {lab: drift_of(r) for lab, r in (("fp64", a64), ("mixed", amx), ("fp32", a32))}
+    err_32 = rel_moments(a32["Q"], a64["Q"])
     first = first_solve(W, w, mesh, dict(base, precision=MIXED, rk=1), weights)
     cfg.update(mixed=MIXED_LABEL + "; LSRK3-2N; learned then warm Newton start",
                plain="FP64 everything; SSP-RK3; warm Newton start")
@@ -536,6 +544,17 @@ def main():
            "kernels_ms_per_step": {k: v[0] / rmx["steps"] for k, v in rmx["prof"].items()},
            "newton": rmx["newton"], "learned_guess": {k: tinfo[k] for k in ("n_converged", "train_seconds")},
            "learned_start_first_solve": first,
+           "fp32_form": {"label": "FP32 f (stochastic rounding), FP32 FR/RK arithmetic, FP64 moments + Newton; "
+                                  "LSRK3-2N; learned then warm Newton start",
+                         "value": r32["value"], "ms_per_step": r32["ms_per_step"],
+                         "speedup_vs_fp64": r32["value"] / r64["value"],
+                         "kernels_ms_per_step": {k: v[0] / r32["steps"] for k, v in r32["prof"].items()},
+                         "mixed_vs_fp64_rel_l2": err_32,
+                         "ratio_to_fp64_discretisation": None if err is None else
+                         {k: err_32[k] / err["total"][k] for k in err_32},
+                         "equal_error_holds": None if err is None else
+                         all(err_32[k] <= 0.1 * err["total"][k] for k in err_32),
+                         "roofline": roofline(r32, w["p"], w["name"])},
            "roofline": roofline(rmx, w["p"], w["name"])}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, p64, args.cpu_seconds)

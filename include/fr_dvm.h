@@ -21,7 +21,8 @@
  *    listed x-fastest.  Faces: face = 2 d + side, side 0 at xi_d = -1, side 1
  *    at xi_d = +1.
  *  - All f / R / S buffers are caller-owned DEVICE pointers of the handle's
- *    precision (double for FR_DVM_FP64, float for FR_DVM_FP32).  Q / Qp /
+ *    precision (double for FR_DVM_FP64, float for FR_DVM_FP32 and
+ *    FR_DVM_FP32_DEV).  Q / Qp /
  *    totals are caller-owned DEVICE double buffers unless said otherwise.
  *    The library never frees or reallocates caller memory.
  *  - Every call is asynchronous on the handle's stream (default: the null
@@ -58,6 +59,20 @@ extern "C" {
 /* storage / arithmetic precision of f and of the FR operators */
 #define FR_DVM_FP64 0
 #define FR_DVM_FP32 1
+/* FP32 deviation storage: f buffers are float, all stage arithmetic, traces,
+ * moments and Newton are FP64.  Inside one fr_dvm_rk_step(s) call every
+ * stage leaves its result in the caller's buffer as the FP32 deviation
+ * d = f - r from a reference r close to the conservative equilibrium that
+ * the stage's collision used at that point (eq. discrete_compatibility; r
+ * is that equilibrium's FP64 exponent through the FP32 hardware exp2), and
+ * the next stage reads f = r + d with the same bits of r; the call's last
+ * stage leaves f itself, rounded to FP32.  The stored deviation is small
+ * where f is near equilibrium, so its rounding is far below that of f in
+ * FP32.  Periodic box meshes, monatomic gas,
+ * low-storage RK (FR_DVM_LSRK3_2N), collision models BGK / ES-BGK, no
+ * positivity limiter and no overlap; other calls (residual, collide,
+ * moments, Kn) take f as plain float values. */
+#define FR_DVM_FP32_DEV 2
 
 /* Newton initial guess for the conservative equilibrium */
 #define FR_DVM_GUESS_COLD 0 /* continuous equilibrium of the moments of f */
@@ -110,7 +125,7 @@ typedef struct {
     double mu_ref, theta_ref, omega; /* power law mu = mu_ref (theta/theta_ref)^omega */
     int32_t visc_law;     /* 0 power law, 1 Sutherland with theta_s */
     double theta_s;
-    int32_t precision;    /* FR_DVM_FP64 | FR_DVM_FP32 */
+    int32_t precision;    /* FR_DVM_FP64 | FR_DVM_FP32 | FR_DVM_FP32_DEV */
     double newton_tol;    /* max-norm of the scaled compatibility residual */
     int32_t newton_max_iter;
     int32_t guess;        /* FR_DVM_GUESS_* */

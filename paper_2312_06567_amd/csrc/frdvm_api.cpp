@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <utility>
 
 #include "../../include/fr_dvm_mlp.h"
 #include "frdvm_common.h"
@@ -101,6 +102,8 @@ StageArgs stage_args(fr_dvm *h, void *f, double dt, int st, int collide) {
     a.dt = dt;
     a.collide = collide;
     a.positivity = h->prm.positivity;
+    a.eq_prev = h->d_eq_prev;
+    a.seed = (h->stage_count++) * 0x9e3779b9u;  // a different seed for every stage
     a.eq = h->d_eq;
     a.tr_in = h->d_tr[h->cur_tr];
     a.tr_out = h->d_tr[h->cur_tr ^ 1];
@@ -161,17 +164,26 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
     // halves on its own stream (the neighbour traces it reads).  Per point
     // the work and its order are those of the single-stream path.
     // (decided after the first solve: a learned-then-warm start is warm from here on)
-    const bool split = h->prm.overlap && h->axis_mode && collide && h->ne >= 2 && newton_part_ok(h, guess);
+    // FP32 deviation storage: each stage reads its value relative to the
+    // previous stage's records and writes relative to its own, so the two
+    // record sets alternate before every Newton launch after the first
+    const bool dev = h->prm.precision == FR_DVM_FP32_DEV && collide;
+    const bool split = h->prm.overlap && h->axis_mode && collide && !dev && h->ne >= 2 && newton_part_ok(h, guess);
     if (split && (rc = ensure_aux(h))) return rc;
     const int64_t eh[3] = {0, h->ne / 2, h->ne};
     const int nst = 3 * nsteps;
     for (int k = 0; k < nst; ++k) {
         const int st = k % 3;
         const int last = k == nst - 1;
-        StageArgs a = stage_args(h, f, dt, st, collide);
         const int traces = last ? 0 : 1, moments = (last || !collide) ? 0 : 1;
+        if (!split && k > 0 && collide) {
+            if (dev) std::swap(h->d_eq, h->d_eq_prev);
+            if ((rc = launch_newton(h, guess))) return rc;
+        }
+        StageArgs a = stage_args(h, f, dt, st, collide);
+        a.in_dev = dev && k > 0;
+        a.out_dev = dev && !last;
         if (!split) {
-            if (k > 0 && collide && (rc = launch_newton(h, guess))) return rc;
             ProfScope ps(h, 0);
             if ((rc = launch_fr(h, 1, a, traces, moments))) return rc;
         } else {

@@ -121,9 +121,11 @@ struct fr_dvm {
     int cur_tr = 0;
     double *d_Q = nullptr;       // [ne*ns][nmom]
     double *d_eq = nullptr;      // [ne*ns][kEqW]
+    double *d_eq_prev = nullptr; // [ne*ns][kEqW] records of the previous stage (FP32 deviation storage)
     double *d_z = nullptr;       // [ne*ns][5] Newton solution (warm start)
     double *d_prim = nullptr;    // [ne*ns][5] primitive state of g(Q')
     int zvalid = 0;
+    uint32_t stage_count = 0;   // RK stages since fr_dvm_set_params (seeds of the stochastic rounding)
     bool newton_done = false;    // a solve has filled the per-point outcome arrays
     int32_t *d_pt_iters = nullptr;   // [ne*ns] per-point Newton outcome of the last solve
     int32_t *d_pt_evals = nullptr;
@@ -192,6 +194,12 @@ struct StageArgs {
     int keep_dF;             // LSRK: store dF (not after the last stage of a step, where it is dead)
     int collide;             // include the collision source
     int positivity;          // limit the stage result to f >= 0 (general-mesh kernel)
+    // FP32 deviation storage (FR_DVM_FP32_DEV): the stage value is read as
+    // f = g(eq_prev) + d (in_dev) and the result written as d = f - g(eq)
+    // (out_dev), g the equilibrium of a point's record at the lane's velocity
+    const double *eq_prev;   // records of the previous stage [ne*ns][kEqW]
+    int in_dev, out_dev;
+    uint32_t seed;           // random bits of the stage's stochastic rounding of FP32 state values
     int64_t e0, ecount;      // element range [e0, e0 + ecount); ecount 0: all elements
 };
 int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);

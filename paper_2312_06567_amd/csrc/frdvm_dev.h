@@ -40,4 +40,35 @@ __device__ __forceinline__ float exp_to_f32(double E) {
     return (float)ldexp(p, (int)n);
 }
 
+// Stochastic rounding of the FP32 state.  A value computed in FP64 is stored
+// in FP32 rounded up or down with probabilities that make the rounding
+// unbiased: r (32 random bits) shifted to the 29 mantissa bits that the
+// conversion drops is added to the magnitude and those bits are cut, so the
+// stored magnitude is the next one up with probability equal to the dropped
+// fraction.  Round to nearest instead leaves a rounding error that repeats
+// from stage to stage on a smooth, slowly changing state and accumulates in
+// the conserved moments.  (Values below the FP32 normal range are rounded
+// once more by the conversion.)
+__device__ __forceinline__ float round_stochastic(double x, uint32_t r) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    b += (unsigned long long)(r >> 3);
+    b &= ~((1ull << 29) - 1ull);
+    return (float)__longlong_as_double((long long)b);
+}
+
+// 32-bit integer hash "lowbias32" (C. Wellons' hash-prospector search: two
+// multiply-xorshift rounds); the random bits of the stochastic rounding of
+// state value k of solution point pt in a stage with seed `seed`.
+__device__ __forceinline__ uint32_t hash_lowbias32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ uint32_t round_bits(uint32_t seed, uint32_t pt, uint32_t k) {
+    return hash_lowbias32(seed ^ hash_lowbias32(pt * 0x01000193u ^ k));
+}
+
 }  // namespace frdvm

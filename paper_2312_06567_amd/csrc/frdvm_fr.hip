@@ -108,6 +108,49 @@ __device__ __forceinline__ double exp_r<double>(double E) {
     return exp(E);
 }
 
+// Exponent of a point's equilibrium at velocity u: c0 - (u-V)^T B (u-V)/2
+// from the staged form b = (-B_xx/2, -B_yy/2, -B_zz/2, -B_xy, -B_xz, -B_yz,
+// c0).  One fixed sequence of IEEE operations: the collision of a stage and
+// the reconstruction f = g + d in the next stage (FP32 deviation storage)
+// evaluate it with the same bits.
+__device__ __forceinline__ double eq_exponent(double b0, double b1, double b2, double b3, double b4, double b5,
+                                              double b6, double V0, double V1, double V2, const double u[3]) {
+    const double c0 = u[0] - V0, c1 = u[1] - V1, c2 = u[2] - V2;
+    double t0 = b0 * c0;
+    t0 = fma(b3, c1, t0);
+    t0 = fma(b4, c2, t0);
+    double t1 = b1 * c1;
+    t1 = fma(b5, c2, t1);
+    const double t2 = b2 * c2;
+    double E = fma(c0, t0, b6);
+    E = fma(c1, t1, E);
+    return fma(c2, t2, E);
+}
+
+// Reference value of the FP32 deviation storage at exponent E: the hardware
+// FP32 exp2 of E log2(e).  It needs to be close to the equilibrium (the
+// stored deviation f - ref is then small) and to be the same bits wherever it
+// is evaluated (it is subtracted when a value is stored and added back when
+// it is read), not accurate: one FP64 multiply, two conversions and one
+// transcendental instruction.
+__device__ __forceinline__ double dev_ref(double E) {
+    return (double)__builtin_amdgcn_exp2f((float)(E * 1.4426950408889634074));
+}
+
+// The value of lane `lane` (wave-uniform) of a double held per lane.
+__device__ __forceinline__ double read_lane(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Coefficient c of a record in the staged form read by eq_exponent:
+// -B_xx/2, -B_yy/2, -B_zz/2, -B_xy, -B_xz, -B_yz, c0, V_x, V_y, V_z.
+__device__ __forceinline__ double eq_coef(const double *q, int c) {
+    return c < 3 ? -0.5 * q[EQ_B + c] : (c < 6 ? -q[EQ_B + c] : (c == 6 ? q[EQ_C0] : q[EQ_V + c - 7]));
+}
+constexpr int kEqCoef = 10;
+
 // Element-relative access: `base` is uniform (one element's slab), `boff`
 // the lane's byte offset inside it (a slab stays below 4 GiB: at most
 // 64 solution points x 2 components x 64^3 velocities x 8 bytes).
@@ -238,7 +281,12 @@ __device__ __forceinline__ int tix(int row, int col) {
     return row * kTileLd + col;
 }
 
-template <typename Real, int P, int NMOM, int MODE>
+typedef const __attribute__((address_space(4))) double cdouble;
+
+// Real: arithmetic, LDS tiles and traces; SReal: storage of the state, the
+// second RK register and the output (float with Real = double: the FP32
+// deviation storage).
+template <typename Real, typename SReal, int P, int NMOM, int MODE>
 __global__ __launch_bounds__(kChunk *(P + 1)) __attribute__((amdgpu_waves_per_eu(fr_waves<Real, MODE>()))) void
 k_fr_layer(const FrArgs A) {
     constexpr int N = P + 1, NS = N * N * N, NL = N * N;
@@ -278,13 +326,27 @@ k_fr_layer(const FrArgs A) {
     const int nu = A.nu;
     const int64_t ebase = e * (int64_t)NS * nu * NCOMP;
     const uint32_t lrow = (uint32_t)(l * NL) * (uint32_t)(nu * NCOMP);  // offset of the layer inside the element
-    const uint32_t QB = (uint32_t)(nu * NCOMP) * (uint32_t)sizeof(Real);  // bytes between solution points
+    const uint32_t QB = (uint32_t)(nu * NCOMP) * (uint32_t)sizeof(SReal);  // bytes between solution points
+    constexpr bool DEVS = sizeof(SReal) < sizeof(Real);  // FP32 deviation storage
+    const bool in_dev = DEVS && STAGE && A.sa.in_dev;
+    const bool out_dev = DEVS && STAGE && A.sa.out_dev;
+    // the previous stage's records of this wave's layer (FP32 deviation
+    // storage), read once per element and spread over the lanes: coefficient
+    // c of layer point q in slot t = q kEqCoef + c, lane t % 64, register t / 64
+    constexpr int NPR = DEVS ? (NL * kEqCoef + kChunk - 1) / kChunk : 1;
+    double prv[NPR];
+#pragma unroll
+    for (int r = 0; r < NPR; ++r) {
+        const int t = r * kChunk + (tid & (kChunk - 1));
+        prv[r] = (in_dev && t < NL * kEqCoef)
+                     ? eq_coef(A.sa.eq_prev + (e * NS + l * NL + t / kEqCoef) * kEqW, t % kEqCoef)
+                     : 0.0;
+    }
 
     const bool collide = STAGE && A.sa.collide;
     // equilibrium records of this wave's layer: c0, V, B, 1/tau per point,
     // wave-uniform, read through the scalar cache (written by the previous
     // launch)
-    typedef const __attribute__((address_space(4))) double cdouble;
     cdouble *eqL = (cdouble *)(A.sa.eq + (e * NS + l * NL) * kEqW);
     if (EQ_LDS && collide) {
         for (int s = tid; s < NS; s += NT) {
@@ -339,15 +401,15 @@ k_fr_layer(const FrArgs A) {
     // the lane tables (and the staged records) are complete from here on
     __syncthreads();
 
-    const Real *__restrict__ fE = reinterpret_cast<const Real *>(A.sa.f) + ebase;
+    const SReal *__restrict__ fE = reinterpret_cast<const SReal *>(A.sa.f) + ebase;
     Real *__restrict__ trout = reinterpret_cast<Real *>(A.sa.tr_out);
-    Real *__restrict__ outE = reinterpret_cast<Real *>(A.sa.fout) + ebase;
-    Real *__restrict__ dFE = reinterpret_cast<Real *>(A.sa.dF) + ebase;
+    SReal *__restrict__ outE = reinterpret_cast<SReal *>(A.sa.fout) + ebase;
+    SReal *__restrict__ dFE = reinterpret_cast<SReal *>(A.sa.dF) + ebase;
     // second register read by the stage: f^n (SSP, alpha != 0) or dF (LSRK, A != 0)
     const bool useX = STAGE && (A.sa.scheme == 0 ? A.sa.alpha != 0.0 : A.sa.lsA != 0.0);
-    const Real *__restrict__ XE = STAGE ? (A.sa.scheme == 0 ? reinterpret_cast<const Real *>(A.sa.fn) + ebase
-                                                            : reinterpret_cast<const Real *>(A.sa.dF) + ebase)
-                                        : nullptr;
+    const SReal *__restrict__ XE = STAGE ? (A.sa.scheme == 0 ? reinterpret_cast<const SReal *>(A.sa.fn) + ebase
+                                                              : reinterpret_cast<const SReal *>(A.sa.dF) + ebase)
+                                         : nullptr;
     const int nchunk = (nu + kChunk - 1) / kChunk;
     const int ntot = NCOMP * nchunk;  // chunks of all components, F first
 
@@ -355,10 +417,11 @@ k_fr_layer(const FrArgs A) {
     // chunk c is computed.  Of the z-face traces (N^2 points per velocity,
     // needed by every layer) the wave of layer l fetches the points (i, l)
     // and passes them on through the tile.
-    Real fc[NL], TX[N], TY[N], TZ[N];
+    SReal fc[NL];
+    Real TX[N], TY[N], TZ[N];
     {
         const Vel v0 = velocity(A, vl, true);
-        const uint32_t o = (lrow + (uint32_t)v0.k) * (uint32_t)sizeof(Real);
+        const uint32_t o = (lrow + (uint32_t)v0.k) * (uint32_t)sizeof(SReal);
 #pragma unroll
         for (int q = 0; q < NL; ++q) fc[q] = ldb(fE, o + q * QB);
         if (FLUX) {
@@ -378,7 +441,7 @@ k_fr_layer(const FrArgs A) {
         const int comp = NCOMP == 2 && cc >= nchunk ? 1 : 0;
         const int ch = cc - comp * nchunk;
         const Vel v = velocity(A, ch * kChunk + vl, true);
-        const uint32_t o = (lrow + (uint32_t)(comp * nu + v.k)) * (uint32_t)sizeof(Real);
+        const uint32_t o = (lrow + (uint32_t)(comp * nu + v.k)) * (uint32_t)sizeof(SReal);
         // tile taking the stage value of the chunk, and tile read by the z
         // traces and the moment pass (the same, alternating, for the prime pass)
         Real *const tpub = FLUX ? tS : ((cc & 1) ? tP : tS);
@@ -387,8 +450,23 @@ k_fr_layer(const FrArgs A) {
         // and moments read) and this wave's z-face traces; every later use of
         // the stage value reads the tile, so its registers take the next
         // chunk's loads right away.
+        if (in_dev) {
+            // f = ref(previous stage's record) + d at each point of the layer
 #pragma unroll
-        for (int q = 0; q < NL; ++q) tpub[tix<Real>(l * NL + q, vl)] = fc[q];
+            for (int q = 0; q < NL; ++q) {
+                double b[kEqCoef];
+#pragma unroll
+                for (int c = 0; c < kEqCoef; ++c) {
+                    const int t = q * kEqCoef + c;
+                    b[c] = read_lane(prv[t / kChunk], t % kChunk);
+                }
+                const double E = eq_exponent(b[0], b[1], b[2], b[3], b[4], b[5], b[6], b[7], b[8], b[9], v.u);
+                tpub[tix<Real>(l * NL + q, vl)] = (Real)fc[q] + (Real)dev_ref(E);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NL; ++q) tpub[tix<Real>(l * NL + q, vl)] = (Real)fc[q];
+        }
         if (FLUX) {
 #pragma unroll
             for (int a = 0; a < N; ++a) tZ[tix<Real>(N * l + a, vl)] = TZ[a];
@@ -400,7 +478,7 @@ k_fr_layer(const FrArgs A) {
         {
             const int chn = cc + 1 - compn * nchunk;
             const Vel vn = velocity(A, chn * kChunk + vl, NCOMP == 1 || cc + 1 < ntot);
-            const uint32_t on = (lrow + (uint32_t)(compn * nu + vn.k)) * (uint32_t)sizeof(Real);
+            const uint32_t on = (lrow + (uint32_t)(compn * nu + vn.k)) * (uint32_t)sizeof(SReal);
 #pragma unroll
             for (int q = 0; q < NL; ++q) fc[q] = ldb(fE, on + q * QB);
             if (FLUX) {
@@ -413,7 +491,7 @@ k_fr_layer(const FrArgs A) {
         }
         // the second RK register of this chunk, requested before the x/y/z
         // passes so that they cover its latency
-        Real X[NL];
+        SReal X[NL];
         if (useX) {
 #pragma unroll
             for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
@@ -488,7 +566,7 @@ k_fr_layer(const FrArgs A) {
             if (MODE == MODE_RESID) {
                 if (v.act) {
 #pragma unroll
-                    for (int q = 0; q < NL; ++q) stb(outE, o + q * QB, -r[q]);
+                    for (int q = 0; q < NL; ++q) stb(outE, o + q * QB, (SReal)(-r[q]));
                 }
                 __syncthreads();  // every layer is done with the stage tile
                 continue;
@@ -499,25 +577,14 @@ k_fr_layer(const FrArgs A) {
             for (int q = 0; q < NL; ++q) {
                 const Real fq = tS[tix<Real>(l * NL + q, vl)];
                 Real L = -r[q];
+                double Eq = 0.0;  // the equilibrium's exponent at this point and velocity
                 if (EQ_LDS && collide) {
                     const int s = l * NL + q;
                     const double *b = &s_eb[s * 8];
                     const double *V = &s_ev[s * 4];
-                    const double c0 = v.u[0] - V[0], c1 = v.u[1] - V[1], c2 = v.u[2] - V[2];
-                    double t0 = b[0] * c0;
-                    t0 = fma(b[3], c1, t0);
-                    t0 = fma(b[4], c2, t0);
-                    double t1 = b[1] * c1;
-                    t1 = fma(b[5], c2, t1);
-                    const double t2 = b[2] * c2;
-                    double E;
-                    if constexpr (NCOMP == 2)
-                        E = fma(c0, t0, comp ? b[6] + V[3] : b[6]);
-                    else
-                        E = fma(c0, t0, b[6]);
-                    E = fma(c1, t1, E);
-                    E = fma(c2, t2, E);
-                    L += (exp_r<Real>(E) - fq) * (Real)b[7];
+                    const double b6 = (NCOMP == 2 && comp) ? b[6] + V[3] : b[6];
+                    Eq = eq_exponent(b[0], b[1], b[2], b[3], b[4], b[5], b6, V[0], V[1], V[2], v.u);
+                    L += (exp_r<Real>(Eq) - fq) * (Real)b[7];
                 } else if (collide) {
                     // E = c0 - (c^T B c)/2, c = u - V, formed in FP64
                     cdouble *rq = eqL + q * kEqW;
@@ -541,18 +608,25 @@ k_fr_layer(const FrArgs A) {
                     const double E = fma(-0.5, S, lc);
                     L += (exp_r<Real>(E) - fq) * (Real)rq[EQ_INVTAU];
                 }
-                Real fo;
+                // the result, in FP64 for the stochastic rounding of the FP32 state
+                double fod;
                 if (A.sa.scheme == 0) {
-                    fo = (Real)A.sa.beta * (fq + dt * L);
-                    if (useX) fo += (Real)A.sa.alpha * X[q];
+                    fod = A.sa.beta * ((double)fq + (double)(dt * L));
+                    if (useX) fod = fma(A.sa.alpha, (double)X[q], fod);
                 } else {
                     Real dd = dt * L;
-                    if (useX) dd += (Real)A.sa.lsA * X[q];
-                    if (v.act && A.sa.keep_dF) stb(dFE, o + q * QB, dd);
-                    fo = fq + (Real)A.sa.lsB * dd;
+                    if (useX) dd += (Real)A.sa.lsA * (Real)X[q];
+                    if (v.act && A.sa.keep_dF) stb(dFE, o + q * QB, (SReal)dd);
+                    fod = fma(A.sa.lsB, (double)dd, (double)fq);
                 }
+                Real fo;
+                if constexpr (sizeof(Real) == 4)
+                    fo = round_stochastic(
+                        fod, round_bits(A.sa.seed, (uint32_t)(e * NS + l * NL + q), (uint32_t)(comp * nu + v.k)));
+                else
+                    fo = (Real)fod;
                 f[q] = v.act ? fo : Real(0);
-                if (v.act) stb(outE, o + q * QB, fo);
+                if (v.act) stb(outE, o + q * QB, (SReal)(out_dev ? fo - (Real)dev_ref(Eq) : fo));
                 if (q % 4 == 3) phase_fence();
             }
         }
@@ -692,26 +766,26 @@ k_fr_layer(const FrArgs A) {
     }
 }
 
-template <typename Real, int P, int NMOM>
+template <typename Real, typename SReal, int P, int NMOM>
 int launch_p(fr_dvm *h, int mode, const FrArgs &A) {
     dim3 grid((unsigned)(A.sa.ecount ? A.sa.ecount : h->ne)), block(kChunk * (P + 1));
     if (mode == MODE_PRIME)
-        hipLaunchKernelGGL((k_fr_layer<Real, P, NMOM, MODE_PRIME>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_fr_layer<Real, SReal, P, NMOM, MODE_PRIME>), grid, block, 0, h->stream, A);
     else if (mode == MODE_STAGE)
-        hipLaunchKernelGGL((k_fr_layer<Real, P, NMOM, MODE_STAGE>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_fr_layer<Real, SReal, P, NMOM, MODE_STAGE>), grid, block, 0, h->stream, A);
     else
-        hipLaunchKernelGGL((k_fr_layer<Real, P, NMOM, MODE_RESID>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_fr_layer<Real, SReal, P, NMOM, MODE_RESID>), grid, block, 0, h->stream, A);
     hipError_t st = hipGetLastError();
     if (st != hipSuccess) return h->fail(FR_DVM_EHIP, std::string("FR kernel launch: ") + hipGetErrorString(st));
     return FR_DVM_OK;
 }
 
-template <typename Real, int NMOM>
+template <typename Real, typename SReal, int NMOM>
 int launch_np(fr_dvm *h, int mode, const FrArgs &A) {
     switch (h->p) {
-        case 1: return launch_p<Real, 1, NMOM>(h, mode, A);
-        case 2: return launch_p<Real, 2, NMOM>(h, mode, A);
-        case 3: return launch_p<Real, 3, NMOM>(h, mode, A);
+        case 1: return launch_p<Real, SReal, 1, NMOM>(h, mode, A);
+        case 2: return launch_p<Real, SReal, 2, NMOM>(h, mode, A);
+        case 3: return launch_p<Real, SReal, 3, NMOM>(h, mode, A);
     }
     return h->fail(FR_DVM_EUNSUPPORTED, "order");
 }
@@ -763,13 +837,19 @@ int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int 
     A.do_moments = do_moments;
     A.elem_comp = h->tl.elem / h->ncomp;
     A.gfp = h->d_gfp;
+    if (h->prm.precision == FR_DVM_FP32_DEV) {
+        // FP64 arithmetic and traces on FP32-stored deviations (monatomic)
+        if (h->nmom == 5) return launch_np<double, float, 5>(h, mode, A);
+        if (h->nmom == 10) return launch_np<double, float, 10>(h, mode, A);
+        return h->fail(FR_DVM_EUNSUPPORTED, "FP32 deviation storage needs a monatomic gas");
+    }
     const bool fp64 = h->prm.precision == FR_DVM_FP64;
     switch (h->nmom) {
-        case 5: return fp64 ? launch_np<double, 5>(h, mode, A) : launch_np<float, 5>(h, mode, A);
-        case 6: return fp64 ? launch_np<double, 6>(h, mode, A) : launch_np<float, 6>(h, mode, A);
-        case 10: return fp64 ? launch_np<double, 10>(h, mode, A) : launch_np<float, 10>(h, mode, A);
+        case 5: return fp64 ? launch_np<double, double, 5>(h, mode, A) : launch_np<float, float, 5>(h, mode, A);
+        case 6: return fp64 ? launch_np<double, double, 6>(h, mode, A) : launch_np<float, float, 6>(h, mode, A);
+        case 10: return fp64 ? launch_np<double, double, 10>(h, mode, A) : launch_np<float, float, 10>(h, mode, A);
     }
-    return fp64 ? launch_np<double, 11>(h, mode, A) : launch_np<float, 11>(h, mode, A);
+    return fp64 ? launch_np<double, double, 11>(h, mode, A) : launch_np<float, float, 11>(h, mode, A);
 }
 
 }  // namespace frdvm

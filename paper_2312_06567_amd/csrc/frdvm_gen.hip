@@ -485,16 +485,22 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
                 E = fma(c2, t2, E);
                 L += (gexp<Real>(E) - fq) * (Real)bq[7];
             }
-            Real fo;
+            // the result, in FP64 for the stochastic rounding of the FP32 state
+            double fod;
             if (A.sa.scheme == 0) {
-                fo = (Real)A.sa.beta * (fq + dt * L);
-                if (useX) fo += (Real)A.sa.alpha * xv[r];
+                fod = A.sa.beta * ((double)fq + (double)(dt * L));
+                if (useX) fod = fma(A.sa.alpha, (double)xv[r], fod);
             } else {
                 Real dd = dt * L;
                 if (useX) dd += (Real)A.sa.lsA * xv[r];
                 if (A.sa.keep_dF) sto(dFE + s * nu, ko, dd);
-                fo = fq + (Real)A.sa.lsB * dd;
+                fod = fma(A.sa.lsB, (double)dd, (double)fq);
             }
+            Real fo;
+            if constexpr (sizeof(Real) == 4)
+                fo = round_stochastic(fod, round_bits(A.sa.seed, (uint32_t)(e * NS + s), (uint32_t)k));
+            else
+                fo = (Real)fod;
             sf[s][lane] = fo;
             if (limit) {
                 lim_int = fma(gW[s], (double)fo, lim_int);

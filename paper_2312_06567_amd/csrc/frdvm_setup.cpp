@@ -590,7 +590,7 @@ namespace {
 // boundary tables.  The box path's trace buffers are released here (their
 // size depends on the path) and reallocated by the caller.
 int move_to_general(fr_dvm *h) {
-    const size_t es = h->prm.precision == FR_DVM_FP64 ? sizeof(double) : sizeof(float);
+    const size_t es = h->prm.precision == FR_DVM_FP32 ? sizeof(float) : sizeof(double);  // trace values
     for (int b = 0; b < 2; ++b)
         if (h->d_tr[b]) {
             hipFree(h->d_tr[b]);
@@ -619,7 +619,13 @@ int move_to_general(fr_dvm *h) {
 extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     if (!h || !p) return FR_DVM_EINVAL;
     if (p->model < 0 || p->model > 2) return h->fail(FR_DVM_EINVAL, "unknown model");
-    if (p->precision != FR_DVM_FP64 && p->precision != FR_DVM_FP32) return h->fail(FR_DVM_EINVAL, "unknown precision");
+    if (p->precision != FR_DVM_FP64 && p->precision != FR_DVM_FP32 && p->precision != FR_DVM_FP32_DEV)
+        return h->fail(FR_DVM_EINVAL, "unknown precision");
+    if (p->precision == FR_DVM_FP32_DEV &&
+        (!h->axis_mode || p->positivity || h->ncomp != 1 || p->rk != FR_DVM_LSRK3_2N))
+        return h->fail(FR_DVM_EUNSUPPORTED,
+                       "FP32 deviation storage needs a periodic box mesh, a monatomic gas, the low-storage RK "
+                       "scheme and no positivity limiter");
     if (p->model == FR_DVM_ESBGK && !(p->prandtl > 0)) return h->fail(FR_DVM_EINVAL, "Prandtl number must be positive");
     if (!(p->mu_ref > 0) && p->model != FR_DVM_FREE) return h->fail(FR_DVM_EINVAL, "mu_ref must be positive");
     if (p->newton_max_iter < 1 || p->newton_max_iter > 200) return h->fail(FR_DVM_EINVAL, "newton_max_iter out of range");
@@ -638,24 +644,29 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     int nmom = ((p->model == FR_DVM_ESBGK) ? 10 : 5) + (h->ncomp == 2 ? 1 : 0);
     bool realloc_mom = !h->have_params || nmom != h->nmom;
     // element size of the buffers allocated under the previous parameters
-    const size_t es_old = h->have_params && h->prm.precision == FR_DVM_FP32 ? sizeof(float) : sizeof(double);
+    const size_t es_old = h->have_params && h->prm.precision != FR_DVM_FP64 ? sizeof(float) : sizeof(double);
+    // traces: FP64 unless the whole stage is FP32
+    const size_t tes_old = h->have_params && h->prm.precision == FR_DVM_FP32 ? sizeof(float) : sizeof(double);
     h->prm = *p;
     h->nmom = nmom;
+    h->stage_count = 0;
     size_t es = p->precision == FR_DVM_FP64 ? sizeof(double) : sizeof(float);
+    size_t tes = p->precision == FR_DVM_FP32 ? sizeof(float) : sizeof(double);
     int64_t npts = h->ne * h->ns;
     int64_t nu = h->vg.nu * h->ncomp;  // state values per point
     int rc;
     if (realloc_all) {
         if (h->d_reg) { hipFree(h->d_reg); h->owned_bytes -= npts * nu * es_old; h->d_reg = nullptr; }
         for (int b = 0; b < 2; ++b)
-            if (h->d_tr[b]) { hipFree(h->d_tr[b]); h->d_tr[b] = nullptr; h->owned_bytes -= h->ne * h->tl.elem * es_old; }
+            if (h->d_tr[b]) { hipFree(h->d_tr[b]); h->d_tr[b] = nullptr; h->owned_bytes -= h->ne * h->tl.elem * tes_old; }
         if (hipMalloc(&h->d_reg, npts * nu * es) != hipSuccess) { h->d_reg = nullptr; return h->fail(FR_DVM_ENOMEM, "register allocation failed"); }
         h->owned_bytes += npts * nu * es;
         for (int b = 0; b < 2; ++b) {
-            if (hipMalloc(&h->d_tr[b], h->ne * h->tl.elem * es) != hipSuccess) { h->d_tr[b] = nullptr; return h->fail(FR_DVM_ENOMEM, "trace allocation failed"); }
-            h->owned_bytes += h->ne * h->tl.elem * es;
+            if (hipMalloc(&h->d_tr[b], h->ne * h->tl.elem * tes) != hipSuccess) { h->d_tr[b] = nullptr; return h->fail(FR_DVM_ENOMEM, "trace allocation failed"); }
+            h->owned_bytes += h->ne * h->tl.elem * tes;
         }
         if ((rc = dev_alloc(h, &h->d_eq, npts * kEqW))) return rc;
+        if ((rc = dev_alloc(h, &h->d_eq_prev, p->precision == FR_DVM_FP32_DEV ? npts * kEqW : 0))) return rc;
         if ((rc = dev_alloc(h, &h->d_z, npts * 5))) return rc;
         if ((rc = dev_alloc(h, &h->d_prim, npts * 5))) return rc;
         if ((rc = dev_alloc(h, &h->d_pt_iters, npts))) return rc;
@@ -777,7 +788,7 @@ extern "C" void fr_dvm_destroy(fr_dvm_t h) {
     if (!h) return;
     if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
     void *ptrs[] = {h->d_gfac, h->d_nbr, h->d_wq3J, h->d_wx3, h->d_wrow, h->d_wax, h->d_reg, h->d_tr[0], h->d_tr[1],
-                    h->d_Q, h->d_eq, h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
+                    h->d_Q, h->d_eq, h->d_eq_prev, h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
                     h->d_mlp_x, h->d_mlp_work, h->d_mlp_dz, h->d_pt_iters, h->d_pt_evals, h->d_pt_status,
                     h->d_pt_resid, h->d_S, h->d_ijac, h->d_nf, h->d_conn, h->d_wall, h->d_rw, h->d_mw,
                     h->d_finf, h->d_Sf, h->d_ijacf, h->d_nff, h->d_gfp};

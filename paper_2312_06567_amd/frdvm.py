@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fr_dvm.h")
 BGK, ESBGK, FREE = 0, 1, 2
 E_SCRATCH = -5  # FR_DVM_ESCRATCH of fr_dvm.h
 MLP_NOALLOC_FLOATS = 1 << 22  # FR_MLP_NOALLOC_FLOATS of fr_dvm_mlp.h
-FP64, FP32 = 0, 1
+FP64, FP32, FP32_DEV = 0, 1, 2
 GUESS_COLD, GUESS_WARM, GUESS_MLP, GUESS_MLP_WARM = 0, 1, 2, 3
 MLP_INPUTS = 13  # FR_MLP_INPUTS of fr_dvm_mlp.h
 SSPRK3, LSRK3_2N = 0, 1

@@ -15,6 +15,16 @@ velocities.
     launches) to 1e-12 relative L2 (Section "Numerical method": the FR
     residual with the upwind interface flux; eq. discrete_compatibility:
     the conservative equilibrium).
+(c) FP32 deviation storage (FP32 f buffers, FP64 stage arithmetic, traces,
+    moments and Newton; between the stages of one call the state is held as
+    the FP32 deviation from the local equilibrium), low-storage RK, warm
+    start: five steps.  Bounds: f to 1e-7 relative L2 and rho, rho U and E
+    to 2e-8; and, since the call returns f rounded once to FP32, f within
+    1.5x and each moment within 2x of the error of the oracle's own result
+    rounded once to FP32 (FP32-sized errors inside the call, such as a
+    reconstruction that did not reproduce the writer's equilibrium to the
+    last bit, would leave errors of the FP32 path's size: about 4x that
+    floor).
 (b) FP32 storage and operators, low-storage RK, FP64 moments and Newton,
     warm start: five steps.  Bounds: f to 5e-7 relative L2 and the moments
     rho, rho U and E to 3e-7 relative L2 per field.  Each of the 15 stages
@@ -100,3 +110,42 @@ def test_fp32_lsrk_stage_bounds(F, orc, gi):
     print(f"grid {grid['n']}: f {ef:.2e}, rho {eq[0]:.2e}, rho U {eq[1]:.2e}, E {eq[2]:.2e}")
     assert ef < 5e-7, ef
     assert max(eq) < 3e-7, eq
+
+
+def _fp32_run(F, orc, gi, precision):
+    grid = GRIDS[gi]
+    mesh, par, f0 = _case(grid)
+    f0 = f0.astype(np.float32).astype(np.float64)
+    s = F.FrDvm(mesh, HEADLINE["p"], grid, dict(par, precision=precision, rk=1, guess=1))
+    dt = _dt(s)
+    P = orc.Problem(mesh, HEADLINE["p"], grid, par)
+    ref = P.rk_step(f0, dt, scheme=1, nsteps=5)
+    f = torch.as_tensor(f0, dtype=torch.float32).cuda().contiguous()
+    s.newton_stats(reset=True)
+    s.rk_steps(f, dt, 5)
+    got = f.double().cpu().numpy()
+    st = s.newton_stats(reset=True)
+    assert st["n_fallback"] == 0 and st["n_guard"] == 0
+    return P, ref, got
+
+
+def _errors(P, got, ref):
+    Qg, Qr = P.moments(got), P.moments(ref)
+    return rel(got, ref), [rel(Qg[..., 0], Qr[..., 0]), rel(Qg[..., 1:4], Qr[..., 1:4]), rel(Qg[..., 4], Qr[..., 4])]
+
+
+@pytest.mark.parametrize("gi", [0, 1])
+def test_fp32_deviation_storage_bounds(F, orc, gi):
+    P, ref, got = _fp32_run(F, orc, gi, F.FP32_DEV)
+    ef, eq = _errors(P, got, ref)
+    # the floor: the oracle's own result rounded once to FP32
+    ff, fq = _errors(P, ref.astype(np.float32).astype(np.float64), ref)
+    _, _, got32 = _fp32_run(F, orc, gi, F.FP32)
+    ef32, eq32 = _errors(P, got32, ref)
+    print(f"grid {GRIDS[gi]['n']}: deviation storage f {ef:.2e}, moments {[f'{x:.2e}' for x in eq]}; "
+          f"one FP32 rounding f {ff:.2e}, moments {[f'{x:.2e}' for x in fq]}; "
+          f"FP32 path f {ef32:.2e}, moments {[f'{x:.2e}' for x in eq32]}")
+    assert ef < 1e-7, ef
+    assert max(eq) < 2e-8, eq
+    assert ef < 1.5 * ff, (ef, ff)
+    assert all(a < 2.0 * b for a, b in zip(eq, fq)), (eq, fq)

@@ -306,3 +306,14 @@ def test_invalid_inputs_raise(F):
         s.residual(f, f)  # aliasing output
     with pytest.raises(F.FrDvmError):
         s.rk_step(f.float(), 1e-3)  # wrong precision
+    # FP32 deviation storage: box meshes, low-storage RK, monatomic, no limiter
+    with pytest.raises(F.FrDvmError):
+        s.set_params(**_params(precision=F.FP32_DEV, rk=0))
+    with pytest.raises(F.FrDvmError):
+        s.set_params(**_params(precision=F.FP32_DEV, rk=1, positivity=1))
+    with pytest.raises(F.FrDvmError):
+        F.FrDvm(W.box_mesh(2), 1, grid, delta=2.0).set_params(**_params(precision=F.FP32_DEV, rk=1))
+    with pytest.raises(F.FrDvmError):
+        F.FrDvm(W.cylinder_mesh(n_theta=4, n_r=1, n_z=1), 1, grid).set_params(**_params(precision=F.FP32_DEV, rk=1))
+    with pytest.raises(F.FrDvmError):
+        s.set_params(**_params(positivity=2))
