@@ -12,6 +12,7 @@ the FP64 tolerance (falling back to the cold start if the guess fails).
 from __future__ import annotations
 
 import math
+import sys
 
 import numpy as np
 
@@ -87,7 +88,7 @@ def solve_targets(states: dict, nv: int = 32, guess=frdvm.GUESS_COLD, handles=No
     return out
 
 
-def train(X, T, H=64, steps=3000, batch=4096, lr=1e-3, seed=4, log_every=0):
+def train(X, T, H=64, steps=3000, batch=4096, lr=1e-3, seed=4, log_every=0, verbose=False):
     """Adam on the GPU with cosine learning-rate decay.  X [n,7], T [n,5]
     (unnormalised dz) float32 CUDA tensors.  Returns the flat weights (CUDA
     float32, with the target z-score folded into the output affine) and the
@@ -126,10 +127,13 @@ def train(X, T, H=64, steps=3000, batch=4096, lr=1e-3, seed=4, log_every=0):
         net.adam(w, g, m1, m2, step, lr_t)
         if log_every and (step % log_every == 0 or step == 1):
             hist.append((step, float(loss.item())))
+            if verbose:
+                print(f"[learned] step {step}/{steps} loss {hist[-1][1]:.4e}", file=sys.stderr, flush=True)
     return w, hist
 
 
-def fit_guess(n_states=100_000, nv=32, H=64, steps=3000, seed=4, umax_choices=(6.0, 10.0, 14.0), extra=None):
+def fit_guess(n_states=100_000, nv=32, H=64, steps=3000, seed=4, umax_choices=(6.0, 10.0, 14.0), extra=None,
+              verbose=False):
     """Generate states, solve them, train the network.  `extra` may add
     solver-harvested states (dict of arrays rho, U, theta, umax).  Returns
     (weights as numpy float32, info dict)."""
@@ -141,10 +145,12 @@ def fit_guess(n_states=100_000, nv=32, H=64, steps=3000, seed=4, umax_choices=(6
             st[k] = np.concatenate([st[k], extra[k]])
     sol = solve_targets(st, nv=nv)
     ok = sol["status"] == frdvm.NEWTON_OK
+    if verbose:
+        print(f"[learned] {int(ok.sum())} of {len(ok)} training states solved", file=sys.stderr, flush=True)
     X = features(st["rho"][ok], st["U"][ok], st["theta"][ok], st["umax"][ok], nv).cuda()
     env = envelope(st["U"][ok], st["theta"][ok], st["umax"][ok], nv)
     T = torch.as_tensor((sol["z"][ok] - Z_COLD) / env[:, None], dtype=torch.float32, device="cuda")
-    w, hist = train(X, T, H=H, steps=steps, seed=seed, log_every=max(steps // 10, 1))
+    w, hist = train(X, T, H=H, steps=steps, seed=seed, log_every=max(steps // 10, 1), verbose=verbose)
     info = {"n_states": int(len(ok)), "n_converged": int(ok.sum()), "reject_rate": float(st["reject_rate"]),
             "cold_mean_iters": float(sol["iters"][ok].mean()), "loss_history": hist}
     return w.cpu().numpy(), info
@@ -189,8 +195,10 @@ if __name__ == "__main__":
     ap.add_argument("--hidden", type=int, default=64)
     args = ap.parse_args()
     t0 = time.perf_counter()
-    w, info = fit_guess(n_states=args.train, H=args.hidden, steps=args.steps, seed=4)
+    w, info = fit_guess(n_states=args.train, H=args.hidden, steps=args.steps, seed=4, verbose=True)
     t1 = time.perf_counter()
+    print(f"[learned] trained in {t1 - t0:.1f} s; evaluating on {args.test} held-out states", file=sys.stderr,
+          flush=True)
     ev = evaluate(w, n_states=args.test)
     out = {"train_states": args.train, "train_steps": args.steps, "hidden": args.hidden,
            "train_seconds": t1 - t0, "final_loss": info["loss_history"][-1][1] if info["loss_history"] else None,
