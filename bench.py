@@ -295,6 +295,17 @@ def coarse_to_fine(Qc, Nc, p):
     return F.reshape(-1, k)
 
 
+def f_rel_l2(fa, fb):
+    """Relative L2 difference of two distributions on the GPU, in FP64,
+    taken in slabs (fa may be FP32)."""
+    num = 0.0
+    den = 0.0
+    for a, b in zip(fa.reshape(-1, fa.shape[-1]).split(4096), fb.reshape(-1, fb.shape[-1]).split(4096)):
+        num += float((a.double() - b.double()).pow(2).sum().item())
+        den += float(b.double().pow(2).sum().item())
+    return math.sqrt(num / den)
+
+
 def rel_moments(Qa, Qb):
     import numpy as np
     out = {}
@@ -484,6 +495,7 @@ def main():
     p32 = dict(base, precision=1, rk=1, guess=3)
     r32 = run_config(W, w, mesh, p32, args.steps, args.warmup, "fp32-learned", weights=weights, keep_moments=True)
     err = None
+    f_err = None
     if args.no_error:
         # moment difference after the timed runs only
         horizon = args.steps + args.warmup
@@ -495,11 +507,17 @@ def main():
         # temporal from a dt/2 run, spatial from the N/2 mesh at the same dt
         # (Richardson with order p+1: e_N ~ |Q_N - I Q_N/2| / (2^(p+1) - 1))
         horizon = args.horizon if args.horizon is not None else int(w.get("steps", args.steps + args.warmup))
-        a64 = run_config(W, w, mesh, p64, 0, 0, "fp64-horizon", keep_moments=True, nsteps_override=horizon)
+        a64 = run_config(W, w, mesh, p64, 0, 0, "fp64-horizon", keep_moments=True, nsteps_override=horizon,
+                         keep_f=True)
         amx = run_config(W, w, mesh, pmx, 0, 0, "mixed-horizon", weights=weights, keep_moments=True,
-                         nsteps_override=horizon)
+                         nsteps_override=horizon, keep_f=True)
         a32 = run_config(W, w, mesh, p32, 0, 0, "fp32-horizon", weights=weights, keep_moments=True,
-                         nsteps_override=horizon)
+                         nsteps_override=horizon, keep_f=True)
+        # relative L2 difference of f itself from the FP64 run
+        f_err = {"mixed": f_rel_l2(amx.pop("f"), a64["f"]), "fp32": f_rel_l2(a32.pop("f"), a64["f"])}
+        del a64["f"]
+        import torch
+        torch.cuda.empty_cache()
         rh = run_config(W, w, mesh, p64, 0, 0, "fp64-half-dt", keep_moments=True, dt_scale=0.5,
                         nsteps_override=2 * horizon)
         mesh_c = W.box_mesh(w["N"] // 2)
@@ -539,6 +557,7 @@ def main():
                           "newton": r64["newton"], "roofline": roofline(r64, w["p"], w["name"])},
            "speedup_vs_fp64": rmx["value"] / r64["value"],
            "equal_error": {"mixed_vs_fp64_rel_l2": err_m, "fp64_discretisation_rel_l2": err, "holds": holds,
+                           "f_vs_fp64_rel_l2": f_err,
                            "criterion": "mixed_vs_fp64 <= 0.1 * (temporal + spatial) per conserved field",
                            "horizon_steps": horizon, "conservation_drift": drift},
            "kernels_ms_per_step": {k: v[0] / rmx["steps"] for k, v in rmx["prof"].items()},
@@ -576,15 +595,11 @@ def horizon_compare(W, w, mesh, base, args, cfg):
     rmx = run_config(W, w, mesh, dict(base, precision=mprec, rk=1, guess=1), 0, 0, "mixed-horizon",
                      keep_moments=True, nsteps_override=H, keep_f=True)
     f64, fmx = r64.pop("f"), rmx.pop("f")
-    num = 0.0
-    den = 0.0
-    for a, b in zip(fmx.reshape(-1, fmx.shape[-1]).split(4096), f64.reshape(-1, f64.shape[-1]).split(4096)):
-        num += float((a.double() - b).pow(2).sum().item())
-        den += float(b.pow(2).sum().item())
+    ferr = f_rel_l2(fmx, f64)
     del f64, fmx
     torch.cuda.empty_cache()
     err = bench_rel = rel_moments(rmx["Q"], r64["Q"])
-    err["f"] = math.sqrt(num / den)
+    err["f"] = ferr
     cfg = dict(cfg, mixed=(MIXED_LABEL if mprec == MIXED else "FP32 f, FP32 FR/RK arithmetic, FP64 moments + Newton")
                + "; LSRK3-2N; warm Newton start",
                plain="FP64 everything; SSP-RK3; warm Newton start", positivity=base.get("positivity", 0))
