@@ -294,7 +294,9 @@ __global__ __launch_bounds__(kGBlock) void k_gen_wall(const GenArgs A, const Rea
 // One wave per (element, 64 velocities).  Each lane keeps its velocity's N^3
 // stage values and residual accumulators in its own LDS column (lane-private:
 // no barrier between the phases), so the loops over source points and flux
-// points stay rolled and the registers hold only the current line.
+// points stay rolled and the registers hold only the current line.  (With the
+// accumulators in registers and the direction loop unrolled, p = 2 needs 175
+// VGPRs in FP32 and p = 3 all 256 with scratch: no occupancy is gained.)
 template <typename Real, int P, int MODE>
 __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     constexpr int N = P + 1, NS = N * N * N, NFP = N * N;
@@ -502,42 +504,23 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
             else
                 fo = (Real)fod;
             sf[s][lane] = fo;
+            sto(outE + s * nu, ko, fo);
             if (limit) {
                 lim_int = fma(gW[s], (double)fo, lim_int);
                 lim_w += gW[s];
                 lim_min = s == 0 ? fo : (fo < lim_min ? fo : lim_min);
-            } else {
-                sto(outE + s * nu, ko, fo);
             }
         }
     }
-    if (limit) {
-        // the smallest value of the element polynomial at its solution and
-        // flux points; if negative, scale about the element mean (weights
-        // Gauss x |J|) so that it becomes zero there: the element integral of
-        // the value, hence every moment, is kept
-#pragma unroll 1
-        for (int face = 0; face < 6; ++face) {
-            const int d = face / 2, side = face & 1;
-#pragma unroll 1
-            for (int q = 0; q < NFP; ++q) {
-                Real t = Real(0);
-#pragma unroll
-                for (int m = 0; m < N; ++m) t += op.lam[side][m] * sf[line_pt<N>(d, q % N, q / N, m)][lane];
-                lim_min = t < lim_min ? t : lim_min;
-            }
-        }
-        if (lim_min < Real(0)) {
-            const double mean = lim_int / lim_w;
-            const double th = mean > 0.0 ? mean / (mean - (double)lim_min) : 0.0;
-#pragma unroll 1
-            for (int s = 0; s < NS; ++s) sf[s][lane] = (Real)fma(th, (double)sf[s][lane] - mean, mean);
-        }
-#pragma unroll 4
-        for (int s = 0; s < NS; ++s) sto(outE + s * nu, ko, sf[s][lane]);
-    }
-    if (A.do_traces) {
-        Real *te = reinterpret_cast<Real *>(A.sa.tr_out) + e * 6 * NFP * nu;
+    // Traces of the result at every flux point; with the positivity limiter
+    // the same pass finds the smallest value of the element polynomial at its
+    // solution and flux points.  Where that is negative (rare: f is positive
+    // almost everywhere) the lane scales its polynomial about the element mean
+    // (weights Gauss x |J|), so that the smallest value becomes zero and the
+    // element integral of the value, hence every moment, is kept, and stores
+    // the values and traces again.
+    Real *te = reinterpret_cast<Real *>(A.sa.tr_out) + e * 6 * NFP * nu;
+    auto trace_pass = [&](bool store, bool find_min) {
 #pragma unroll 1
         for (int face = 0; face < 6; ++face) {
             const int d = face / 2, side = face & 1;
@@ -547,9 +530,22 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
                 Real t = Real(0);
 #pragma unroll
                 for (int m = 0; m < N; ++m) t += op.lam[side][m] * sf[line_pt<N>(d, a, b, m)][lane];
-                sto(te + (face * NFP + q) * nu, ko, t);
+                if (store) sto(te + (face * NFP + q) * nu, ko, t);
+                if (find_min) lim_min = t < lim_min ? t : lim_min;
             }
         }
+    };
+    if (A.do_traces || limit) trace_pass(A.do_traces, limit);
+    if (limit && lim_min < Real(0)) {
+        const double mean = lim_int / lim_w;
+        const double th = mean > 0.0 ? mean / (mean - (double)lim_min) : 0.0;
+#pragma unroll 1
+        for (int s = 0; s < NS; ++s) {
+            const Real v = (Real)fma(th, (double)sf[s][lane] - mean, mean);
+            sf[s][lane] = v;
+            sto(outE + s * nu, ko, v);
+        }
+        if (A.do_traces) trace_pass(true, false);
     }
 }
 
