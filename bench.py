@@ -47,12 +47,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 # The mixed storage form of the compare mode (precision code of fr_dvm_params):
-# FR_DVM_FP32_DEV, f held in FP32 as its deviation from the local conservative
-# equilibrium between stages, all stage arithmetic in FP64.
+# FR_DVM_FP32_DEV, f held in FP32 as its deviation from an element reference
+# equilibrium between stages, FP32 stage arithmetic on the deviations.
 MIXED = 2
-MIXED_LABEL = ("FP32 storage of f as the deviation from the local equilibrium (FP32 f at call boundaries), "
-               "FP32 RK register, FP64 stage arithmetic, traces, moments and Newton")
-MIXED_DTYPE = "f32 storage (deviation from equilibrium), f64 arithmetic"
+MIXED_LABEL = ("FP32 storage and FP32 FR/RK arithmetic of the deviation of f from an element reference "
+               "equilibrium (FP32 f at call boundaries), FP32 traces and RK register, FP64 moments and Newton")
+MIXED_DTYPE = "f32 (deviation from an element reference), FP64 moments and Newton"
 
 
 def log(msg):
@@ -61,8 +61,8 @@ def log(msg):
 
 def value_sizes(precision: int):
     """Bytes of a state value and of a trace value: FP64 (0) 8 / 8, FP32 (1)
-    4 / 4, FP32 deviation storage (2) 4 / 8 (its traces are FP64)."""
-    return (8 if precision == 0 else 4), (4 if precision == 1 else 8)
+    and FP32 deviation storage (2) 4 / 4."""
+    return (8, 8) if precision == 0 else (4, 4)
 
 
 def stage_values_per_dof(p: int, rk: int, stage: int, last: bool):

@@ -59,19 +59,23 @@ extern "C" {
 /* storage / arithmetic precision of f and of the FR operators */
 #define FR_DVM_FP64 0
 #define FR_DVM_FP32 1
-/* FP32 deviation storage: f buffers are float, all stage arithmetic, traces,
- * moments and Newton are FP64.  Inside one fr_dvm_rk_step(s) call every
- * stage leaves its result in the caller's buffer as the FP32 deviation
- * d = f - r from a reference r close to the conservative equilibrium that
- * the stage's collision used at that point (eq. discrete_compatibility; r
- * is that equilibrium's FP64 exponent through the FP32 hardware exp2), and
- * the next stage reads f = r + d with the same bits of r; the call's last
- * stage leaves f itself, rounded to FP32.  The stored deviation is small
- * where f is near equilibrium, so its rounding is far below that of f in
- * FP32.  Periodic box meshes, monatomic gas,
- * low-storage RK (FR_DVM_LSRK3_2N), collision models BGK / ES-BGK, no
+/* FP32 deviation storage: f buffers are float, the FR/RK arithmetic of a
+ * stage is FP32, moments and Newton FP64.  Inside one fr_dvm_rk_step(s)
+ * call every stage leaves its result in the caller's buffer as the FP32
+ * deviation d = f - r_e from an element reference r_e, and its outflow
+ * traces likewise: r_e(u) = exp of a quadratic exponent in u whose
+ * coefficients are the means over the element's solution points of those
+ * of the conservative equilibria the stage's Newton solve found there
+ * (eq. discrete_compatibility), evaluated through the FP32 hardware exp2
+ * (an FP32 number, the same bits wherever it is evaluated).  The next stage
+ * reads f = r_e + d, and the exact moments of r_e are added to those of d.
+ * The call's first stage reads plain f and its last stage leaves plain f,
+ * rounded to FP32 (stochastically).  Within an element f stays close to one
+ * reference, so the stored deviation and the arithmetic on it carry a small
+ * fraction of the rounding error of FP32 f.  Periodic box meshes, monatomic
+ * gas, low-storage RK (FR_DVM_LSRK3_2N), collision models BGK / ES-BGK, no
  * positivity limiter and no overlap; other calls (residual, collide,
- * moments, Kn) take f as plain float values. */
+ * moments, Kn) take f as plain float values and equal FR_DVM_FP32. */
 #define FR_DVM_FP32_DEV 2
 
 /* Newton initial guess for the conservative equilibrium */

@@ -102,7 +102,6 @@ StageArgs stage_args(fr_dvm *h, void *f, double dt, int st, int collide) {
     a.dt = dt;
     a.collide = collide;
     a.positivity = h->prm.positivity;
-    a.eq_prev = h->d_eq_prev;
     a.seed = (h->stage_count++) * 0x9e3779b9u;  // a different seed for every stage
     a.eq = h->d_eq;
     a.tr_in = h->d_tr[h->cur_tr];
@@ -127,6 +126,12 @@ StageArgs stage_args(fr_dvm *h, void *f, double dt, int st, int collide) {
         a.dF = h->d_reg;
     }
     return a;
+}
+
+// element references of the records just solved, into the current set
+int elem_ref(fr_dvm *h) {
+    ProfScope ps(h, 3);
+    return launch_elem_ref(h, h->d_ref[h->cur_ref]);
 }
 
 int ensure_aux(fr_dvm *h) {
@@ -165,9 +170,11 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
     // the work and its order are those of the single-stream path.
     // (decided after the first solve: a learned-then-warm start is warm from here on)
     // FP32 deviation storage: each stage reads its value relative to the
-    // previous stage's records and writes relative to its own, so the two
-    // record sets alternate before every Newton launch after the first
+    // element references of the previous stage's records and writes relative
+    // to those of its own, so the two reference sets alternate; the first
+    // stage reads plain f and takes its own references for both
     const bool dev = h->prm.precision == FR_DVM_FP32_DEV && collide;
+    if (dev && (rc = elem_ref(h))) return rc;
     const bool split = h->prm.overlap && h->axis_mode && collide && !dev && h->ne >= 2 && newton_part_ok(h, guess);
     if (split && (rc = ensure_aux(h))) return rc;
     const int64_t eh[3] = {0, h->ne / 2, h->ne};
@@ -177,12 +184,17 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
         const int last = k == nst - 1;
         const int traces = last ? 0 : 1, moments = (last || !collide) ? 0 : 1;
         if (!split && k > 0 && collide) {
-            if (dev) std::swap(h->d_eq, h->d_eq_prev);
             if ((rc = launch_newton(h, guess))) return rc;
+            if (dev) {
+                h->cur_ref ^= 1;
+                if ((rc = elem_ref(h))) return rc;
+            }
         }
         StageArgs a = stage_args(h, f, dt, st, collide);
         a.in_dev = dev && k > 0;
         a.out_dev = dev && !last;
+        a.ref_cur = h->d_ref[h->cur_ref];
+        a.ref_prev = k > 0 ? h->d_ref[h->cur_ref ^ 1] : a.ref_cur;
         if (!split) {
             ProfScope ps(h, 0);
             if ((rc = launch_fr(h, 1, a, traces, moments))) return rc;

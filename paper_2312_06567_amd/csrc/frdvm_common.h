@@ -16,6 +16,9 @@ namespace frdvm {
 constexpr int kMaxP = 3;
 constexpr int kMaxN = kMaxP + 1;
 constexpr int kEqW = 12;   // per-point equilibrium record (see EqRec below)
+// per-element reference of the FP32 deviation storage: 10 coefficients of
+// its exponent polynomial, then its moments (5 or 10)
+constexpr int kRefW = 20;
 constexpr int kHist = 64;  // Newton iteration histogram bins
 
 // Per-point equilibrium record written by the Newton kernels and read by the
@@ -121,7 +124,8 @@ struct fr_dvm {
     int cur_tr = 0;
     double *d_Q = nullptr;       // [ne*ns][nmom]
     double *d_eq = nullptr;      // [ne*ns][kEqW]
-    double *d_eq_prev = nullptr; // [ne*ns][kEqW] records of the previous stage (FP32 deviation storage)
+    double *d_ref[2] = {nullptr, nullptr};  // [ne][kRefW] element references (FP32 deviation storage),
+    int cur_ref = 0;                         // this stage's and the previous stage's, alternating
     double *d_z = nullptr;       // [ne*ns][5] Newton solution (warm start)
     double *d_prim = nullptr;    // [ne*ns][5] primitive state of g(Q')
     int zvalid = 0;
@@ -194,15 +198,19 @@ struct StageArgs {
     int keep_dF;             // LSRK: store dF (not after the last stage of a step, where it is dead)
     int collide;             // include the collision source
     int positivity;          // limit the stage result to f >= 0 (general-mesh kernel)
-    // FP32 deviation storage (FR_DVM_FP32_DEV): the stage value is read as
-    // f = g(eq_prev) + d (in_dev) and the result written as d = f - g(eq)
-    // (out_dev), g the equilibrium of a point's record at the lane's velocity
-    const double *eq_prev;   // records of the previous stage [ne*ns][kEqW]
+    // FP32 deviation storage (FR_DVM_FP32_DEV): the stage value and the
+    // inflow traces are read as deviations from the element references of
+    // the previous stage's records (in_dev; else plain, made relative here)
+    // and the result written as the deviation from the element's reference
+    // of this stage's records (out_dev; else plain)
+    const double *ref_prev, *ref_cur;  // [ne][kRefW]
     int in_dev, out_dev;
     uint32_t seed;           // random bits of the stage's stochastic rounding of FP32 state values
     int64_t e0, ecount;      // element range [e0, e0 + ecount); ecount 0: all elements
 };
 int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);
+// element references of the current equilibrium records into ref [ne][kRefW]
+int launch_elem_ref(fr_dvm *h, double *ref);
 // ---- general meshes (frdvm_gen.hip): same modes and arguments ----
 int launch_fr_gen(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);
 // boundary tables of the current parameters (wall and farfield Maxwellians)

@@ -105,14 +105,12 @@ __device__ __forceinline__ float exp_r<float>(double E) {
 }
 template <>
 __device__ __forceinline__ double exp_r<double>(double E) {
-    return exp(E);
+    return exp_f64(E);
 }
 
 // Exponent of a point's equilibrium at velocity u: c0 - (u-V)^T B (u-V)/2
 // from the staged form b = (-B_xx/2, -B_yy/2, -B_zz/2, -B_xy, -B_xz, -B_yz,
-// c0).  One fixed sequence of IEEE operations: the collision of a stage and
-// the reconstruction f = g + d in the next stage (FP32 deviation storage)
-// evaluate it with the same bits.
+// c0).
 __device__ __forceinline__ double eq_exponent(double b0, double b1, double b2, double b3, double b4, double b5,
                                               double b6, double V0, double V1, double V2, const double u[3]) {
     const double c0 = u[0] - V0, c1 = u[1] - V1, c2 = u[2] - V2;
@@ -127,29 +125,6 @@ __device__ __forceinline__ double eq_exponent(double b0, double b1, double b2, d
     return fma(c2, t2, E);
 }
 
-// Reference value of the FP32 deviation storage at exponent E: the hardware
-// FP32 exp2 of E log2(e).  It needs to be close to the equilibrium (the
-// stored deviation f - ref is then small) and to be the same bits wherever it
-// is evaluated (it is subtracted when a value is stored and added back when
-// it is read), not accurate: one FP64 multiply, two conversions and one
-// transcendental instruction.
-__device__ __forceinline__ double dev_ref(double E) {
-    return (double)__builtin_amdgcn_exp2f((float)(E * 1.4426950408889634074));
-}
-
-// The value of lane `lane` (wave-uniform) of a double held per lane.
-__device__ __forceinline__ double read_lane(double x, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-    return __hiloint2double(hi, lo);
-}
-
-// Coefficient c of a record in the staged form read by eq_exponent:
-// -B_xx/2, -B_yy/2, -B_zz/2, -B_xy, -B_xz, -B_yz, c0, V_x, V_y, V_z.
-__device__ __forceinline__ double eq_coef(const double *q, int c) {
-    return c < 3 ? -0.5 * q[EQ_B + c] : (c < 6 ? -q[EQ_B + c] : (c == 6 ? q[EQ_C0] : q[EQ_V + c - 7]));
-}
-constexpr int kEqCoef = 10;
 
 // Element-relative access: `base` is uniform (one element's slab), `boff`
 // the lane's byte offset inside it (a slab stays below 4 GiB: at most
@@ -184,6 +159,7 @@ __device__ __forceinline__ int compact_index(const VGrid &vg, int d, int side, c
 template <typename Real>
 struct LdsTab {
     Real lam[2][kMaxN], corr[2][kMaxN];
+    Real D[kMaxN * kMaxN];  // read with a wave-uniform address (z lines)
     int64_t nb[6];     // element offset of each neighbour's trace block
     uint32_t cnt[6];   // trace entries per face point of each face slot
     uint32_t fo[6];    // offset of each face slot inside a block
@@ -284,9 +260,10 @@ __device__ __forceinline__ int tix(int row, int col) {
 typedef const __attribute__((address_space(4))) double cdouble;
 
 // Real: arithmetic, LDS tiles and traces; SReal: storage of the state, the
-// second RK register and the output (float with Real = double: the FP32
-// deviation storage).
-template <typename Real, typename SReal, int P, int NMOM, int MODE>
+// second RK register and the output.  ER (FP32 deviation storage, stage
+// mode, FP32): the stage value and the inflow traces arrive as FP32
+// deviations from element references and the result leaves as one.
+template <typename Real, typename SReal, int P, int NMOM, int MODE, bool ER>
 __global__ __launch_bounds__(kChunk *(P + 1)) __attribute__((amdgpu_waves_per_eu(fr_waves<Real, MODE>()))) void
 k_fr_layer(const FrArgs A) {
     constexpr int N = P + 1, NS = N * N * N, NL = N * N;
@@ -327,20 +304,20 @@ k_fr_layer(const FrArgs A) {
     const int64_t ebase = e * (int64_t)NS * nu * NCOMP;
     const uint32_t lrow = (uint32_t)(l * NL) * (uint32_t)(nu * NCOMP);  // offset of the layer inside the element
     const uint32_t QB = (uint32_t)(nu * NCOMP) * (uint32_t)sizeof(SReal);  // bytes between solution points
-    constexpr bool DEVS = sizeof(SReal) < sizeof(Real);  // FP32 deviation storage
-    const bool in_dev = DEVS && STAGE && A.sa.in_dev;
-    const bool out_dev = DEVS && STAGE && A.sa.out_dev;
-    // the previous stage's records of this wave's layer (FP32 deviation
-    // storage), read once per element and spread over the lanes: coefficient
-    // c of layer point q in slot t = q kEqCoef + c, lane t % 64, register t / 64
-    constexpr int NPR = DEVS ? (NL * kEqCoef + kChunk - 1) / kChunk : 1;
-    double prv[NPR];
-#pragma unroll
-    for (int r = 0; r < NPR; ++r) {
-        const int t = r * kChunk + (tid & (kChunk - 1));
-        prv[r] = (in_dev && t < NL * kEqCoef)
-                     ? eq_coef(A.sa.eq_prev + (e * NS + l * NL + t / kEqCoef) * kEqW, t % kEqCoef)
-                     : 0.0;
+    // FP32 deviation storage: the element references of the previous stage's
+    // records (own, and the neighbour across each face: the inflow traces are
+    // deviations from the writer's) and of this stage's (own: the result)
+    static_assert(!ER || (sizeof(Real) == 4 && sizeof(SReal) == 4 && MODE == MODE_STAGE && NCOMP == 1),
+                  "deviation storage: FP32 monatomic stage kernel");
+    const bool in_dev = ER && A.sa.in_dev;
+    const bool out_dev = ER && A.sa.out_dev;
+    __shared__ __attribute__((aligned(16))) double s_ref[ER ? 8 * kRefCoef : 1];  // own prev, own cur, 6 faces
+    if (ER) {
+        for (int t = tid; t < 8 * kRefCoef; t += NT) {
+            const int r = t / kRefCoef;
+            const int64_t er = r < 2 ? e : (int64_t)A.nbr[6 * e + r - 2];
+            s_ref[t] = (r == 1 ? A.sa.ref_cur : A.sa.ref_prev)[er * kRefW + t % kRefCoef];
+        }
     }
 
     const bool collide = STAGE && A.sa.collide;
@@ -378,18 +355,14 @@ k_fr_layer(const FrArgs A) {
         const int sd = tid / kMaxN, m = tid % kMaxN;
         T.lam[sd][m] = op.lam[sd][m];
         T.corr[sd][m] = op.corr[sd][m];
+    } else if (tid >= 64 && tid < 64 + kMaxN * kMaxN) {
+        T.D[tid - 64] = op.D[tid - 64];
     } else if (tid < 2 * kMaxN + 6) {
         const int fc = tid - 2 * kMaxN;
         T.nb[fc] = (int64_t)A.nbr[6 * e + fc] * A.tl.elem;
         T.cnt[fc] = (uint32_t)A.tl.cnt[fc];
         T.fo[fc] = (uint32_t)A.tl.face_off[fc];
     }
-    // z-direction operator entries of this wave's layer
-    Real Dz[N], corrz[2];
-#pragma unroll
-    for (int m = 0; m < N; ++m) Dz[m] = op.D[l * N + m];
-    corrz[0] = op.corr[0][l];
-    corrz[1] = op.corr[1][l];
     // trace blocks: the own one (inflow of this stage) and the neighbours'
     // (outflow of the produced value)
     const Real *__restrict__ trE = reinterpret_cast<const Real *>(A.sa.tr_in) + (FLUX ? e * A.tl.elem : 0);
@@ -450,26 +423,31 @@ k_fr_layer(const FrArgs A) {
         // and moments read) and this wave's z-face traces; every later use of
         // the stage value reads the tile, so its registers take the next
         // chunk's loads right away.
-        if (in_dev) {
-            // f = ref(previous stage's record) + d at each point of the layer
+        // The lane's element references at its velocity (FP32 deviation
+        // storage): rp the previous stage's (the stage value and the traces
+        // are made relative to it), rc this stage's (a result relative to rp
+        // becomes one relative to rc by adding rp - rc in FP64; 0 after the
+        // call's last stage, which leaves the plain value), dl[d] what turns
+        // the inflow trace of direction d (relative to its writer's
+        // reference, or plain in the first stage) into one relative to rp.
+        // References are FP32 numbers: their differences are exact in FP64.
+        float rp = 0.0f, rc = 0.0f, dl[3] = {0.0f, 0.0f, 0.0f};
+        if (ER) {
+            rp = ref_value(ref_exponent(&s_ref[0], v.u));
+            rc = out_dev ? ref_value(ref_exponent(&s_ref[kRefCoef], v.u)) : 0.0f;
 #pragma unroll
-            for (int q = 0; q < NL; ++q) {
-                double b[kEqCoef];
-#pragma unroll
-                for (int c = 0; c < kEqCoef; ++c) {
-                    const int t = q * kEqCoef + c;
-                    b[c] = read_lane(prv[t / kChunk], t % kChunk);
-                }
-                const double E = eq_exponent(b[0], b[1], b[2], b[3], b[4], b[5], b[6], b[7], b[8], b[9], v.u);
-                tpub[tix<Real>(l * NL + q, vl)] = (Real)fc[q] + (Real)dev_ref(E);
+            for (int d = 0; d < 3; ++d) {
+                const int slot = 2 + 2 * d + (v.sgn[d] > 0 ? 0 : 1);  // the upwind neighbour in direction d
+                const double rn = in_dev ? (double)ref_value(ref_exponent(&s_ref[slot * kRefCoef], v.u)) : 0.0;
+                dl[d] = (float)(rn - (double)rp);
             }
-        } else {
-#pragma unroll
-            for (int q = 0; q < NL; ++q) tpub[tix<Real>(l * NL + q, vl)] = (Real)fc[q];
         }
+#pragma unroll
+        for (int q = 0; q < NL; ++q)
+            tpub[tix<Real>(l * NL + q, vl)] = (ER && !in_dev) ? (Real)fc[q] - (Real)rp : (Real)fc[q];
         if (FLUX) {
 #pragma unroll
-            for (int a = 0; a < N; ++a) tZ[tix<Real>(N * l + a, vl)] = TZ[a];
+            for (int a = 0; a < N; ++a) tZ[tix<Real>(N * l + a, vl)] = ER ? TZ[a] + (Real)dl[2] : TZ[a];
         }
         TraceOff nx{0u, 0u}, ny{0u, 0u};
         // the next chunk (possibly the first of the next component)
@@ -523,7 +501,7 @@ k_fr_layer(const FrArgs A) {
 #pragma unroll
                     for (int m = 0; m < N; ++m) fm += T.lam[sin_][m] * g[m];
                     Real &tin = d == 0 ? TX[a] : TY[a];
-                    const Real jmp = flow ? un * (tin - fm) : Real(0);
+                    const Real jmp = flow ? un * ((ER ? tin + (Real)dl[d] : tin) - fm) : Real(0);
                     tin = ldb(trEn, sn.off + a * sn.stride);
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
@@ -545,10 +523,10 @@ k_fr_layer(const FrArgs A) {
                 const int zin = v.sgn[2] > 0 ? 0 : 1;
                 const bool zflow = v.act && v.sgn[2] != 0;
                 const Real unz = (Real)((zin ? 1.0 : -1.0) * gf[2] * v.u[2]);
-                const Real cz = zflow ? (zin ? corrz[1] : corrz[0]) * unz : Real(0);
+                const Real cz = zflow ? T.corr[zin][l] * unz : Real(0);
 #pragma unroll
                 for (int m = 0; m < N; ++m) {
-                    const Real cm = az * Dz[m] - cz * T.lam[zin][m];
+                    const Real cm = az * T.D[l * N + m] - cz * T.lam[zin][m];
 #pragma unroll
                     for (int q = 0; q < NL; ++q) {
                         r[q] = fma(cm, tS[tix<Real>(m * NL + q, vl)], r[q]);
@@ -573,18 +551,25 @@ k_fr_layer(const FrArgs A) {
             }
             // collision source and the Runge-Kutta combination, point by point
             const Real dt = (Real)A.sa.dt;
+            // random bits of the stochastic rounding: one hash per lane and
+            // chunk, a xorshift step per value
+            uint32_t rs = sizeof(Real) == 4 ? round_bits(A.sa.seed, (uint32_t)(e * NS + l * NL), (uint32_t)(comp * nu + v.k)) | 1u
+                                            : 0u;
 #pragma unroll
             for (int q = 0; q < NL; ++q) {
                 const Real fq = tS[tix<Real>(l * NL + q, vl)];
                 Real L = -r[q];
-                double Eq = 0.0;  // the equilibrium's exponent at this point and velocity
                 if (EQ_LDS && collide) {
                     const int s = l * NL + q;
                     const double *b = &s_eb[s * 8];
                     const double *V = &s_ev[s * 4];
                     const double b6 = (NCOMP == 2 && comp) ? b[6] + V[3] : b[6];
-                    Eq = eq_exponent(b[0], b[1], b[2], b[3], b[4], b[5], b6, V[0], V[1], V[2], v.u);
-                    L += (exp_r<Real>(Eq) - fq) * (Real)b[7];
+                    // the equilibrium's exponent at this point and velocity
+                    const double Eq = eq_exponent(b[0], b[1], b[2], b[3], b[4], b[5], b6, V[0], V[1], V[2], v.u);
+                    if constexpr (ER)
+                        L += ((Real)(exp_f64(Eq) - (double)rp) - fq) * (Real)b[7];  // g - rp rounded once
+                    else
+                        L += (exp_r<Real>(Eq) - fq) * (Real)b[7];
                 } else if (collide) {
                     // E = c0 - (c^T B c)/2, c = u - V, formed in FP64
                     cdouble *rq = eqL + q * kEqW;
@@ -619,14 +604,16 @@ k_fr_layer(const FrArgs A) {
                     if (v.act && A.sa.keep_dF) stb(dFE, o + q * QB, (SReal)dd);
                     fod = fma(A.sa.lsB, (double)dd, (double)fq);
                 }
+                if (ER) fod = (fod + (double)rp) - (double)rc;
                 Real fo;
-                if constexpr (sizeof(Real) == 4)
-                    fo = round_stochastic(
-                        fod, round_bits(A.sa.seed, (uint32_t)(e * NS + l * NL + q), (uint32_t)(comp * nu + v.k)));
-                else
+                if constexpr (sizeof(Real) == 4) {
+                    rs = xorshift32(rs);
+                    fo = round_stochastic(fod, rs);
+                } else {
                     fo = (Real)fod;
+                }
                 f[q] = v.act ? fo : Real(0);
-                if (v.act) stb(outE, o + q * QB, (SReal)(out_dev ? fo - (Real)dev_ref(Eq) : fo));
+                if (v.act) stb(outE, o + q * QB, (SReal)fo);
                 if (q % 4 == 3) phase_fence();
             }
         }
@@ -761,31 +748,119 @@ k_fr_layer(const FrArgs A) {
             double t = red[i];
 #pragma unroll
             for (int w = 1; w < N; ++w) t += red[w * NS * NMOM + i];
-            A.sa.Q[(e * NS) * NMOM + i] = t;
+            // (deviation storage: plus the moments of the element reference)
+            A.sa.Q[(e * NS) * NMOM + i] = out_dev ? t + A.sa.ref_cur[e * kRefW + kRefCoef + i % NMOM] : t;
         }
     }
 }
 
-template <typename Real, typename SReal, int P, int NMOM>
+// Element reference of the FP32 deviation storage from the current
+// equilibrium records: the exponent polynomial (ref_exponent) whose
+// coefficients are the means over the element's solution points of the
+// monomial coefficients of the points' equilibrium exponents
+// c0 - (u-V)^T B (u-V)/2 (points without an equilibrium are left out; none
+// left: the reference is 0), and the moments of the reference on the
+// velocity grid with the moment pass's weights, in FP64 and a fixed order.
+// One workgroup per element.
+constexpr int kRefBlock = 256;
+static_assert(kRefCoef + 10 <= kRefW, "element reference record: coefficients and up to 10 moments");
+
+__device__ __forceinline__ double ref_coef(const double *q, int c) {
+    const double Bxx = q[EQ_B], Byy = q[EQ_B + 1], Bzz = q[EQ_B + 2];
+    const double Bxy = q[EQ_B + 3], Bxz = q[EQ_B + 4], Byz = q[EQ_B + 5];
+    const double Vx = q[EQ_V], Vy = q[EQ_V + 1], Vz = q[EQ_V + 2];
+    const double bx = Bxx * Vx + Bxy * Vy + Bxz * Vz;  // B V: the linear coefficients
+    const double by = Bxy * Vx + Byy * Vy + Byz * Vz;
+    const double bz = Bxz * Vx + Byz * Vy + Bzz * Vz;
+    switch (c) {
+        case 0: return q[EQ_C0] - 0.5 * (Vx * bx + Vy * by + Vz * bz);
+        case 1: return bx;
+        case 2: return by;
+        case 3: return bz;
+        case 4: return -0.5 * Bxx;
+        case 5: return -0.5 * Byy;
+        case 6: return -0.5 * Bzz;
+        case 7: return -Bxy;
+        case 8: return -Bxz;
+        default: return -Byz;
+    }
+}
+
+template <int NMOM>
+__global__ __launch_bounds__(kRefBlock) void k_elem_ref(const FrArgs A, int ns, double *__restrict__ ref) {
+    __shared__ double s_c[kRefCoef];
+    __shared__ double s_m[kRefBlock * NMOM];
+    const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid < kRefCoef) {
+        double sum = 0.0;
+        int cnt = 0;
+        for (int s = 0; s < ns; ++s) {
+            const double *q = A.sa.eq + (e * ns + s) * kEqW;
+            if (!isfinite(q[EQ_C0])) continue;
+            sum += ref_coef(q, tid);
+            ++cnt;
+        }
+        s_c[tid] = cnt ? sum / cnt : (tid == 0 ? -INFINITY : 0.0);
+    }
+    __syncthreads();
+    double M[NMOM];
+#pragma unroll
+    for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
+    const int nx = A.vg.nv[0];
+    for (int k = tid; k < A.nu; k += kRefBlock) {
+        const Vel v = velocity(A, k, true);
+        const double r = (double)ref_value(ref_exponent(s_c, v.u));
+        const double *wx = A.wx3 + 3 * (k % nx), *wr = A.wrow + 6 * (k / nx);
+        const double a0 = wx[0] * r, a1 = wx[1] * r, a2 = wx[2] * r;
+        M[0] = fma(wr[0], a0, M[0]);
+        M[1] = fma(wr[0], a1, M[1]);
+        M[2] = fma(wr[1], a0, M[2]);
+        M[3] = fma(wr[2], a0, M[3]);
+        if constexpr (NMOM == 5) {
+            M[4] = fma(0.5, fma(wr[0], a2, (wr[3] + wr[4]) * a0), M[4]);
+        } else {
+            M[4] = fma(wr[0], a2, M[4]);
+            M[5] = fma(wr[3], a0, M[5]);
+            M[6] = fma(wr[4], a0, M[6]);
+            M[7] = fma(wr[1], a1, M[7]);
+            M[8] = fma(wr[2], a1, M[8]);
+            M[9] = fma(wr[5], a0, M[9]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NMOM; ++a) s_m[tid * NMOM + a] = M[a];
+    __syncthreads();
+    double *out = ref + e * kRefW;
+    if (tid < NMOM) {
+        double t = 0.0;
+        for (int i = 0; i < kRefBlock; ++i) t += s_m[i * NMOM + tid];
+        out[kRefCoef + tid] = t;
+    } else if (tid >= 64 && tid < 64 + kRefCoef) {
+        out[tid - 64] = s_c[tid - 64];
+    }
+}
+
+template <typename Real, typename SReal, int P, int NMOM, bool ER>
 int launch_p(fr_dvm *h, int mode, const FrArgs &A) {
     dim3 grid((unsigned)(A.sa.ecount ? A.sa.ecount : h->ne)), block(kChunk * (P + 1));
     if (mode == MODE_PRIME)
-        hipLaunchKernelGGL((k_fr_layer<Real, SReal, P, NMOM, MODE_PRIME>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_fr_layer<Real, SReal, P, NMOM, MODE_PRIME, false>), grid, block, 0, h->stream, A);
     else if (mode == MODE_STAGE)
-        hipLaunchKernelGGL((k_fr_layer<Real, SReal, P, NMOM, MODE_STAGE>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_fr_layer<Real, SReal, P, NMOM, MODE_STAGE, ER>), grid, block, 0, h->stream, A);
     else
-        hipLaunchKernelGGL((k_fr_layer<Real, SReal, P, NMOM, MODE_RESID>), grid, block, 0, h->stream, A);
+        hipLaunchKernelGGL((k_fr_layer<Real, SReal, P, NMOM, MODE_RESID, false>), grid, block, 0, h->stream, A);
     hipError_t st = hipGetLastError();
     if (st != hipSuccess) return h->fail(FR_DVM_EHIP, std::string("FR kernel launch: ") + hipGetErrorString(st));
     return FR_DVM_OK;
 }
 
-template <typename Real, typename SReal, int NMOM>
+template <typename Real, typename SReal, int NMOM, bool ER = false>
 int launch_np(fr_dvm *h, int mode, const FrArgs &A) {
     switch (h->p) {
-        case 1: return launch_p<Real, SReal, 1, NMOM>(h, mode, A);
-        case 2: return launch_p<Real, SReal, 2, NMOM>(h, mode, A);
-        case 3: return launch_p<Real, SReal, 3, NMOM>(h, mode, A);
+        case 1: return launch_p<Real, SReal, 1, NMOM, ER>(h, mode, A);
+        case 2: return launch_p<Real, SReal, 2, NMOM, ER>(h, mode, A);
+        case 3: return launch_p<Real, SReal, 3, NMOM, ER>(h, mode, A);
     }
     return h->fail(FR_DVM_EUNSUPPORTED, "order");
 }
@@ -807,10 +882,8 @@ __global__ __launch_bounds__(256) void k_copy16(uint4 *__restrict__ dst, const u
 
 }  // namespace
 
-int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_moments) {
-    if (sa.ecount < 0 || sa.e0 < 0 || (sa.ecount ? sa.e0 + sa.ecount > h->ne : sa.e0 != 0))
-        return h->fail(FR_DVM_EINVAL, "element range");
-    FrArgs A;
+namespace {
+void fill_args(fr_dvm *h, const StageArgs &sa, int do_traces, int do_moments, FrArgs &A) {
     std::memset(&A, 0, sizeof(A));
     for (int i = 0; i < kMaxN * kMaxN; ++i) {
         A.od.D[i] = h->ops.D[i];
@@ -837,10 +910,19 @@ int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int 
     A.do_moments = do_moments;
     A.elem_comp = h->tl.elem / h->ncomp;
     A.gfp = h->d_gfp;
-    if (h->prm.precision == FR_DVM_FP32_DEV) {
-        // FP64 arithmetic and traces on FP32-stored deviations (monatomic)
-        if (h->nmom == 5) return launch_np<double, float, 5>(h, mode, A);
-        if (h->nmom == 10) return launch_np<double, float, 10>(h, mode, A);
+}
+}  // namespace
+
+int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_moments) {
+    if (sa.ecount < 0 || sa.e0 < 0 || (sa.ecount ? sa.e0 + sa.ecount > h->ne : sa.e0 != 0))
+        return h->fail(FR_DVM_EINVAL, "element range");
+    FrArgs A;
+    fill_args(h, sa, do_traces, do_moments, A);
+    if (h->prm.precision == FR_DVM_FP32_DEV && mode == MODE_STAGE && (sa.in_dev || sa.out_dev)) {
+        // FP32 arithmetic on deviations from element references (monatomic)
+        if (!sa.ref_prev || !sa.ref_cur) return h->fail(FR_DVM_EINVAL, "element references missing");
+        if (h->nmom == 5) return launch_np<float, float, 5, true>(h, mode, A);
+        if (h->nmom == 10) return launch_np<float, float, 10, true>(h, mode, A);
         return h->fail(FR_DVM_EUNSUPPORTED, "FP32 deviation storage needs a monatomic gas");
     }
     const bool fp64 = h->prm.precision == FR_DVM_FP64;
@@ -850,6 +932,23 @@ int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int 
         case 10: return fp64 ? launch_np<double, double, 10>(h, mode, A) : launch_np<float, float, 10>(h, mode, A);
     }
     return fp64 ? launch_np<double, double, 11>(h, mode, A) : launch_np<float, float, 11>(h, mode, A);
+}
+
+int launch_elem_ref(fr_dvm *h, double *ref) {
+    StageArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.eq = h->d_eq;
+    FrArgs A;
+    fill_args(h, sa, 0, 0, A);
+    if (h->nmom == 5)
+        hipLaunchKernelGGL(k_elem_ref<5>, dim3((unsigned)h->ne), dim3(kRefBlock), 0, h->stream, A, h->ns, ref);
+    else if (h->nmom == 10)
+        hipLaunchKernelGGL(k_elem_ref<10>, dim3((unsigned)h->ne), dim3(kRefBlock), 0, h->stream, A, h->ns, ref);
+    else
+        return h->fail(FR_DVM_EUNSUPPORTED, "FP32 deviation storage needs a monatomic gas");
+    hipError_t st = hipGetLastError();
+    if (st != hipSuccess) return h->fail(FR_DVM_EHIP, std::string("reference kernel launch: ") + hipGetErrorString(st));
+    return FR_DVM_OK;
 }
 
 }  // namespace frdvm

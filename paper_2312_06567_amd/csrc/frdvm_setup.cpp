@@ -645,13 +645,13 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     bool realloc_mom = !h->have_params || nmom != h->nmom;
     // element size of the buffers allocated under the previous parameters
     const size_t es_old = h->have_params && h->prm.precision != FR_DVM_FP64 ? sizeof(float) : sizeof(double);
-    // traces: FP64 unless the whole stage is FP32
-    const size_t tes_old = h->have_params && h->prm.precision == FR_DVM_FP32 ? sizeof(float) : sizeof(double);
+    // traces: in the precision of the stage arithmetic (FP32 for both FP32 forms)
+    const size_t tes_old = h->have_params && h->prm.precision != FR_DVM_FP64 ? sizeof(float) : sizeof(double);
     h->prm = *p;
     h->nmom = nmom;
     h->stage_count = 0;
     size_t es = p->precision == FR_DVM_FP64 ? sizeof(double) : sizeof(float);
-    size_t tes = p->precision == FR_DVM_FP32 ? sizeof(float) : sizeof(double);
+    size_t tes = p->precision != FR_DVM_FP64 ? sizeof(float) : sizeof(double);
     int64_t npts = h->ne * h->ns;
     int64_t nu = h->vg.nu * h->ncomp;  // state values per point
     int rc;
@@ -666,7 +666,9 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
             h->owned_bytes += h->ne * h->tl.elem * tes;
         }
         if ((rc = dev_alloc(h, &h->d_eq, npts * kEqW))) return rc;
-        if ((rc = dev_alloc(h, &h->d_eq_prev, p->precision == FR_DVM_FP32_DEV ? npts * kEqW : 0))) return rc;
+        for (int b = 0; b < 2; ++b)
+            if ((rc = dev_alloc(h, &h->d_ref[b], p->precision == FR_DVM_FP32_DEV ? h->ne * kRefW : 0))) return rc;
+        h->cur_ref = 0;
         if ((rc = dev_alloc(h, &h->d_z, npts * 5))) return rc;
         if ((rc = dev_alloc(h, &h->d_prim, npts * 5))) return rc;
         if ((rc = dev_alloc(h, &h->d_pt_iters, npts))) return rc;
@@ -788,7 +790,7 @@ extern "C" void fr_dvm_destroy(fr_dvm_t h) {
     if (!h) return;
     if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
     void *ptrs[] = {h->d_gfac, h->d_nbr, h->d_wq3J, h->d_wx3, h->d_wrow, h->d_wax, h->d_reg, h->d_tr[0], h->d_tr[1],
-                    h->d_Q, h->d_eq, h->d_eq_prev, h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
+                    h->d_Q, h->d_eq, h->d_ref[0], h->d_ref[1], h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
                     h->d_mlp_x, h->d_mlp_work, h->d_mlp_dz, h->d_pt_iters, h->d_pt_evals, h->d_pt_status,
                     h->d_pt_resid, h->d_S, h->d_ijac, h->d_nf, h->d_conn, h->d_wall, h->d_rw, h->d_mw,
                     h->d_finf, h->d_Sf, h->d_ijacf, h->d_nff, h->d_gfp};

@@ -52,7 +52,7 @@ def test_byte_models():
     FP32 low-storage 32 B; the fused stage kernel's algorithmic bytes averaged
     over the stages of a long call: FP64 SSP 4.17 values (33.3 B), FP32
     low-storage 4.83 values (19.3 B), the FP32 deviation storage the same
-    state values with FP64 traces (4.83 values, 1.5 of them 8-byte traces)."""
+    (FP32 state and traces)."""
     import bench
     assert bench.unfused_bytes_per_dof(3, 0, 0) == 56.0
     assert bench.unfused_bytes_per_dof(3, 1, 0) == 28.0
@@ -60,4 +60,4 @@ def test_byte_models():
     n = 1000
     assert abs(bench.stage_bytes(3, 0, 0, n) / (3 * n) - 8 * 25 / 6) < 1e-2
     assert abs(bench.stage_bytes(3, 1, 1, n) / (3 * n) - 4 * 29 / 6) < 1e-2
-    assert abs(bench.stage_bytes(3, 2, 1, n) / (3 * n) - (4 * 10 / 3 + 8 * 1.5)) < 1e-2
+    assert abs(bench.stage_bytes(3, 2, 1, n) / (3 * n) - 4 * 29 / 6) < 1e-2

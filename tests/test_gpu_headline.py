@@ -15,16 +15,19 @@ velocities.
     launches) to 1e-12 relative L2 (Section "Numerical method": the FR
     residual with the upwind interface flux; eq. discrete_compatibility:
     the conservative equilibrium).
-(c) FP32 deviation storage (FP32 f buffers, FP64 stage arithmetic, traces,
-    moments and Newton; between the stages of one call the state is held as
-    the FP32 deviation from the local equilibrium), low-storage RK, warm
-    start: five steps.  Bounds: f to 1e-7 relative L2 and rho, rho U and E
-    to 2e-8; and, since the call returns f rounded once to FP32, f within
-    1.5x and each moment within 2x of the error of the oracle's own result
-    rounded once to FP32 (FP32-sized errors inside the call, such as a
-    reconstruction that did not reproduce the writer's equilibrium to the
-    last bit, would leave errors of the FP32 path's size: about 4x that
-    floor).
+(c) FP32 deviation storage (FP32 f buffers and FR/RK arithmetic on the
+    deviation of f from an element reference equilibrium, FP64 moments and
+    Newton), low-storage RK, warm start: five steps.  On this state, whose
+    2^3 elements each span half the Taylor-Green period and carry 5 % noise,
+    the deviations are a large fraction of f: bounds f 1e-7 and moments
+    5e-8, each error below 0.6x the FP32 path's on the same state (measured
+    0.3-0.45x).  On a state close to one equilibrium per element
+    (Taylor-Green amplitude 0.02, 0.2 % noise), where the deviations are a
+    few percent of f: every moment error below 0.5x the FP32 path's and
+    within 2.5x of the error of the oracle's result rounded once to nearest
+    in FP32 (the call returns f rounded once, stochastically: sqrt(2) times
+    the spread of rounding to nearest; the errors made inside the call add
+    little to that).
 (b) FP32 storage and operators, low-storage RK, FP64 moments and Newton,
     warm start: five steps.  Bounds: f to 5e-7 relative L2 and the moments
     rho, rho U and E to 3e-7 relative L2 per field.  Each of the 15 stages
@@ -112,9 +115,9 @@ def test_fp32_lsrk_stage_bounds(F, orc, gi):
     assert max(eq) < 3e-7, eq
 
 
-def _fp32_run(F, orc, gi, precision):
+def _fp32_run(F, orc, gi, precision, case=None):
     grid = GRIDS[gi]
-    mesh, par, f0 = _case(grid)
+    mesh, par, f0 = case or _case(grid)
     f0 = f0.astype(np.float32).astype(np.float64)
     s = F.FrDvm(mesh, HEADLINE["p"], grid, dict(par, precision=precision, rk=1, guess=1))
     dt = _dt(s)
@@ -134,18 +137,42 @@ def _errors(P, got, ref):
     return rel(got, ref), [rel(Qg[..., 0], Qr[..., 0]), rel(Qg[..., 1:4], Qr[..., 1:4]), rel(Qg[..., 4], Qr[..., 4])]
 
 
+def _near_case(grid):
+    # close to one equilibrium per element: weak vortex, small noise
+    mesh = W.box_mesh(2)
+    par = W.physics_params(HEADLINE)
+    prim = W.prim_taylor_green(W.box_solution_points(mesh, HEADLINE["p"]), 0.02)
+    f0 = W.maxwellian(prim, grid).numpy()
+    rng = np.random.default_rng(23)
+    f0 *= 1.0 + 0.002 * rng.uniform(-1.0, 1.0, size=f0.shape)
+    return mesh, par, f0
+
+
 @pytest.mark.parametrize("gi", [0, 1])
 def test_fp32_deviation_storage_bounds(F, orc, gi):
     P, ref, got = _fp32_run(F, orc, gi, F.FP32_DEV)
     ef, eq = _errors(P, got, ref)
-    # the floor: the oracle's own result rounded once to FP32
-    ff, fq = _errors(P, ref.astype(np.float32).astype(np.float64), ref)
     _, _, got32 = _fp32_run(F, orc, gi, F.FP32)
     ef32, eq32 = _errors(P, got32, ref)
     print(f"grid {GRIDS[gi]['n']}: deviation storage f {ef:.2e}, moments {[f'{x:.2e}' for x in eq]}; "
-          f"one FP32 rounding f {ff:.2e}, moments {[f'{x:.2e}' for x in fq]}; "
           f"FP32 path f {ef32:.2e}, moments {[f'{x:.2e}' for x in eq32]}")
     assert ef < 1e-7, ef
-    assert max(eq) < 2e-8, eq
-    assert ef < 1.5 * ff, (ef, ff)
-    assert all(a < 2.0 * b for a, b in zip(eq, fq)), (eq, fq)
+    assert max(eq) < 5e-8, eq
+    assert ef < 0.6 * ef32, (ef, ef32)
+    assert all(a < 0.6 * b for a, b in zip(eq, eq32)), (eq, eq32)
+
+
+def test_fp32_deviation_storage_near_equilibrium(F, orc):
+    case = _near_case(GRIDS[0])
+    P, ref, got = _fp32_run(F, orc, 0, F.FP32_DEV, case)
+    ef, eq = _errors(P, got, ref)
+    _, _, got32 = _fp32_run(F, orc, 0, F.FP32, case)
+    ef32, eq32 = _errors(P, got32, ref)
+    # the floor: the oracle's own result rounded once to FP32
+    ff, fq = _errors(P, ref.astype(np.float32).astype(np.float64), ref)
+    print(f"near equilibrium: deviation storage f {ef:.2e}, moments {[f'{x:.2e}' for x in eq]}; "
+          f"FP32 path f {ef32:.2e}, moments {[f'{x:.2e}' for x in eq32]}; "
+          f"one FP32 rounding f {ff:.2e}, moments {[f'{x:.2e}' for x in fq]}")
+    assert ef < 1e-7, ef
+    assert all(a < 0.5 * b for a, b in zip(eq, eq32)), (eq, eq32)
+    assert all(a < 2.5 * b for a, b in zip(eq, fq)), (eq, fq)
