@@ -113,19 +113,21 @@ def stage_bytes(p: int, precision: int, rk: int, nsteps: int, general: bool = Fa
 
 
 KERNEL_SOURCES = ("frdvm_fr.hip", "frdvm_dev.h", "frdvm_common.h")
+GEN_KERNEL_SOURCES = ("frdvm_gen.hip", "frdvm_dev.h", "frdvm_common.h")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the sources the fused stage kernel is compiled from."""
+def kernel_source_hash(general: bool = False) -> str:
+    """Hash of the sources the stage kernel (box meshes, or with general=True
+    the general-mesh stage, wall and moment kernels) is compiled from."""
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in (GEN_KERNEL_SOURCES if general else KERNEL_SOURCES):
         with open(os.path.join(ROOT, "paper_2312_06567_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: int, rk: int, delta: float = 0.0):
+def measured_traffic(workload: str, precision: int, rk: int, delta: float = 0.0, general: bool = False):
     """HBM bytes per stage launch from the committed rocprofv3 counter runs
     (FETCH_SIZE and WRITE_SIZE, calibrated on a copy kernel), or None when
     no run matches this configuration or the kernel source has changed since."""
@@ -134,7 +136,7 @@ def measured_traffic(workload: str, precision: int, rk: int, delta: float = 0.0)
         return None
     with open(path) as fh:
         recs = json.load(fh)
-    src = kernel_source_hash()
+    src = kernel_source_hash(general)
     for r in recs:
         if (r["workload"] == workload and r["precision"] == precision and r["rk"] == rk
                 and r.get("delta", 0.0) == delta and r["source"] == src):
@@ -242,11 +244,10 @@ def roofline(r, p, workload, general=False):
     # the same launches priced with the unfused per-DOF traffic of the FR x
     # DVM stage (read f twice, the RK register, traces at both ends): p = 3
     # SSP FP64 56 B, FP32 28 B, low-storage FP32 32 B per DOF and stage
-    if not general:
-        ub = unfused_bytes_per_dof(p, r["precision"], r["rk"]) * r["dof"] * r.get("ncomp", 1)
-        out["unfused_bytes_per_dof"] = unfused_bytes_per_dof(p, r["precision"], r["rk"])
-        out["frac_unfused_bytes"] = ub / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS
-    t = measured_traffic(workload, r["precision"], r["rk"], r.get("delta", 0.0))
+    ub = unfused_bytes_per_dof(p, r["precision"], r["rk"]) * r["dof"] * r.get("ncomp", 1)
+    out["unfused_bytes_per_dof"] = unfused_bytes_per_dof(p, r["precision"], r["rk"])
+    out["frac_unfused_bytes"] = ub / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS
+    t = measured_traffic(workload, r["precision"], r["rk"], r.get("delta", 0.0), general)
     if t is not None:
         out["traffic"] = t["bytes_per_launch"]
         out["traffic_source"] = t["profile"]

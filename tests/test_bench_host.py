@@ -19,17 +19,21 @@ def test_traffic_lookup_matches_configuration_and_source(monkeypatch):
     recs = _records()
     assert recs
     for r in recs:
-        monkeypatch.setattr(bench, "kernel_source_hash", lambda r=r: r["source"])
-        assert bench.measured_traffic(r["workload"], r["precision"], r["rk"]) == r
+        gen = r.get("general", False)
+        monkeypatch.setattr(bench, "kernel_source_hash", lambda general=False, r=r: r["source"])
+        assert bench.measured_traffic(r["workload"], r["precision"], r["rk"], general=gen) == r
         # counters of the monatomic gas never stand in for the (F, G) pair
-        assert bench.measured_traffic(r["workload"], r["precision"], r["rk"], 2.0) is None
+        assert bench.measured_traffic(r["workload"], r["precision"], r["rk"], 2.0, general=gen) is None
         # nor for another precision / scheme pair without its own record
-        other = [x for x in recs if x["precision"] == 1 - r["precision"] and x["rk"] == r["rk"]]
+        other = [x for x in recs if x["workload"] == r["workload"] and x["precision"] == 1 - r["precision"]
+                 and x["rk"] == r["rk"]]
         if not other:
-            assert bench.measured_traffic(r["workload"], 1 - r["precision"], r["rk"]) is None
+            assert bench.measured_traffic(r["workload"], 1 - r["precision"], r["rk"], general=gen) is None
         # a changed kernel source invalidates the stored counters
-        monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-        assert bench.measured_traffic(r["workload"], r["precision"], r["rk"]) is None
+        monkeypatch.setattr(bench, "kernel_source_hash", lambda general=False: "0" * 16)
+        assert bench.measured_traffic(r["workload"], r["precision"], r["rk"], general=gen) is None
+    # the box and general-mesh kernels are hashed from different sources
+    assert bench.kernel_source_hash(False) != bench.kernel_source_hash(True)
 
 
 def test_traffic_records_are_at_least_algorithmic():
