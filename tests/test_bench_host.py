@@ -18,6 +18,8 @@ def _records():
 def test_traffic_lookup_matches_configuration_and_source(monkeypatch):
     recs = _records()
     assert recs
+    # the box and general-mesh kernels are hashed from different sources
+    assert bench.kernel_source_hash(False) != bench.kernel_source_hash(True)
     for r in recs:
         gen = r.get("general", False)
         monkeypatch.setattr(bench, "kernel_source_hash", lambda general=False, r=r: r["source"])
@@ -32,8 +34,6 @@ def test_traffic_lookup_matches_configuration_and_source(monkeypatch):
         # a changed kernel source invalidates the stored counters
         monkeypatch.setattr(bench, "kernel_source_hash", lambda general=False: "0" * 16)
         assert bench.measured_traffic(r["workload"], r["precision"], r["rk"], general=gen) is None
-    # the box and general-mesh kernels are hashed from different sources
-    assert bench.kernel_source_hash(False) != bench.kernel_source_hash(True)
 
 
 def test_traffic_records_are_at_least_algorithmic():
