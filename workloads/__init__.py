@@ -304,6 +304,164 @@ def box_solution_points(mesh: dict, p: int) -> np.ndarray:
     return lo[:, None, :] + ref[None, :, :] * (hi - lo)[:, None, :]
 
 
+# ---- mixed meshes: hexahedra, prisms, tetrahedra (straight elements) ----
+# Element types and vertex orders of the C ABI.  Hexahedron: 8 vertices,
+# x-fastest (reference [-1,1]^3).  Prism: the triangle (v0, v1, v2) at
+# reference zeta = -1 and (v3, v4, v5) over it at zeta = +1, reference
+# triangle (-1,-1), (1,-1), (-1,1).  Tetrahedron: reference vertices
+# (-1,-1,-1), (1,-1,-1), (-1,1,-1), (-1,-1,1).  Faces are numbered as in
+# MIXED_FACE_VERTS.
+HEX, PRISM, TET = 0, 1, 2
+MIXED_FACE_VERTS = {
+    HEX: [[0, 2, 4, 6], [1, 3, 5, 7], [0, 1, 4, 5], [2, 3, 6, 7], [0, 1, 2, 3], [4, 5, 6, 7]],
+    PRISM: [[0, 1, 2], [3, 4, 5], [0, 1, 4, 3], [1, 2, 5, 4], [2, 0, 3, 5]],
+    TET: [[0, 1, 2], [0, 1, 3], [1, 2, 3], [0, 2, 3]],
+}
+MIXED_NVERT = {HEX: 8, PRISM: 6, TET: 4}
+# the vertices whose offsets from v0 span the affine map of each type
+_AFFINE_AXES = {HEX: (1, 2, 4), PRISM: (1, 2, 3), TET: (1, 2, 3)}
+
+
+def mixed_box_mesh(N: int = 3, length: float = 1.0) -> dict:
+    """Periodic box [0, L]^3 of N^3 cells: the centre cell (b, b, b), b = N // 2,
+    split into the six Kuhn tetrahedra around its main diagonal; the other
+    cells of the x row through it (j = k = b) split into two prisms extruded
+    along x whose triangles halve the (y, z) square along its (min, min) -
+    (max, max) diagonal, likewise the y and z rows; every other cell a
+    hexahedron.  Every face is met by a face of the same shape and vertices
+    (the Kuhn split halves each face of the centre cell along the same
+    diagonal as the prisms).  Neighbours (element, face) are found by
+    matching face vertices modulo the period."""
+    import itertools
+    assert N >= 3
+    b = N // 2
+    h = length / N
+    n1 = N + 1
+    g = np.arange(n1) * h
+    nodes = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+
+    def nid(c):
+        return int(c[0] + n1 * (c[1] + n1 * c[2]))
+
+    types, verts, gverts = [], [], []  # gverts: integer grid coordinates of each vertex
+    for k in range(N):
+        for j in range(N):
+            for i in range(N):
+                o = np.array([i, j, k])
+                if (i, j, k) == (b, b, b):
+                    for perm in itertools.permutations(range(3)):
+                        P = [o.copy()]
+                        for d in perm:
+                            q = P[-1].copy()
+                            q[d] += 1
+                            P.append(q)
+                        e1, e2, e3 = P[1] - P[0], P[2] - P[0], P[3] - P[0]
+                        if np.dot(np.cross(e1, e2), e3) < 0:
+                            P[1], P[2] = P[2], P[1]
+                        types.append(TET)
+                        gverts.append(P)
+                    continue
+                axis = 0 if (j == b and k == b) else 1 if (i == b and k == b) else 2 if (i == b and j == b) else -1
+                if axis < 0:
+                    types.append(HEX)
+                    gverts.append([o + np.array([a, bb, cc]) for cc in (0, 1) for bb in (0, 1) for a in (0, 1)])
+                    continue
+                d1, d2 = (axis + 1) % 3, (axis + 2) % 3
+                for tri in (((0, 0), (1, 0), (1, 1)), ((0, 0), (1, 1), (0, 1))):
+                    P = []
+                    for end in (0, 1):
+                        for (a1, a2) in tri:
+                            q = o.copy()
+                            q[d1] += a1
+                            q[d2] += a2
+                            q[axis] += end
+                            P.append(q)
+                    types.append(PRISM)
+                    gverts.append(P)
+    ne = len(types)
+    en = np.full((ne, 8), -1, np.int32)
+    for e, P in enumerate(gverts):
+        en[e, :len(P)] = [nid(c) for c in P]
+    nbr = np.full((ne, 6), -1, np.int32)
+    nbf = np.full((ne, 6), -1, np.int8)
+    seen = {}
+    for e, (t, P) in enumerate(zip(types, gverts)):
+        for f, fv in enumerate(MIXED_FACE_VERTS[t]):
+            key = frozenset(tuple(int(x) % N for x in P[v]) for v in fv)
+            if key in seen:
+                e2, f2 = seen.pop(key)
+                nbr[e, f], nbf[e, f] = e2, f2
+                nbr[e2, f2], nbf[e2, f2] = e, f
+            else:
+                seen[key] = (e, f)
+    assert not seen, "unmatched faces"
+    return {"n_elem": ne, "n_nodes": nodes.shape[0], "nodes": np.ascontiguousarray(nodes),
+            "elem_type": np.asarray(types, np.int8), "elem_nodes": en, "nbr_elem": nbr, "nbr_face": nbf,
+            "period": (length,) * 3, "N": N}
+
+
+def gll_points(p: int) -> np.ndarray:
+    """Gauss-Lobatto points on [-1, 1]: the ends and the roots of P_p'."""
+    if p == 1:
+        return np.array([-1.0, 1.0])
+    inner = np.polynomial.legendre.Legendre.basis(p).deriv().roots()
+    return np.concatenate([[-1.0], np.sort(inner.real), [1.0]])
+
+
+def _simplex_points(p: int, dim: int) -> np.ndarray:
+    """Solution points of the reference triangle (dim 2) or tetrahedron
+    (dim 3) for p <= 3, in the ABI's order (barycentric indices (i, j[, k])
+    with i + j [+ k] <= p, the last index outermost): the equispaced points
+    with every point on an edge moved to the Gauss-Lobatto position along
+    that edge (the alpha-optimised warp & blend points reduce to this for
+    p <= 3)."""
+    assert 1 <= p <= 3
+    X = np.array([[-1, -1, -1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float)[:dim + 1, :dim]
+    gl = gll_points(p)
+    pts = []
+    rng = range(p + 1)
+    idx = [(i, j, 0) for j in rng for i in rng if i + j <= p] if dim == 2 else \
+          [(i, j, k) for k in rng for j in rng for i in rng if i + j + k <= p]
+    for (i, j, k) in idx:
+        lam = np.array([p - i - j - k, i, j, k][:dim + 1], float) / p
+        nz = np.nonzero(lam)[0]
+        if len(nz) == 2:
+            a, c = nz
+            m = int(round(lam[c] * p))
+            lam[c] = (1.0 + gl[m]) / 2.0
+            lam[a] = 1.0 - lam[c]
+        pts.append(lam @ X)
+    return np.array(pts)
+
+
+def mixed_reference_points(etype: int, p: int) -> np.ndarray:
+    """Reference coordinates [ns][3] of the solution points of an element
+    type, in the ABI's order: hexahedron Gauss-Lobatto tensor points
+    i + n (j + n l); prism triangle point t + n_tri l over the Gauss-Lobatto
+    points l of the extrusion coordinate; tetrahedron as _simplex_points."""
+    gl = gll_points(p)
+    if etype == HEX:
+        r = np.meshgrid(gl, gl, gl, indexing="ij")
+        return np.stack(r, -1).transpose(2, 1, 0, 3).reshape(-1, 3)
+    if etype == PRISM:
+        tri = _simplex_points(p, 2)
+        return np.array([[a, b_, z] for z in gl for (a, b_) in tri])
+    return _simplex_points(p, 3)
+
+
+def mixed_solution_points(mesh: dict, p: int) -> np.ndarray:
+    """Physical coordinates [npts][3] of the solution points of a mixed mesh,
+    element after element (straight elements: affine maps)."""
+    out = []
+    for e in range(mesh["n_elem"]):
+        t = int(mesh["elem_type"][e])
+        V = mesh["nodes"][mesh["elem_nodes"][e, :MIXED_NVERT[t]]]
+        A = np.stack([V[a] - V[0] for a in _AFFINE_AXES[t]], 1)
+        ref = mixed_reference_points(t, p)
+        out.append(V[0] + (ref + 1.0) / 2.0 @ A.T)
+    return np.concatenate(out, 0)
+
+
 def velocity_axes(grid: dict):
     out = []
     for d in range(3):
