@@ -202,6 +202,61 @@ int fr_dvm_create_nodes(const fr_dvm_mesh *mesh, int order, int nodes, const fr_
 int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, double delta,
                       const fr_dvm_vgrid *grid, fr_dvm_t *out);
 
+/* Mixed meshes of straight hexahedra, prisms and tetrahedra (Section
+ * "Implementation & problem setup": the paper's meshes mix prisms and
+ * tetrahedra, with alpha-optimised solution points on simplices and
+ * Gauss-Lobatto points on tensor-product elements).
+ *
+ * Element types and their vertex order (elem_nodes, the type's vertices
+ * first, the rest of the 8 slots ignored):
+ *   FR_DVM_HEX   8 vertices, x-fastest over the reference cube [-1,1]^3;
+ *   FR_DVM_PRISM 6 vertices: the triangle v0 v1 v2 at reference zeta = -1
+ *                (reference triangle (-1,-1), (1,-1), (-1,1)) and v3 v4 v5
+ *                over it at zeta = +1;
+ *   FR_DVM_TET   4 vertices: reference (-1,-1,-1), (1,-1,-1), (-1,1,-1),
+ *                (-1,-1,1).
+ * Every element must be the affine image of its reference element with a
+ * positive Jacobian (straight elements, parallelogram quadrilateral faces).
+ * Faces (nbr_elem / nbr_face numbering), by their vertices:
+ *   hexahedron 0:{0,2,4,6} 1:{1,3,5,7} 2:{0,1,4,5} 3:{2,3,6,7} 4:{0,1,2,3} 5:{4,5,6,7};
+ *   prism      0:{0,1,2} 1:{3,4,5} 2:{0,1,4,3} 3:{1,2,5,4} 4:{2,0,3,5};
+ *   tetrahedron 0:{0,1,2} 1:{0,1,3} 2:{1,2,3} 3:{0,2,3}.
+ * Every face must have a neighbour (closed or periodic meshes); the face
+ * points of two neighbours are matched by position, modulo the period.
+ *
+ * Solution points (order p = 1..3), element after element in the state
+ * buffers ([point][velocity]): hexahedron the Gauss-Lobatto tensor points
+ * i + n (j + n l); prism the triangle points t + n_tri l over the
+ * Gauss-Lobatto points l of zeta; triangle and tetrahedron the alpha-
+ * optimised warp & blend points, which for p <= 3 are the vertices, the
+ * Gauss-Lobatto points along every edge and the face centroids (tetrahedron
+ * p = 3), indexed by barycentric (i, j[, k]) / p with i + j [+ k] <= p, the
+ * last index outermost.  The flux points of a face are the solution points
+ * on it.  The scheme is FR with the DG-recovering correction (nodal DG with
+ * exact mass matrices) and the upwind flux.
+ *
+ * The handle treats every solution point as an element of one point:
+ * fr_dvm_sizes reports n_elem = the number of points and ns = 1, and
+ * residual / collide / moments / rk_step(s) / dt / newton_* work on
+ * [points][nu] buffers; the domain totals weight each point by the
+ * integral of its basis function.  dt uses h = element volume / largest
+ * face area.  FP64 and FP32, BGK / ES-BGK / free, both RK schemes; no
+ * FR_DVM_FP32_DEV, no positivity limiter, no reduced pair, no
+ * fr_dvm_kn_gll (FR_DVM_EUNSUPPORTED). */
+#define FR_DVM_HEX 0
+#define FR_DVM_PRISM 1
+#define FR_DVM_TET 2
+typedef struct {
+    int32_t n_elem, n_nodes;
+    const double *nodes;       /* [n_nodes][3] */
+    const int8_t *elem_type;   /* [n_elem] FR_DVM_HEX | FR_DVM_PRISM | FR_DVM_TET */
+    const int32_t *elem_nodes; /* [n_elem][8] */
+    const int32_t *nbr_elem;   /* [n_elem][6] neighbour across each face (slots past the type's faces ignored) */
+    const int8_t *nbr_face;    /* [n_elem][6] that neighbour's face */
+    double period[3];          /* translation of the periodic domain along x, y, z (0: none) */
+} fr_dvm_mixed_mesh;
+int fr_dvm_create_mixed(const fr_dvm_mixed_mesh *mesh, int order, const fr_dvm_vgrid *grid, fr_dvm_t *out);
+
 /* Set physics / precision / solver parameters; allocates the work buffers
  * of the chosen precision.  Must be called before any compute call. */
 int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p);

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfrdvm.so")
-SOURCES = ["frdvm_setup.cpp", "frdvm_api.cpp", "frdvm_fr.hip", "frdvm_gen.hip", "frdvm_newton.hip", "frdvm_mlp.hip"]
+SOURCES = ["frdvm_setup.cpp", "frdvm_mixed.cpp", "frdvm_api.cpp", "frdvm_fr.hip", "frdvm_gen.hip", "frdvm_newton.hip",
+           "frdvm_mlp.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -56,6 +56,7 @@ extern "C" int fr_dvm_kn_gll(fr_dvm_t h, const void *f, double *kn) {
     int rc = ready(h);
     if (rc) return rc;
     if (!f || !kn) return h->fail(FR_DVM_EINVAL, "null f or kn");
+    if (h->mx) return h->fail(FR_DVM_EUNSUPPORTED, "the Knudsen-number field needs a hexahedral mesh");
     if ((rc = prime(h, f, 0, 1))) return rc;
     return launch_kn_gll(h, kn);
 }

@@ -55,6 +55,31 @@ struct TraceLayout {
 
 struct Handle;
 
+// Mixed meshes (fr_dvm_create_mixed): per element type, the reference
+// operators of the nodal DG / FR-DG scheme and the elements of that type.
+constexpr int kMixGeo = 33;  // per element: dxi/dx (9), unit outward face normals (6x3), |J_face| / |J| (6)
+struct MixType {
+    int etype = -1, ns = 0, nft = 0, nface = 0;
+    std::vector<int32_t> fnode;  // [nft] solution point of each face point (faces in order)
+    std::vector<int32_t> ffac;   // [nft] face of each face point
+    std::vector<double> D;       // [3][ns][ns] reference derivatives
+    std::vector<double> lift;    // [ns][nft] correction of a unit jump at each face point
+    std::vector<double> W;       // [ns] integral of each Lagrange function (reference)
+    std::vector<int32_t> elems;  // elements of this type
+    double *d_D = nullptr, *d_lift = nullptr;
+    float *d_Df = nullptr, *d_liftf = nullptr;
+    int32_t *d_elems = nullptr, *d_fnode = nullptr, *d_ffac = nullptr;
+};
+struct Mixed {
+    int64_t ne = 0, npts = 0, nfp = 0;  // elements, solution points, face points (all elements)
+    std::vector<int64_t> poff, toff;    // [ne+1] first solution point / face point of each element
+    int64_t *d_poff = nullptr, *d_toff = nullptr;
+    int64_t *d_tnb = nullptr;           // [nfp] the neighbour's face point at the same position
+    double *d_geo = nullptr;            // [ne][kMixGeo]
+    float *d_geof = nullptr;
+    MixType t[3];
+};
+
 }  // namespace frdvm
 
 struct fr_dvm {
@@ -71,6 +96,9 @@ struct fr_dvm {
     int nodes = 0;  // solution points: 0 Gauss-Legendre, 1 Gauss-Lobatto
     double delta = 0;  // internal degrees of freedom of the gas
     int ncomp = 1;     // 1: f; 2: the reduced pair (F, G), per point F then G (nu values each)
+    // mixed meshes: every solution point is an "element" of one point for the
+    // point-wise machinery (ne = points, ns = 1); the element structure is here
+    frdvm::Mixed *mx = nullptr;
     int64_t ne = 0;
     frdvm::VGrid vg{};
     std::vector<double> wax[3];  // 1-D trapezoid weights per axis
@@ -211,14 +239,25 @@ struct StageArgs {
 int launch_fr_axis(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);
 // element references of the current equilibrium records into ref [ne][kRefW]
 int launch_elem_ref(fr_dvm *h, double *ref);
+// ---- mixed meshes (frdvm_gen.hip): same modes and arguments ----
+int launch_fr_mixed(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);
 // ---- general meshes (frdvm_gen.hip): same modes and arguments ----
 int launch_fr_gen(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments);
 // boundary tables of the current parameters (wall and farfield Maxwellians)
 int gen_boundary_tables(fr_dvm *h);
 inline int launch_fr(fr_dvm *h, int mode, const StageArgs &a, int do_traces, int do_moments) {
+    if (h->mx) return launch_fr_mixed(h, mode, a, do_traces, do_moments);
     return h->axis_mode ? launch_fr_axis(h, mode, a, do_traces, do_moments)
                         : launch_fr_gen(h, mode, a, do_traces, do_moments);
 }
+
+// ---- host set-up shared by the mesh kinds (frdvm_setup.cpp) ----
+void gauss_legendre_rule(int n, double *x, double *w);
+void gauss_lobatto_rule(int n, double *x, double *w);
+int setup_vgrid(fr_dvm *h, const fr_dvm_vgrid *grid);
+int finish_create(fr_dvm *h, const std::vector<double> &wq3J);
+// ---- mixed meshes (frdvm_mixed.cpp) ----
+void free_mixed(fr_dvm *h);
 
 // ---- launchers (frdvm_newton.hip) ----
 int launch_newton(fr_dvm *h, int guess);

@@ -602,7 +602,253 @@ int gen_p(fr_dvm *h, int mode, const GenArgs &A, int do_moments) {
     return h->fail(FR_DVM_EUNSUPPORTED, "order");
 }
 
+// ---- mixed meshes of straight hexahedra, prisms and tetrahedra ----
+//
+// Nodal FR with the DG-recovering correction on each element (Section
+// "Numerical method"): with f the element's values at its solution points,
+//   R_i = -sum_j (sum_a c_a D_a[i][j]) f_j
+//         - sum_t lift[i][t] s_f min(u.n_f, 0) (f_nb,t - f_node(t)),
+// c_a = u . grad xi_a (constant on a straight element), t running over the
+// face points (the solution points on each face, faces in order), f_nb,t the
+// neighbour's trace at the same position, s_f = |J_face| / |J|.  One wave per
+// (element, 64 velocities), one lane per velocity, the values and residuals
+// of the lane in LDS columns, the operators read through the scalar cache.
+// The collision source and the RK combination are those of the hexahedral
+// kernels; the result's traces are its values at the face points.
+struct MixArgs {
+    VGrid vg;
+    int nu, nvw;
+    const int32_t *elems;                 // elements of the launched type
+    const int64_t *poff, *toff, *tnb;     // first point / face point of each element; neighbour face point
+    const double *geo;                    // [ne][kMixGeo]
+    const float *geof;
+    const double *D, *lift;               // the type's operators
+    const float *Df, *liftf;
+    const int32_t *fnode, *ffac;          // [nft] solution point and face of each face point
+    StageArgs sa;
+    int do_traces;
+};
+
+template <typename Real>
+struct MixOps {
+    cptr<Real> geo, D, lift;
+};
+__device__ __forceinline__ MixOps<float> mix_ops(const MixArgs &A, float) {
+    return {(cptr<float>)A.geof, (cptr<float>)A.Df, (cptr<float>)A.liftf};
+}
+__device__ __forceinline__ MixOps<double> mix_ops(const MixArgs &A, double) {
+    return {(cptr<double>)A.geo, (cptr<double>)A.D, (cptr<double>)A.lift};
+}
+
+template <typename Real, int NS, int NFT, int MODE>
+__global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
+    __shared__ Real sf[NS][kGWave];
+    __shared__ Real sa[NS][kGWave];
+    const int64_t e = A.elems[blockIdx.x / A.nvw];
+    const int lane = threadIdx.x;
+    const int k = (int)(blockIdx.x % A.nvw) * kGWave + lane;
+    const bool act = k < A.nu;
+    const int kk = act ? k : 0;  // an idle lane works on node 0 and stores nothing
+    const int64_t nu = A.nu;
+    const uint32_t ko = (uint32_t)kk * (uint32_t)sizeof(Real);
+    const int64_t p0 = A.poff[e], t0 = A.toff[e];
+    const MixOps<Real> op = mix_ops(A, Real(0));
+    const cptr<Real> g = op.geo + e * kMixGeo;
+    int iv[3];
+    split_k(A.vg, kk, iv);
+    const double ud[3] = {node_u(A.vg, 0, iv[0]), node_u(A.vg, 1, iv[1]), node_u(A.vg, 2, iv[2])};
+    const Real u0 = (Real)ud[0], u1 = (Real)ud[1], u2 = (Real)ud[2];
+    Real c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c[a] = u0 * g[3 * a] + u1 * g[3 * a + 1] + u2 * g[3 * a + 2];
+    const Real *fE = reinterpret_cast<const Real *>(A.sa.f) + p0 * nu;
+#pragma unroll 4
+    for (int i = 0; i < NS; ++i) sf[i][lane] = ldo(fE + i * nu, ko);
+    // volume: the derivative along u
+#pragma unroll 1
+    for (int i = 0; i < NS; ++i) {
+        Real acc = Real(0);
+#pragma unroll 4
+        for (int j = 0; j < NS; ++j) {
+            const Real w = c[0] * op.D[i * NS + j] + c[1] * op.D[(NS + i) * NS + j] + c[2] * op.D[(2 * NS + i) * NS + j];
+            acc = fma(w, sf[j][lane], acc);
+        }
+        sa[i][lane] = -acc;
+    }
+    // faces: the upwind jump at each face point, lifted into the element
+    const Real *trI = reinterpret_cast<const Real *>(A.sa.tr_in);
+#pragma unroll 1
+    for (int t = 0; t < NFT; ++t) {
+        const int f = A.ffac[t], node = A.fnode[t];
+        const Real un = u0 * g[9 + 3 * f] + u1 * g[10 + 3 * f] + u2 * g[11 + 3 * f];
+        Real jump = Real(0);
+        if (un < Real(0)) jump = un * g[27 + f] * (ldo(trI + A.tnb[t0 + t] * nu, ko) - sf[node][lane]);
+#pragma unroll 4
+        for (int i = 0; i < NS; ++i) sa[i][lane] -= op.lift[i * NFT + t] * jump;
+    }
+    if (MODE == GMODE_RESID) {
+        Real *R = reinterpret_cast<Real *>(A.sa.fout) + p0 * nu;
+        if (act)
+#pragma unroll 4
+            for (int i = 0; i < NS; ++i) sto(R + i * nu, ko, sa[i][lane]);
+        return;
+    }
+    // collision source and the Runge-Kutta combination, point by point
+    const Real dt = (Real)A.sa.dt;
+    const bool collide = A.sa.collide;
+    const bool useX = A.sa.scheme == 0 ? A.sa.alpha != 0.0 : A.sa.lsA != 0.0;
+    const Real *XE = reinterpret_cast<const Real *>(A.sa.scheme == 0 ? A.sa.fn : A.sa.dF) + p0 * nu;
+    Real *outE = reinterpret_cast<Real *>(A.sa.fout) + p0 * nu;
+    Real *dFE = reinterpret_cast<Real *>(A.sa.dF) + p0 * nu;
+#pragma unroll 1
+    for (int i = 0; i < NS; ++i) {
+        const Real fq = sf[i][lane];
+        Real L = sa[i][lane];
+        if (collide) {
+            const cptr<double> q = (cptr<double>)A.sa.eq + (p0 + i) * kEqW;
+            const double c0 = ud[0] - q[EQ_V], c1 = ud[1] - q[EQ_V + 1], c2 = ud[2] - q[EQ_V + 2];
+            double t0_ = -0.5 * q[EQ_B] * c0;
+            t0_ = fma(-q[EQ_B + 3], c1, t0_);
+            t0_ = fma(-q[EQ_B + 4], c2, t0_);
+            double t1 = -0.5 * q[EQ_B + 1] * c1;
+            t1 = fma(-q[EQ_B + 5], c2, t1);
+            const double t2 = -0.5 * q[EQ_B + 2] * c2;
+            double E = fma(c0, t0_, q[EQ_C0]);
+            E = fma(c1, t1, E);
+            E = fma(c2, t2, E);
+            L += (gexp<Real>(E) - fq) * (Real)q[EQ_INVTAU];
+        }
+        const Real xv = useX ? ldo(XE + i * nu, ko) : Real(0);
+        double fod;
+        if (A.sa.scheme == 0) {
+            fod = A.sa.beta * ((double)fq + (double)(dt * L));
+            if (useX) fod = fma(A.sa.alpha, (double)xv, fod);
+        } else {
+            Real dd = dt * L;
+            if (useX) dd += (Real)A.sa.lsA * xv;
+            if (act && A.sa.keep_dF) sto(dFE + i * nu, ko, dd);
+            fod = fma(A.sa.lsB, (double)dd, (double)fq);
+        }
+        Real fo;
+        if constexpr (sizeof(Real) == 4)
+            fo = round_stochastic(fod, round_bits(A.sa.seed, (uint32_t)(p0 + i), (uint32_t)k));
+        else
+            fo = (Real)fod;
+        sf[i][lane] = fo;
+        if (act) sto(outE + i * nu, ko, fo);
+    }
+    if (A.do_traces && act) {
+        Real *trO = reinterpret_cast<Real *>(A.sa.tr_out) + t0 * nu;
+#pragma unroll 1
+        for (int t = 0; t < NFT; ++t) sto(trO + t * nu, ko, sf[A.fnode[t]][lane]);
+    }
+}
+
+// Traces of f: its values at the face points.
+template <typename Real, int NS, int NFT>
+__global__ __launch_bounds__(kGWave) void k_mix_traces(const MixArgs A, const Real *__restrict__ f, Real *__restrict__ tr) {
+    const int64_t e = A.elems[blockIdx.x / A.nvw];
+    const int k = (int)(blockIdx.x % A.nvw) * kGWave + threadIdx.x;
+    if (k >= A.nu) return;
+    const int64_t nu = A.nu, p0 = A.poff[e], t0 = A.toff[e];
+#pragma unroll 1
+    for (int t = 0; t < NFT; ++t) tr[(t0 + t) * nu + k] = f[(p0 + A.fnode[t]) * nu + k];
+}
+
+template <typename Real, int NS, int NFT>
+int mix_launch(fr_dvm *h, int mode, const MixArgs &A, unsigned blocks) {
+    if (mode == 0)
+        hipLaunchKernelGGL((k_mix_traces<Real, NS, NFT>), dim3(blocks), dim3(kGWave), 0, h->stream, A,
+                           reinterpret_cast<const Real *>(A.sa.f), reinterpret_cast<Real *>(A.sa.tr_out));
+    else if (mode == GMODE_RESID)
+        hipLaunchKernelGGL((k_mix_stage<Real, NS, NFT, GMODE_RESID>), dim3(blocks), dim3(kGWave), 0, h->stream, A);
+    else
+        hipLaunchKernelGGL((k_mix_stage<Real, NS, NFT, GMODE_STAGE>), dim3(blocks), dim3(kGWave), 0, h->stream, A);
+    return gcheck(h, "mixed-mesh kernel");
+}
+
+// (type, order) -> the kernel instantiation for its point counts
+template <typename Real>
+int mix_dispatch(fr_dvm *h, int mode, const MixArgs &A, int t, const MixType &T, unsigned blocks) {
+    const int key = 10 * t + h->p;
+    int ns = 0, nft = 0, rc = FR_DVM_EUNSUPPORTED;
+    switch (key) {
+        case 1: ns = 8; nft = 24; rc = mix_launch<Real, 8, 24>(h, mode, A, blocks); break;
+        case 2: ns = 27; nft = 54; rc = mix_launch<Real, 27, 54>(h, mode, A, blocks); break;
+        case 3: ns = 64; nft = 96; rc = mix_launch<Real, 64, 96>(h, mode, A, blocks); break;
+        case 11: ns = 6; nft = 18; rc = mix_launch<Real, 6, 18>(h, mode, A, blocks); break;
+        case 12: ns = 18; nft = 39; rc = mix_launch<Real, 18, 39>(h, mode, A, blocks); break;
+        case 13: ns = 40; nft = 68; rc = mix_launch<Real, 40, 68>(h, mode, A, blocks); break;
+        case 21: ns = 4; nft = 12; rc = mix_launch<Real, 4, 12>(h, mode, A, blocks); break;
+        case 22: ns = 10; nft = 24; rc = mix_launch<Real, 10, 24>(h, mode, A, blocks); break;
+        case 23: ns = 20; nft = 40; rc = mix_launch<Real, 20, 40>(h, mode, A, blocks); break;
+        default: return h->fail(FR_DVM_EUNSUPPORTED, "mixed-mesh element type / order");
+    }
+    (void)ns;
+    (void)nft;
+    return rc;
+}
+
+template <typename Real>
+int mix_run(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_moments) {
+    const Mixed &mx = *h->mx;
+    MixArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.vg = h->vg;
+    A.nu = h->vg.nu;
+    A.nvw = (A.nu + kGWave - 1) / kGWave;
+    A.poff = mx.d_poff;
+    A.toff = mx.d_toff;
+    A.tnb = mx.d_tnb;
+    A.geo = mx.d_geo;
+    A.geof = mx.d_geof;
+    A.sa = sa;
+    A.do_traces = do_traces;
+    int rc;
+    if (mode != 0 || do_traces) {
+        for (int t = 0; t < 3; ++t) {
+            const MixType &T = mx.t[t];
+            if (T.elems.empty()) continue;
+            const int key_ns[3][4] = {{0, 8, 27, 64}, {0, 6, 18, 40}, {0, 4, 10, 20}};
+            if (T.ns != key_ns[t][h->p]) return h->fail(FR_DVM_EINVAL, "mixed-mesh operator size");
+            A.elems = T.d_elems;
+            A.D = T.d_D;
+            A.lift = T.d_lift;
+            A.Df = T.d_Df;
+            A.liftf = T.d_liftf;
+            A.fnode = T.d_fnode;
+            A.ffac = T.d_ffac;
+            if ((rc = mix_dispatch<Real>(h, mode, A, t, T, (unsigned)(T.elems.size() * A.nvw)))) return rc;
+        }
+    }
+    const bool moments = (mode == 0 || mode == GMODE_STAGE) && do_moments;
+    if (!moments) return FR_DVM_OK;
+    // moments of every point: the general-mesh reduction over the velocity axis
+    GenArgs G;
+    std::memset(&G, 0, sizeof(G));
+    G.vg = h->vg;
+    G.nu = h->vg.nu;
+    G.ncomp = 1;
+    G.nut = G.nu;
+    G.wax = h->d_wax;
+    const Real *src = reinterpret_cast<const Real *>(mode == 0 ? sa.f : sa.fout);
+    const unsigned npts = (unsigned)mx.npts;
+    if (h->nmom == 5)
+        hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3(npts), dim3(kGBlock), 0, h->stream, G, src, sa.Q);
+    else if (h->nmom == 10)
+        hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3(npts), dim3(kGBlock), 0, h->stream, G, src, sa.Q);
+    else
+        return h->fail(FR_DVM_EUNSUPPORTED, "mixed meshes need a monatomic gas");
+    return gcheck(h, "moment kernel");
+}
+
 }  // namespace
+
+int launch_fr_mixed(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_moments) {
+    if (sa.e0 != 0 || sa.ecount != 0) return h->fail(FR_DVM_EINVAL, "element ranges need an axis-aligned box mesh");
+    return h->prm.precision == FR_DVM_FP64 ? mix_run<double>(h, mode, sa, do_traces, do_moments)
+                                           : mix_run<float>(h, mode, sa, do_traces, do_moments);
+}
 
 int launch_fr_gen(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_moments) {
     if (sa.e0 != 0 || sa.ecount != 0) return h->fail(FR_DVM_EINVAL, "element ranges need an axis-aligned box mesh");

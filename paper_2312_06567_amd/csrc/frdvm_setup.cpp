@@ -17,7 +17,7 @@
 
 using namespace frdvm;
 
-namespace {
+namespace frdvm {
 
 // Legendre P_n and its derivative at x (recurrence on n).
 void legendre_eval(int n, double x, double &P, double &dP) {
@@ -79,6 +79,10 @@ void gauss_lobatto_rule(int n, double *x, double *w) {
         w[i] = 2.0 / (p * (p + 1.0) * pc * pc);
     }
 }
+
+}  // namespace frdvm
+
+namespace {
 
 // FR operators in barycentric form on Gauss-Legendre (nodes 0) or
 // Gauss-Lobatto (nodes 1) points.  D: l_m'(xi_i) from barycentric weights;
@@ -469,6 +473,57 @@ extern "C" void fr_dvm_default_params(fr_dvm_params *p) {
     p->overlap = 0;
 }
 
+namespace frdvm {
+
+// Velocity grid of a handle: nodes umin + i du per axis, trapezoid weights,
+// the sign split of each axis.
+int setup_vgrid(fr_dvm *h, const fr_dvm_vgrid *grid) {
+    VGrid &vg = h->vg;
+    int64_t nu = 1;
+    for (int d = 0; d < 3; ++d) {
+        int nd = grid->n[d];
+        if (nd < 1 || nd > 64) return h->fail(FR_DVM_EINVAL, "velocity nodes per axis must be 1..64");
+        if (nd > 1 && !(grid->umax[d] > grid->umin[d])) return h->fail(FR_DVM_EINVAL, "umax <= umin");
+        vg.nv[d] = nd;
+        vg.umin[d] = grid->umin[d];
+        vg.du[d] = nd > 1 ? (grid->umax[d] - grid->umin[d]) / (nd - 1) : 0.0;
+        h->wax[d].assign(nd, 1.0);
+        for (int i = 0; i < nd && nd > 1; ++i) h->wax[d][i] = (i == 0 || i == nd - 1) ? 0.5 * vg.du[d] : vg.du[d];
+        int ne_ = 0, ps = nd;
+        for (int i = 0; i < nd; ++i) {
+            double u = vg.umin[d] + i * vg.du[d];
+            if (u < 0) ne_ = i + 1;
+            if (u > 0 && ps == nd) ps = i;
+        }
+        vg.neg_end[d] = ne_;
+        vg.pos_start[d] = ps;
+        nu *= nd;
+    }
+    vg.nu = (int)nu;
+    return FR_DVM_OK;
+}
+
+// Point weights (integral of each solution point's basis function, times
+// |J|), the 1-D velocity weights and the statistics buffers on the device.
+int finish_create(fr_dvm *h, const std::vector<double> &wq3J) {
+    int rc;
+    if ((rc = dev_alloc(h, &h->d_wq3J, h->ne * h->ns))) return rc;
+    if ((rc = upload(h, h->d_wq3J, wq3J.data(), wq3J.size() * sizeof(double)))) return rc;
+    std::vector<double> wax(3 * 64, 0.0);
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < h->vg.nv[d]; ++i) wax[64 * d + i] = h->wax[d][i];
+    if ((rc = dev_alloc(h, &h->d_wax, 3 * 64))) return rc;
+    if ((rc = upload(h, h->d_wax, wax.data(), wax.size() * sizeof(double)))) return rc;
+    if ((rc = dev_alloc(h, &h->d_stats, kHist + 4))) return rc;
+    if ((rc = dev_alloc(h, &h->d_maxres, 1))) return rc;
+    if ((rc = dev_alloc(h, &h->d_tot, 8))) return rc;
+    hipMemset(h->d_stats, 0, (kHist + 4) * sizeof(int64_t));
+    hipMemset(h->d_maxres, 0, sizeof(double));
+    return FR_DVM_OK;
+}
+
+}  // namespace frdvm
+
 extern "C" int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, double delta,
                                  const fr_dvm_vgrid *grid, fr_dvm_t *out) {
     if (!out) return FR_DVM_EINVAL;
@@ -493,29 +548,8 @@ extern "C" int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, 
     h->ncomp = delta > 0.0 ? 2 : 1;
     build_ops(order, nodes, h->ops);
 
-    // velocity grid
-    VGrid &vg = h->vg;
-    int64_t nu = 1;
-    for (int d = 0; d < 3; ++d) {
-        int nd = grid->n[d];
-        if (nd < 1 || nd > 64) return bail(h->fail(FR_DVM_EINVAL, "velocity nodes per axis must be 1..64"));
-        if (nd > 1 && !(grid->umax[d] > grid->umin[d])) return bail(h->fail(FR_DVM_EINVAL, "umax <= umin"));
-        vg.nv[d] = nd;
-        vg.umin[d] = grid->umin[d];
-        vg.du[d] = nd > 1 ? (grid->umax[d] - grid->umin[d]) / (nd - 1) : 0.0;
-        h->wax[d].assign(nd, 1.0);
-        for (int i = 0; i < nd && nd > 1; ++i) h->wax[d][i] = (i == 0 || i == nd - 1) ? 0.5 * vg.du[d] : vg.du[d];
-        int ne_ = 0, ps = nd;
-        for (int i = 0; i < nd; ++i) {
-            double u = vg.umin[d] + i * vg.du[d];
-            if (u < 0) ne_ = i + 1;
-            if (u > 0 && ps == nd) ps = i;
-        }
-        vg.neg_end[d] = ne_;
-        vg.pos_start[d] = ps;
-        nu *= nd;
-    }
-    vg.nu = (int)nu;
+    int rc = setup_vgrid(h, grid);
+    if (rc) return bail(rc);
 
     // mesh: connectivity and tags
     if (mesh->geom_order != 1 && mesh->geom_order != 2) return bail(h->fail(FR_DVM_EINVAL, "geom_order must be 1 or 2"));
@@ -538,7 +572,7 @@ extern "C" int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, 
                 return bail(h->fail(FR_DVM_EINVAL, "neighbour relation is not symmetric"));
         }
     std::vector<double> wq3J(h->ne * h->ns);
-    int rc = setup_axis(h, mesh, wq3J);
+    rc = setup_axis(h, mesh, wq3J);
     if (rc == kNotAxis) rc = setup_general(h, mesh, wq3J);
     if (rc) return bail(rc);
     if (h->axis_mode) {
@@ -558,18 +592,7 @@ extern "C" int fr_dvm_create_gas(const fr_dvm_mesh *mesh, int order, int nodes, 
     // device tables
     if ((rc = dev_alloc(h, &h->d_nbr, 6 * h->ne))) return bail(rc);
     if ((rc = upload(h, h->d_nbr, mesh->nbr_elem, 6 * h->ne * sizeof(int32_t)))) return bail(rc);
-    if ((rc = dev_alloc(h, &h->d_wq3J, h->ne * h->ns))) return bail(rc);
-    if ((rc = upload(h, h->d_wq3J, wq3J.data(), wq3J.size() * sizeof(double)))) return bail(rc);
-    std::vector<double> wax(3 * 64, 0.0);
-    for (int d = 0; d < 3; ++d)
-        for (int i = 0; i < vg.nv[d]; ++i) wax[64 * d + i] = h->wax[d][i];
-    if ((rc = dev_alloc(h, &h->d_wax, 3 * 64))) return bail(rc);
-    if ((rc = upload(h, h->d_wax, wax.data(), wax.size() * sizeof(double)))) return bail(rc);
-    if ((rc = dev_alloc(h, &h->d_stats, kHist + 4))) return bail(rc);
-    if ((rc = dev_alloc(h, &h->d_maxres, 1))) return bail(rc);
-    if ((rc = dev_alloc(h, &h->d_tot, 8))) return bail(rc);
-    hipMemset(h->d_stats, 0, (kHist + 4) * sizeof(int64_t));
-    hipMemset(h->d_maxres, 0, sizeof(double));
+    if ((rc = finish_create(h, wq3J))) return bail(rc);
     *out = h;
     return FR_DVM_OK;
 }
@@ -633,6 +656,7 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     if (p->guess < 0 || p->guess > 3) return h->fail(FR_DVM_EINVAL, "unknown guess mode");
     if (p->overlap != 0 && p->overlap != 1) return h->fail(FR_DVM_EINVAL, "overlap must be 0 or 1");
     if (p->positivity != 0 && p->positivity != 1) return h->fail(FR_DVM_EINVAL, "positivity must be 0 or 1");
+    if (h->mx && p->positivity) return h->fail(FR_DVM_EUNSUPPORTED, "no positivity limiter on mixed meshes");
     bool realloc_all = !h->have_params || p->precision != h->prm.precision;
     if (p->positivity && h->axis_mode) {
         int rc0 = move_to_general(h);
@@ -654,16 +678,18 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     size_t tes = p->precision != FR_DVM_FP64 ? sizeof(float) : sizeof(double);
     int64_t npts = h->ne * h->ns;
     int64_t nu = h->vg.nu * h->ncomp;  // state values per point
+    // trace values per buffer
+    const size_t trn = h->mx ? (size_t)h->mx->nfp * h->vg.nu : (size_t)(h->ne * h->tl.elem);
     int rc;
     if (realloc_all) {
         if (h->d_reg) { hipFree(h->d_reg); h->owned_bytes -= npts * nu * es_old; h->d_reg = nullptr; }
         for (int b = 0; b < 2; ++b)
-            if (h->d_tr[b]) { hipFree(h->d_tr[b]); h->d_tr[b] = nullptr; h->owned_bytes -= h->ne * h->tl.elem * tes_old; }
+            if (h->d_tr[b]) { hipFree(h->d_tr[b]); h->d_tr[b] = nullptr; h->owned_bytes -= trn * tes_old; }
         if (hipMalloc(&h->d_reg, npts * nu * es) != hipSuccess) { h->d_reg = nullptr; return h->fail(FR_DVM_ENOMEM, "register allocation failed"); }
         h->owned_bytes += npts * nu * es;
         for (int b = 0; b < 2; ++b) {
-            if (hipMalloc(&h->d_tr[b], h->ne * h->tl.elem * tes) != hipSuccess) { h->d_tr[b] = nullptr; return h->fail(FR_DVM_ENOMEM, "trace allocation failed"); }
-            h->owned_bytes += h->ne * h->tl.elem * tes;
+            if (hipMalloc(&h->d_tr[b], trn * tes) != hipSuccess) { h->d_tr[b] = nullptr; return h->fail(FR_DVM_ENOMEM, "trace allocation failed"); }
+            h->owned_bytes += trn * tes;
         }
         if ((rc = dev_alloc(h, &h->d_eq, npts * kEqW))) return rc;
         for (int b = 0; b < 2; ++b)
@@ -703,7 +729,7 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
         if ((rc = dev_alloc(h, &h->d_wrow, wrow.size()))) return rc;
         if ((rc = upload(h, h->d_wrow, wrow.data(), wrow.size() * sizeof(double)))) return rc;
     }
-    if (!h->axis_mode && (rc = gen_boundary_tables(h))) return rc;
+    if (!h->axis_mode && !h->mx && (rc = gen_boundary_tables(h))) return rc;
     // verification switch: FRDVM_ES_DIRECT=1 makes the ES Newton use the
     // direct per-node sums instead of the factorised ones
     const char *ev = std::getenv("FRDVM_ES_DIRECT");
@@ -789,6 +815,7 @@ extern "C" const char *fr_dvm_last_error(fr_dvm_t h) { return h ? h->err.c_str()
 extern "C" void fr_dvm_destroy(fr_dvm_t h) {
     if (!h) return;
     if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
+    free_mixed(h);
     void *ptrs[] = {h->d_gfac, h->d_nbr, h->d_wq3J, h->d_wx3, h->d_wrow, h->d_wax, h->d_reg, h->d_tr[0], h->d_tr[1],
                     h->d_Q, h->d_eq, h->d_ref[0], h->d_ref[1], h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
                     h->d_mlp_x, h->d_mlp_work, h->d_mlp_dz, h->d_pt_iters, h->d_pt_evals, h->d_pt_status,

@@ -37,6 +37,13 @@ class _Mesh(C.Structure):
                 ("nbr_orient", C.POINTER(C.c_int8)), ("bc", C.POINTER(C.c_int8))]
 
 
+class _MixedMesh(C.Structure):
+    _fields_ = [("n_elem", C.c_int32), ("n_nodes", C.c_int32), ("nodes", C.POINTER(C.c_double)),
+                ("elem_type", C.POINTER(C.c_int8)), ("elem_nodes", C.POINTER(C.c_int32)),
+                ("nbr_elem", C.POINTER(C.c_int32)), ("nbr_face", C.POINTER(C.c_int8)),
+                ("period", C.c_double * 3)]
+
+
 class _VGrid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("umin", C.c_double * 3), ("umax", C.c_double * 3)]
 
@@ -67,6 +74,7 @@ def lib():
         L.fr_dvm_create_nodes.argtypes = [C.POINTER(_Mesh), C.c_int, C.c_int, C.POINTER(_VGrid), C.POINTER(vp)]
         L.fr_dvm_create_gas.argtypes = [C.POINTER(_Mesh), C.c_int, C.c_int, C.c_double, C.POINTER(_VGrid),
                                         C.POINTER(vp)]
+        L.fr_dvm_create_mixed.argtypes = [C.POINTER(_MixedMesh), C.c_int, C.POINTER(_VGrid), C.POINTER(vp)]
         L.fr_dvm_set_params.argtypes = [vp, C.POINTER(_Params)]
         L.fr_dvm_set_stream.argtypes = [vp, vp]
         L.fr_dvm_sizes.argtypes = [vp, i64p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -184,8 +192,35 @@ class FrDvm:
     def __init__(self, mesh: dict, order: int, grid: dict, params: dict | None = None, nodes: int = 0,
                  delta: float = 0.0):
         """nodes: solution points per axis, 0 Gauss-Legendre, 1 Gauss-Lobatto;
-        delta > 0: a gas with delta internal degrees of freedom, state (F, G)."""
+        delta > 0: a gas with delta internal degrees of freedom, state (F, G).
+        A mesh with "elem_type" is a mixed mesh (fr_dvm_create_mixed): the
+        handle's state is [points][nu] (ne = points, ns = 1)."""
         L = lib()
+        g = _VGrid()
+        for d in range(3):
+            g.n[d] = int(grid["n"][d])
+            g.umin[d] = float(grid["umin"][d])
+            g.umax[d] = float(grid["umax"][d])
+        if "elem_type" in mesh:
+            self._keep = {
+                "nodes": np.ascontiguousarray(mesh["nodes"], np.float64),
+                "elem_type": np.ascontiguousarray(mesh["elem_type"], np.int8),
+                "elem_nodes": np.ascontiguousarray(mesh["elem_nodes"], np.int32),
+                "nbr_elem": np.ascontiguousarray(mesh["nbr_elem"], np.int32),
+                "nbr_face": np.ascontiguousarray(mesh["nbr_face"], np.int8),
+            }
+            k = self._keep
+            m = _MixedMesh(int(mesh["n_elem"]), int(k["nodes"].shape[0]),
+                           k["nodes"].ctypes.data_as(C.POINTER(C.c_double)),
+                           k["elem_type"].ctypes.data_as(C.POINTER(C.c_int8)),
+                           k["elem_nodes"].ctypes.data_as(C.POINTER(C.c_int32)),
+                           k["nbr_elem"].ctypes.data_as(C.POINTER(C.c_int32)),
+                           k["nbr_face"].ctypes.data_as(C.POINTER(C.c_int8)),
+                           (C.c_double * 3)(*[float(x) for x in mesh.get("period", (0.0, 0.0, 0.0))]))
+            h = C.c_void_p()
+            rc = L.fr_dvm_create_mixed(C.byref(m), int(order), C.byref(g), C.byref(h))
+            self._finish(h, rc, order, 1, 0.0, params)
+            return
         self._keep = {
             "nodes": np.ascontiguousarray(mesh["nodes"], np.float64),
             "elem_nodes": np.ascontiguousarray(mesh["elem_nodes"], np.int32),
@@ -202,13 +237,12 @@ class FrDvm:
                   k["nbr_face"].ctypes.data_as(C.POINTER(C.c_int8)),
                   k["nbr_orient"].ctypes.data_as(C.POINTER(C.c_int8)),
                   k["bc"].ctypes.data_as(C.POINTER(C.c_int8)))
-        g = _VGrid()
-        for d in range(3):
-            g.n[d] = int(grid["n"][d])
-            g.umin[d] = float(grid["umin"][d])
-            g.umax[d] = float(grid["umax"][d])
         h = C.c_void_p()
         rc = L.fr_dvm_create_gas(C.byref(m), int(order), int(nodes), float(delta), C.byref(g), C.byref(h))
+        self._finish(h, rc, order, nodes, delta, params)
+
+    def _finish(self, h, rc, order, nodes, delta, params):
+        L = lib()
         self._h = h
         if rc != 0:
             msg = self.last_error() if h.value else "invalid argument"
