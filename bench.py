@@ -257,6 +257,51 @@ def roofline(r, p, workload, general=False):
     return out
 
 
+# solution points and face points of each mixed-mesh element type at order p
+# (hexahedron, prism, tetrahedron)
+MIXED_SIZES = {1: ((8, 24), (6, 18), (4, 12)), 2: ((27, 54), (18, 39), (10, 24)),
+               3: ((64, 96), (40, 68), (20, 40))}
+VALU_PEAK_TFLOPS = {0: 78.6, 1: 157.3}  # MI355X vector FP64 / FP32
+
+
+def mixed_flops_per_dof(mesh, p: int) -> float:
+    """Algorithmic flops per DOF of a mixed-mesh stage: per solution point
+    and velocity the three reference-derivative rows (3 N_s multiply-adds)
+    and the lifting row (N_ft multiply-adds) of its element's dense
+    operators, averaged over the mesh's points."""
+    import numpy as np
+    counts = np.bincount(np.asarray(mesh["elem_type"]), minlength=3)
+    pts = sum(int(counts[t]) * MIXED_SIZES[p][t][0] for t in range(3))
+    fl = sum(int(counts[t]) * MIXED_SIZES[p][t][0] * 2 * (3 * MIXED_SIZES[p][t][0] + MIXED_SIZES[p][t][1])
+             for t in range(3))
+    return fl / pts
+
+
+def mixed_roofline(r, p, mesh):
+    """The mixed-mesh stage (dense element operators, VALU) against the
+    vector ALU peak of its precision: algorithmic flops of the stage launches
+    over their summed HIP-event durations."""
+    ms, n = r["prof"]["stage"]
+    fpd = mixed_flops_per_dof(mesh, p)
+    ach = fpd * r["dof"] * 3 * r["steps"] / (ms / 1e3) / 1e12
+    peak = VALU_PEAK_TFLOPS[0 if r["precision"] == 0 else 1]
+    # HBM: read f, write the result, the low-storage register (read in 2 of 3
+    # stages, written in 2 of 3), read the neighbour traces where the velocity
+    # enters (half the face points), write the result's traces, read the
+    # result again for its moments
+    import numpy as np
+    counts = np.bincount(np.asarray(mesh["elem_type"]), minlength=3)
+    pts = sum(int(counts[t]) * MIXED_SIZES[p][t][0] for t in range(3))
+    fpts = sum(int(counts[t]) * MIXED_SIZES[p][t][1] for t in range(3))
+    vals = 3.0 + (4.0 / 3.0 if r["rk"] == 1 else 2.0 / 3.0) + 1.5 * fpts / pts
+    bpd = vals * (8 if r["precision"] == 0 else 4)
+    gbs = bpd * r["dof"] * 3 * r["steps"] / (ms / 1e3) / 1e9
+    return {"kernel": "k_mix_stage (+ k_gen_moments), dense FR-DG operators", "bound": "alu", "achieved": ach,
+            "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+            "flops_per_dof": fpd, "avg_launch_ms": ms / max(n, 1),
+            "hbm_bytes_per_dof": bpd, "hbm_GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+
+
 def unfused_bytes_per_dof(p: int, precision: int, rk: int) -> float:
     """Per-DOF traffic of one RK stage when its parts are separate passes
     (moments read f, the residual reads f and writes traces of r = 6/(p+1)
@@ -477,7 +522,14 @@ def main():
                "dtype": ["f64", "f32 (FP64 moments and Newton)", MIXED_DTYPE][par["precision"]],
                "data": "synthetic (seeded initial Maxwellian of the workload's macroscopic field)", "config": cfg,
                "kernels_ms_per_step": {k: v[0] / r["steps"] for k, v in r["prof"].items()},
-               "newton": r["newton"], "roofline": roofline(r, w["p"], w["name"], w.get("mesh") == "cylinder")}
+               "newton": r["newton"],
+               "roofline": mixed_roofline(r, w["p"], mesh) if "elem_type" in mesh
+               else roofline(r, w["p"], w["name"], w.get("mesh") == "cylinder")}
+        if "elem_type" in mesh:
+            import numpy as np
+            cnt = np.bincount(np.asarray(mesh["elem_type"]), minlength=3)
+            cfg.update(elements={"hexahedra": int(cnt[0]), "prisms": int(cnt[1]), "tetrahedra": int(cnt[2])},
+                       points=int(r["dof"] // cfg["nu"]), ns=None)
         if not args.no_cpu:
             out["cpu_baseline"] = cpu_baseline(w, par, args.cpu_seconds)
         print(json.dumps(out), flush=True)

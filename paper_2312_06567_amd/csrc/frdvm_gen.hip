@@ -642,8 +642,13 @@ __device__ __forceinline__ MixOps<double> mix_ops(const MixArgs &A, double) {
 
 template <typename Real, int NS, int NFT, int MODE>
 __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
+    // up to 40 points (tetrahedra, prisms, hexahedra to p = 2) a lane keeps
+    // its values and residuals in registers and the dense products run fully
+    // unrolled with the operator entries as scalar operands; above, both sit
+    // in LDS columns
+    constexpr bool REG = NS <= 40;
     __shared__ Real sf[NS][kGWave];
-    __shared__ Real sa[NS][kGWave];
+    __shared__ Real sa[REG ? 1 : NS][kGWave];
     const int64_t e = A.elems[blockIdx.x / A.nvw];
     const int lane = threadIdx.x;
     const int k = (int)(blockIdx.x % A.nvw) * kGWave + lane;
@@ -654,6 +659,7 @@ __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
     const int64_t p0 = A.poff[e], t0 = A.toff[e];
     const MixOps<Real> op = mix_ops(A, Real(0));
     const cptr<Real> g = op.geo + e * kMixGeo;
+    const cptr<int32_t> fnode = (cptr<int32_t>)A.fnode, ffac = (cptr<int32_t>)A.ffac;
     int iv[3];
     split_k(A.vg, kk, iv);
     const double ud[3] = {node_u(A.vg, 0, iv[0]), node_u(A.vg, 1, iv[1]), node_u(A.vg, 2, iv[2])};
@@ -662,35 +668,74 @@ __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) c[a] = u0 * g[3 * a] + u1 * g[3 * a + 1] + u2 * g[3 * a + 2];
     const Real *fE = reinterpret_cast<const Real *>(A.sa.f) + p0 * nu;
-#pragma unroll 4
-    for (int i = 0; i < NS; ++i) sf[i][lane] = ldo(fE + i * nu, ko);
-    // volume: the derivative along u
-#pragma unroll 1
-    for (int i = 0; i < NS; ++i) {
-        Real acc = Real(0);
-#pragma unroll 4
-        for (int j = 0; j < NS; ++j) {
-            const Real w = c[0] * op.D[i * NS + j] + c[1] * op.D[(NS + i) * NS + j] + c[2] * op.D[(2 * NS + i) * NS + j];
-            acc = fma(w, sf[j][lane], acc);
-        }
-        sa[i][lane] = -acc;
-    }
-    // faces: the upwind jump at each face point, lifted into the element
     const Real *trI = reinterpret_cast<const Real *>(A.sa.tr_in);
-#pragma unroll 1
-    for (int t = 0; t < NFT; ++t) {
-        const int f = A.ffac[t], node = A.fnode[t];
+    // the upwind jump at face point t, scaled (0 where the velocity leaves)
+    auto jump_at = [&](int t) {
+        const int f = ffac[t];
         const Real un = u0 * g[9 + 3 * f] + u1 * g[10 + 3 * f] + u2 * g[11 + 3 * f];
         Real jump = Real(0);
-        if (un < Real(0)) jump = un * g[27 + f] * (ldo(trI + A.tnb[t0 + t] * nu, ko) - sf[node][lane]);
+        if (un < Real(0)) jump = un * g[27 + f] * (ldo(trI + A.tnb[t0 + t] * nu, ko) - sf[fnode[t]][lane]);
+        return jump;
+    };
+    Real fv[REG ? NS : 1], r[REG ? NS : 1];
+    if constexpr (REG) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            fv[i] = ldo(fE + i * nu, ko);
+            sf[i][lane] = fv[i];
+            r[i] = Real(0);
+        }
+        // volume: r_i = -sum_a c_a (D_a f)_i
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+                Real gi = Real(0);
+#pragma unroll
+                for (int j = 0; j < NS; ++j) gi = fma(op.D[(a * NS + i) * NS + j], fv[j], gi);
+                r[i] = fma(-c[a], gi, r[i]);
+            }
+        }
+        // faces
+#pragma unroll 1
+        for (int t = 0; t < NFT; ++t) {
+            const Real jump = jump_at(t);
+#pragma unroll
+            for (int i = 0; i < NS; ++i) r[i] = fma(-op.lift[i * NFT + t], jump, r[i]);
+        }
+    } else {
 #pragma unroll 4
-        for (int i = 0; i < NS; ++i) sa[i][lane] -= op.lift[i * NFT + t] * jump;
+        for (int i = 0; i < NS; ++i) sf[i][lane] = ldo(fE + i * nu, ko);
+#pragma unroll 1
+        for (int i = 0; i < NS; ++i) {
+            Real acc = Real(0);
+#pragma unroll 4
+            for (int j = 0; j < NS; ++j) {
+                const Real w = c[0] * op.D[i * NS + j] + c[1] * op.D[(NS + i) * NS + j] + c[2] * op.D[(2 * NS + i) * NS + j];
+                acc = fma(w, sf[j][lane], acc);
+            }
+            sa[i][lane] = -acc;
+        }
+#pragma unroll 1
+        for (int t = 0; t < NFT; ++t) {
+            const Real jump = jump_at(t);
+#pragma unroll 4
+            for (int i = 0; i < NS; ++i) sa[i][lane] -= op.lift[i * NFT + t] * jump;
+        }
     }
+    auto res = [&](int i) -> Real {
+        if constexpr (REG) return r[i];
+        else return sa[i][lane];
+    };
+    auto val = [&](int i) -> Real {
+        if constexpr (REG) return fv[i];
+        else return sf[i][lane];
+    };
     if (MODE == GMODE_RESID) {
         Real *R = reinterpret_cast<Real *>(A.sa.fout) + p0 * nu;
         if (act)
-#pragma unroll 4
-            for (int i = 0; i < NS; ++i) sto(R + i * nu, ko, sa[i][lane]);
+#pragma unroll
+            for (int i = 0; i < NS; ++i) sto(R + i * nu, ko, res(i));
         return;
     }
     // collision source and the Runge-Kutta combination, point by point
@@ -700,10 +745,10 @@ __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
     const Real *XE = reinterpret_cast<const Real *>(A.sa.scheme == 0 ? A.sa.fn : A.sa.dF) + p0 * nu;
     Real *outE = reinterpret_cast<Real *>(A.sa.fout) + p0 * nu;
     Real *dFE = reinterpret_cast<Real *>(A.sa.dF) + p0 * nu;
-#pragma unroll 1
+#pragma unroll
     for (int i = 0; i < NS; ++i) {
-        const Real fq = sf[i][lane];
-        Real L = sa[i][lane];
+        const Real fq = val(i);
+        Real L = res(i);
         if (collide) {
             const cptr<double> q = (cptr<double>)A.sa.eq + (p0 + i) * kEqW;
             const double c0 = ud[0] - q[EQ_V], c1 = ud[1] - q[EQ_V + 1], c2 = ud[2] - q[EQ_V + 2];
@@ -740,7 +785,7 @@ __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
     if (A.do_traces && act) {
         Real *trO = reinterpret_cast<Real *>(A.sa.tr_out) + t0 * nu;
 #pragma unroll 1
-        for (int t = 0; t < NFT; ++t) sto(trO + t * nu, ko, sf[A.fnode[t]][lane]);
+        for (int t = 0; t < NFT; ++t) sto(trO + t * nu, ko, sf[fnode[t]][lane]);
     }
 }
 

@@ -186,3 +186,14 @@ def test_input_points_follow_the_documented_order(p):
     mesh = W.mixed_box_mesh(3)
     mm = M.MixedMesh(mesh, p)
     assert np.abs(W.mixed_solution_points(mesh, p) - mm.xs).max() < 1e-14
+
+
+def test_prism_tetrahedron_box_conserves():
+    # the prism / tetrahedron workload mesh: conforming faces, free stream, conservation
+    mesh = W.prism_tet_box_mesh(3)
+    assert np.bincount(mesh["elem_type"], minlength=3).tolist() == [0, 18, 108]
+    P = M.MixedProblem(mesh, 2, W.grid_spec(4, 3.0), _params())
+    assert np.abs(P.residual(np.ones(P.shape))).max() < 1e-12
+    f = np.random.default_rng(11).uniform(0.5, 1.5, P.shape)
+    R = P.residual(f)
+    assert np.abs((P.point_weights()[:, None] * R).sum(0)).max() < 1e-14 * np.abs(R).max()

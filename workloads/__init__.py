@@ -339,11 +339,7 @@ def mixed_box_mesh(N: int = 3, length: float = 1.0) -> dict:
     n1 = N + 1
     g = np.arange(n1) * h
     nodes = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
-
-    def nid(c):
-        return int(c[0] + n1 * (c[1] + n1 * c[2]))
-
-    types, verts, gverts = [], [], []  # gverts: integer grid coordinates of each vertex
+    types, gverts = [], []  # gverts: integer grid coordinates of each vertex
     for k in range(N):
         for j in range(N):
             for i in range(N):
@@ -378,10 +374,57 @@ def mixed_box_mesh(N: int = 3, length: float = 1.0) -> dict:
                             P.append(q)
                     types.append(PRISM)
                     gverts.append(P)
+    return _mixed_from_cells(N, length, nodes, types, gverts)
+
+
+def prism_tet_box_mesh(N: int, length: float = 1.0) -> dict:
+    """Periodic box [0, L]^3 of N^3 cells standing in for the paper's capsule
+    mesh of prisms and tetrahedra: the lower N // 2 layers of cells each split
+    into two prisms extruded along z (triangles halving the (x, y) square
+    along its (min, min) - (max, max) diagonal, a boundary-layer stand-in),
+    the upper layers each into the six Kuhn tetrahedra of its main diagonal.
+    The Kuhn split halves every face of a cell along the same diagonal as the
+    prisms, so all faces conform (triangles meet triangles, quadrilaterals
+    quadrilaterals).  N >= 3 (with 2 cells per period distinct faces would
+    have the same vertices modulo the period)."""
+    import itertools
+    assert N >= 3
+    n1 = N + 1
+    h = length / N
+    g = np.arange(n1) * h
+    nodes = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+    types, gverts = [], []
+    for k in range(N):
+        for j in range(N):
+            for i in range(N):
+                o = np.array([i, j, k])
+                if k < N // 2:
+                    for tri in (((0, 0), (1, 0), (1, 1)), ((0, 0), (1, 1), (0, 1))):
+                        types.append(PRISM)
+                        gverts.append([o + np.array([a, b, end]) for end in (0, 1) for (a, b) in tri])
+                else:
+                    for perm in itertools.permutations(range(3)):
+                        P = [o.copy()]
+                        for d in perm:
+                            q = P[-1].copy()
+                            q[d] += 1
+                            P.append(q)
+                        if np.dot(np.cross(P[1] - P[0], P[2] - P[0]), P[3] - P[0]) < 0:
+                            P[1], P[2] = P[2], P[1]
+                        types.append(TET)
+                        gverts.append(P)
+    return _mixed_from_cells(N, length, nodes, types, gverts)
+
+
+def _mixed_from_cells(N, length, nodes, types, gverts) -> dict:
+    """Mesh dictionary of elements given by integer grid vertices: element
+    node lists and face neighbours found by matching face vertices modulo the
+    period."""
+    n1 = N + 1
     ne = len(types)
     en = np.full((ne, 8), -1, np.int32)
     for e, P in enumerate(gverts):
-        en[e, :len(P)] = [nid(c) for c in P]
+        en[e, :len(P)] = [int(c[0] + n1 * (c[1] + n1 * c[2])) for c in P]
     nbr = np.full((ne, 6), -1, np.int32)
     nbf = np.full((ne, 6), -1, np.int8)
     seen = {}
@@ -650,6 +693,13 @@ def workload(name: str) -> dict:
         # x 2 spanwise quadratic hexes, p=2, 24^3 grid on [-14,14]^3, ES-BGK Pr=2/3,
         # Kn=0.01, uniform Mach-8 inflow at theta=1 (1% seeded density noise),
         # diffuse wall at theta_w=2, farfield outside
+        # prisms + tetrahedra standing in for the paper's capsule mesh: 12^3 cells,
+        # lower half prisms, upper half Kuhn tetrahedra (1728 prisms, 5184
+        # tetrahedra, 172800 solution points), p=3, 24^3 grid on [-8,8]^3 (the
+        # paper's velocity resolution), ES-BGK Pr=2/3, Kn=1e-3, Taylor-Green U0=0.3
+        "ptbox12_p3_v24_es": dict(mesh="prism_tet", N=12, p=3, grid=grid_spec(24, 8.0), model=1,
+                                  prandtl=2.0 / 3.0, kn=1e-3, ic="tgv", U0=0.3, pert=0.01, seed=7,
+                                  steps=50, rk=1, precision=1),
         "cyl48x24x2_p2_v24_es": dict(mesh="cylinder", p=2, grid=grid_spec(24, 14.0), model=1,
                                      prandtl=2.0 / 3.0, kn=0.01, ic="uniform", mach=8.0, noise=0.01,
                                      theta_wall=2.0, seed=31, steps=2000, rk=1, precision=1, positivity=1),
@@ -677,6 +727,8 @@ def paper_freestream(mach: float, reynolds: float, alpha_deg: float = 0.0, t_inf
 def workload_mesh(w: dict) -> dict:
     if w.get("mesh") == "cylinder":
         return cylinder_mesh()
+    if w.get("mesh") == "prism_tet":
+        return prism_tet_box_mesh(w["N"])
     return box_mesh(w["N"])
 
 
@@ -688,7 +740,8 @@ def initial_prim(mesh: dict, p: int, w: dict) -> np.ndarray:
         prim = np.tile(np.asarray(w["farfield"], dtype=float), (mesh["n_elem"], ns, 1))
         prim[..., 0] *= 1.0 + w["noise"] * rng.uniform(-1.0, 1.0, size=(mesh["n_elem"], ns))
         return prim
-    xs = box_solution_points(mesh, p)
+    # mixed meshes: [points][5] (the library's point-per-element view)
+    xs = mixed_solution_points(mesh, p)[:, None, :] if "elem_type" in mesh else box_solution_points(mesh, p)
     if w["ic"] == "modes":
         return prim_random_modes(xs, seed=w["seed"])
     if w["ic"] == "tgv":
