@@ -425,16 +425,18 @@ k_fr_layer(const FrArgs A) {
         // chunk's loads right away.
         // The lane's element references at its velocity (FP32 deviation
         // storage): rp the previous stage's (the stage value and the traces
-        // are made relative to it), rc this stage's (a result relative to rp
-        // becomes one relative to rc by adding rp - rc in FP64; 0 after the
-        // call's last stage, which leaves the plain value), dl[d] what turns
-        // the inflow trace of direction d (relative to its writer's
+        // are made relative to it), sh what turns a result relative to rp
+        // into one relative to this stage's reference rc (rp - rc; rp after
+        // the call's last stage, which leaves the plain value), dl[d] what
+        // turns the inflow trace of direction d (relative to its writer's
         // reference, or plain in the first stage) into one relative to rp.
-        // References are FP32 numbers: their differences are exact in FP64.
-        float rp = 0.0f, rc = 0.0f, dl[3] = {0.0f, 0.0f, 0.0f};
+        // References are FP32 numbers: the difference of two within a factor
+        // 2 of each other is exact in FP32 (consecutive stages' references
+        // of an element are), and rounded once otherwise.
+        float rp = 0.0f, sh = 0.0f, dl[3] = {0.0f, 0.0f, 0.0f};
         if (ER) {
             rp = ref_value(ref_exponent(&s_ref[0], v.u));
-            rc = out_dev ? ref_value(ref_exponent(&s_ref[kRefCoef], v.u)) : 0.0f;
+            sh = out_dev ? rp - ref_value(ref_exponent(&s_ref[kRefCoef], v.u)) : rp;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const int slot = 2 + 2 * d + (v.sgn[d] > 0 ? 0 : 1);  // the upwind neighbour in direction d
@@ -604,7 +606,7 @@ k_fr_layer(const FrArgs A) {
                     if (v.act && A.sa.keep_dF) stb(dFE, o + q * QB, (SReal)dd);
                     fod = fma(A.sa.lsB, (double)dd, (double)fq);
                 }
-                if (ER) fod = (fod + (double)rp) - (double)rc;
+                if (ER) fod += (double)sh;
                 Real fo;
                 if constexpr (sizeof(Real) == 4) {
                     rs = xorshift32(rs);
