@@ -167,18 +167,23 @@ struct LdsTab {
 
 // The velocity node a lane works on in one chunk.
 struct Vel {
-    int k;  // node index (0 for a lane past the end of the grid)
-    bool act;
+    int k;  // node index (the last node for a lane past the end of the grid)
+    bool act;  // a node of the grid (false: the lane duplicates the last one)
     int iv[3];
     int sgn[3];
     double u[3];
+};
+
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
 };
 
 __device__ __forceinline__ Vel velocity(const FrArgs &A, int k, bool lane_ok) {
     const VGrid &vg = A.vg;
     Vel v;
     v.act = lane_ok && k < A.nu;
-    v.k = v.act ? k : 0;
+    v.k = v.act ? k : A.nu - 1;
     // integer split through single precision; exact for node counts below
     // 2^21 (enforced at set-up): (k + 1/2)/n stays 1/(2n) away from integers
     const int nx = vg.nv[0], nxy = vg.nv[0] * vg.nv[1];
@@ -215,7 +220,7 @@ struct TraceOff {
 template <typename Real>
 __device__ __forceinline__ TraceOff trace_in(const FrArgs &A, const LdsTab<Real> &T, const Vel &v, int d, int fp0) {
     TraceOff t;
-    const bool flow = v.act && v.sgn[d] != 0;
+    const bool flow = v.sgn[d] != 0;  // (a lane past the end reads what the last node reads)
     const int sin_ = v.sgn[d] > 0 ? 0 : 1;  // inflow face side
     const int slot = 2 * d + (sin_ ^ 1);     // the upwind neighbour's outflow face
     const uint32_t cnt = T.cnt[slot], fo = T.fo[slot];
@@ -475,6 +480,9 @@ k_fr_layer(const FrArgs A) {
         if (useX) {
 #pragma unroll
             for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NL; ++q) X[q] = SReal(0);
         }
         if (FLUX) __syncthreads();  // the chunk's stage value of every layer is in the tile
         Real f[NL];  // the produced value (stage and residual modes)
@@ -489,7 +497,7 @@ k_fr_layer(const FrArgs A) {
             // (face points (j, l) / (i, l))
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
-                const bool flow = v.act && v.sgn[d] != 0;
+                const bool flow = v.sgn[d] != 0;
                 const int sin_ = v.sgn[d] > 0 ? 0 : 1;
                 const Real un = (Real)((sin_ ? 1.0 : -1.0) * gf[d] * v.u[d]);
                 const Real ad = d == 0 ? ax : ay;
@@ -523,7 +531,7 @@ k_fr_layer(const FrArgs A) {
             // then r += cz f+ (the interior trace folded into the coefficients)
             {
                 const int zin = v.sgn[2] > 0 ? 0 : 1;
-                const bool zflow = v.act && v.sgn[2] != 0;
+                const bool zflow = v.sgn[2] != 0;
                 const Real unz = (Real)((zin ? 1.0 : -1.0) * gf[2] * v.u[2]);
                 const Real cz = zflow ? T.corr[zin][l] * unz : Real(0);
 #pragma unroll
@@ -544,10 +552,8 @@ k_fr_layer(const FrArgs A) {
                 phase_fence();
             }
             if (MODE == MODE_RESID) {
-                if (v.act) {
 #pragma unroll
-                    for (int q = 0; q < NL; ++q) stb(outE, o + q * QB, (SReal)(-r[q]));
-                }
+                for (int q = 0; q < NL; ++q) stb(outE, o + q * QB, (SReal)(-r[q]));
                 __syncthreads();  // every layer is done with the stage tile
                 continue;
             }
@@ -557,72 +563,73 @@ k_fr_layer(const FrArgs A) {
             // chunk, a xorshift step per value
             uint32_t rs = sizeof(Real) == 4 ? round_bits(A.sa.seed, (uint32_t)(e * NS + l * NL), (uint32_t)(comp * nu + v.k)) | 1u
                                             : 0u;
+            // One loop per combination of the launch-uniform switches (the
+            // collision, the RK scheme, whether dF is kept), and lanes past
+            // the end of the grid computing and storing exactly what the lane
+            // of the last node does: no branch splits the points, so the
+            // scheduler can interleave their independent chains.
+            auto points = [&](auto coll_c, auto lsrk_c, auto keep_c) {
+                constexpr bool COLL = decltype(coll_c)::value, LSRK = decltype(lsrk_c)::value;
+                constexpr bool KEEP = decltype(keep_c)::value;
 #pragma unroll
-            for (int q = 0; q < NL; ++q) {
-                const Real fq = tS[tix<Real>(l * NL + q, vl)];
-                Real L = -r[q];
-                if (EQ_LDS && collide) {
-                    const int s = l * NL + q;
-                    const double *b = &s_eb[s * 8];
-                    const double *V = &s_ev[s * 4];
-                    const double b6 = (NCOMP == 2 && comp) ? b[6] + V[3] : b[6];
-                    // the equilibrium's exponent at this point and velocity
-                    const double Eq = eq_exponent(b[0], b[1], b[2], b[3], b[4], b[5], b6, V[0], V[1], V[2], v.u);
-                    if constexpr (ER)
-                        L += ((Real)(exp_f64(Eq) - (double)rp) - fq) * (Real)b[7];  // g - rp rounded once
-                    else
-                        L += (exp_r<Real>(Eq) - fq) * (Real)b[7];
-                } else if (collide) {
-                    // E = c0 - (c^T B c)/2, c = u - V, formed in FP64
-                    cdouble *rq = eqL + q * kEqW;
-                    const double c0 = v.u[0] - rq[EQ_V], c1 = v.u[1] - rq[EQ_V + 1], c2 = v.u[2] - rq[EQ_V + 2];
-                    const double d1 = c1 + c1, d2 = c2 + c2;
-                    double t0 = rq[EQ_B] * c0;
-                    t0 = fma(rq[EQ_B + 3], d1, t0);
-                    t0 = fma(rq[EQ_B + 4], d2, t0);
-                    double t1 = rq[EQ_B + 1] * c1;
-                    t1 = fma(rq[EQ_B + 5], d2, t1);
-                    double S = c0 * t0;
-                    S = fma(c1, t1, S);
-                    S = fma(c2 * rq[EQ_B + 2], c2, S);
-                    double lc = rq[EQ_C0];
-                    if constexpr (NCOMP == 2) {
-                        if (comp) {
-                            const double gq = A.gfp[e * NS + l * NL + q];
-                            lc += gq > 0.0 ? log(gq) : -1000.0;
-                        }
+                for (int q = 0; q < NL; ++q) {
+                    const Real fq = tS[tix<Real>(l * NL + q, vl)];
+                    Real L = -r[q];
+                    if constexpr (COLL) {
+                        const int s = l * NL + q;
+                        const double *b = &s_eb[s * 8];
+                        const double *V = &s_ev[s * 4];
+                        const double b6 = (NCOMP == 2 && comp) ? b[6] + V[3] : b[6];
+                        // the equilibrium's exponent at this point and velocity
+                        const double Eq = eq_exponent(b[0], b[1], b[2], b[3], b[4], b[5], b6, V[0], V[1], V[2], v.u);
+                        if constexpr (ER)
+                            L += ((Real)(exp_f64(Eq) - (double)rp) - fq) * (Real)b[7];  // g - rp rounded once
+                        else
+                            L += (exp_r<Real>(Eq) - fq) * (Real)b[7];
                     }
-                    const double E = fma(-0.5, S, lc);
-                    L += (exp_r<Real>(E) - fq) * (Real)rq[EQ_INVTAU];
+                    // the result, in FP64 for the stochastic rounding of the FP32 state
+                    double fod;
+                    if constexpr (!LSRK) {
+                        fod = A.sa.beta * ((double)fq + (double)(dt * L));
+                        fod = fma(A.sa.alpha, (double)X[q], fod);  // (X = 0 when not read)
+                    } else {
+                        Real dd = dt * L;
+                        dd += (Real)A.sa.lsA * (Real)X[q];
+                        if constexpr (KEEP) stb(dFE, o + q * QB, (SReal)dd);
+                        fod = fma(A.sa.lsB, (double)dd, (double)fq);
+                    }
+                    if (ER) fod += (double)sh;
+                    Real fo;
+                    if constexpr (sizeof(Real) == 4) {
+                        rs = xorshift32(rs);
+                        fo = round_stochastic(fod, rs);
+                    } else {
+                        fo = (Real)fod;
+                    }
+                    f[q] = fo;
+                    stb(outE, o + q * QB, (SReal)fo);
+                    // (a fence every two points in FP32, four in FP64: the
+                    // chains in flight at once, against register pressure)
+                    if (q % (sizeof(Real) == 4 ? 2 : 4) == (sizeof(Real) == 4 ? 1 : 3)) phase_fence();
                 }
-                // the result, in FP64 for the stochastic rounding of the FP32 state
-                double fod;
-                if (A.sa.scheme == 0) {
-                    fod = A.sa.beta * ((double)fq + (double)(dt * L));
-                    if (useX) fod = fma(A.sa.alpha, (double)X[q], fod);
+            };
+            if constexpr (STAGE) {
+                if (!ER && A.sa.scheme == 0) {
+                    if (collide) points(BoolC<true>{}, BoolC<false>{}, BoolC<false>{});
+                    else points(BoolC<false>{}, BoolC<false>{}, BoolC<false>{});
+                } else if (A.sa.keep_dF) {
+                    if (collide) points(BoolC<true>{}, BoolC<true>{}, BoolC<true>{});
+                    else points(BoolC<false>{}, BoolC<true>{}, BoolC<true>{});
                 } else {
-                    Real dd = dt * L;
-                    if (useX) dd += (Real)A.sa.lsA * (Real)X[q];
-                    if (v.act && A.sa.keep_dF) stb(dFE, o + q * QB, (SReal)dd);
-                    fod = fma(A.sa.lsB, (double)dd, (double)fq);
+                    if (collide) points(BoolC<true>{}, BoolC<true>{}, BoolC<false>{});
+                    else points(BoolC<false>{}, BoolC<true>{}, BoolC<false>{});
                 }
-                if (ER) fod += (double)sh;
-                Real fo;
-                if constexpr (sizeof(Real) == 4) {
-                    rs = xorshift32(rs);
-                    fo = round_stochastic(fod, rs);
-                } else {
-                    fo = (Real)fod;
-                }
-                f[q] = v.act ? fo : Real(0);
-                if (v.act) stb(outE, o + q * QB, (SReal)fo);
-                if (q % 4 == 3) phase_fence();
             }
         }
 
         // outflow traces of the produced value on the x and y faces, into
         // the neighbours' blocks
-        if (A.do_traces && v.act) {
+        if (A.do_traces) {
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
                 if (v.sgn[d] != 0) {
@@ -657,7 +664,7 @@ k_fr_layer(const FrArgs A) {
                 for (int q = 0; q < NL; ++q) tP[tix<Real>(l * NL + q, vl)] = f[q];
             }
             __syncthreads();  // the produced tile is complete (and the stage tile no longer read)
-            if (A.do_traces && v.act && v.sgn[2] != 0) {
+            if (A.do_traces && v.sgn[2] != 0) {
                 // this wave writes the z-face points (i, j = l)
                 const int side = v.sgn[2] > 0 ? 1 : 0;
                 const int face = 4 + side;

@@ -156,3 +156,26 @@ def test_mixed_refuses_unsupported_options(F):
     bad["nodes"][5] += 0.01  # a moved vertex: elements no longer straight or faces unmatched
     with pytest.raises(F.FrDvmError):
         F.FrDvm(bad, 2, grid)
+
+
+@pytest.mark.parametrize("prec,rk", [(0, 0), (1, 1)])
+def test_mixed_bitwise_reproducible(F, prec, rk):
+    """Runs from the same state give the same bits: twice on one handle
+    (parameters set again in between: the stage seeds of the stochastic
+    rounding start over) and once on a second handle."""
+    mesh = W.mixed_box_mesh(3)
+    grid = W.grid_spec(8, 5.0)
+    p = 3
+    par = dict(_params(1), precision=prec, rk=rk, guess=0)
+    f0 = _state(mesh, p, grid)
+    s, t = F.FrDvm(mesh, p, grid, par), F.FrDvm(mesh, p, grid, par)
+    dt = s.dt(0.2)
+    dtype = torch.float64 if prec == 0 else torch.float32
+    runs = []
+    for h in (s, s, t):
+        h.set_params(**par)
+        f = torch.as_tensor(f0, dtype=dtype).cuda().contiguous()
+        h.rk_steps(f, dt, 3)
+        runs.append(f)
+    assert torch.equal(runs[0], runs[1]) and torch.equal(runs[0], runs[2])
+    assert not torch.equal(runs[0], torch.as_tensor(f0, dtype=dtype).cuda())
