@@ -72,9 +72,11 @@ extern "C" {
  * The call's first stage reads plain f and its last stage leaves plain f,
  * rounded to FP32 (stochastically).  Within an element f stays close to one
  * reference, so the stored deviation and the arithmetic on it carry a small
- * fraction of the rounding error of FP32 f.  Periodic box meshes, monatomic
- * gas, low-storage RK (FR_DVM_LSRK3_2N), collision models BGK / ES-BGK, no
- * positivity limiter and no overlap; other calls (residual, collide,
+ * fraction of the rounding error of FP32 f.  With FR_DVM_SSPRK3 the step's
+ * initial value (read by the second and third stages) stays a deviation from
+ * the references it was written with.  Periodic box meshes, monatomic gas,
+ * both RK schemes, collision models BGK / ES-BGK, no positivity limiter and
+ * no overlap; other calls (residual, collide,
  * moments, Kn) take f as plain float values and equal FR_DVM_FP32. */
 #define FR_DVM_FP32_DEV 2
 

@@ -172,10 +172,17 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
     // (decided after the first solve: a learned-then-warm start is warm from here on)
     // FP32 deviation storage: each stage reads its value relative to the
     // element references of the previous stage's records and writes relative
-    // to those of its own, so the two reference sets alternate; the first
-    // stage reads plain f and takes its own references for both
+    // to those of its own (SSP also reads the step's initial value, relative
+    // to the references it was written with): each stage's references go to
+    // a set that neither of the others it reads holds; the first stage reads
+    // plain f and takes its own references for both
     const bool dev = h->prm.precision == FR_DVM_FP32_DEV && collide;
-    if (dev && (rc = elem_ref(h))) return rc;
+    const bool ssp = h->prm.rk == FR_DVM_SSPRK3;
+    if (dev) {
+        h->cur_ref = h->prev_ref = h->u0_ref = 0;
+        if ((rc = elem_ref(h))) return rc;
+    }
+    bool fn_dev = false;  // (SSP) f holds the step's initial value as deviations
     const bool split = h->prm.overlap && h->axis_mode && collide && !dev && h->ne >= 2 && newton_part_ok(h, guess);
     if (split && (rc = ensure_aux(h))) return rc;
     const int64_t eh[3] = {0, h->ne / 2, h->ne};
@@ -187,15 +194,20 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
         if (!split && k > 0 && collide) {
             if ((rc = launch_newton(h, guess))) return rc;
             if (dev) {
-                h->cur_ref ^= 1;
+                h->prev_ref = h->cur_ref;
+                int c = 0;
+                while (c == h->prev_ref || (ssp && fn_dev && c == h->u0_ref)) ++c;
+                h->cur_ref = c;
                 if ((rc = elem_ref(h))) return rc;
             }
         }
         StageArgs a = stage_args(h, f, dt, st, collide);
         a.in_dev = dev && k > 0;
         a.out_dev = dev && !last;
+        a.fn_dev = dev && fn_dev;
         a.ref_cur = h->d_ref[h->cur_ref];
-        a.ref_prev = k > 0 ? h->d_ref[h->cur_ref ^ 1] : a.ref_cur;
+        a.ref_prev = h->d_ref[h->prev_ref];
+        a.ref_u0 = h->d_ref[h->u0_ref];
         if (!split) {
             ProfScope ps(h, 0);
             if ((rc = launch_fr(h, 1, a, traces, moments))) return rc;
@@ -220,6 +232,11 @@ extern "C" int fr_dvm_rk_steps(fr_dvm_t h, void *f, double dt, int nsteps) {
             }
         }
         h->cur_tr ^= 1;
+        // the result of a step's last stage is the next step's initial value
+        if (dev && st == 2) {
+            fn_dev = !last;
+            h->u0_ref = h->cur_ref;
+        }
     }
     return FR_DVM_OK;
 }

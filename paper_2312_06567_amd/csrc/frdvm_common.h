@@ -152,8 +152,11 @@ struct fr_dvm {
     int cur_tr = 0;
     double *d_Q = nullptr;       // [ne*ns][nmom]
     double *d_eq = nullptr;      // [ne*ns][kEqW]
-    double *d_ref[2] = {nullptr, nullptr};  // [ne][kRefW] element references (FP32 deviation storage),
-    int cur_ref = 0;                         // this stage's and the previous stage's, alternating
+    // [ne][kRefW] element references (FP32 deviation storage): three sets,
+    // those of the value read by a stage, of its result, and (SSP) of the
+    // step's initial value
+    double *d_ref[3] = {nullptr, nullptr, nullptr};
+    int cur_ref = 0, prev_ref = 0, u0_ref = 0;
     double *d_z = nullptr;       // [ne*ns][5] Newton solution (warm start)
     double *d_prim = nullptr;    // [ne*ns][5] primitive state of g(Q')
     int zvalid = 0;
@@ -230,9 +233,10 @@ struct StageArgs {
     // inflow traces are read as deviations from the element references of
     // the previous stage's records (in_dev; else plain, made relative here)
     // and the result written as the deviation from the element's reference
-    // of this stage's records (out_dev; else plain)
-    const double *ref_prev, *ref_cur;  // [ne][kRefW]
-    int in_dev, out_dev;
+    // of this stage's records (out_dev; else plain); SSP: the step's initial
+    // value fn relative to ref_u0 (fn_dev; else plain)
+    const double *ref_prev, *ref_cur, *ref_u0;  // [ne][kRefW]
+    int in_dev, out_dev, fn_dev;
     uint32_t seed;           // random bits of the stage's stochastic rounding of FP32 state values
     int64_t e0, ecount;      // element range [e0, e0 + ecount); ecount 0: all elements
 };

@@ -316,12 +316,14 @@ k_fr_layer(const FrArgs A) {
                   "deviation storage: FP32 monatomic stage kernel");
     const bool in_dev = ER && A.sa.in_dev;
     const bool out_dev = ER && A.sa.out_dev;
-    __shared__ __attribute__((aligned(16))) double s_ref[ER ? 8 * kRefCoef : 1];  // own prev, own cur, 6 faces
+    // own prev, own cur, 6 faces' prev, own reference of the step's initial value (SSP)
+    __shared__ __attribute__((aligned(16))) double s_ref[ER ? 9 * kRefCoef : 1];
     if (ER) {
-        for (int t = tid; t < 8 * kRefCoef; t += NT) {
+        for (int t = tid; t < 9 * kRefCoef; t += NT) {
             const int r = t / kRefCoef;
-            const int64_t er = r < 2 ? e : (int64_t)A.nbr[6 * e + r - 2];
-            s_ref[t] = (r == 1 ? A.sa.ref_cur : A.sa.ref_prev)[er * kRefW + t % kRefCoef];
+            const int64_t er = (r < 2 || r == 8) ? e : (int64_t)A.nbr[6 * e + r - 2];
+            const double *src = r == 1 ? A.sa.ref_cur : (r == 8 ? A.sa.ref_u0 : A.sa.ref_prev);
+            s_ref[t] = src[er * kRefW + t % kRefCoef];
         }
     }
 
@@ -437,11 +439,19 @@ k_fr_layer(const FrArgs A) {
         // reference, or plain in the first stage) into one relative to rp.
         // References are FP32 numbers: the difference of two within a factor
         // 2 of each other is exact in FP32 (consecutive stages' references
-        // of an element are), and rounded once otherwise.
+        // of an element are), and rounded once otherwise.  SSP adds the
+        // step's initial value fn (relative to its reference r0) with weight
+        // alpha: shd = alpha r0 + beta rp - rc, in FP64.
         float rp = 0.0f, sh = 0.0f, dl[3] = {0.0f, 0.0f, 0.0f};
+        double shd = 0.0;
         if (ER) {
             rp = ref_value(ref_exponent(&s_ref[0], v.u));
-            sh = out_dev ? rp - ref_value(ref_exponent(&s_ref[kRefCoef], v.u)) : rp;
+            const float rc = out_dev ? ref_value(ref_exponent(&s_ref[kRefCoef], v.u)) : 0.0f;
+            sh = rp - rc;
+            if (A.sa.scheme == 0) {
+                const double r0 = A.sa.fn_dev ? (double)ref_value(ref_exponent(&s_ref[8 * kRefCoef], v.u)) : 0.0;
+                shd = fma(A.sa.alpha, r0, fma(A.sa.beta, (double)rp, -(double)rc));
+            }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const int slot = 2 + 2 * d + (v.sgn[d] > 0 ? 0 : 1);  // the upwind neighbour in direction d
@@ -598,7 +608,7 @@ k_fr_layer(const FrArgs A) {
                         if constexpr (KEEP) stb(dFE, o + q * QB, (SReal)dd);
                         fod = fma(A.sa.lsB, (double)dd, (double)fq);
                     }
-                    if (ER) fod += (double)sh;
+                    if constexpr (ER) fod += LSRK ? (double)sh : shd;
                     Real fo;
                     if constexpr (sizeof(Real) == 4) {
                         rs = xorshift32(rs);
@@ -614,7 +624,7 @@ k_fr_layer(const FrArgs A) {
                 }
             };
             if constexpr (STAGE) {
-                if (!ER && A.sa.scheme == 0) {
+                if (A.sa.scheme == 0) {
                     if (collide) points(BoolC<true>{}, BoolC<false>{}, BoolC<false>{});
                     else points(BoolC<false>{}, BoolC<false>{}, BoolC<false>{});
                 } else if (A.sa.keep_dF) {

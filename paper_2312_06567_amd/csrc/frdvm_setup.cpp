@@ -644,11 +644,9 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
     if (p->model < 0 || p->model > 2) return h->fail(FR_DVM_EINVAL, "unknown model");
     if (p->precision != FR_DVM_FP64 && p->precision != FR_DVM_FP32 && p->precision != FR_DVM_FP32_DEV)
         return h->fail(FR_DVM_EINVAL, "unknown precision");
-    if (p->precision == FR_DVM_FP32_DEV &&
-        (!h->axis_mode || p->positivity || h->ncomp != 1 || p->rk != FR_DVM_LSRK3_2N))
+    if (p->precision == FR_DVM_FP32_DEV && (!h->axis_mode || p->positivity || h->ncomp != 1))
         return h->fail(FR_DVM_EUNSUPPORTED,
-                       "FP32 deviation storage needs a periodic box mesh, a monatomic gas, the low-storage RK "
-                       "scheme and no positivity limiter");
+                       "FP32 deviation storage needs a periodic box mesh, a monatomic gas and no positivity limiter");
     if (p->model == FR_DVM_ESBGK && !(p->prandtl > 0)) return h->fail(FR_DVM_EINVAL, "Prandtl number must be positive");
     if (!(p->mu_ref > 0) && p->model != FR_DVM_FREE) return h->fail(FR_DVM_EINVAL, "mu_ref must be positive");
     if (p->newton_max_iter < 1 || p->newton_max_iter > 200) return h->fail(FR_DVM_EINVAL, "newton_max_iter out of range");
@@ -692,9 +690,9 @@ extern "C" int fr_dvm_set_params(fr_dvm_t h, const fr_dvm_params *p) {
             h->owned_bytes += trn * tes;
         }
         if ((rc = dev_alloc(h, &h->d_eq, npts * kEqW))) return rc;
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < 3; ++b)
             if ((rc = dev_alloc(h, &h->d_ref[b], p->precision == FR_DVM_FP32_DEV ? h->ne * kRefW : 0))) return rc;
-        h->cur_ref = 0;
+        h->cur_ref = h->prev_ref = h->u0_ref = 0;
         if ((rc = dev_alloc(h, &h->d_z, npts * 5))) return rc;
         if ((rc = dev_alloc(h, &h->d_prim, npts * 5))) return rc;
         if ((rc = dev_alloc(h, &h->d_pt_iters, npts))) return rc;
@@ -817,7 +815,7 @@ extern "C" void fr_dvm_destroy(fr_dvm_t h) {
     if (h->stream) hipStreamSynchronize(h->stream); else hipDeviceSynchronize();
     free_mixed(h);
     void *ptrs[] = {h->d_gfac, h->d_nbr, h->d_wq3J, h->d_wx3, h->d_wrow, h->d_wax, h->d_reg, h->d_tr[0], h->d_tr[1],
-                    h->d_Q, h->d_eq, h->d_ref[0], h->d_ref[1], h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
+                    h->d_Q, h->d_eq, h->d_ref[0], h->d_ref[1], h->d_ref[2], h->d_z, h->d_prim, h->d_stats, h->d_maxres, h->d_tot, h->d_mlp,
                     h->d_mlp_x, h->d_mlp_work, h->d_mlp_dz, h->d_pt_iters, h->d_pt_evals, h->d_pt_status,
                     h->d_pt_resid, h->d_S, h->d_ijac, h->d_nf, h->d_conn, h->d_wall, h->d_rw, h->d_mw,
                     h->d_finf, h->d_Sf, h->d_ijacf, h->d_nff, h->d_gfp};

@@ -17,7 +17,7 @@ velocities.
     the conservative equilibrium).
 (c) FP32 deviation storage (FP32 f buffers and FR/RK arithmetic on the
     deviation of f from an element reference equilibrium, FP64 moments and
-    Newton), low-storage RK, warm start: five steps.  On this state, whose
+    Newton), low-storage RK and SSP-RK3, warm start: five steps.  On this state, whose
     2^3 elements each span half the Taylor-Green period and carry 5 % noise,
     the deviations are a large fraction of f: bounds f 1e-7 and moments
     5e-8, each error below 0.6x the FP32 path's on the same state (measured
@@ -28,8 +28,8 @@ velocities.
     in FP32 (the call returns f rounded once, stochastically: sqrt(2) times
     the spread of rounding to nearest; the errors made inside the call add
     little to that).
-(b) FP32 storage and operators, low-storage RK, FP64 moments and Newton,
-    warm start: five steps.  Bounds: f to 5e-7 relative L2 and the moments
+(b) FP32 storage and operators, low-storage RK and SSP-RK3, FP64 moments
+    and Newton, warm start: five steps.  Bounds: f to 5e-7 relative L2 and the moments
     rho, rho U and E to 3e-7 relative L2 per field.  Each of the 15 stages
     rounds f (and the low-storage register) to FP32, 2^-24 = 6e-8 relative
     per value, and forms its update in FP32; the collision relaxes the
@@ -92,15 +92,15 @@ def test_fp64_ssprk3_stage_matches_oracle(F, orc, gi):
     assert err < 1e-12, err
 
 
-@pytest.mark.parametrize("gi", [0, 1])
-def test_fp32_lsrk_stage_bounds(F, orc, gi):
+@pytest.mark.parametrize("gi,rk", [(0, 1), (1, 1), (0, 0)])
+def test_fp32_stage_bounds(F, orc, gi, rk):
     grid = GRIDS[gi]
     mesh, par, f0 = _case(grid)
     f0 = f0.astype(np.float32).astype(np.float64)
-    s = F.FrDvm(mesh, HEADLINE["p"], grid, dict(par, precision=1, rk=1, guess=1))
+    s = F.FrDvm(mesh, HEADLINE["p"], grid, dict(par, precision=1, rk=rk, guess=1))
     dt = _dt(s)
     P = orc.Problem(mesh, HEADLINE["p"], grid, par)
-    ref = P.rk_step(f0, dt, scheme=1, nsteps=5)
+    ref = P.rk_step(f0, dt, scheme=rk, nsteps=5)
     f = torch.as_tensor(f0, dtype=torch.float32).cuda().contiguous()
     s.newton_stats(reset=True)
     s.rk_steps(f, dt, 5)
@@ -115,14 +115,14 @@ def test_fp32_lsrk_stage_bounds(F, orc, gi):
     assert max(eq) < 3e-7, eq
 
 
-def _fp32_run(F, orc, gi, precision, case=None):
+def _fp32_run(F, orc, gi, precision, case=None, rk=1):
     grid = GRIDS[gi]
     mesh, par, f0 = case or _case(grid)
     f0 = f0.astype(np.float32).astype(np.float64)
-    s = F.FrDvm(mesh, HEADLINE["p"], grid, dict(par, precision=precision, rk=1, guess=1))
+    s = F.FrDvm(mesh, HEADLINE["p"], grid, dict(par, precision=precision, rk=rk, guess=1))
     dt = _dt(s)
     P = orc.Problem(mesh, HEADLINE["p"], grid, par)
-    ref = P.rk_step(f0, dt, scheme=1, nsteps=5)
+    ref = P.rk_step(f0, dt, scheme=rk, nsteps=5)
     f = torch.as_tensor(f0, dtype=torch.float32).cuda().contiguous()
     s.newton_stats(reset=True)
     s.rk_steps(f, dt, 5)
@@ -148,13 +148,13 @@ def _near_case(grid):
     return mesh, par, f0
 
 
-@pytest.mark.parametrize("gi", [0, 1])
-def test_fp32_deviation_storage_bounds(F, orc, gi):
-    P, ref, got = _fp32_run(F, orc, gi, F.FP32_DEV)
+@pytest.mark.parametrize("gi,rk", [(0, 1), (1, 1), (0, 0), (1, 0)])
+def test_fp32_deviation_storage_bounds(F, orc, gi, rk):
+    P, ref, got = _fp32_run(F, orc, gi, F.FP32_DEV, rk=rk)
     ef, eq = _errors(P, got, ref)
-    _, _, got32 = _fp32_run(F, orc, gi, F.FP32)
+    _, _, got32 = _fp32_run(F, orc, gi, F.FP32, rk=rk)
     ef32, eq32 = _errors(P, got32, ref)
-    print(f"grid {GRIDS[gi]['n']}: deviation storage f {ef:.2e}, moments {[f'{x:.2e}' for x in eq]}; "
+    print(f"grid {GRIDS[gi]['n']} rk {rk}: deviation storage f {ef:.2e}, moments {[f'{x:.2e}' for x in eq]}; "
           f"FP32 path f {ef32:.2e}, moments {[f'{x:.2e}' for x in eq32]}")
     assert ef < 1e-7, ef
     assert max(eq) < 5e-8, eq
@@ -162,17 +162,37 @@ def test_fp32_deviation_storage_bounds(F, orc, gi):
     assert all(a < 0.6 * b for a, b in zip(eq, eq32)), (eq, eq32)
 
 
-def test_fp32_deviation_storage_near_equilibrium(F, orc):
+@pytest.mark.parametrize("rk", [1, 0])
+def test_fp32_deviation_storage_near_equilibrium(F, orc, rk):
     case = _near_case(GRIDS[0])
-    P, ref, got = _fp32_run(F, orc, 0, F.FP32_DEV, case)
+    P, ref, got = _fp32_run(F, orc, 0, F.FP32_DEV, case, rk=rk)
     ef, eq = _errors(P, got, ref)
-    _, _, got32 = _fp32_run(F, orc, 0, F.FP32, case)
+    _, _, got32 = _fp32_run(F, orc, 0, F.FP32, case, rk=rk)
     ef32, eq32 = _errors(P, got32, ref)
     # the floor: the oracle's own result rounded once to FP32
     ff, fq = _errors(P, ref.astype(np.float32).astype(np.float64), ref)
-    print(f"near equilibrium: deviation storage f {ef:.2e}, moments {[f'{x:.2e}' for x in eq]}; "
+    print(f"near equilibrium, rk {rk}: deviation storage f {ef:.2e}, moments {[f'{x:.2e}' for x in eq]}; "
           f"FP32 path f {ef32:.2e}, moments {[f'{x:.2e}' for x in eq32]}; "
           f"one FP32 rounding f {ff:.2e}, moments {[f'{x:.2e}' for x in fq]}")
     assert ef < 1e-7, ef
     assert all(a < 0.5 * b for a, b in zip(eq, eq32)), (eq, eq32)
     assert all(a < 2.5 * b for a, b in zip(eq, fq)), (eq, fq)
+
+
+@pytest.mark.parametrize("rk", [1, 0])
+def test_deviation_storage_bitwise_reproducible(F, rk):
+    """Two calls from the same state give the same bits (parameters set again
+    in between: the stage seeds of the stochastic rounding start over), with
+    calls of one and of several steps (the reference sets rotate)."""
+    mesh, par, f0 = _case(GRIDS[1])
+    pr = dict(par, precision=F.FP32_DEV, rk=rk, guess=0)
+    s = F.FrDvm(mesh, HEADLINE["p"], GRIDS[1], pr)
+    dt = _dt(s)
+    runs = []
+    for _ in range(2):
+        s.set_params(**pr)
+        f = torch.as_tensor(f0, dtype=torch.float32).cuda().contiguous()
+        s.rk_steps(f, dt, 1)
+        s.rk_steps(f, dt, 3)
+        runs.append(f)
+    assert torch.equal(runs[0], runs[1])

@@ -306,9 +306,7 @@ def test_invalid_inputs_raise(F):
         s.residual(f, f)  # aliasing output
     with pytest.raises(F.FrDvmError):
         s.rk_step(f.float(), 1e-3)  # wrong precision
-    # FP32 deviation storage: box meshes, low-storage RK, monatomic, no limiter
-    with pytest.raises(F.FrDvmError):
-        s.set_params(**_params(precision=F.FP32_DEV, rk=0))
+    # FP32 deviation storage: box meshes, monatomic, no limiter
     with pytest.raises(F.FrDvmError):
         s.set_params(**_params(precision=F.FP32_DEV, rk=1, positivity=1))
     with pytest.raises(F.FrDvmError):
