@@ -108,21 +108,41 @@ __device__ __forceinline__ double exp_r<double>(double E) {
     return exp_f64(E);
 }
 
-// Exponent of a point's equilibrium at velocity u: c0 - (u-V)^T B (u-V)/2
-// from the staged form b = (-B_xx/2, -B_yy/2, -B_zz/2, -B_xy, -B_xz, -B_yz,
-// c0).
-__device__ __forceinline__ double eq_exponent(double b0, double b1, double b2, double b3, double b4, double b5,
-                                              double b6, double V0, double V1, double V2, const double u[3]) {
-    const double c0 = u[0] - V0, c1 = u[1] - V1, c2 = u[2] - V2;
-    double t0 = b0 * c0;
-    t0 = fma(b3, c1, t0);
-    t0 = fma(b4, c2, t0);
-    double t1 = b1 * c1;
-    t1 = fma(b5, c2, t1);
-    const double t2 = b2 * c2;
-    double E = fma(c0, t0, b6);
-    E = fma(c1, t1, E);
-    return fma(c2, t2, E);
+// Coefficient c (in the order of ref_exponent) of the exponent of an
+// equilibrium record, c0 - (u-V)^T B (u-V)/2, as a polynomial in u.
+__device__ __forceinline__ double ref_coef(const double *q, int c) {
+    const double Bxx = q[EQ_B], Byy = q[EQ_B + 1], Bzz = q[EQ_B + 2];
+    const double Bxy = q[EQ_B + 3], Bxz = q[EQ_B + 4], Byz = q[EQ_B + 5];
+    const double Vx = q[EQ_V], Vy = q[EQ_V + 1], Vz = q[EQ_V + 2];
+    const double bx = Bxx * Vx + Bxy * Vy + Bxz * Vz;  // B V: the linear coefficients
+    const double by = Bxy * Vx + Byy * Vy + Byz * Vz;
+    const double bz = Bxz * Vx + Byz * Vy + Bzz * Vz;
+    switch (c) {
+        case 0: return q[EQ_C0] - 0.5 * (Vx * bx + Vy * by + Vz * bz);
+        case 1: return bx;
+        case 2: return by;
+        case 3: return bz;
+        case 4: return -0.5 * Bxx;
+        case 5: return -0.5 * Byy;
+        case 6: return -0.5 * Bzz;
+        case 7: return -Bxy;
+        case 8: return -Bxz;
+        default: return -Byz;
+    }
+}
+
+// The exponent of a staged record at velocity u: the polynomial of
+// ref_exponent with the constant term c0 given.
+__device__ __forceinline__ double eq_exponent(const double *c, double c0, const double u[3]) {
+    double tx = fma(c[4], u[0], c[1]);
+    tx = fma(c[7], u[1], tx);
+    tx = fma(c[8], u[2], tx);
+    double ty = fma(c[5], u[1], c[2]);
+    ty = fma(c[9], u[2], ty);
+    const double tz = fma(c[6], u[2], c[3]);
+    double E = fma(u[0], tx, c0);
+    E = fma(u[1], ty, E);
+    return fma(u[2], tz, E);
 }
 
 
@@ -293,12 +313,13 @@ k_fr_layer(const FrArgs A) {
     Real *const tP = tZ + TZ_;
     double *const red = reinterpret_cast<double *>(s_tiles);
     __shared__ __attribute__((aligned(16))) LdsTab<Real> T;
-    // equilibrium records staged per workgroup (b: the exponent's quadratic
-    // form, -1/2 B with doubled off-diagonal terms, c0, 1/tau; V), read with
-    // a wave-uniform address
+    // equilibrium records staged per workgroup: the exponent as a polynomial
+    // in u (10 coefficients), the G exponent shift (reduced pair), and 1/tau
+    // in the working precision, read with a wave-uniform address
     constexpr bool EQ_LDS = STAGE;
-    __shared__ __attribute__((aligned(16))) double s_eb[EQ_LDS ? NS * 8 : 1];
-    __shared__ __attribute__((aligned(16))) double s_ev[EQ_LDS ? NS * 4 : 1];
+    constexpr int kEb = 12;
+    __shared__ __attribute__((aligned(16))) double s_eb[EQ_LDS ? NS * kEb : 1];
+    __shared__ __attribute__((aligned(16))) Real s_it[EQ_LDS ? NS : 1];
 
     const OpsR<Real> &op = ops_of<Real>(A);
     const int64_t e = A.sa.e0 + blockIdx.x;
@@ -328,31 +349,22 @@ k_fr_layer(const FrArgs A) {
     }
 
     const bool collide = STAGE && A.sa.collide;
-    // equilibrium records of this wave's layer: c0, V, B, 1/tau per point,
-    // wave-uniform, read through the scalar cache (written by the previous
-    // launch)
-    cdouble *eqL = (cdouble *)(A.sa.eq + (e * NS + l * NL) * kEqW);
     if (EQ_LDS && collide) {
-        for (int s = tid; s < NS; s += NT) {
+        for (int t = tid; t < NS * kEb; t += NT) {
+            const int s = t / kEb, c = t % kEb;
             const double *q = A.sa.eq + (e * NS + s) * kEqW;
-            double *b = &s_eb[s * 8];
-            b[0] = -0.5 * q[EQ_B];
-            b[1] = -0.5 * q[EQ_B + 1];
-            b[2] = -0.5 * q[EQ_B + 2];
-            b[3] = -q[EQ_B + 3];
-            b[4] = -q[EQ_B + 4];
-            b[5] = -q[EQ_B + 5];
-            b[6] = q[EQ_C0];
-            b[7] = q[EQ_INVTAU];
-            s_ev[s * 4] = q[EQ_V];
-            s_ev[s * 4 + 1] = q[EQ_V + 1];
-            s_ev[s * 4 + 2] = q[EQ_V + 2];
-            if constexpr (NCOMP == 2) {
-                const double gf = A.gfp[e * NS + s];
-                s_ev[s * 4 + 3] = gf > 0.0 ? log(gf) : -1000.0;  // the G exponent shift
+            double v = 0.0;
+            if (c < kRefCoef) {
+                v = ref_coef(q, c);
+            } else if (c == kRefCoef) {
+                if constexpr (NCOMP == 2) {
+                    const double gf = A.gfp[e * NS + s];
+                    v = gf > 0.0 ? log(gf) : -1000.0;  // the G exponent shift
+                }
             } else {
-                s_ev[s * 4 + 3] = 0.0;
+                s_it[s] = (Real)q[EQ_INVTAU];
             }
+            s_eb[t] = v;
         }
     }
 
@@ -587,15 +599,14 @@ k_fr_layer(const FrArgs A) {
                     Real L = -r[q];
                     if constexpr (COLL) {
                         const int s = l * NL + q;
-                        const double *b = &s_eb[s * 8];
-                        const double *V = &s_ev[s * 4];
-                        const double b6 = (NCOMP == 2 && comp) ? b[6] + V[3] : b[6];
+                        const double *b = &s_eb[s * kEb];
+                        const double c0 = (NCOMP == 2 && comp) ? b[0] + b[kRefCoef] : b[0];
                         // the equilibrium's exponent at this point and velocity
-                        const double Eq = eq_exponent(b[0], b[1], b[2], b[3], b[4], b[5], b6, V[0], V[1], V[2], v.u);
+                        const double Eq = eq_exponent(b, c0, v.u);
                         if constexpr (ER)
-                            L += ((Real)(exp_f64(Eq) - (double)rp) - fq) * (Real)b[7];  // g - rp rounded once
+                            L += ((Real)(exp_f64(Eq) - (double)rp) - fq) * s_it[s];  // g - rp rounded once
                         else
-                            L += (exp_r<Real>(Eq) - fq) * (Real)b[7];
+                            L += (exp_r<Real>(Eq) - fq) * s_it[s];
                     }
                     // the result, in FP64 for the stochastic rounding of the FP32 state
                     double fod;
@@ -784,26 +795,6 @@ k_fr_layer(const FrArgs A) {
 constexpr int kRefBlock = 256;
 static_assert(kRefCoef + 10 <= kRefW, "element reference record: coefficients and up to 10 moments");
 
-__device__ __forceinline__ double ref_coef(const double *q, int c) {
-    const double Bxx = q[EQ_B], Byy = q[EQ_B + 1], Bzz = q[EQ_B + 2];
-    const double Bxy = q[EQ_B + 3], Bxz = q[EQ_B + 4], Byz = q[EQ_B + 5];
-    const double Vx = q[EQ_V], Vy = q[EQ_V + 1], Vz = q[EQ_V + 2];
-    const double bx = Bxx * Vx + Bxy * Vy + Bxz * Vz;  // B V: the linear coefficients
-    const double by = Bxy * Vx + Byy * Vy + Byz * Vz;
-    const double bz = Bxz * Vx + Byz * Vy + Bzz * Vz;
-    switch (c) {
-        case 0: return q[EQ_C0] - 0.5 * (Vx * bx + Vy * by + Vz * bz);
-        case 1: return bx;
-        case 2: return by;
-        case 3: return bz;
-        case 4: return -0.5 * Bxx;
-        case 5: return -0.5 * Byy;
-        case 6: return -0.5 * Bzz;
-        case 7: return -Bxy;
-        case 8: return -Bxz;
-        default: return -Byz;
-    }
-}
 
 template <int NMOM>
 __global__ __launch_bounds__(kRefBlock) void k_elem_ref(const FrArgs A, int ns, double *__restrict__ ref) {
