@@ -292,18 +292,34 @@ __global__ __launch_bounds__(kGBlock) void k_gen_wall(const GenArgs A, const Rea
 }
 
 // One wave per (element, 64 velocities).  Each lane keeps its velocity's N^3
-// stage values and residual accumulators in its own LDS column (lane-private:
-// no barrier between the phases), so the loops over source points and flux
-// points stay rolled and the registers hold only the current line.  (With the
-// accumulators in registers and the direction loop unrolled, p = 2 needs 175
-// VGPRs in FP32 and p = 3 all 256 with scratch: no occupancy is gained.)
+// residual accumulators in its own LDS column (lane-private: no barrier
+// between the phases), and its N^3 stage values in registers (p <= 2: the
+// loops over directions, lines and flux points unrolled, so every value has
+// a fixed register; the LDS left per wave admits 3 (FP32) / 2 (FP64) waves
+// per SIMD, which the register target matches) or in a second LDS column
+// (p = 3: loops rolled, the registers holding only the current line).  (With the accumulators in
+// registers and the direction loop unrolled, p = 2 needs 175 VGPRs in FP32
+// and p = 3 all 256 with scratch: no occupancy is gained.)
+template <typename Real, int P>
+constexpr bool gen_freg() {
+    return P <= 2;
+}
 template <typename Real, int P, int MODE>
-__global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
+__global__ __launch_bounds__(kGWave) __attribute__((amdgpu_waves_per_eu(gen_freg<Real, P>() ? (sizeof(Real) == 4 ? 3 : 2) : 1))) void
+k_gen_stage(const GenArgs A) {
     constexpr int N = P + 1, NS = N * N * N, NFP = N * N;
     constexpr bool STAGE = MODE == GMODE_STAGE;
     constexpr int CHF = NS <= 27 ? NS : 2 * NFP;  // values requested together
-    constexpr bool EARLY_X = STAGE && NS <= 27;
-    __shared__ Real sf[NS][kGWave];
+    constexpr bool FREG = gen_freg<Real, P>();
+    constexpr bool EARLY_X = STAGE && NS <= 27 && !FREG;
+    constexpr int UNR = FREG ? 64 : 1;  // unroll of the loops that index the stage values
+    __shared__ Real sf[FREG ? 1 : NS][kGWave];
+    Real fv[FREG ? NS : 1];
+    // the lane's stage value at point s (s a compile-time index where FREG)
+    auto F = [&](int s) -> Real & {
+        if constexpr (FREG) return fv[s];
+        else return sf[s][threadIdx.x];
+    };
     __shared__ Real sa[NS][kGWave];
     __shared__ double sEb[STAGE ? NS * 8 : 1];
     __shared__ double sEv[STAGE ? NS * 3 : 1];
@@ -353,7 +369,7 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
 #pragma unroll
         for (int r = 0; r < CHF; ++r) v[r] = ldo(fe + (s0 + r) * nu, ko);
 #pragma unroll
-        for (int r = 0; r < CHF; ++r) sf[s0 + r][lane] = v[r];
+        for (int r = 0; r < CHF; ++r) F(s0 + r) = v[r];
     }
     // the second RK register of the stage, requested now (p <= 2) so that
     // the FR work covers its latency
@@ -371,8 +387,13 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     // is then written once per direction (the first direction initialises
     // it), so no accumulator waits on another update of itself.
     const Real *tin = reinterpret_cast<const Real *>(A.sa.tr_in);
-#pragma unroll 1
+#pragma unroll UNR
     for (int d = 0; d < 3; ++d) {
+        if constexpr (FREG) {
+            // one direction's exterior values in registers at a time
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+        }
         // the exterior values of both faces of the axis, requested together
         Real un[2][NFP], ext[2][NFP];
 #pragma unroll
@@ -418,7 +439,7 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
 #pragma unroll
             for (int m = 0; m < N; ++m) {
                 pts[m] = line_pt<N>(d, a, b, m);
-                fl[m] = sf[pts[m]][lane];
+                fl[m] = F(pts[m]);
                 const cptr<Real> Sm = gS + pts[m] * 9 + 3 * d;
                 Fd[m] = (Sm[0] * u0 + Sm[1] * u1 + Sm[2] * u2) * fl[m];
             }
@@ -471,7 +492,7 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
 #pragma unroll
         for (int r = 0; r < NFP; ++r) {
             const int s = s0 + r;
-            const Real fq = sf[s][lane];
+            const Real fq = F(s);
             Real L = -sa[s][lane] * gJ[s];
             if (collide) {
                 const double *bq = &sEb[s * 8];
@@ -503,13 +524,26 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
                 fo = round_stochastic(fod, round_bits(A.sa.seed, (uint32_t)(e * NS + s), (uint32_t)k));
             else
                 fo = (Real)fod;
-            sf[s][lane] = fo;
+            F(s) = fo;
             sto(outE + s * nu, ko, fo);
-            if (limit) {
-                lim_int = fma(gW[s], (double)fo, lim_int);
-                lim_w += gW[s];
-                lim_min = s == 0 ? fo : (fo < lim_min ? fo : lim_min);
+            if constexpr (FREG) {
+                // two points' chains in flight at a time
+                if (r % 2 == 1) {
+                    asm volatile("" ::: "memory");
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
+        }
+    }
+    if (limit) {
+        // the result's element integral and smallest value at the solution points
+#pragma unroll UNR
+        for (int s = 0; s < NS; ++s) {
+            Real fo = F(s);
+            asm volatile("" : "+v"(fo));  // (converted here, not kept in FP64 from the stage loop)
+            lim_int = fma(gW[s], (double)fo, lim_int);
+            lim_w += gW[s];
+            lim_min = s == 0 ? fo : (fo < lim_min ? fo : lim_min);
         }
     }
     // Traces of the result at every flux point; with the positivity limiter
@@ -521,15 +555,20 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     // the values and traces again.
     Real *te = reinterpret_cast<Real *>(A.sa.tr_out) + e * 6 * NFP * nu;
     auto trace_pass = [&](bool store, bool find_min) {
-#pragma unroll 1
+#pragma unroll UNR
         for (int face = 0; face < 6; ++face) {
             const int d = face / 2, side = face & 1;
-#pragma unroll 1
+            if constexpr (FREG) {
+                // one face's traces in registers at a time
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll UNR
             for (int q = 0; q < NFP; ++q) {
                 const int a = q % N, b = q / N;
                 Real t = Real(0);
 #pragma unroll
-                for (int m = 0; m < N; ++m) t += op.lam[side][m] * sf[line_pt<N>(d, a, b, m)][lane];
+                for (int m = 0; m < N; ++m) t += op.lam[side][m] * F(line_pt<N>(d, a, b, m));
                 if (store) sto(te + (face * NFP + q) * nu, ko, t);
                 if (find_min) lim_min = t < lim_min ? t : lim_min;
             }
@@ -539,10 +578,10 @@ __global__ __launch_bounds__(kGWave) void k_gen_stage(const GenArgs A) {
     if (limit && lim_min < Real(0)) {
         const double mean = lim_int / lim_w;
         const double th = mean > 0.0 ? mean / (mean - (double)lim_min) : 0.0;
-#pragma unroll 1
+#pragma unroll UNR
         for (int s = 0; s < NS; ++s) {
-            const Real v = (Real)fma(th, (double)sf[s][lane] - mean, mean);
-            sf[s][lane] = v;
+            const Real v = (Real)fma(th, (double)F(s) - mean, mean);
+            F(s) = v;
             sto(outE + s * nu, ko, v);
         }
         if (A.do_traces) trace_pass(true, false);
