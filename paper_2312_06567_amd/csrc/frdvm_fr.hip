@@ -251,6 +251,12 @@ __device__ __forceinline__ TraceOff trace_in(const FrArgs &A, const LdsTab<Real>
     return t;
 }
 
+// A value the compiler cannot see through (nor hoist out of a loop).
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // Keeps the compiler from moving memory accesses (and the scheduler from
 // moving anything) across this point: bounds how many LDS values are in
 // registers at once.
@@ -430,6 +436,10 @@ k_fr_layer(const FrArgs A) {
     }
 
     for (int cc = 0; cc < ntot; ++cc) {
+        // the lane's tile column, recomputed every chunk: tile addresses are
+        // then formed from it with immediate offsets instead of being kept
+        // in registers across the loop
+        const int vt = opaque(vl);
         const int comp = NCOMP == 2 && cc >= nchunk ? 1 : 0;
         const int ch = cc - comp * nchunk;
         const Vel v = velocity(A, ch * kChunk + vl, true);
@@ -473,10 +483,10 @@ k_fr_layer(const FrArgs A) {
         }
 #pragma unroll
         for (int q = 0; q < NL; ++q)
-            tpub[tix<Real>(l * NL + q, vl)] = (ER && !in_dev) ? (Real)fc[q] - (Real)rp : (Real)fc[q];
+            tpub[tix<Real>(l * NL + q, vt)] = (ER && !in_dev) ? (Real)fc[q] - (Real)rp : (Real)fc[q];
         if (FLUX) {
 #pragma unroll
-            for (int a = 0; a < N; ++a) tZ[tix<Real>(N * l + a, vl)] = ER ? TZ[a] + (Real)dl[2] : TZ[a];
+            for (int a = 0; a < N; ++a) tZ[tix<Real>(N * l + a, vt)] = ER ? TZ[a] + (Real)dl[2] : TZ[a];
         }
         TraceOff nx{0u, 0u}, ny{0u, 0u};
         // the next chunk (possibly the first of the next component)
@@ -528,7 +538,7 @@ k_fr_layer(const FrArgs A) {
                 for (int a = 0; a < N; ++a) {
                     Real g[N];
 #pragma unroll
-                    for (int m = 0; m < N; ++m) g[m] = tS[tix<Real>(l * NL + (d == 0 ? m + N * a : a + N * m), vl)];
+                    for (int m = 0; m < N; ++m) g[m] = tS[tix<Real>(l * NL + (d == 0 ? m + N * a : a + N * m), vt)];
                     Real fm = Real(0);
 #pragma unroll
                     for (int m = 0; m < N; ++m) fm += T.lam[sin_][m] * g[m];
@@ -561,14 +571,14 @@ k_fr_layer(const FrArgs A) {
                     const Real cm = az * T.D[l * N + m] - cz * T.lam[zin][m];
 #pragma unroll
                     for (int q = 0; q < NL; ++q) {
-                        r[q] = fma(cm, tS[tix<Real>(m * NL + q, vl)], r[q]);
+                        r[q] = fma(cm, tS[tix<Real>(m * NL + q, vt)], r[q]);
                         keep(r[q]);
                     }
                     phase_fence();
                 }
 #pragma unroll
                 for (int q = 0; q < NL; ++q) {
-                    const Real fp = zflow ? tZ[tix<Real>(q, vl)] : Real(0);
+                    const Real fp = zflow ? tZ[tix<Real>(q, vt)] : Real(0);
                     r[q] = fma(cz, fp, r[q]);
                 }
                 phase_fence();
@@ -595,7 +605,7 @@ k_fr_layer(const FrArgs A) {
                 constexpr bool KEEP = decltype(keep_c)::value;
 #pragma unroll
                 for (int q = 0; q < NL; ++q) {
-                    const Real fq = tS[tix<Real>(l * NL + q, vl)];
+                    const Real fq = tS[tix<Real>(l * NL + q, vt)];
                     Real L = -r[q];
                     if constexpr (COLL) {
                         const int s = l * NL + q;
@@ -670,7 +680,7 @@ k_fr_layer(const FrArgs A) {
                         } else {
 #pragma unroll
                             for (int m = 0; m < N; ++m)
-                                t += T.lam[side][m] * tpub[tix<Real>(l * NL + (d == 0 ? m + N * a : a + N * m), vl)];
+                                t += T.lam[side][m] * tpub[tix<Real>(l * NL + (d == 0 ? m + N * a : a + N * m), vt)];
                         }
                         tp[a * cnt] = t;
                     }
@@ -682,7 +692,7 @@ k_fr_layer(const FrArgs A) {
         if (A.do_moments || A.do_traces) {
             if (FLUX) {
 #pragma unroll
-                for (int q = 0; q < NL; ++q) tP[tix<Real>(l * NL + q, vl)] = f[q];
+                for (int q = 0; q < NL; ++q) tP[tix<Real>(l * NL + q, vt)] = f[q];
             }
             __syncthreads();  // the produced tile is complete (and the stage tile no longer read)
             if (A.do_traces && v.sgn[2] != 0) {
@@ -698,7 +708,7 @@ k_fr_layer(const FrArgs A) {
                     const int q = i + N * l;
                     Real t = Real(0);
 #pragma unroll
-                    for (int m = 0; m < N; ++m) t += T.lam[side][m] * tout[tix<Real>(m * NL + q, vl)];
+                    for (int m = 0; m < N; ++m) t += T.lam[side][m] * tout[tix<Real>(m * NL + q, vt)];
                     tp[i * cnt] = t;
                 }
             }
@@ -722,7 +732,7 @@ k_fr_layer(const FrArgs A) {
 #pragma unroll
                 for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
                 for (int j = 0; j < jn; ++j) {
-                    const double x = (double)tout[tix<Real>(vl, j0 + j)];
+                    const double x = (double)tout[tix<Real>(vt, j0 + j)];
                     a0 = fma(wx3[3 * ix], x, a0);
                     a1 = fma(wx3[3 * ix + 1], x, a1);
                     a2 = fma(wx3[3 * ix + 2], x, a2);
