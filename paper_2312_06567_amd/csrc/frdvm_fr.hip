@@ -488,6 +488,18 @@ k_fr_layer(const FrArgs A) {
 #pragma unroll
             for (int a = 0; a < N; ++a) tZ[tix<Real>(N * l + a, vt)] = ER ? TZ[a] + (Real)dl[2] : TZ[a];
         }
+        // the second RK register of this chunk, requested before the next
+        // chunk's values (loads complete in order: waiting for these in the
+        // collision then leaves the next chunk's loads in flight) and before
+        // the x/y/z passes, which cover its latency
+        SReal X[NL];
+        if (useX) {
+#pragma unroll
+            for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NL; ++q) X[q] = SReal(0);
+        }
         TraceOff nx{0u, 0u}, ny{0u, 0u};
         // the next chunk (possibly the first of the next component)
         const int compn = NCOMP == 2 && cc + 1 >= nchunk ? 1 : 0;
@@ -505,16 +517,6 @@ k_fr_layer(const FrArgs A) {
 #pragma unroll
                 for (int a = 0; a < N; ++a) TZ[a] = ldb(trEn, nz.off + a * nz.stride);
             }
-        }
-        // the second RK register of this chunk, requested before the x/y/z
-        // passes so that they cover its latency
-        SReal X[NL];
-        if (useX) {
-#pragma unroll
-            for (int q = 0; q < NL; ++q) X[q] = ldb(XE, o + q * QB);
-        } else {
-#pragma unroll
-            for (int q = 0; q < NL; ++q) X[q] = SReal(0);
         }
         if (FLUX) __syncthreads();  // the chunk's stage value of every layer is in the tile
         Real f[NL];  // the produced value (stage and residual modes)
