@@ -45,6 +45,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {0: 78.6, 1: 157.3}  # MI355X vector FP64 / FP32
 
 # The mixed storage form of the compare mode (precision code of fr_dvm_params):
 # FR_DVM_FP32_DEV, f held in FP32 as its deviation from an element reference
@@ -257,14 +258,42 @@ def roofline(r, p, workload, general=False):
         # bandwidth the launches actually drew: counted bytes over the live time
         out["counted_GBps"] = t["bytes_per_launch"] / (avg_ms / 1e3) / 1e9
         out["frac_counted"] = out["counted_GBps"] / HBM_PEAK_GBS
+    # the FR operators (interpolation, derivative, correction) as flops: the
+    # sum-factorised algorithm the kernel runs, and the dense-operator form
+    # (derivative, lifting and face interpolation as dense products) that an
+    # MFMA formulation would execute
+    fpd = fr_operator_flops_per_dof(p)
+    dofs = r["dof"] * r.get("ncomp", 1)
+    out["fr_operator_flops"] = {
+        "sum_factorised_per_dof": fpd, "dense_per_dof": fr_dense_flops_per_dof(p),
+        "achieved_TFLOPs": fpd * dofs / (avg_ms / 1e3) / 1e12,
+        "frac_of_vector_peak": fpd * dofs / (avg_ms / 1e3) / 1e12 / VALU_PEAK_TFLOPS[0 if r["precision"] == 0 else 1]}
     return out
+
+
+def fr_operator_flops_per_dof(p: int) -> float:
+    """Flops per DOF of the sum-factorised FR operators on a hexahedron of
+    N = p + 1 points per direction: per direction the derivative along the
+    point's line (N multiply-adds) and its metric scaling (one), the lifting
+    of the line's inflow jump (one), and per line the inflow-side trace (N)
+    and the jump (two flops), shared by the line's N points."""
+    n = p + 1
+    return 3.0 * (2 * n + 2 + 2 + (2 * n + 2) / n)
+
+
+def fr_dense_flops_per_dof(p: int) -> float:
+    """Flops per DOF of the same operators as dense products: per point
+    three [N_s x N_s] derivative rows, one [N_s x N_f] lifting row, and its
+    share of the [N_f x N_s] interpolation to the face points (N_s = N^3,
+    N_f = 6 N^2)."""
+    n = p + 1
+    return 2.0 * (3 * n ** 3 + 2 * 6 * n ** 2)
 
 
 # solution points and face points of each mixed-mesh element type at order p
 # (hexahedron, prism, tetrahedron)
 MIXED_SIZES = {1: ((8, 24), (6, 18), (4, 12)), 2: ((27, 54), (18, 39), (10, 24)),
                3: ((64, 96), (40, 68), (20, 40))}
-VALU_PEAK_TFLOPS = {0: 78.6, 1: 157.3}  # MI355X vector FP64 / FP32
 
 
 def mixed_flops_per_dof(mesh, p: int) -> float:

@@ -65,3 +65,13 @@ def test_byte_models():
     assert abs(bench.stage_bytes(3, 0, 0, n) / (3 * n) - 8 * 25 / 6) < 1e-2
     assert abs(bench.stage_bytes(3, 1, 1, n) / (3 * n) - 4 * 29 / 6) < 1e-2
     assert abs(bench.stage_bytes(3, 2, 1, n) / (3 * n) - 4 * 29 / 6) < 1e-2
+
+
+def test_operator_flop_models():
+    # p = 3 (N = 4): per direction 4 multiply-adds of the derivative, one of the
+    # metric scaling, one of the lifting, and a quarter of the line's trace
+    # (4 multiply-adds) and jump (2 flops): 14.5 flops, 43.5 over 3 directions;
+    # dense: 3 x 64 derivative + 96 lifting + 96 interpolation multiply-adds
+    assert bench.fr_operator_flops_per_dof(3) == 43.5
+    assert bench.fr_dense_flops_per_dof(3) == 768.0
+    assert bench.fr_dense_flops_per_dof(1) == 2.0 * (3 * 8 + 2 * 24)
