@@ -175,60 +175,71 @@ __global__ __launch_bounds__(kGBlock) void k_gen_traces(const GenArgs A, const R
     }
 }
 
-// k runs over the state of a point: F (k < nu), then the pair's G, which
-// adds only its integral (last slot of the record).
-template <int NMOM>
-__device__ __forceinline__ void moment_add(const GenArgs &A, int k, double fv, double M[NMOM]) {
-    int iv[3];
-    const bool g = k >= A.nu;
-    split_k(A.vg, g ? k - A.nu : k, iv);
-    const double x = fv * (A.wax[iv[0]] * A.wax[64 + iv[1]] * A.wax[128 + iv[2]]);
-    if constexpr (NMOM == 6 || NMOM == 11) {
-        if (g) {
-            M[NMOM - 1] += x;
-            return;
-        }
-    }
-    const double ux = node_u(A.vg, 0, iv[0]), uy = node_u(A.vg, 1, iv[1]), uz = node_u(A.vg, 2, iv[2]);
-    M[0] += x;
-    M[1] += x * ux;
-    M[2] += x * uy;
-    M[3] += x * uz;
-    if constexpr (NMOM == 5 || NMOM == 6) {
-        M[4] += 0.5 * x * (ux * ux + uy * uy + uz * uz);
-    } else {
-        M[4] += x * ux * ux;
-        M[5] += x * uy * uy;
-        M[6] += x * uz * uz;
-        M[7] += x * ux * uy;
-        M[8] += x * ux * uz;
-        M[9] += x * uy * uz;
-    }
+// Moments of one solution point over the velocity grid (FP64, fixed order).
+// Thread t of the workgroup takes the (x, y) nodes t, t + blockDim, ... and
+// walks each one's z column: the nodes of a z step are consecutive over the
+// threads (coalesced), and along the column only the z weight and u_z vary,
+// so the column is summed as (sum w_z f, sum w_z u_z f, sum w_z u_z^2 f):
+// three multiply-adds per value with workgroup-uniform coefficients; the
+// (x, y) weight and velocity close the column into the moments.  Then a wave
+// butterfly and the waves in order.  BGK: rho, rho U, E; ES: rho, rho U and
+// the raw second moments xx yy zz xy xz yz; the pair's G adds its integral
+// (last slot).
+constexpr int kMomMaxZ = 64;
+inline int gen_moment_block(const VGrid &vg) {
+    const int nxy = vg.nv[0] * vg.nv[1];
+    const int b = (nxy + 63) / 64 * 64;
+    return b < 1024 ? b : 1024;
 }
-
-// Moments of one solution point over the velocity axis (FP64, fixed order:
-// lane-strided partial sums, wave butterfly, waves in order).  BGK: rho,
-// rho U, E; ES: rho, rho U and the raw second moments xx yy zz xy xz yz.
 template <typename Real, int NMOM>
-__global__ __launch_bounds__(kGBlock) void k_gen_moments(const GenArgs A, const Real *__restrict__ f,
-                                                          double *__restrict__ Q) {
-    __shared__ double red[kGBlock / 64][NMOM];
+__global__ __launch_bounds__(1024) void k_gen_moments(const GenArgs A, const Real *__restrict__ f,
+                                                       double *__restrict__ Q) {
+    constexpr bool PAIR = NMOM == 6 || NMOM == 11;
+    __shared__ double red[16][NMOM];
+    __shared__ double tz[kMomMaxZ][3];  // w_z, w_z u_z, w_z u_z^2
+    const int nx = A.vg.nv[0], ny = A.vg.nv[1], nz = A.vg.nv[2], nxy = nx * ny;
+    for (int iz = threadIdx.x; iz < nz; iz += blockDim.x) {
+        const double w = A.wax[128 + iz], u = node_u(A.vg, 2, iz);
+        tz[iz][0] = w;
+        tz[iz][1] = w * u;
+        tz[iz][2] = (w * u) * u;
+    }
+    __syncthreads();
     const int64_t pt = blockIdx.x;
     const Real *fp = f + pt * A.nut;
     double M[NMOM];
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
-    // four values per lane requested at once, then accumulated in order
-    constexpr int kIn = 4;
-    int k0 = threadIdx.x;
-    for (; k0 + (kIn - 1) * kGBlock < A.nut; k0 += kIn * kGBlock) {
-        Real v[kIn];
-#pragma unroll
-        for (int r = 0; r < kIn; ++r) v[r] = fp[k0 + r * kGBlock];
-#pragma unroll
-        for (int r = 0; r < kIn; ++r) moment_add<NMOM>(A, k0 + r * kGBlock, (double)v[r], M);
+    for (int t = threadIdx.x; t < nxy; t += blockDim.x) {
+        const int iy = t / nx, ix = t - iy * nx;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, g0 = 0.0;
+#pragma unroll 4
+        for (int iz = 0; iz < nz; ++iz) {
+            const double x = (double)fp[t + iz * nxy];
+            s0 = fma(tz[iz][0], x, s0);
+            s1 = fma(tz[iz][1], x, s1);
+            s2 = fma(tz[iz][2], x, s2);
+            if constexpr (PAIR) g0 = fma(tz[iz][0], (double)fp[A.nu + t + iz * nxy], g0);
+        }
+        const double W = A.wax[ix] * A.wax[64 + iy];
+        const double ux = node_u(A.vg, 0, ix), uy = node_u(A.vg, 1, iy);
+        const double a0 = W * s0, a1 = W * s1, a2 = W * s2;
+        M[0] += a0;
+        M[1] = fma(ux, a0, M[1]);
+        M[2] = fma(uy, a0, M[2]);
+        M[3] += a1;
+        if constexpr (NMOM == 5 || NMOM == 6) {
+            M[4] = fma(0.5, fma(ux * ux + uy * uy, a0, a2), M[4]);
+        } else {
+            M[4] = fma(ux * ux, a0, M[4]);
+            M[5] = fma(uy * uy, a0, M[5]);
+            M[6] += a2;
+            M[7] = fma(ux * uy, a0, M[7]);
+            M[8] = fma(ux, a1, M[8]);
+            M[9] = fma(uy, a1, M[9]);
+        }
+        if constexpr (PAIR) M[NMOM - 1] = fma(W, g0, M[NMOM - 1]);
     }
-    for (int k = k0; k < A.nut; k += kGBlock) moment_add<NMOM>(A, k, (double)fp[k], M);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) {
@@ -240,8 +251,7 @@ __global__ __launch_bounds__(kGBlock) void k_gen_moments(const GenArgs A, const 
     __syncthreads();
     if (threadIdx.x < NMOM) {
         double t = red[0][threadIdx.x];
-#pragma unroll
-        for (int q = 1; q < kGBlock / 64; ++q) t += red[q][threadIdx.x];
+        for (int q = 1; q < (int)(blockDim.x / 64); ++q) t += red[q][threadIdx.x];
         Q[pt * NMOM + threadIdx.x] = t;
     }
 }
@@ -601,10 +611,10 @@ int gen_run(fr_dvm *h, int mode, const GenArgs &A, int do_moments) {
     auto moments = [&](const void *src) {
         const Real *fs = reinterpret_cast<const Real *>(src);
         switch (h->nmom) {
-            case 5: hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A, fs, A.sa.Q); break;
-            case 6: hipLaunchKernelGGL((k_gen_moments<Real, 6>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A, fs, A.sa.Q); break;
-            case 10: hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A, fs, A.sa.Q); break;
-            default: hipLaunchKernelGGL((k_gen_moments<Real, 11>), dim3((unsigned)npts), dim3(kGBlock), 0, h->stream, A, fs, A.sa.Q);
+            case 5: hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3((unsigned)npts), dim3(gen_moment_block(h->vg)), 0, h->stream, A, fs, A.sa.Q); break;
+            case 6: hipLaunchKernelGGL((k_gen_moments<Real, 6>), dim3((unsigned)npts), dim3(gen_moment_block(h->vg)), 0, h->stream, A, fs, A.sa.Q); break;
+            case 10: hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3((unsigned)npts), dim3(gen_moment_block(h->vg)), 0, h->stream, A, fs, A.sa.Q); break;
+            default: hipLaunchKernelGGL((k_gen_moments<Real, 11>), dim3((unsigned)npts), dim3(gen_moment_block(h->vg)), 0, h->stream, A, fs, A.sa.Q);
         }
         return gcheck(h, "moment kernel");
     };
@@ -918,9 +928,9 @@ int mix_run(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_mome
     const Real *src = reinterpret_cast<const Real *>(mode == 0 ? sa.f : sa.fout);
     const unsigned npts = (unsigned)mx.npts;
     if (h->nmom == 5)
-        hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3(npts), dim3(kGBlock), 0, h->stream, G, src, sa.Q);
+        hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3(npts), dim3(gen_moment_block(h->vg)), 0, h->stream, G, src, sa.Q);
     else if (h->nmom == 10)
-        hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3(npts), dim3(kGBlock), 0, h->stream, G, src, sa.Q);
+        hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3(npts), dim3(gen_moment_block(h->vg)), 0, h->stream, G, src, sa.Q);
     else
         return h->fail(FR_DVM_EUNSUPPORTED, "mixed meshes need a monatomic gas");
     return gcheck(h, "moment kernel");
