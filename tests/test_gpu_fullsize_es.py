@@ -1,8 +1,7 @@
 """GPU parity at the full size of the headline workload — 24^3 periodic
-hexes, p = 3, 20^3 velocities on [-8, 8]^3, ES-BGK Pr 0.71, Kn 2e-4 — in
-the configuration the benchmark times: FP32 f, low-storage RK, FP64 moments
-and Newton, learned-then-warm start (7.08e9 DOFs).  The oracle cannot run
-the whole box, so:
+hexes, p = 3, 20^3 velocities on [-8, 8]^3, ES-BGK Pr 0.71, Kn 2e-4 — with
+FP32 f, low-storage RK, FP64 moments and Newton and the warm Newton start
+(7.08e9 DOFs).  The oracle cannot run the whole box, so:
 
 * the residual of sampled elements is checked against the oracle on the
   7-element patch around each (the same FP32-rounded values);
