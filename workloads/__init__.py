@@ -688,7 +688,7 @@ def workload(name: str) -> dict:
         # Taylor-Green U0=0.5 with a 1% seeded perturbation
         "box24_p3_v20_es": dict(N=24, p=3, grid=grid_spec(20, 8.0), model=1, prandtl=0.71,
                                 kn=2e-4, ic="tgv", U0=0.5, pert=0.01, seed=5, steps=200,
-                                rk=0, precision=2),
+                                rk=1, precision=2),
         # O-grid around the cylinder of diameter 1: 24 radial (growth 1.15) x 48 azimuthal
         # x 2 spanwise quadratic hexes, p=2, 24^3 grid on [-14,14]^3, ES-BGK Pr=2/3,
         # Kn=0.01, uniform Mach-8 inflow at theta=1 (1% seeded density noise),
