@@ -473,7 +473,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="box24_p3_v20_es")
     ap.add_argument("--mode", choices=("compare", "single", "kn", "horizon"), default="compare")
-    ap.add_argument("--precision", type=int, default=None, help="single mode: 0 FP64, 1 FP32")
+    ap.add_argument("--precision", type=int, default=None,
+                    help="single and horizon modes: 0 FP64, 1 FP32, 2 FP32 deviation storage")
     ap.add_argument("--rk", type=int, default=None, help="single mode: 0 SSP-RK3, 1 low-storage")
     ap.add_argument("--guess", type=int, default=None, help="single mode: 0 cold, 1 warm, 2 MLP, 3 MLP then warm")
     ap.add_argument("--model", type=int, default=None, help="0 BGK, 1 ES-BGK, 2 collisionless")
@@ -695,9 +696,11 @@ def horizon_compare(W, w, mesh, base, args, cfg):
     H = args.horizon if args.horizon is not None else int(w.get("steps", 100))
     r64 = run_config(W, w, mesh, dict(base, precision=0, rk=0, guess=1), 0, 0, "fp64-horizon", keep_moments=True,
                      nsteps_override=H, keep_f=True)
-    # the deviation storage runs on box meshes; elsewhere the mixed form is FP32
-    mprec = MIXED if w.get("mesh") != "cylinder" else 1
-    rmx = run_config(W, w, mesh, dict(base, precision=mprec, rk=1, guess=1), 0, 0, "mixed-horizon",
+    # the reduced-precision form: --precision / --rk when given, else the
+    # deviation storage on box meshes (FP32 elsewhere) with the low-storage RK
+    mprec = args.precision if args.precision is not None else (MIXED if w.get("mesh") != "cylinder" else 1)
+    mrk = args.rk if args.rk is not None else 1
+    rmx = run_config(W, w, mesh, dict(base, precision=mprec, rk=mrk, guess=1), 0, 0, "mixed-horizon",
                      keep_moments=True, nsteps_override=H, keep_f=True)
     f64, fmx = r64.pop("f"), rmx.pop("f")
     ferr = f_rel_l2(fmx, f64)
@@ -706,7 +709,7 @@ def horizon_compare(W, w, mesh, base, args, cfg):
     err = bench_rel = rel_moments(rmx["Q"], r64["Q"])
     err["f"] = ferr
     cfg = dict(cfg, mixed=(MIXED_LABEL if mprec == MIXED else "FP32 f, FP32 FR/RK arithmetic, FP64 moments + Newton")
-               + "; LSRK3-2N; warm Newton start",
+               + "; " + ["SSP-RK3", "LSRK3-2N"][mrk] + "; warm Newton start",
                plain="FP64 everything; SSP-RK3; warm Newton start", positivity=base.get("positivity", 0))
     return {"metric": "mixed vs FP64 relative L2 difference at the horizon", "horizon_steps": H,
             "mixed_vs_fp64_rel_l2": bench_rel, "config": cfg,
