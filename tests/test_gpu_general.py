@@ -100,6 +100,21 @@ def test_general_moments_totals_dt_kn(F, orc):
     assert rel(kn.cpu().numpy().reshape(s.ne, s.ns), P.kn_gll(f)) < 1e-12
 
 
+@pytest.mark.parametrize("model", [0, 1])
+def test_general_moments_wide_xy_grid(F, orc, model):
+    """The moment pass with more (x, y) velocity nodes than threads in a
+    workgroup (40 x 30 = 1200 columns of 3): 1e-13 against the oracle."""
+    mesh = _small_cylinder()
+    grid = W.grid_spec((40, 30, 3), 6.0)
+    par = _params(model=model, prandtl=2.0 / 3.0 if model == 1 else 1.0)
+    P = _oracle(orc, mesh, 1, grid, par)
+    f = _state(P, grid, 6)
+    s = F.FrDvm(mesh, 1, grid, par)
+    Q = torch.zeros(s.ne * s.ns * 5, dtype=torch.float64, device="cuda")
+    s.moments(_gpu(s, f), Q)
+    assert rel(Q.cpu().numpy().reshape(s.ne, s.ns, 5), P.moments(f)) < 1e-13
+
+
 def test_general_collide_es(F, orc):
     mesh = _small_cylinder()
     par = _params(model=1, prandtl=2.0 / 3.0, mu_ref=0.02)
