@@ -141,18 +141,20 @@ def test_general_rk_steps_es_fp64(F, orc, rk):
     assert rel(f.cpu().numpy(), ref) < 1e-12
 
 
-def test_general_rk_steps_mixed(F, orc):
-    """FP32 f with FP64 moments and Newton, low-storage RK, learned-free warm
-    start: stated bounds after 5 steps on the cylinder."""
+@pytest.mark.parametrize("p,rk,nsteps", [(2, 1, 5), (1, 0, 5), (3, 1, 3)])
+def test_general_rk_steps_mixed(F, orc, p, rk, nsteps):
+    """FP32 f with FP64 moments and Newton, warm start: stated bounds after
+    a few steps on the cylinder (p <= 2: stage values in registers; p = 3:
+    in the LDS column)."""
     mesh = _small_cylinder()
     par = _params(model=1, prandtl=2.0 / 3.0, mu_ref=0.02)
-    P = _oracle(orc, mesh, 2, GRID, par)
+    P = _oracle(orc, mesh, p, GRID, par)
     f0 = _state(P, GRID, 8, amp=0.1)
     dt = P.dt(0.2)
-    ref = P.rk_step(f0, dt, scheme=1, nsteps=5)
-    s = F.FrDvm(mesh, 2, GRID, dict(par, rk=1, precision=1, guess=1))
+    ref = P.rk_step(f0, dt, scheme=rk, nsteps=nsteps)
+    s = F.FrDvm(mesh, p, GRID, dict(par, rk=rk, precision=1, guess=1))
     f = _gpu(s, f0)
-    s.rk_steps(f, dt, 5)
+    s.rk_steps(f, dt, nsteps)
     got = f.double().cpu().numpy()
     assert rel(got, ref) < 1e-5
     Qg, Qr = P.moments(got), P.moments(ref)
