@@ -66,8 +66,9 @@ extern "C" {
  * traces likewise: r_e(u) = exp of a quadratic exponent in u whose
  * coefficients are the means over the element's solution points of those
  * of the conservative equilibria the stage's Newton solve found there
- * (eq. discrete_compatibility), evaluated through the FP32 hardware exp2
- * (an FP32 number, the same bits wherever it is evaluated).  The next stage
+ * (eq. discrete_compatibility), evaluated in FP32 (the exponent from the
+ * coefficients and the velocity rounded to FP32, then the hardware exp2: an
+ * FP32 number, the same bits wherever it is evaluated).  The next stage
  * reads f = r_e + d, and the exact moments of r_e are added to those of d.
  * The call's first stage reads plain f and its last stage leaves plain f,
  * rounded to FP32 (stochastically).  Within an element f stays close to one

@@ -79,18 +79,19 @@ __device__ __forceinline__ double exp_f64(double E) {
 // The exponent polynomial of an element reference (FP32 deviation storage):
 // E(u) = c0 + c1 ux + c2 uy + c3 uz + c4 ux^2 + c5 uy^2 + c6 uz^2
 //        + c7 ux uy + c8 ux uz + c9 uy uz,
-// one fixed sequence of IEEE operations wherever it is evaluated.
+// in FP32 from the coefficients and the velocity rounded to FP32: one fixed
+// sequence of IEEE operations wherever it is evaluated.
 constexpr int kRefCoef = 10;
-__device__ __forceinline__ double ref_exponent(const double *c, const double u[3]) {
-    double tx = fma(c[4], u[0], c[1]);
-    tx = fma(c[7], u[1], tx);
-    tx = fma(c[8], u[2], tx);
-    double ty = fma(c[5], u[1], c[2]);
-    ty = fma(c[9], u[2], ty);
-    const double tz = fma(c[6], u[2], c[3]);
-    double E = fma(u[0], tx, c[0]);
-    E = fma(u[1], ty, E);
-    return fma(u[2], tz, E);
+__device__ __forceinline__ float ref_exponent(const float *c, const float u[3]) {
+    float tx = fmaf(c[4], u[0], c[1]);
+    tx = fmaf(c[7], u[1], tx);
+    tx = fmaf(c[8], u[2], tx);
+    float ty = fmaf(c[5], u[1], c[2]);
+    ty = fmaf(c[9], u[2], ty);
+    const float tz = fmaf(c[6], u[2], c[3]);
+    float E = fmaf(u[0], tx, c[0]);
+    E = fmaf(u[1], ty, E);
+    return fmaf(u[2], tz, E);
 }
 
 // Reference value at exponent E: the FP32 hardware exp2 of E log2(e).  It
@@ -99,8 +100,8 @@ __device__ __forceinline__ double ref_exponent(const double *c, const double u[3
 // moments are summed separately), not accurate.  An FP32 number, so sums and
 // differences of two references and of a reference and an FP32 value near
 // it are exact or rounded once.
-__device__ __forceinline__ float ref_value(double E) {
-    return __builtin_amdgcn_exp2f((float)(E * 1.4426950408889634074));
+__device__ __forceinline__ float ref_value(float E) {
+    return __builtin_amdgcn_exp2f(E * 1.44269504f);
 }
 
 // Stochastic rounding of the FP32 state.  A value computed in FP64 is stored

@@ -344,13 +344,13 @@ k_fr_layer(const FrArgs A) {
     const bool in_dev = ER && A.sa.in_dev;
     const bool out_dev = ER && A.sa.out_dev;
     // own prev, own cur, 6 faces' prev, own reference of the step's initial value (SSP)
-    __shared__ __attribute__((aligned(16))) double s_ref[ER ? 9 * kRefCoef : 1];
+    __shared__ __attribute__((aligned(16))) float s_ref[ER ? 9 * kRefCoef : 1];
     if (ER) {
         for (int t = tid; t < 9 * kRefCoef; t += NT) {
             const int r = t / kRefCoef;
             const int64_t er = (r < 2 || r == 8) ? e : (int64_t)A.nbr[6 * e + r - 2];
             const double *src = r == 1 ? A.sa.ref_cur : (r == 8 ? A.sa.ref_u0 : A.sa.ref_prev);
-            s_ref[t] = src[er * kRefW + t % kRefCoef];
+            s_ref[t] = (float)src[er * kRefW + t % kRefCoef];
         }
     }
 
@@ -467,18 +467,19 @@ k_fr_layer(const FrArgs A) {
         float rp = 0.0f, sh = 0.0f, dl[3] = {0.0f, 0.0f, 0.0f};
         double shd = 0.0;
         if (ER) {
-            rp = ref_value(ref_exponent(&s_ref[0], v.u));
-            const float rc = out_dev ? ref_value(ref_exponent(&s_ref[kRefCoef], v.u)) : 0.0f;
+            const float uf[3] = {(float)v.u[0], (float)v.u[1], (float)v.u[2]};
+            rp = ref_value(ref_exponent(&s_ref[0], uf));
+            const float rc = out_dev ? ref_value(ref_exponent(&s_ref[kRefCoef], uf)) : 0.0f;
             sh = rp - rc;
             if (A.sa.scheme == 0) {
-                const double r0 = A.sa.fn_dev ? (double)ref_value(ref_exponent(&s_ref[8 * kRefCoef], v.u)) : 0.0;
+                const double r0 = A.sa.fn_dev ? (double)ref_value(ref_exponent(&s_ref[8 * kRefCoef], uf)) : 0.0;
                 shd = fma(A.sa.alpha, r0, fma(A.sa.beta, (double)rp, -(double)rc));
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const int slot = 2 + 2 * d + (v.sgn[d] > 0 ? 0 : 1);  // the upwind neighbour in direction d
-                const double rn = in_dev ? (double)ref_value(ref_exponent(&s_ref[slot * kRefCoef], v.u)) : 0.0;
-                dl[d] = (float)(rn - (double)rp);
+                const float rn = in_dev ? ref_value(ref_exponent(&s_ref[slot * kRefCoef], uf)) : 0.0f;
+                dl[d] = rn - rp;
             }
         }
 #pragma unroll
@@ -811,6 +812,7 @@ static_assert(kRefCoef + 10 <= kRefW, "element reference record: coefficients an
 template <int NMOM>
 __global__ __launch_bounds__(kRefBlock) void k_elem_ref(const FrArgs A, int ns, double *__restrict__ ref) {
     __shared__ double s_c[kRefCoef];
+    __shared__ float s_cf[kRefCoef];  // the coefficients as the stage kernel reads them
     __shared__ double s_m[kRefBlock * NMOM];
     const int64_t e = blockIdx.x;
     const int tid = threadIdx.x;
@@ -824,6 +826,7 @@ __global__ __launch_bounds__(kRefBlock) void k_elem_ref(const FrArgs A, int ns, 
             ++cnt;
         }
         s_c[tid] = cnt ? sum / cnt : (tid == 0 ? -INFINITY : 0.0);
+        s_cf[tid] = (float)s_c[tid];
     }
     __syncthreads();
     double M[NMOM];
@@ -832,7 +835,8 @@ __global__ __launch_bounds__(kRefBlock) void k_elem_ref(const FrArgs A, int ns, 
     const int nx = A.vg.nv[0];
     for (int k = tid; k < A.nu; k += kRefBlock) {
         const Vel v = velocity(A, k, true);
-        const double r = (double)ref_value(ref_exponent(s_c, v.u));
+        const float uf[3] = {(float)v.u[0], (float)v.u[1], (float)v.u[2]};
+        const double r = (double)ref_value(ref_exponent(s_cf, uf));
         const double *wx = A.wx3 + 3 * (k % nx), *wr = A.wrow + 6 * (k / nx);
         const double a0 = wx[0] * r, a1 = wx[1] * r, a2 = wx[2] * r;
         M[0] = fma(wr[0], a0, M[0]);
