@@ -47,7 +47,7 @@ extern "C" {
 #define FR_DVM_EINVAL (-1)      /* invalid argument or inconsistent mesh */
 #define FR_DVM_ENOMEM (-2)      /* device allocation failed */
 #define FR_DVM_EHIP (-3)        /* HIP runtime error */
-#define FR_DVM_EUNSUPPORTED (-4) /* valid input this build does not handle */
+#define FR_DVM_EUNSUPPORTED (-4) /* valid input the library does not handle */
 #define FR_DVM_ESCRATCH (-5)     /* request larger than the fixed scratch of a
                                     no-allocation entry point */
 

@@ -5,7 +5,7 @@
  * The paper finds the modified equilibrium of eq. (discrete_compatibility)
  * per solution point by Newton's method (Section "Numerical method").  This
  * part of the library trains, on the GPU, a small network that predicts the
- * starting point of that Newton solve; Newton stays the judge of the
+ * starting point of that Newton solve; Newton alone decides convergence on the
  * residual and falls back to the cold start when the prediction fails.
  *
  * Network: 13 -> H -> H -> H -> 5, SiLU on the hidden layers, FP32.

@@ -5,7 +5,7 @@ per-point features of the macroscopic state and velocity grid to the
 correction of the Newton unknowns z over the cold guess (the continuous
 equilibrium of the moments).  The paper solves the conservative-equilibrium
 system by Newton (Section "Numerical method"); the network only supplies a
-starting point, Newton remains the judge of the residual.
+starting point, Newton alone decides convergence on the residual.
 
 Flat parameter layout (shared with the GPU kernels through the C ABI, not
 through code): for each layer [W (out x in, row major), b (out)], then the

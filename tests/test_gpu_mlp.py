@@ -1,7 +1,7 @@
 """GPU tests of the learned Newton initial guess: the forward pass and the
 gradient of the hand-written FP32/MFMA kernels against the FP64 oracle, one
 Adam step, the conservative-equilibrium solve on caller moments, and the
-gain of a trained network over the cold start (Newton stays the judge)."""
+gain of a trained network over the cold start (Newton alone decides convergence)."""
 import numpy as np
 import pytest
 
