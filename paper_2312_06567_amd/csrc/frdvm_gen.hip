@@ -175,27 +175,24 @@ __global__ __launch_bounds__(kGBlock) void k_gen_traces(const GenArgs A, const R
     }
 }
 
-// Moments of one solution point over the velocity grid (FP64, fixed order).
-// Thread t of the workgroup takes the (x, y) nodes t, t + blockDim, ... and
-// walks each one's z column: the nodes of a z step are consecutive over the
-// threads (coalesced), and along the column only the z weight and u_z vary,
-// so the column is summed as (sum w_z f, sum w_z u_z f, sum w_z u_z^2 f):
-// three multiply-adds per value with workgroup-uniform coefficients; the
-// (x, y) weight and velocity close the column into the moments.  Then a wave
-// butterfly and the waves in order.  BGK: rho, rho U, E; ES: rho, rho U and
-// the raw second moments xx yy zz xy xz yz; the pair's G adds its integral
-// (last slot).
+// Moments of one solution point over the velocity grid (FP64, fixed order),
+// one wave per point and kMomPts points per workgroup.  Lane t of the wave
+// takes the (x, y) nodes t, t + 64, ... and walks each one's z column: the
+// nodes of a z step are consecutive over the lanes (coalesced), and along
+// the column only the z weight and u_z vary, so the column is summed as
+// (sum w_z f, sum w_z u_z f, sum w_z u_z^2 f): three multiply-adds per value
+// with wave-uniform coefficients; the (x, y) weight and velocity close the
+// column into the moments, and a wave butterfly sums the lanes.  (A
+// workgroup per point, its threads over the columns, spent most of its time
+// starting workgroups and reducing across waves.)  BGK: rho, rho U, E; ES:
+// rho, rho U and the raw second moments xx yy zz xy xz yz; the pair's G adds
+// its integral (last slot).
 constexpr int kMomMaxZ = 64;
-inline int gen_moment_block(const VGrid &vg) {
-    const int nxy = vg.nv[0] * vg.nv[1];
-    const int b = (nxy + 63) / 64 * 64;
-    return b < 1024 ? b : 1024;
-}
+constexpr int kMomPts = 4;  // points (waves) per workgroup
 template <typename Real, int NMOM>
-__global__ __launch_bounds__(1024) void k_gen_moments(const GenArgs A, const Real *__restrict__ f,
-                                                       double *__restrict__ Q) {
+__global__ __launch_bounds__(64 * kMomPts) void k_gen_moments(const GenArgs A, const Real *__restrict__ f,
+                                                              double *__restrict__ Q, int64_t npts) {
     constexpr bool PAIR = NMOM == 6 || NMOM == 11;
-    __shared__ double red[16][NMOM];
     __shared__ double tz[kMomMaxZ][3];  // w_z, w_z u_z, w_z u_z^2
     const int nx = A.vg.nv[0], ny = A.vg.nv[1], nz = A.vg.nv[2], nxy = nx * ny;
     for (int iz = threadIdx.x; iz < nz; iz += blockDim.x) {
@@ -205,12 +202,14 @@ __global__ __launch_bounds__(1024) void k_gen_moments(const GenArgs A, const Rea
         tz[iz][2] = (w * u) * u;
     }
     __syncthreads();
-    const int64_t pt = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t pt = (int64_t)blockIdx.x * kMomPts + (threadIdx.x >> 6);
+    if (pt >= npts) return;  // (no barrier follows)
     const Real *fp = f + pt * A.nut;
     double M[NMOM];
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) M[a] = 0.0;
-    for (int t = threadIdx.x; t < nxy; t += blockDim.x) {
+    for (int t = lane; t < nxy; t += 64) {
         const int iy = t / nx, ix = t - iy * nx;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, g0 = 0.0;
 #pragma unroll 4
@@ -240,21 +239,15 @@ __global__ __launch_bounds__(1024) void k_gen_moments(const GenArgs A, const Rea
         }
         if constexpr (PAIR) M[NMOM - 1] = fma(W, g0, M[NMOM - 1]);
     }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int a = 0; a < NMOM; ++a) {
         double v = M[a];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) red[w][a] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < NMOM) {
-        double t = red[0][threadIdx.x];
-        for (int q = 1; q < (int)(blockDim.x / 64); ++q) t += red[q][threadIdx.x];
-        Q[pt * NMOM + threadIdx.x] = t;
+        if (lane == a) Q[pt * NMOM + a] = v;
     }
 }
+inline unsigned gen_moment_grid(int64_t npts) { return (unsigned)((npts + kMomPts - 1) / kMomPts); }
 
 // Wall density at each flux point of the diffuse-wall faces: the outflow
 // mass flux of the interior trace over the inflow flux of the unit wall
@@ -611,10 +604,10 @@ int gen_run(fr_dvm *h, int mode, const GenArgs &A, int do_moments) {
     auto moments = [&](const void *src) {
         const Real *fs = reinterpret_cast<const Real *>(src);
         switch (h->nmom) {
-            case 5: hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3((unsigned)npts), dim3(gen_moment_block(h->vg)), 0, h->stream, A, fs, A.sa.Q); break;
-            case 6: hipLaunchKernelGGL((k_gen_moments<Real, 6>), dim3((unsigned)npts), dim3(gen_moment_block(h->vg)), 0, h->stream, A, fs, A.sa.Q); break;
-            case 10: hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3((unsigned)npts), dim3(gen_moment_block(h->vg)), 0, h->stream, A, fs, A.sa.Q); break;
-            default: hipLaunchKernelGGL((k_gen_moments<Real, 11>), dim3((unsigned)npts), dim3(gen_moment_block(h->vg)), 0, h->stream, A, fs, A.sa.Q);
+            case 5: hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3(gen_moment_grid(npts)), dim3(64 * kMomPts), 0, h->stream, A, fs, A.sa.Q, (int64_t)npts); break;
+            case 6: hipLaunchKernelGGL((k_gen_moments<Real, 6>), dim3(gen_moment_grid(npts)), dim3(64 * kMomPts), 0, h->stream, A, fs, A.sa.Q, (int64_t)npts); break;
+            case 10: hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3(gen_moment_grid(npts)), dim3(64 * kMomPts), 0, h->stream, A, fs, A.sa.Q, (int64_t)npts); break;
+            default: hipLaunchKernelGGL((k_gen_moments<Real, 11>), dim3(gen_moment_grid(npts)), dim3(64 * kMomPts), 0, h->stream, A, fs, A.sa.Q, (int64_t)npts);
         }
         return gcheck(h, "moment kernel");
     };
@@ -928,9 +921,9 @@ int mix_run(fr_dvm *h, int mode, const StageArgs &sa, int do_traces, int do_mome
     const Real *src = reinterpret_cast<const Real *>(mode == 0 ? sa.f : sa.fout);
     const unsigned npts = (unsigned)mx.npts;
     if (h->nmom == 5)
-        hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3(npts), dim3(gen_moment_block(h->vg)), 0, h->stream, G, src, sa.Q);
+        hipLaunchKernelGGL((k_gen_moments<Real, 5>), dim3(gen_moment_grid(npts)), dim3(64 * kMomPts), 0, h->stream, G, src, sa.Q, (int64_t)npts);
     else if (h->nmom == 10)
-        hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3(npts), dim3(gen_moment_block(h->vg)), 0, h->stream, G, src, sa.Q);
+        hipLaunchKernelGGL((k_gen_moments<Real, 10>), dim3(gen_moment_grid(npts)), dim3(64 * kMomPts), 0, h->stream, G, src, sa.Q, (int64_t)npts);
     else
         return h->fail(FR_DVM_EUNSUPPORTED, "mixed meshes need a monatomic gas");
     return gcheck(h, "moment kernel");
