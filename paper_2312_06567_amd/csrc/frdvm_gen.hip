@@ -682,7 +682,14 @@ __device__ __forceinline__ MixOps<double> mix_ops(const MixArgs &A, double) {
     return {(cptr<double>)A.geo, (cptr<double>)A.D, (cptr<double>)A.lift};
 }
 
-template <typename Real, int NS, int NFT, int MODE>
+// PL: Gauss-Lobatto layers of a prism (0: other element types).  A prism's
+// in-plane derivative operators couple only the points of one layer and its
+// axial one only those of one column, an end-face point lifts onto its
+// column and a side-face point onto its layer (the host stores the other
+// entries as exact zeros and checks the face order): the volume term reads
+// 2 NS (NS / PL) + NS PL operator entries instead of 3 NS^2 and the faces
+// 2 NS + 3 PL NS instead of NS NFT, in the order of the dense sums.
+template <typename Real, int NS, int NFT, int MODE, int PL>
 __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
     // up to 40 points (tetrahedra, prisms, hexahedra to p = 2) a lane keeps
     // its values and residuals in registers and the dense products run fully
@@ -733,17 +740,63 @@ __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
 #pragma unroll
             for (int i = 0; i < NS; ++i) {
                 Real gi = Real(0);
+                if constexpr (PL > 0) {
+                    constexpr int NT = NS / PL;  // points per layer
+                    if (a < 2) {
+                        const int j0 = i / NT * NT;  // the layer of point i
 #pragma unroll
-                for (int j = 0; j < NS; ++j) gi = fma(op.D[(a * NS + i) * NS + j], fv[j], gi);
+                        for (int m = 0; m < NT; ++m) gi = fma(op.D[(a * NS + i) * NS + j0 + m], fv[j0 + m], gi);
+                    } else {
+                        const int m0 = i % NT;  // the column of point i
+#pragma unroll
+                        for (int k = 0; k < PL; ++k) gi = fma(op.D[(a * NS + i) * NS + m0 + NT * k], fv[m0 + NT * k], gi);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) gi = fma(op.D[(a * NS + i) * NS + j], fv[j], gi);
+                }
                 r[i] = fma(-c[a], gi, r[i]);
             }
         }
         // faces
+        if constexpr (PL > 0) {
+            constexpr int NT = NS / PL;
+            // bottom and top faces: face point m lifts onto column m
 #pragma unroll 1
-        for (int t = 0; t < NFT; ++t) {
-            const Real jump = jump_at(t);
+            for (int f = 0; f < 2; ++f) {
 #pragma unroll
-            for (int i = 0; i < NS; ++i) r[i] = fma(-op.lift[i * NFT + t], jump, r[i]);
+                for (int m = 0; m < NT; ++m) {
+                    const int t = f * NT + m;
+                    const Real jump = jump_at(t);
+#pragma unroll
+                    for (int k = 0; k < PL; ++k) {
+                        const int i = m + NT * k;
+                        r[i] = fma(-op.lift[i * NFT + t], jump, r[i]);
+                    }
+                }
+            }
+            // side faces, per (face, edge point): face point e + PL k lifts
+            // onto layer k
+#pragma unroll 1
+            for (int u = 0; u < 3 * PL; ++u) {
+#pragma unroll
+                for (int k = 0; k < PL; ++k) {
+                    const int t = 2 * NT + u / PL * (PL * PL) + u % PL + PL * k;
+                    const Real jump = jump_at(t);
+#pragma unroll
+                    for (int m = 0; m < NT; ++m) {
+                        const int i = m + NT * k;
+                        r[i] = fma(-op.lift[i * NFT + t], jump, r[i]);
+                    }
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int t = 0; t < NFT; ++t) {
+                const Real jump = jump_at(t);
+#pragma unroll
+                for (int i = 0; i < NS; ++i) r[i] = fma(-op.lift[i * NFT + t], jump, r[i]);
+            }
         }
     } else {
 #pragma unroll 4
@@ -842,15 +895,15 @@ __global__ __launch_bounds__(kGWave) void k_mix_traces(const MixArgs A, const Re
     for (int t = 0; t < NFT; ++t) tr[(t0 + t) * nu + k] = f[(p0 + A.fnode[t]) * nu + k];
 }
 
-template <typename Real, int NS, int NFT>
+template <typename Real, int NS, int NFT, int PL = 0>
 int mix_launch(fr_dvm *h, int mode, const MixArgs &A, unsigned blocks) {
     if (mode == 0)
         hipLaunchKernelGGL((k_mix_traces<Real, NS, NFT>), dim3(blocks), dim3(kGWave), 0, h->stream, A,
                            reinterpret_cast<const Real *>(A.sa.f), reinterpret_cast<Real *>(A.sa.tr_out));
     else if (mode == GMODE_RESID)
-        hipLaunchKernelGGL((k_mix_stage<Real, NS, NFT, GMODE_RESID>), dim3(blocks), dim3(kGWave), 0, h->stream, A);
+        hipLaunchKernelGGL((k_mix_stage<Real, NS, NFT, GMODE_RESID, PL>), dim3(blocks), dim3(kGWave), 0, h->stream, A);
     else
-        hipLaunchKernelGGL((k_mix_stage<Real, NS, NFT, GMODE_STAGE>), dim3(blocks), dim3(kGWave), 0, h->stream, A);
+        hipLaunchKernelGGL((k_mix_stage<Real, NS, NFT, GMODE_STAGE, PL>), dim3(blocks), dim3(kGWave), 0, h->stream, A);
     return gcheck(h, "mixed-mesh kernel");
 }
 
@@ -863,9 +916,9 @@ int mix_dispatch(fr_dvm *h, int mode, const MixArgs &A, int t, const MixType &T,
         case 1: ns = 8; nft = 24; rc = mix_launch<Real, 8, 24>(h, mode, A, blocks); break;
         case 2: ns = 27; nft = 54; rc = mix_launch<Real, 27, 54>(h, mode, A, blocks); break;
         case 3: ns = 64; nft = 96; rc = mix_launch<Real, 64, 96>(h, mode, A, blocks); break;
-        case 11: ns = 6; nft = 18; rc = mix_launch<Real, 6, 18>(h, mode, A, blocks); break;
-        case 12: ns = 18; nft = 39; rc = mix_launch<Real, 18, 39>(h, mode, A, blocks); break;
-        case 13: ns = 40; nft = 68; rc = mix_launch<Real, 40, 68>(h, mode, A, blocks); break;
+        case 11: ns = 6; nft = 18; rc = mix_launch<Real, 6, 18, 2>(h, mode, A, blocks); break;
+        case 12: ns = 18; nft = 39; rc = mix_launch<Real, 18, 39, 3>(h, mode, A, blocks); break;
+        case 13: ns = 40; nft = 68; rc = mix_launch<Real, 40, 68, 4>(h, mode, A, blocks); break;
         case 21: ns = 4; nft = 12; rc = mix_launch<Real, 4, 12>(h, mode, A, blocks); break;
         case 22: ns = 10; nft = 24; rc = mix_launch<Real, 10, 24>(h, mode, A, blocks); break;
         case 23: ns = 20; nft = 40; rc = mix_launch<Real, 20, 40>(h, mode, A, blocks); break;

@@ -268,6 +268,58 @@ std::vector<V3> ref_verts(int t) {
     return v;
 }
 
+// The prism's points are the triangle's points on every Gauss-Lobatto layer
+// (point m + nt k, nt triangle points, k the layer) and its space is
+// P_p(triangle) x P_p(line), so its nodal basis is the product of the two
+// Lagrange bases and its operators inherit the product structure: the
+// in-plane derivatives couple only points of one layer, the axial one only
+// points of one column; a bottom or top face point (that column's end)
+// lifts onto its column, a side face point (edge point e on layer k, face
+// index e + (p + 1) k) onto its layer.  The inverted matrices leave
+// rounding in the other entries; they are set to their exact value, zero,
+// so that the kernel can skip them.  The face order (bottom, top, three
+// sides) and a structure that does not hold are reported as errors.
+int prism_structure(fr_dvm *h, MixType &T, int p) {
+    const int ns = T.ns, nl = p + 1, nt = ns / nl, nft = T.nft;
+    if (nt * nl != ns || nft != 2 * nt + 3 * nl * nl)
+        return h->fail(FR_DVM_EINVAL, "prism point counts differ from the layered set");
+    // the set a face point t lifts onto: column m (end faces) or layer k (sides)
+    std::vector<int> col(nft, -1), lay(nft, -1);
+    for (int t = 0; t < nft; ++t) {
+        const int f = T.ffac[t], i = T.fnode[t];
+        if (t < 2 * nt) {
+            const int m = t % nt, k = t < nt ? 0 : nl - 1;
+            if (f != t / nt || i != m + nt * k) return h->fail(FR_DVM_EINVAL, "prism end-face points out of order");
+            col[t] = m;
+        } else {
+            const int u = t - 2 * nt, k = (u % (nl * nl)) / nl;
+            if (f != 2 + u / (nl * nl) || i / nt != k) return h->fail(FR_DVM_EINVAL, "prism side-face points out of order");
+            lay[t] = k;
+        }
+    }
+    double dmax = 0.0, lmax = 0.0;
+    for (double v : T.D) dmax = std::max(dmax, std::fabs(v));
+    for (double v : T.lift) lmax = std::max(lmax, std::fabs(v));
+    for (int d = 0; d < 3; ++d)
+        for (int i = 0; i < ns; ++i)
+            for (int j = 0; j < ns; ++j) {
+                double &v = T.D[(d * ns + i) * ns + j];
+                const bool couple = d < 2 ? i / nt == j / nt : i % nt == j % nt;
+                if (couple) continue;
+                if (std::fabs(v) > 1e-9 * dmax) return h->fail(FR_DVM_EINVAL, "prism derivative lacks the layer structure");
+                v = 0.0;
+            }
+    for (int i = 0; i < ns; ++i)
+        for (int t = 0; t < nft; ++t) {
+            double &v = T.lift[(size_t)i * nft + t];
+            const bool onto = col[t] >= 0 ? i % nt == col[t] : i / nt == lay[t];
+            if (onto) continue;
+            if (std::fabs(v) > 1e-9 * lmax) return h->fail(FR_DVM_EINVAL, "prism lifting lacks the layer structure");
+            v = 0.0;
+        }
+    return FR_DVM_OK;
+}
+
 // Reference operators of one element type.
 int build_type(fr_dvm *h, MixType &T, int t, int p) {
     T.etype = t;
@@ -356,7 +408,7 @@ int build_type(fr_dvm *h, MixType &T, int t, int p) {
     T.lift.assign((size_t)ns * T.nft, 0.0);
     for (int tt = 0; tt < T.nft; ++tt)
         for (int i = 0; i < ns; ++i) T.lift[(size_t)i * T.nft + tt] = cols[tt][i];
-    return FR_DVM_OK;
+    return t == FR_DVM_PRISM ? prism_structure(h, T, p) : FR_DVM_OK;
 }
 
 template <typename T>

@@ -116,6 +116,32 @@ def test_derivatives_exact_and_lifting_integrates_the_face(etype, p):
         assert np.allclose(ints @ x[fc["nodes"]], area * verts.mean(0), atol=1e-13)
 
 
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_prism_operators_have_the_layer_structure(p):
+    """The prism's points are the triangle's points on every Gauss-Lobatto
+    layer (point m + nt k) and its space is P_p(triangle) x P_p(line), so its
+    Lagrange basis is a product: the in-plane derivatives couple only points
+    of one layer, the axial one only points of one column, an end-face point
+    lifts onto its own column and a side-face point onto its own layer.  The
+    GPU prism kernel skips every other entry; here the oracle's operators,
+    formed without that assumption, show them to vanish."""
+    R = M.ref_element(M.PRISM, p)
+    nl = p + 1
+    nt = R.ns // nl
+    i, j = np.meshgrid(np.arange(R.ns), np.arange(R.ns), indexing="ij")
+    scale = max(np.abs(d).max() for d in R.D)
+    assert np.abs(R.D[0][i // nt != j // nt]).max() < 1e-14 * scale
+    assert np.abs(R.D[1][i // nt != j // nt]).max() < 1e-14 * scale
+    assert np.abs(R.D[2][i % nt != j % nt]).max() < 1e-14 * scale
+    for fc in R.faces:
+        L, nodes = fc["lift"], fc["nodes"]
+        end = len(fc["verts"]) == 3
+        for c, node in enumerate(nodes):
+            onto = (np.arange(R.ns) % nt == node % nt) if end else (np.arange(R.ns) // nt == node // nt)
+            assert np.abs(L[~onto, c]).max() < 1e-14 * np.abs(L).max()
+            assert np.abs(L[onto, c]).max() > 1e-3 * np.abs(L).max()
+
 def _params():
     return {"model": 0, "mu_ref": 0.05, "prandtl": 1.0, "theta_ref": 1.0, "omega": 0.81}
 
