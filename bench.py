@@ -298,16 +298,29 @@ MIXED_SIZES = {1: ((8, 24), (6, 18), (4, 12)), 2: ((27, 54), (18, 39), (10, 24))
                3: ((64, 96), (40, 68), (20, 40))}
 
 
+def mixed_row_madds(t: int, p: int) -> int:
+    """Multiply-adds per solution point and velocity of the operator rows of
+    element type t (0 hexahedron, 1 prism, 2 tetrahedron): hexahedra and
+    tetrahedra dense (three derivative rows of N_s entries, a lifting row of
+    N_ft); the prism's rows hold only its layer / column structure (two
+    in-plane rows of N_s / (p + 1) entries and an axial one of p + 1; lifting
+    from the two end-face points of its column and the 3 (p + 1) side-face
+    points of its layer)."""
+    ns, nft = MIXED_SIZES[p][t]
+    if t == 1:
+        nl = p + 1
+        return 2 * (ns // nl) + nl + 2 + 3 * nl
+    return 3 * ns + nft
+
+
 def mixed_flops_per_dof(mesh, p: int) -> float:
-    """Algorithmic flops per DOF of a mixed-mesh stage: per solution point
-    and velocity the three reference-derivative rows (3 N_s multiply-adds)
-    and the lifting row (N_ft multiply-adds) of its element's dense
-    operators, averaged over the mesh's points."""
+    """Algorithmic flops per DOF of a mixed-mesh stage: 2 x the operator
+    multiply-adds per point (mixed_row_madds), averaged over the mesh's
+    points."""
     import numpy as np
     counts = np.bincount(np.asarray(mesh["elem_type"]), minlength=3)
     pts = sum(int(counts[t]) * MIXED_SIZES[p][t][0] for t in range(3))
-    fl = sum(int(counts[t]) * MIXED_SIZES[p][t][0] * 2 * (3 * MIXED_SIZES[p][t][0] + MIXED_SIZES[p][t][1])
-             for t in range(3))
+    fl = sum(int(counts[t]) * MIXED_SIZES[p][t][0] * 2 * mixed_row_madds(t, p) for t in range(3))
     return fl / pts
 
 
@@ -330,7 +343,7 @@ def mixed_roofline(r, p, mesh):
     vals = 3.0 + (4.0 / 3.0 if r["rk"] == 1 else 2.0 / 3.0) + 1.5 * fpts / pts
     bpd = vals * (8 if r["precision"] == 0 else 4)
     gbs = bpd * r["dof"] * 3 * r["steps"] / (ms / 1e3) / 1e9
-    return {"kernel": "k_mix_stage (+ k_gen_moments), dense FR-DG operators", "bound": "alu", "achieved": ach,
+    return {"kernel": "k_mix_stage (+ k_gen_moments), element operators (prisms: layer/column structure)", "bound": "alu", "achieved": ach,
             "peak": peak, "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
             "flops_per_dof": fpd, "avg_launch_ms": ms / max(n, 1),
             "hbm_bytes_per_dof": bpd, "hbm_GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}

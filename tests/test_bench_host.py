@@ -5,6 +5,9 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+import pytest
+
 import bench
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -75,3 +78,38 @@ def test_operator_flop_models():
     assert bench.fr_operator_flops_per_dof(3) == 43.5
     assert bench.fr_dense_flops_per_dof(3) == 768.0
     assert bench.fr_dense_flops_per_dof(1) == 2.0 * (3 * 8 + 2 * 24)
+
+
+@pytest.mark.parametrize("t,p", [(1, 1), (1, 2), (1, 3), (2, 3)])
+def test_mixed_operator_row_counts_match_the_oracle_operators(t, p):
+    """The mixed-mesh flop model counts, per solution point, the operator
+    entries the kernel reads.  Prisms: the pairs of points on one layer
+    (in-plane derivatives, side-face lifting) or one column (axial
+    derivative, end-face lifting), found here from the oracle's point
+    coordinates; every nonzero entry of the oracle's operators lies among
+    them.  Tetrahedra: dense rows, an upper bound of the nonzeros."""
+    import bench
+    from oracle import mixed as M
+    R = M.ref_element([M.HEX, M.PRISM, M.TET][t], p)
+    x = R.x
+    lift = np.concatenate([fc["lift"] for fc in R.faces], axis=1)
+    assert lift.shape[1] == bench.MIXED_SIZES[p][t][1]
+    tol_d = 1e-12 * max(np.abs(d).max() for d in R.D)
+    tol_l = 1e-12 * np.abs(lift).max()
+    if t == 1:
+        same_z = np.abs(x[:, None, 2] - x[None, :, 2]) < 1e-12
+        same_xy = np.all(np.abs(x[:, None, :2] - x[None, :, :2]) < 1e-12, axis=2)
+        pats = [same_z, same_z, same_xy]
+        cols = []
+        for fc in R.faces:
+            end = len(fc["verts"]) == 3
+            for node in fc["nodes"]:
+                cols.append((same_xy if end else same_z)[:, node])
+        lpat = np.stack(cols, axis=1)
+        for d, pat in zip(R.D, pats):
+            assert np.all(np.abs(d[~pat]) < tol_d)
+        assert np.all(np.abs(lift[~lpat]) < tol_l)
+        assert sum(int(pt.sum()) for pt in pats) + int(lpat.sum()) == R.ns * bench.mixed_row_madds(t, p)
+    else:
+        nz = sum(int((np.abs(d) > tol_d).sum()) for d in R.D) + int((np.abs(lift) > tol_l).sum())
+        assert nz <= R.ns * bench.mixed_row_madds(t, p) == R.ns * (3 * R.ns + lift.shape[1])
