@@ -63,7 +63,7 @@ struct MixType {
     std::vector<int32_t> fnode;  // [nft] solution point of each face point (faces in order)
     std::vector<int32_t> ffac;   // [nft] face of each face point
     std::vector<double> D;       // [3][ns][ns] reference derivatives
-    std::vector<double> lift;    // [ns][nft] correction of a unit jump at each face point
+    std::vector<double> lift;    // [nft][ns] correction of a unit jump at each face point
     std::vector<double> W;       // [ns] integral of each Lagrange function (reference)
     std::vector<int32_t> elems;  // elements of this type
     double *d_D = nullptr, *d_lift = nullptr;

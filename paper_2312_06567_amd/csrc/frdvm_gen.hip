@@ -664,7 +664,7 @@ struct MixArgs {
     const int64_t *poff, *toff, *tnb;     // first point / face point of each element; neighbour face point
     const double *geo;                    // [ne][kMixGeo]
     const float *geof;
-    const double *D, *lift;               // the type's operators
+    const double *D, *lift;               // the type's operators: D [3][ns][ns], lift [nft][ns]
     const float *Df, *liftf;
     const int32_t *fnode, *ffac;          // [nft] solution point and face of each face point
     StageArgs sa;
@@ -771,7 +771,7 @@ __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
 #pragma unroll
                     for (int k = 0; k < PL; ++k) {
                         const int i = m + NT * k;
-                        r[i] = fma(-op.lift[i * NFT + t], jump, r[i]);
+                        r[i] = fma(-op.lift[t * NS + i], jump, r[i]);
                     }
                 }
             }
@@ -786,7 +786,7 @@ __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
 #pragma unroll
                     for (int m = 0; m < NT; ++m) {
                         const int i = m + NT * k;
-                        r[i] = fma(-op.lift[i * NFT + t], jump, r[i]);
+                        r[i] = fma(-op.lift[t * NS + i], jump, r[i]);
                     }
                 }
             }
@@ -795,7 +795,7 @@ __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
             for (int t = 0; t < NFT; ++t) {
                 const Real jump = jump_at(t);
 #pragma unroll
-                for (int i = 0; i < NS; ++i) r[i] = fma(-op.lift[i * NFT + t], jump, r[i]);
+                for (int i = 0; i < NS; ++i) r[i] = fma(-op.lift[t * NS + i], jump, r[i]);
             }
         }
     } else {
@@ -815,7 +815,7 @@ __global__ __launch_bounds__(kGWave) void k_mix_stage(const MixArgs A) {
         for (int t = 0; t < NFT; ++t) {
             const Real jump = jump_at(t);
 #pragma unroll 4
-            for (int i = 0; i < NS; ++i) sa[i][lane] -= op.lift[i * NFT + t] * jump;
+            for (int i = 0; i < NS; ++i) sa[i][lane] -= op.lift[t * NS + i] * jump;
         }
     }
     auto res = [&](int i) -> Real {

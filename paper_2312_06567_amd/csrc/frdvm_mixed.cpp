@@ -8,7 +8,9 @@
 // the solution points, D_a[i][j] = d l_j / d xi_a (x_i), and the correction of
 // a unit jump at face point t of face f, lift[i][t] = (M^-1 E_f)[i][t] with
 // M_ij = int l_i l_j over the element and E_f[i][t] = int over f of
-// l_i l_(node of t).  Derivation: a basis of Legendre products
+// l_i l_(node of t), stored by face point (row t: the column of face point
+// t, contiguous, so that a kernel reading it for one face point reads
+// consecutive entries).  Derivation: a basis of Legendre products
 // P_a(xi) P_b(eta) P_c(zeta) over the type's exponent set (total degree <= p
 // on the tetrahedron; <= p in (xi, eta) times <= p in zeta on the prism;
 // <= p per axis on the hexahedron), its Vandermonde matrix at the solution
@@ -311,7 +313,7 @@ int prism_structure(fr_dvm *h, MixType &T, int p) {
             }
     for (int i = 0; i < ns; ++i)
         for (int t = 0; t < nft; ++t) {
-            double &v = T.lift[(size_t)i * nft + t];
+            double &v = T.lift[(size_t)t * ns + i];
             const bool onto = col[t] >= 0 ? i % nt == col[t] : i / nt == lay[t];
             if (onto) continue;
             if (std::fabs(v) > 1e-9 * lmax) return h->fail(FR_DVM_EINVAL, "prism lifting lacks the layer structure");
@@ -407,7 +409,7 @@ int build_type(fr_dvm *h, MixType &T, int t, int p) {
     T.nft = (int)T.fnode.size();
     T.lift.assign((size_t)ns * T.nft, 0.0);
     for (int tt = 0; tt < T.nft; ++tt)
-        for (int i = 0; i < ns; ++i) T.lift[(size_t)i * T.nft + tt] = cols[tt][i];
+        for (int i = 0; i < ns; ++i) T.lift[(size_t)tt * ns + i] = cols[tt][i];
     return t == FR_DVM_PRISM ? prism_structure(h, T, p) : FR_DVM_OK;
 }
 
