@@ -115,6 +115,23 @@ def test_general_moments_wide_xy_grid(F, orc, model):
     assert rel(Q.cpu().numpy().reshape(s.ne, s.ns, 5), P.moments(f)) < 1e-13
 
 
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_general_moments_point_count_not_a_multiple_of_four(F, orc, model):
+    """The moment pass takes four solution points per workgroup (one wave
+    each); one quadratic-map element at p = 2 has 27, so the last workgroup
+    has a single working wave: 1e-13 against the oracle on a ragged grid."""
+    mesh = W.quadratic_map_mesh(1, eps=0.1, bc_all=1)
+    grid = W.grid_spec((7, 6, 5), 5.0)
+    par = _params(model=model, prandtl=2.0 / 3.0 if model == 1 else 1.0)
+    P = _oracle(orc, mesh, 2, grid, par)
+    f = _state(P, grid, 9)
+    s = F.FrDvm(mesh, 2, grid, par)
+    assert (s.ne * s.ns) % 4 == 3
+    Q = torch.zeros(s.ne * s.ns * 5, dtype=torch.float64, device="cuda")
+    s.moments(_gpu(s, f), Q)
+    assert rel(Q.cpu().numpy().reshape(s.ne, s.ns, 5), P.moments(f)) < 1e-13
+
 def test_general_collide_es(F, orc):
     mesh = _small_cylinder()
     par = _params(model=1, prandtl=2.0 / 3.0, mu_ref=0.02)
